@@ -1,0 +1,136 @@
+"""Pins of the oracle's Gauss-Newton-Krylov solver (section III-A of the
+paper: Armijo-globalised Newton, inexact PCG with a gradient-dependent
+tolerance, the inverse biharmonic preconditioner, beta continuation) and of
+its failure paths. The paper prints no per-iteration values, so parity with
+the paper itself is unpinned; these tests check what must hold for any
+correct run plus the stored oracle regression fixture."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TWO_PI = 2 * np.pi
+
+
+def inner(u, w):
+    h3 = np.prod([TWO_PI / m for m in u.shape[-3:]])
+    return h3 * float(np.sum(u * w))
+
+
+@pytest.fixture(scope="module")
+def smooth32(orc):
+    shape = (32, 32, 32)
+    c = synth.smooth_case(shape)
+    P = orc.params(shape, 4, 1e-2, max_newton=5)
+    rhoR = orc.transport_forward(P, c["v_true"], c["rhoT"])
+    return shape, c["rhoT"], rhoR
+
+
+def test_smooth_case_converges_monotonically(orc, smooth32):
+    shape, rhoT, rhoR = smooth32
+    P = orc.params(shape, 4, 1e-2, max_newton=5)
+    J0, _ = orc.objective(P, rhoT, rhoR, np.zeros((3,) + shape))
+    v, rep = orc.solve(P, rhoT, rhoR)
+    assert rep["status"] == 0 and rep["stop_reason"] == 0
+    J = [J0] + rep["J"]
+    assert all(J[i + 1] < J[i] for i in range(len(J) - 1)), J
+    assert rep["grel"][-1] <= 1e-2
+    # the reported final values are those of the returned velocity
+    g, Jv, mis = orc.gradient(P, rhoT, rhoR, v)
+    assert abs(Jv - rep["final_J"]) <= 1e-12 * Jv
+    assert abs(mis - rep["final_mismatch"]) <= 1e-12
+
+
+def test_matches_stored_oracle_fixture(orc, smooth32):
+    """Regression against the report written by tests/golden/make_golden.py."""
+    shape, rhoT, rhoR = smooth32
+    with open(os.path.join(HERE, "golden", "smooth32_solve.json")) as f:
+        gold = json.load(f)
+    P = orc.params(shape, 4, 1e-2, max_newton=5)
+    _, rep = orc.solve(P, rhoT, rhoR)
+    assert rep["pcg_iters"] == gold["pcg_iters"]
+    assert np.allclose(rep["J"], gold["J"], rtol=1e-10, atol=0)
+    assert np.allclose(rep["mismatch"], gold["mismatch"], rtol=1e-10, atol=0)
+
+
+def test_mismatch_stop(orc, smooth32):
+    shape, rhoT, rhoR = smooth32
+    P = orc.params(shape, 4, 1e-2, max_newton=5, mismatch_tol=0.8)
+    _, rep = orc.solve(P, rhoT, rhoR)
+    assert rep["stop_reason"] == 1 and rep["n_iter"] >= 1
+    assert rep["mismatch"][-1] <= 0.8 and all(m > 0.8 for m in rep["mismatch"][:-1])
+
+
+def test_line_search_failure_keeps_velocity(orc, smooth32):
+    """With no line-search trials allowed no step can be accepted: the solver
+    reports the failure and leaves v at its input."""
+    shape, rhoT, rhoR = smooth32
+    P = orc.params(shape, 4, 1e-2, max_newton=5, max_ls=0)
+    v0 = 0.01 * synth.smooth_velocity_paper(shape)
+    v, rep = orc.solve(P, rhoT, rhoR, v0)
+    assert rep["status"] == 6
+    assert np.array_equal(v, v0)
+
+
+def test_beta_continuation_levels(orc):
+    shape = (16, 16, 16)
+    c = synth.smooth_case(shape)
+    P0 = orc.params(shape, 4, 1e-2)
+    rhoR = orc.transport_forward(P0, c["v_true"], c["rhoT"])
+    P = orc.params(shape, 4, 1e-1, beta_final=1e-3, beta_factor=0.1, max_newton=4)
+    _, rep = orc.solve(P, c["rhoT"], rhoR)
+    levels = sorted(set(rep["beta"]), reverse=True)
+    assert np.allclose(levels, [1e-1, 1e-2, 1e-3][: len(levels)]) and len(levels) >= 2
+    # mismatch improves as beta falls
+    assert rep["mismatch"][-1] < rep["mismatch"][0]
+
+
+def test_isochoric_solve_stays_divergence_free(orc):
+    shape = (16, 16, 16)
+    b = synth.blob_case(shape)
+    P = orc.params(shape, 4, 1e-3, isochoric=True, max_newton=3)
+    rhoR = orc.transport_forward(P, b["v_true"], b["rhoT"])
+    v, rep = orc.solve(P, b["rhoT"], rhoR)
+    assert rep["status"] == 0 and rep["n_iter"] >= 1
+    dv = orc.div(v)
+    assert np.sqrt(inner(dv, dv)) <= 1e-12 * np.sqrt(inner(v, v))
+
+
+def test_preconditioned_cg_reduces_the_residual(orc, smooth32):
+    """One Newton system solved to a tight tolerance: the Hessian is SPD at
+    v = 0, so PCG from s = 0 must bring ||H s + g|| below eta ||g||."""
+    shape, rhoT, rhoR = smooth32
+    P = orc.params(shape, 4, 1e-2)
+    v0 = np.zeros((3,) + shape)
+    g, _, _ = orc.gradient(P, rhoT, rhoR, v0)
+    # plain PCG written out here against the oracle's operators
+    s = np.zeros_like(g)
+    r = -g
+    z = orc.precond(r, 1e-2)
+    p = z.copy()
+    rz = inner(r, z)
+    for _ in range(30):
+        q = orc.hessian_matvec(P, rhoT, v0, p)
+        a = rz / inner(p, q)
+        s += a * p
+        r -= a * q
+        if np.sqrt(inner(r, r)) <= 1e-6 * np.sqrt(inner(g, g)):
+            break
+        z = orc.precond(r, 1e-2)
+        rz1 = inner(r, z)
+        p = z + rz1 / rz * p
+        rz = rz1
+    res = orc.hessian_matvec(P, rhoT, v0, s) + g
+    assert np.sqrt(inner(res, res)) <= 1e-6 * np.sqrt(inner(g, g))
+
+
+def test_paper_parameters_fixture():
+    """The paper's stated run parameters (section IV-A3), stored with their
+    citation, are what the solver defaults must encode."""
+    with open(os.path.join(HERE, "golden", "paper_parameters.json")) as f:
+        gold = json.load(f)
+    assert gold["beta"] == 1e-2 and gold["nt"] == 4 and gold["gtol"] == 1e-2
