@@ -1,0 +1,200 @@
+/*
+ * reg.h -- C ABI of the MI355X (gfx950) semi-Lagrangian Gauss-Newton-Krylov
+ * diffeomorphic registration library (method of Mang, Gholami and Biros,
+ * "Distributed-memory large deformation diffeomorphic 3D image
+ * registration", SC16).
+ *
+ * Problem (section II-B, eq. (2)): given a template rho_T and a reference
+ * rho_R on the periodic box [0, 2*pi)^3, find a stationary velocity v that
+ * minimises J(v) = 1/2 ||rho(1) - rho_R||^2 + beta/2 ||lap v||^2 subject to
+ * the transport equation d_t rho + v . grad rho = 0, rho(0) = rho_T, and
+ * optionally div v = 0.
+ *
+ * Conventions shared by every entry point
+ *  - Grid: n[0] x n[1] x n[2] points x_i = 2*pi*i/n (section III-B1); arrays
+ *    are C-order [n0][n1][n2], x3 fastest. A vector field is three such
+ *    arrays back to back ([3][n0][n1][n2]).
+ *  - Element type: float when params.prec == 0, double when prec == 1. Every
+ *    field pointer is a DEVICE pointer on the device that was current at
+ *    reg_create, contiguous, aligned to its element size.
+ *  - Semi-Lagrangian points are stored as displacements in cell units,
+ *    D = (X - x)/h per axis, in the same element type.
+ *  - Ownership: the caller owns every buffer it passes, including the
+ *    workspace handed to reg_create (sized by reg_workspace_size). The
+ *    library allocates no device memory; it keeps views into the workspace
+ *    and a small pinned host buffer for scalar read-back.
+ *  - Streams: all work is enqueued on the stream given to reg_create, in
+ *    call order. Calls that return host scalars (reg_gradient, reg_solve,
+ *    reg_deformation, reg_objective, reg_dot) synchronise that stream.
+ *  - Errors: every call returns a reg_status; no C++ exception crosses the
+ *    ABI. Arguments are checked before any kernel is launched; on REG_EINVAL
+ *    nothing was enqueued. reg_last_error gives a message for the most recent
+ *    failing call on a context.
+ *  - Threading: one context per stream; a context is not re-entrant.
+ *  - Inner products are the grid L2 ones, <u,w> = h1 h2 h3 sum u*w, and all
+ *    reductions accumulate in double precision whatever the field type.
+ */
+#ifndef REG_H
+#define REG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct reg_ctx reg_ctx;
+
+typedef enum {
+    REG_OK = 0,
+    REG_EINVAL = 1,       /* bad argument or shape; nothing was enqueued        */
+    REG_ENOMEM = 2,       /* workspace smaller than reg_workspace_size          */
+    REG_EHIP = 3,         /* a HIP runtime call failed                          */
+    REG_ENONFINITE = 4,   /* NaN/Inf met in an objective, norm or PCG product   */
+    REG_ENOTCONV = 5,     /* reserved                                            */
+    REG_ELINESEARCH = 6,  /* Armijo search found no acceptable step              */
+    REG_ENONDIFFEO = 7,   /* reserved                                            */
+    REG_ENOTIMPL = 8
+} reg_status;
+
+/* Discretisation and solver settings. reg_default_params fills the values of
+ * the paper's runs (section IV-A3): beta = 1e-2, nt = 4, gradient tolerance
+ * 1e-2, quadratic forcing, no continuation, no incompressibility. */
+typedef struct {
+    int32_t n[3];          /* grid; each even, 2^a 3^b, 8 <= n <= 1024            */
+    int32_t nt;            /* time steps, >= 1                                    */
+    double beta;           /* regularisation weight (> 0); first continuation level */
+    double beta_final;     /* last continuation level; <= 0 means no continuation */
+    double beta_factor;    /* continuation factor in (0, 1); default 0.1           */
+    int32_t isochoric;     /* 1: enforce div v = 0 (Leray projection)              */
+    int32_t prec;          /* 0: float fields, 1: double fields                    */
+    double gtol;           /* stop a level at ||g|| <= gtol ||g0||                 */
+    double mismatch_tol;   /* > 0: stop the solve at ||rho1-rhoR||/||rhoT-rhoR|| <= tol */
+    int32_t max_newton;    /* Newton steps per continuation level                  */
+    int32_t max_pcg;       /* PCG iterations per Newton step                       */
+    int32_t max_ls;        /* Armijo trials per Newton step                        */
+    int32_t forcing;       /* 0: eta = min(.5, r); 1: eta = min(.5, sqrt r); r = ||g||/||g0|| */
+    double armijo_c1;      /* sufficient-decrease constant                         */
+} reg_params;
+
+#define REG_MAXIT 512
+
+/* What reg_solve did, per accepted Newton step and in total. */
+typedef struct {
+    int32_t status;        /* the reg_status the solve returned                    */
+    int32_t n_iter;        /* accepted Newton steps (entries below)                */
+    int32_t matvecs, gradients, objectives;
+    int32_t stop_reason;   /* 0 gradient tolerance, 1 mismatch, 2 step limit       */
+    double J[REG_MAXIT], mismatch[REG_MAXIT], grel[REG_MAXIT], alpha[REG_MAXIT], beta[REG_MAXIT];
+    int32_t pcg_iters[REG_MAXIT], ls_trials[REG_MAXIT];
+    double final_J, final_mismatch, final_grel;
+    double seconds_total;  /* host wall clock of the solve                         */
+    double seconds_matvec, seconds_gradient, seconds_objective, seconds_precond;
+    int64_t interps;       /* scalar field interpolations of n0*n1*n2 points       */
+} reg_report;
+
+/* Fills *p with the paper's defaults for an n^3 grid (section IV-A3). */
+reg_status reg_default_params(reg_params *p);
+
+/* Bytes of device workspace a context with these parameters needs. */
+reg_status reg_workspace_size(const reg_params *p, size_t *bytes);
+
+/* Creates a context over a caller-owned device workspace of at least
+ * reg_workspace_size bytes (256-byte aligned). hip_stream is a hipStream_t
+ * (NULL = the null stream). Uploads twiddle tables on that stream. */
+reg_status reg_create(const reg_params *p, void *workspace, size_t bytes, void *hip_stream, reg_ctx **out);
+
+/* Frees the context (not the workspace). */
+reg_status reg_destroy(reg_ctx *ctx);
+
+/* Message of the last failing call on ctx ("" if none); valid until the next call. */
+const char *reg_last_error(const reg_ctx *ctx);
+
+/* Changes beta (> 0) used by reg_gradient, reg_hessian_matvec, reg_precond. */
+reg_status reg_set_beta(reg_ctx *ctx, double beta);
+
+/* Copies rho_T and rho_R (device fields) into the context and records
+ * ||rho_T - rho_R|| for the relative mismatch. Invalidates cached state. */
+reg_status reg_set_images(reg_ctx *ctx, const void *rho_T, const void *rho_R);
+
+/* ---------------------------------------------------------------- kernels */
+
+/* out(x_i) = f(x_i + h D_i) by periodic tricubic Lagrange interpolation on the
+ * 4x4x4 stencil m-1..m+2 per axis, m = i + floor(D), t = D - floor(D)
+ * (sections III-B2, III-C2). f, out: fields; D: vector field (cell units).
+ * out must not alias f. */
+reg_status reg_interp(reg_ctx *ctx, const void *f, const void *D, void *out);
+
+/* RK2 departure points of the velocity sign*v for one step dt = 1/nt
+ * (eq. (6)): X* = x - dt u(x), X = x - dt/2 (u(x) + u(X*)), u = sign*v,
+ * returned as D = (X - x)/h. sign must be +1 or -1. D must not alias v. */
+reg_status reg_backtrace(reg_ctx *ctx, const void *v, double sign, void *D);
+
+/* Spectral derivative along axis (0, 1, 2) by line FFTs with symbol i k~
+ * (Nyquist dropped) (section III-B1 and the line-FFT remark of III-C1). */
+reg_status reg_deriv(reg_ctx *ctx, int axis, const void *u, void *du);
+
+/* g = grad u (vector field) and d = div v (scalar), spectral as above. */
+reg_status reg_grad(reg_ctx *ctx, const void *u, void *g);
+reg_status reg_div(reg_ctx *ctx, const void *v, void *d);
+
+/* Even and projection operators on vector fields by 3D real FFTs:
+ *  op 0: out = scale * lap^2 v            (symbol scale*|k|^4)
+ *  op 1: out = (scale * lap^2)^-1 v       (identity on the k = 0 mode)
+ *  op 2: out = Gaussian filter of width scale (radians), exp(-scale^2 |k|^2/2)
+ *  op 3: out = P v, P = I - grad lap^-1 div (Leray; eq. (4))
+ * ncomp is 1 or 3 (op 3 needs 3). out may alias v. */
+reg_status reg_spectral(reg_ctx *ctx, int op, double scale, int ncomp, const void *v, void *out);
+
+/* Spectral preconditioner of section III-A: z^ = r^/(beta |k|^4) for k != 0,
+ * z^_0 = r^_0, followed by P when isochoric. z may alias r. */
+reg_status reg_precond(reg_ctx *ctx, const void *r, void *z);
+
+/* ------------------------------------------------------ transport solves */
+
+/* State solve (eq. (2b)) with the RK2 semi-Lagrangian scheme (eqs. (6),(7)):
+ * rho1 = rho(1) for rho(0) = rho0 under v. Does not disturb the state cached
+ * by reg_gradient. */
+reg_status reg_transport_forward(reg_ctx *ctx, const void *v, const void *rho0, void *rho1);
+
+/* Adjoint solve (eq. (3)) backward from lam(1) = lam1 to lam0 = lam(0),
+ * written in tau = 1 - t as transport by -v with source lam*div v (dropped
+ * when isochoric). Does not disturb the cached state. */
+reg_status reg_transport_adjoint(reg_ctx *ctx, const void *v, const void *lam1, void *lam0);
+
+/* Reduced gradient g(v) = beta lap^2 v + P int_0^1 lam grad rho dt (eq. (4)),
+ * plus J(v), the relative mismatch ||rho1 - rhoR|| / ||rhoT - rhoR|| and
+ * ||g||. Needs reg_set_images. Caches the plans, the state history, grad rho
+ * at every time level and div v for reg_hessian_matvec. Any of J, mismatch,
+ * gnorm may be NULL. Synchronises. */
+reg_status reg_gradient(reg_ctx *ctx, const void *v, void *g, double *J, double *mismatch, double *gnorm);
+
+/* Objective and relative mismatch only (plan + state solve). Synchronises. */
+reg_status reg_objective(reg_ctx *ctx, const void *v, double *J, double *mismatch);
+
+/* Gauss-Newton Hessian matvec at the velocity of the last reg_gradient
+ * (eqs. (5a)-(5e) without the two adjoint terms, section II-B): incremental
+ * state, incremental adjoint, H vt = beta lap^2 vt + P b~. */
+reg_status reg_hessian_matvec(reg_ctx *ctx, const void *vt, void *Hvt);
+
+/* Gauss-Newton-Krylov solve (section III-A): truncated PCG with the spectral
+ * preconditioner and forcing eta, Armijo backtracking, beta continuation
+ * from params.beta to params.beta_final. v_inout holds the initial velocity
+ * (zero for a cold start) and receives the result; on REG_ELINESEARCH it
+ * holds the last accepted iterate. rep may be NULL. Synchronises. */
+reg_status reg_solve(reg_ctx *ctx, void *v_inout, reg_report *rep);
+
+/* Deformation map of eq. (1) through u = y1 - x, transported like the state
+ * (u^{n+1} = u^n(X) + h D), and min/max of det(I + grad u) over the grid.
+ * u_or_null receives u (vector field) when not NULL. Synchronises. */
+reg_status reg_deformation(reg_ctx *ctx, const void *v, void *u_or_null, double *detmin, double *detmax);
+
+/* <a, b> over ncomp components in double precision (h1 h2 h3 weights). */
+reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REG_H */

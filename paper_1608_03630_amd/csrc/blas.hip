@@ -1,0 +1,233 @@
+// Vector updates and double-precision reductions for the Newton-Krylov
+// driver (section III-A of the paper: matrix-free PCG and Armijo line search
+// over grid vectors). Reductions are deterministic: a fixed grid of blocks
+// reduces by wavefront shuffles (64 lanes) and a fixed-order block sum, and
+// one block adds the per-block partials in index order, so repeated runs give
+// bitwise identical scalars.
+#include "common.hpp"
+
+namespace regk {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_down(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_dot_partials(const T *__restrict__ a, const T *__restrict__ b, long n,
+                                                           int mode, double *__restrict__ partials) {
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads) {
+        const double x = (double)a[i];
+        if (mode == 0) acc += x * (double)b[i];
+        else if (mode == 1) {
+            const double d = x - (double)b[i];
+            acc += d * d;
+        } else acc += x * x;
+    }
+    acc = wave_sum(acc);
+    __shared__ double ws[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; i++) t += ws[i];
+        partials[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nparts, double scale,
+                                                       double *__restrict__ out) {
+    // each thread sums a strided subset in order, then a fixed tree
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) acc += partials[i];
+    acc = wave_sum(acc);
+    __shared__ double ws[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; i++) t += ws[i];
+        out[0] = scale * t;
+    }
+}
+
+// det of F = I + grad u with F_ab = delta_ab + d_b u_a, du[(a*3+b)*n + i]
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_det_partials(const T *__restrict__ du, long n,
+                                                           double *__restrict__ pmin, double *__restrict__ pmax,
+                                                           T *__restrict__ det_out) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < n; i += (long)gridDim.x * kThreads) {
+        double F[3][3];
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) F[a][b] = (a == b ? 1.0 : 0.0) + (double)du[(a * 3 + b) * n + i];
+        const double d = F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) -
+                         F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+                         F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+        if (det_out) det_out[i] = (T)d;
+        mn = fmin(mn, d);
+        mx = fmax(mx, d);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    __shared__ double wmn[kThreads / 64], wmx[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wmn[threadIdx.x >> 6] = mn;
+        wmx[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kThreads / 64; i++) {
+            mn = fmin(mn, wmn[i]);
+            mx = fmax(mx, wmx[i]);
+        }
+        mn = fmin(mn, wmn[0]);
+        mx = fmax(mx, wmx[0]);
+        pmin[blockIdx.x] = mn;
+        pmax[blockIdx.x] = mx;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize_minmax(const double *__restrict__ pmin,
+                                                              const double *__restrict__ pmax, int nparts,
+                                                              double *__restrict__ out2) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int i = threadIdx.x; i < nparts; i += kThreads) {
+        mn = fmin(mn, pmin[i]);
+        mx = fmax(mx, pmax[i]);
+    }
+    mn = wave_min(mn);
+    mx = wave_max(mx);
+    __shared__ double wmn[kThreads / 64], wmx[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wmn[threadIdx.x >> 6] = mn;
+        wmx[threadIdx.x >> 6] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kThreads / 64; i++) {
+            mn = fmin(mn, wmn[i]);
+            mx = fmax(mx, wmx[i]);
+        }
+        out2[0] = mn;
+        out2[1] = mx;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_axpby(long n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_xpay(long n, const T *__restrict__ x, T a, const T *__restrict__ y,
+                                                   T *__restrict__ z) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) z[i] = x[i] + a * y[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_cg_update(long n, T a, const T *__restrict__ p, const T *__restrict__ q,
+                                                        T *__restrict__ s, T *__restrict__ r) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) {
+        s[i] += a * p[i];
+        r[i] -= a * q[i];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fill(long n, T v, T *__restrict__ y) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_copy(long n, const T *__restrict__ x, T *__restrict__ y) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = x[i];
+}
+
+inline unsigned nb(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_dot_partials(const T *a, const T *b, long n, int mode, double *partials, hipStream_t s) {
+    hipLaunchKernelGGL(k_dot_partials<T>, dim3(RED_BLOCKS), dim3(kThreads), 0, s, a, b, n, mode, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double *partials, int nparts, double scale, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nparts, scale, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_det_partials(const T *du, long n, double *pmin, double *pmax, T *det_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_det_partials<T>, dim3(RED_BLOCKS), dim3(kThreads), 0, s, du, n, pmin, pmax, det_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_minmax(const double *pmin, const double *pmax, int nparts, double *out2, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_minmax, dim3(1), dim3(kThreads), 0, s, pmin, pmax, nparts, out2);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axpby(long n, double a, const T *x, double b, T *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpby<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(a), x, T(b), y);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xpay(long n, const T *x, double a, const T *y, T *z, hipStream_t s) {
+    hipLaunchKernelGGL(k_xpay<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, x, T(a), y, z);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(long n, double a, const T *p, const T *q, T *sv, T *r, hipStream_t s) {
+    hipLaunchKernelGGL(k_cg_update<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(a), p, q, sv, r);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill(long n, double val, T *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(val), y);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy(long n, const T *x, T *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, x, y);
+    return hipGetLastError();
+}
+
+#define REGK_BLAS_INST(T)                                                                                          \
+    template hipError_t launch_dot_partials<T>(const T *, const T *, long, int, double *, hipStream_t);            \
+    template hipError_t launch_det_partials<T>(const T *, long, double *, double *, T *, hipStream_t);             \
+    template hipError_t launch_axpby<T>(long, double, const T *, double, T *, hipStream_t);                        \
+    template hipError_t launch_xpay<T>(long, const T *, double, const T *, T *, hipStream_t);                      \
+    template hipError_t launch_cg_update<T>(long, double, const T *, const T *, T *, T *, hipStream_t);            \
+    template hipError_t launch_fill<T>(long, double, T *, hipStream_t);                                            \
+    template hipError_t launch_copy<T>(long, const T *, T *, hipStream_t);
+
+REGK_BLAS_INST(float)
+REGK_BLAS_INST(double)
+
+}  // namespace regk

@@ -1,0 +1,119 @@
+// Internal declarations shared by the HIP translation units of libreg.
+// Grid geometry, complex helpers and the host-side launchers that the C ABI
+// layer (capi.hip) drives. Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace regk {
+
+// A regular periodic grid [n1][n2][n3], x3 fastest.
+struct Grid {
+    int n1, n2, n3;
+    __host__ __device__ long N() const { return (long)n1 * n2 * n3; }
+    __host__ __device__ int n3h() const { return n3 / 2 + 1; }
+    __host__ __device__ long Nh() const { return (long)n1 * n2 * n3h(); }
+};
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using cplx_t = typename cplx_of<T>::type;
+
+// Radix plan of one line length: radices 4, then 2, then 3 (Stockham order).
+struct FftPlan {
+    int n;
+    int npass;
+    int radix[12];
+};
+
+bool make_plan(int n, FftPlan *p);
+
+// ------------------------------------------------------------------ interp.hip
+// Every launcher enqueues on `s` and returns the hipError_t of the launch.
+template <typename T>
+hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStream_t s);
+template <typename T>
+hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hipStream_t s);
+// adjoint-type step: lam_out = Heun step of nu with source nu*c (if c), and
+// b += wn * lam_out * grad (if b); lam_out may be null when b is set.
+template <typename T>
+hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *c, const T *cX,
+                               const T *grad, T *b, T *lam_out, double dt, double wn, hipStream_t s);
+// lam = rhoR - rho1 (or -scale*src): initial adjoint level; b = w * lam * grad
+template <typename T>
+hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, const T *grad, T *lam, T *b, double w,
+                               hipStream_t s);
+// incremental state: q_out = interp(q_in, Df) + cs * (vt . grad); with last,
+// lam_out = -(that) and b = w * lam_out * grad
+template <typename T>
+hipError_t launch_incstate_step(const Grid &g, const T *q_in, const T *Df, const T *vt, const T *grad, T *q_out,
+                                double cs, int last, T *b, double w, hipStream_t s);
+template <typename T>
+hipError_t launch_incstate_init(const Grid &g, const T *vt, const T *grad, T *q, double cs, hipStream_t s);
+template <typename T>
+hipError_t launch_deform_step(const Grid &g, const T *u_in, const T *Df, T *u_out, hipStream_t s);
+
+// --------------------------------------------------------------------- fft.hip
+struct SpecCtx {
+    Grid g;
+    FftPlan plan[3];
+    const void *tw[3];   // per-axis twiddles exp(-2 pi i m / n_axis), element type complex T
+    void *H;             // half-spectrum buffer of up to 6 components, complex T
+};
+// derivative along axis of ncomp fields u + k*in_stride into out + k*out_stride
+// (accumulate: out += d_axis u)
+template <typename T>
+hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T *out, long out_stride, int accumulate,
+                      int ncomp, hipStream_t s);
+// forward 3D real FFT of ncomp fields into H components [h0, h0+ncomp)
+template <typename T>
+hipError_t spec_forward(const SpecCtx &c, const T *x, int ncomp, int h0, hipStream_t s);
+// inverse 3D FFT of H components [0, ncomp) into real fields (divides by N)
+template <typename T>
+hipError_t spec_inverse(const SpecCtx &c, T *out, int ncomp, hipStream_t s);
+
+enum SymbolOp {
+    SYM_BIHARM = 0,      // H_c *= a |k|^4
+    SYM_INVBIHARM = 1,   // H_c *= 1/(a |k|^4), 1 at k = 0
+    SYM_GAUSS = 2,       // H_c *= exp(-a^2 |k|^2 / 2)
+    SYM_LERAY = 3,       // H_0..2 = P H_0..2
+    SYM_PRECOND = 4,     // inverse biharmonic, then P if flag
+    SYM_ASSEMBLE = 5     // H_c = a |k|^4 H_c + [P] H_{3+c}, c < 3
+};
+template <typename T>
+hipError_t spec_symbol(const SpecCtx &c, int op, double a, int ncomp, int leray, hipStream_t s);
+// partial sums over blocks of sum_k w(k3) |k|^4 |H_c|^2, c < 3 -> partials (double)
+template <typename T>
+hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s);
+
+// -------------------------------------------------------------------- blas.hip
+constexpr int RED_BLOCKS = 1024;
+constexpr int RED_THREADS = 256;
+// partials[b] = sum over block b of a*b (mode 0), (a-b)^2 (mode 1), a*a (mode 2)
+template <typename T>
+hipError_t launch_dot_partials(const T *a, const T *b, long n, int mode, double *partials, hipStream_t s);
+// out[slot] = scale * sum(partials[0..nparts)) in a fixed order
+hipError_t launch_finalize(const double *partials, int nparts, double scale, double *out, hipStream_t s);
+// det(I + grad u) per point from du[9][N] (du[a*3+b] = d_b u_a); per-block min and max
+template <typename T>
+hipError_t launch_det_partials(const T *du, long n, double *pmin, double *pmax, T *det_out, hipStream_t s);
+hipError_t launch_finalize_minmax(const double *pmin, const double *pmax, int nparts, double *out2, hipStream_t s);
+// y = a*x + b*y
+template <typename T>
+hipError_t launch_axpby(long n, double a, const T *x, double b, T *y, hipStream_t s);
+// z = x + a*y
+template <typename T>
+hipError_t launch_xpay(long n, const T *x, double a, const T *y, T *z, hipStream_t s);
+// s += a p; r -= a q
+template <typename T>
+hipError_t launch_cg_update(long n, double a, const T *p, const T *q, T *sv, T *r, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(long n, double val, T *y, hipStream_t s);
+template <typename T>
+hipError_t launch_copy(long n, const T *x, T *y, hipStream_t s);
+
+}  // namespace regk

@@ -1,0 +1,625 @@
+// Spectral kernels for gfx950 (section III-B1 of the paper: Fourier
+// discretisation on the periodic grid; section III-C1: derivatives need only
+// 1D FFTs along the differentiated axis, while P, lap^2 and lap^-2 are
+// diagonal after a full 3D transform).
+//
+// All transforms are line FFTs in LDS: a workgroup stages L complex lines of
+// one axis as a [j][l] tile (pitch >= L), runs a Stockham autosort FFT with
+// radix-4/2/3 passes between two LDS buffers, and writes the tile back. For
+// the x1 and x2 axes the L lines are L adjacent x3 columns, so every global
+// access is a coalesced row of L complex values; for the contiguous x3 axis
+// the lines are loaded along x3 and transposed into the tile. Real data is
+// packed two lines per complex line: a derivative symbol i k~ is Hermitian,
+// so the real and imaginary parts of the inverse are the two derivatives;
+// the R2C/C2R passes split and merge the two half spectra explicitly.
+#include "common.hpp"
+
+namespace regk {
+
+bool make_plan(int n, FftPlan *p) {
+    p->n = n;
+    p->npass = 0;
+    int m = n;
+    while (m % 4 == 0 && p->npass < 12) {
+        p->radix[p->npass++] = 4;
+        m /= 4;
+    }
+    while (m % 2 == 0 && p->npass < 12) {
+        p->radix[p->npass++] = 2;
+        m /= 2;
+    }
+    while (m % 3 == 0 && p->npass < 12) {
+        p->radix[p->npass++] = 3;
+        m /= 3;
+    }
+    return m == 1;
+}
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+    C r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+    C r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+    C r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+// multiply by sign*i
+template <typename C>
+__device__ __forceinline__ C cmul_si(C a, int sign) {
+    C r;
+    r.x = sign > 0 ? -a.y : a.y;
+    r.y = sign > 0 ? a.x : -a.x;
+    return r;
+}
+
+// R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4}
+template <typename T>
+__device__ __forceinline__ void butterfly(cplx_t<T> *v, int R, int sign) {
+    using C = cplx_t<T>;
+    if (R == 4) {
+        const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+        const C s13 = cadd(v[1], v[3]), d13 = cmul_si(csub(v[1], v[3]), sign);
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+    } else if (R == 2) {
+        const C a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    } else {  // R == 3
+        const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
+        const C s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        C m;
+        m.x = v[0].x - T(0.5) * s.x;
+        m.y = v[0].y - T(0.5) * s.y;
+        C e = cmul_si(d, sign);
+        e.x *= h;
+        e.y *= h;
+        v[0] = cadd(v[0], s);
+        v[1] = cadd(m, e);
+        v[2] = csub(m, e);
+    }
+}
+
+// Stockham FFT of L lines held in LDS as element (j, l) at a[j*pitch + l].
+// tw[m] = exp(-2 pi i m / n); the inverse uses the conjugate. Returns the
+// buffer that holds the result; ends with a barrier.
+template <typename T>
+__device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int L, int pitch, int sign,
+                              const cplx_t<T> *__restrict__ tw) {
+    using C = cplx_t<T>;
+    const int n = pl.n;
+    int Ns = 1;
+    for (int ps = 0; ps < pl.npass; ps++) {
+        const int R = pl.radix[ps];
+        const int nr = n / R;
+        const int tstep = n / (Ns * R);
+        for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
+            const int l = e % L, j = e / L;
+            const int k = j % Ns;
+            C v[4];
+            for (int r = 0; r < R; r++) v[r] = a[(j + r * nr) * pitch + l];
+            for (int r = 1; r < R; r++) {
+                C w = tw[r * k * tstep];
+                if (sign > 0) w.y = -w.y;
+                v[r] = cmul(v[r], w);
+            }
+            butterfly<T>(v, R, sign);
+            const int d = (j / Ns) * Ns * R + k;
+            for (int r = 0; r < R; r++) b[(d + r * Ns) * pitch + l] = v[r];
+        }
+        __syncthreads();
+        C *t = a;
+        a = b;
+        b = t;
+        Ns *= R;
+    }
+    return a;
+}
+
+// wavenumber of index m on an axis of length n, and its odd variant (Nyquist -> 0)
+__device__ __forceinline__ int kwave(int m, int n) { return 2 * m <= n ? m : m - n; }
+__device__ __forceinline__ int kwave_odd(int m, int n) { return 2 * m == n ? 0 : kwave(m, n); }
+
+// ----------------------------------------------------------- derivatives
+
+// Lines along axis 0 or 1 of a real field: the tile holds L complex columns,
+// each the pair of adjacent x3 columns (2l, 2l+1) of the block.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
+                                                            int axis, const T *__restrict__ u, long in_stride,
+                                                            T *__restrict__ out, long out_stride, int accumulate,
+                                                            int L) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + (long)pl.n * L;
+    const int ncol = g.n3 / 2;
+    const int nb3 = (ncol + L - 1) / L;
+    const int outer = blockIdx.x / nb3, cb = blockIdx.x % nb3;
+    const int leff = min(L, ncol - cb * L);
+    long base, stride;
+    if (axis == 1) {
+        base = (long)outer * g.n2 * g.n3 + 2L * cb * L;
+        stride = g.n3;
+    } else {
+        base = (long)outer * g.n3 + 2L * cb * L;
+        stride = (long)g.n2 * g.n3;
+    }
+    const T *src = u + blockIdx.y * in_stride;
+    T *dst = out + blockIdx.y * out_stride;
+    const int n = pl.n;
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (l < leff) z = *reinterpret_cast<const C *>(src + base + j * stride + 2 * l);
+        A[j * L + l] = z;
+    }
+    __syncthreads();
+    C *R = lds_fft<T>(A, B, pl, L, L, -1, tw);
+    const T inv = T(1) / T(n);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        const T f = T(kwave_odd(j, n)) * inv;
+        const C z = R[j * L + l];
+        C w;
+        w.x = -f * z.y;
+        w.y = f * z.x;
+        R[j * L + l] = w;
+    }
+    __syncthreads();
+    C *Q = lds_fft<T>(R, R == A ? B : A, pl, L, L, +1, tw);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        if (l >= leff) continue;
+        C *p = reinterpret_cast<C *>(dst + base + j * stride + 2 * l);
+        C z = Q[j * L + l];
+        if (accumulate) {
+            const C o = *p;
+            z.x += o.x;
+            z.y += o.y;
+        }
+        *p = z;
+    }
+}
+
+// Lines along the contiguous x3 axis: L complex lines, each the pair of real
+// lines (r0 + 2l, r0 + 2l + 1) with r = i1*n2 + i2.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_deriv_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
+                                                       const T *__restrict__ u, long in_stride, T *__restrict__ out,
+                                                       long out_stride, int accumulate, int L) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pitch = L + 1;
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + (long)pl.n * pitch;
+    const int n = pl.n;  // == n3
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    const T *src = u + blockIdx.y * in_stride;
+    T *dst = out + blockIdx.y * out_stride;
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int j = e % n, l = e / n;
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (l < leff) {
+            z.x = src[(r0 + 2 * l) * n + j];
+            z.y = src[(r0 + 2 * l + 1) * n + j];
+        }
+        A[j * pitch + l] = z;
+    }
+    __syncthreads();
+    C *R = lds_fft<T>(A, B, pl, L, pitch, -1, tw);
+    const T inv = T(1) / T(n);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        const T f = T(kwave_odd(j, n)) * inv;
+        const C z = R[j * pitch + l];
+        C w;
+        w.x = -f * z.y;
+        w.y = f * z.x;
+        R[j * pitch + l] = w;
+    }
+    __syncthreads();
+    C *Q = lds_fft<T>(R, R == A ? B : A, pl, L, pitch, +1, tw);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int j = e % n, l = e / n;
+        if (l >= leff) continue;
+        const C z = Q[j * pitch + l];
+        T *p0 = dst + (r0 + 2 * l) * n + j;
+        T *p1 = dst + (r0 + 2 * l + 1) * n + j;
+        if (accumulate) {
+            *p0 += z.x;
+            *p1 += z.y;
+        } else {
+            *p0 = z.x;
+            *p1 = z.y;
+        }
+    }
+}
+
+// ------------------------------------------------------------ 3D transforms
+
+// R2C along x3 of a pair of real lines per complex line, then split the two
+// half spectra: X_a = (Z_k + conj Z_{n-k})/2, X_b = (Z_k - conj Z_{n-k})/(2i).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
+                                                     const T *__restrict__ x, long in_stride, cplx_t<T> *__restrict__ H,
+                                                     long h_stride, int L) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pitch = L + 1;
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + (long)pl.n * pitch;
+    const int n = pl.n, nh = n / 2 + 1;
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    const T *src = x + blockIdx.y * in_stride;
+    C *dst = H + blockIdx.y * h_stride;
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int j = e % n, l = e / n;
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (l < leff) {
+            z.x = src[(r0 + 2 * l) * n + j];
+            z.y = src[(r0 + 2 * l + 1) * n + j];
+        }
+        A[j * pitch + l] = z;
+    }
+    __syncthreads();
+    C *R = lds_fft<T>(A, B, pl, L, pitch, -1, tw);
+    for (int e = threadIdx.x; e < nh * L; e += blockDim.x) {
+        const int k = e % nh, l = e / nh;
+        if (l >= leff) continue;
+        const C z = R[k * pitch + l];
+        const C zc = R[((n - k) % n) * pitch + l];
+        C xa, xb;
+        xa.x = T(0.5) * (z.x + zc.x);
+        xa.y = T(0.5) * (z.y - zc.y);
+        xb.x = T(0.5) * (z.y + zc.y);
+        xb.y = T(-0.5) * (z.x - zc.x);
+        dst[(r0 + 2 * l) * nh + k] = xa;
+        dst[(r0 + 2 * l + 1) * nh + k] = xb;
+    }
+}
+
+// In-place complex FFT of the half spectrum along axis 0 or 1.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
+                                                          int axis, cplx_t<T> *__restrict__ H, long h_stride, int sign,
+                                                          int L) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + (long)pl.n * L;
+    const int nh = g.n3h();
+    const int nb3 = (nh + L - 1) / L;
+    const int outer = blockIdx.x / nb3, cb = blockIdx.x % nb3;
+    const int leff = min(L, nh - cb * L);
+    long base, stride;
+    if (axis == 1) {
+        base = (long)outer * g.n2 * nh + (long)cb * L;
+        stride = nh;
+    } else {
+        base = (long)outer * nh + (long)cb * L;
+        stride = (long)g.n2 * nh;
+    }
+    C *h = H + blockIdx.y * h_stride;
+    const int n = pl.n;
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (l < leff) z = h[base + j * stride + l];
+        A[j * L + l] = z;
+    }
+    __syncthreads();
+    C *R = lds_fft<T>(A, B, pl, L, L, sign, tw);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e % L, j = e / L;
+        if (l < leff) h[base + j * stride + l] = R[j * L + l];
+    }
+}
+
+// Merge two half spectra into one complex line Z = X_a + i X_b (Hermitian
+// extension for k > n/2, real parts only at k = 0 and n/2), inverse FFT,
+// scale, and store the real part to line r0+2l and the imaginary part to
+// line r0+2l+1.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_c2r_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
+                                                     const cplx_t<T> *__restrict__ H, long h_stride,
+                                                     T *__restrict__ out, long out_stride, T scale, int L) {
+    using C = cplx_t<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int pitch = L + 1;
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + (long)pl.n * pitch;
+    const int n = pl.n, nh = n / 2 + 1;
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    const C *src = H + blockIdx.y * h_stride;
+    T *dst = out + blockIdx.y * out_stride;
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int j = e % n, l = e / n;
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (l < leff) {
+            if (2 * j <= n) {
+                C xa = src[(r0 + 2 * l) * nh + j], xb = src[(r0 + 2 * l + 1) * nh + j];
+                if (j == 0 || 2 * j == n) {
+                    xa.y = T(0);
+                    xb.y = T(0);
+                }
+                z.x = xa.x - xb.y;
+                z.y = xa.y + xb.x;
+            } else {
+                const C xa = src[(r0 + 2 * l) * nh + (n - j)], xb = src[(r0 + 2 * l + 1) * nh + (n - j)];
+                z.x = xa.x + xb.y;
+                z.y = xb.x - xa.y;
+            }
+        }
+        A[j * pitch + l] = z;
+    }
+    __syncthreads();
+    C *R = lds_fft<T>(A, B, pl, L, pitch, +1, tw);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int j = e % n, l = e / n;
+        if (l >= leff) continue;
+        const C z = R[j * pitch + l];
+        dst[(r0 + 2 * l) * n + j] = scale * z.x;
+        dst[(r0 + 2 * l + 1) * n + j] = scale * z.y;
+    }
+}
+
+// Pointwise symbols on the half spectrum [n1][n2][n3/2+1].
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_symbol(Grid g, cplx_t<T> *__restrict__ H, long h_stride, int op, T a,
+                                                     int ncomp, int leray) {
+    using C = cplx_t<T>;
+    const long q = (long)blockIdx.x * kThreads + threadIdx.x;
+    const long Nh = g.Nh();
+    if (q >= Nh) return;
+    const int nh = g.n3h();
+    const int m3 = (int)(q % nh);
+    const long r = q / nh;
+    const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
+    const T k1 = T(kwave(m1, g.n1)), k2 = T(kwave(m2, g.n2)), k3 = T(m3);
+    const T kk = k1 * k1 + k2 * k2 + k3 * k3;
+    const T t1 = T(kwave_odd(m1, g.n1)), t2 = T(kwave_odd(m2, g.n2)), t3 = T(2 * m3 == g.n3 ? 0 : m3);
+    const T tt = t1 * t1 + t2 * t2 + t3 * t3;
+    if (op == SYM_BIHARM || op == SYM_INVBIHARM || op == SYM_GAUSS || op == SYM_PRECOND) {
+        T f;
+        if (op == SYM_BIHARM) f = a * kk * kk;
+        else if (op == SYM_GAUSS) f = exp(T(-0.5) * a * a * kk);
+        else f = kk == T(0) ? T(1) : T(1) / (a * kk * kk);
+        for (int c = 0; c < ncomp; c++) {
+            C z = H[c * h_stride + q];
+            z.x *= f;
+            z.y *= f;
+            H[c * h_stride + q] = z;
+        }
+        if (op != SYM_PRECOND || !leray) return;
+    }
+    if (op == SYM_ASSEMBLE) {
+        // H_c <- a |k|^4 H_c + [P] H_{3+c}
+        C y0 = H[3 * h_stride + q], y1 = H[4 * h_stride + q], y2 = H[5 * h_stride + q];
+        if (leray && tt > T(0)) {
+            const T ir = T(1) / tt;
+            const T dx = (t1 * y0.x + t2 * y1.x + t3 * y2.x) * ir, dy = (t1 * y0.y + t2 * y1.y + t3 * y2.y) * ir;
+            y0.x -= t1 * dx;
+            y0.y -= t1 * dy;
+            y1.x -= t2 * dx;
+            y1.y -= t2 * dy;
+            y2.x -= t3 * dx;
+            y2.y -= t3 * dy;
+        }
+        const T f = a * kk * kk;
+        C x0 = H[q], x1 = H[h_stride + q], x2 = H[2 * h_stride + q];
+        x0.x = f * x0.x + y0.x;
+        x0.y = f * x0.y + y0.y;
+        x1.x = f * x1.x + y1.x;
+        x1.y = f * x1.y + y1.y;
+        x2.x = f * x2.x + y2.x;
+        x2.y = f * x2.y + y2.y;
+        H[q] = x0;
+        H[h_stride + q] = x1;
+        H[2 * h_stride + q] = x2;
+        return;
+    }
+    // Leray projection of components 0..2
+    if (tt == T(0)) return;
+    C y0 = H[q], y1 = H[h_stride + q], y2 = H[2 * h_stride + q];
+    const T ir = T(1) / tt;
+    const T dx = (t1 * y0.x + t2 * y1.x + t3 * y2.x) * ir, dy = (t1 * y0.y + t2 * y1.y + t3 * y2.y) * ir;
+    y0.x -= t1 * dx;
+    y0.y -= t1 * dy;
+    y1.x -= t2 * dx;
+    y1.y -= t2 * dy;
+    y2.x -= t3 * dx;
+    y2.y -= t3 * dy;
+    H[q] = y0;
+    H[h_stride + q] = y1;
+    H[2 * h_stride + q] = y2;
+}
+
+// Per-block partial sums of sum_c sum_k w(k3) |k|^4 |H_c(k)|^2 with
+// w = 1 on the k3 = 0 and k3 = n3/2 planes and 2 elsewhere (the half spectrum
+// stands for both k and -k), accumulated in double.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_biharm_norm(Grid g, const cplx_t<T> *__restrict__ H, long h_stride,
+                                                          double *__restrict__ partials) {
+    const long Nh = g.Nh();
+    const int nh = g.n3h();
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
+        const int m3 = (int)(q % nh);
+        const long r = q / nh;
+        const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
+        const double k1 = kwave(m1, g.n1), k2 = kwave(m2, g.n2), k3 = m3;
+        const double kk = k1 * k1 + k2 * k2 + k3 * k3;
+        const double w = (m3 == 0 || 2 * m3 == g.n3) ? 1.0 : 2.0;
+        double s = 0.0;
+        for (int c = 0; c < 3; c++) {
+            const cplx_t<T> z = H[c * h_stride + q];
+            s += (double)z.x * z.x + (double)z.y * z.y;
+        }
+        acc += w * kk * kk * s;
+    }
+    // wavefront then block reduction in a fixed order
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double ws[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; i++) t += ws[i];
+        partials[blockIdx.x] = t;
+    }
+}
+
+// Lines per tile so that the two LDS buffers of n*pitch complex values fit in
+// 64 KiB; padded tiles (pitch = L + 1) lose one line.
+template <typename T>
+int pick_lines(int n, int cap, bool padded) {
+    const int per_buffer = 32768 / (int)sizeof(cplx_t<T>);
+    int L = per_buffer / n - (padded ? 1 : 0);
+    if (L < 1) L = 1;
+    if (L > 64) L = 64;
+    if (L > cap) L = cap;
+    return L;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+template <typename T>
+hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T *out, long out_stride, int accumulate,
+                      int ncomp, hipStream_t s) {
+    using C = cplx_t<T>;
+    const Grid &g = c.g;
+    const FftPlan &pl = c.plan[axis];
+    const C *tw = reinterpret_cast<const C *>(c.tw[axis]);
+    if (axis == 2) {
+        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
+        const size_t lds = 2 * (size_t)pl.n * (L + 1) * sizeof(C);
+        hipLaunchKernelGGL(k_deriv_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, pl, tw, u, in_stride, out,
+                           out_stride, accumulate, L);
+    } else {
+        const int ncol = g.n3 / 2;
+        const int L = pick_lines<T>(pl.n, ncol, false);
+        const int nb3 = (ncol + L - 1) / L;
+        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+        const size_t lds = 2 * (size_t)pl.n * L * sizeof(C);
+        hipLaunchKernelGGL(k_deriv_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, pl, tw, axis, u,
+                           in_stride, out, out_stride, accumulate, L);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_forward(const SpecCtx &c, const T *x, int ncomp, int h0, hipStream_t s) {
+    using C = cplx_t<T>;
+    const Grid &g = c.g;
+    C *H = reinterpret_cast<C *>(c.H) + (long)h0 * g.Nh();
+    {
+        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
+        const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
+        hipLaunchKernelGGL(k_r2c_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
+                           reinterpret_cast<const C *>(c.tw[2]), x, g.N(), H, g.Nh(), L);
+    }
+    for (int axis = 1; axis >= 0; axis--) {
+        const int nh = g.n3h();
+        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
+        const int nb3 = (nh + L - 1) / L;
+        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
+        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
+                           reinterpret_cast<const C *>(c.tw[axis]), axis, H, g.Nh(), -1, L);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_inverse(const SpecCtx &c, T *out, int ncomp, hipStream_t s) {
+    using C = cplx_t<T>;
+    const Grid &g = c.g;
+    C *H = reinterpret_cast<C *>(c.H);
+    for (int axis = 0; axis <= 1; axis++) {
+        const int nh = g.n3h();
+        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
+        const int nb3 = (nh + L - 1) / L;
+        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
+        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
+                           reinterpret_cast<const C *>(c.tw[axis]), axis, H, g.Nh(), +1, L);
+    }
+    {
+        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
+        const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
+        hipLaunchKernelGGL(k_c2r_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
+                           reinterpret_cast<const C *>(c.tw[2]), H, g.Nh(), out, g.N(), T(1.0 / (double)g.N()), L);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_symbol(const SpecCtx &c, int op, double a, int ncomp, int leray, hipStream_t s) {
+    using C = cplx_t<T>;
+    const Grid &g = c.g;
+    const unsigned nb = (unsigned)((g.Nh() + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_symbol<T>, dim3(nb), dim3(kThreads), 0, s, g, reinterpret_cast<C *>(c.H), g.Nh(), op, T(a),
+                       ncomp, leray);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s) {
+    using C = cplx_t<T>;
+    hipLaunchKernelGGL(k_biharm_norm<T>, dim3(nblocks), dim3(kThreads), 0, s, c.g,
+                       reinterpret_cast<const C *>(c.H), c.g.Nh(), partials);
+    return hipGetLastError();
+}
+
+#define REGK_FFT_INST(T)                                                                                           \
+    template hipError_t spec_deriv<T>(const SpecCtx &, int, const T *, long, T *, long, int, int, hipStream_t);    \
+    template hipError_t spec_forward<T>(const SpecCtx &, const T *, int, int, hipStream_t);                        \
+    template hipError_t spec_inverse<T>(const SpecCtx &, T *, int, hipStream_t);                                   \
+    template hipError_t spec_symbol<T>(const SpecCtx &, int, double, int, int, hipStream_t);                       \
+    template hipError_t spec_biharm_norm_partials<T>(const SpecCtx &, double *, int, hipStream_t);
+
+REGK_FFT_INST(float)
+REGK_FFT_INST(double)
+
+}  // namespace regk

@@ -1,0 +1,313 @@
+"""Python binding of libreg (include/reg.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and passes
+torch tensors' device pointers and the current HIP stream through ctypes; all
+arithmetic runs in the library's HIP kernels. Host-side checks cover what the C
+side cannot see: tensor dtype, device, contiguity and element count.
+
+The library must be built (``__graft_entry__.build()`` or
+``python paper_1608_03630_amd/build.py``); importing a function that needs it
+raises if ``libreg.so`` is missing. There is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libreg.so")
+REG_MAXIT = 512
+
+STATUS = {
+    0: "REG_OK", 1: "REG_EINVAL", 2: "REG_ENOMEM", 3: "REG_EHIP", 4: "REG_ENONFINITE", 5: "REG_ENOTCONV",
+    6: "REG_ELINESEARCH", 7: "REG_ENONDIFFEO", 8: "REG_ENOTIMPL",
+}
+REG_OK, REG_EINVAL, REG_ENOMEM, REG_EHIP, REG_ENONFINITE = 0, 1, 2, 3, 4
+REG_ELINESEARCH = 6
+
+SPEC_BIHARM, SPEC_INVBIHARM, SPEC_GAUSS, SPEC_LERAY = 0, 1, 2, 3
+
+
+class RegError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class reg_params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("nt", ctypes.c_int32),
+        ("beta", ctypes.c_double),
+        ("beta_final", ctypes.c_double),
+        ("beta_factor", ctypes.c_double),
+        ("isochoric", ctypes.c_int32),
+        ("prec", ctypes.c_int32),
+        ("gtol", ctypes.c_double),
+        ("mismatch_tol", ctypes.c_double),
+        ("max_newton", ctypes.c_int32),
+        ("max_pcg", ctypes.c_int32),
+        ("max_ls", ctypes.c_int32),
+        ("forcing", ctypes.c_int32),
+        ("armijo_c1", ctypes.c_double),
+    ]
+
+
+class reg_report(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("n_iter", ctypes.c_int32),
+        ("matvecs", ctypes.c_int32),
+        ("gradients", ctypes.c_int32),
+        ("objectives", ctypes.c_int32),
+        ("stop_reason", ctypes.c_int32),
+        ("J", ctypes.c_double * REG_MAXIT),
+        ("mismatch", ctypes.c_double * REG_MAXIT),
+        ("grel", ctypes.c_double * REG_MAXIT),
+        ("alpha", ctypes.c_double * REG_MAXIT),
+        ("beta", ctypes.c_double * REG_MAXIT),
+        ("pcg_iters", ctypes.c_int32 * REG_MAXIT),
+        ("ls_trials", ctypes.c_int32 * REG_MAXIT),
+        ("final_J", ctypes.c_double),
+        ("final_mismatch", ctypes.c_double),
+        ("final_grel", ctypes.c_double),
+        ("seconds_total", ctypes.c_double),
+        ("seconds_matvec", ctypes.c_double),
+        ("seconds_gradient", ctypes.c_double),
+        ("seconds_objective", ctypes.c_double),
+        ("seconds_precond", ctypes.c_double),
+        ("interps", ctypes.c_int64),
+    ]
+
+    def to_dict(self):
+        k = min(self.n_iter, REG_MAXIT)
+        out = {f: getattr(self, f) for f in ("status", "n_iter", "matvecs", "gradients", "objectives",
+                                             "stop_reason", "final_J", "final_mismatch", "final_grel",
+                                             "seconds_total", "seconds_matvec", "seconds_gradient",
+                                             "seconds_objective", "seconds_precond", "interps")}
+        for f in ("J", "mismatch", "grel", "alpha", "beta", "pcg_iters", "ls_trials"):
+            out[f] = list(getattr(self, f)[:k])
+        return out
+
+
+_lib = None
+_P = ctypes.c_void_p
+_SIGS = {
+    "reg_default_params": [ctypes.POINTER(reg_params)],
+    "reg_workspace_size": [ctypes.POINTER(reg_params), ctypes.POINTER(ctypes.c_size_t)],
+    "reg_create": [ctypes.POINTER(reg_params), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "reg_destroy": [_P],
+    "reg_set_beta": [_P, ctypes.c_double],
+    "reg_set_images": [_P, _P, _P],
+    "reg_interp": [_P, _P, _P, _P],
+    "reg_backtrace": [_P, _P, ctypes.c_double, _P],
+    "reg_deriv": [_P, ctypes.c_int, _P, _P],
+    "reg_grad": [_P, _P, _P],
+    "reg_div": [_P, _P, _P],
+    "reg_spectral": [_P, ctypes.c_int, ctypes.c_double, ctypes.c_int, _P, _P],
+    "reg_precond": [_P, _P, _P],
+    "reg_transport_forward": [_P, _P, _P, _P],
+    "reg_transport_adjoint": [_P, _P, _P, _P],
+    "reg_gradient": [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                     ctypes.POINTER(ctypes.c_double)],
+    "reg_objective": [_P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "reg_hessian_matvec": [_P, _P, _P],
+    "reg_solve": [_P, _P, ctypes.POINTER(reg_report)],
+    "reg_deformation": [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "reg_dot": [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_double)],
+}
+
+
+def lib():
+    """Loads libreg.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.reg_last_error.argtypes = [_P]
+        L.reg_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _chk(st, ctx=None, what=""):
+    if st != REG_OK:
+        msg = lib().reg_last_error(ctx).decode() if ctx else ""
+        raise RegError(st, f"{what}: {msg}")
+
+
+def reg_default_params(n=(64, 64, 64), **kw):
+    p = reg_params()
+    _chk(lib().reg_default_params(ctypes.byref(p)), what="reg_default_params")
+    n = tuple(int(x) for x in (n if hasattr(n, "__len__") else (n, n, n)))
+    p.n[:] = n
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, type(getattr(p, k))(v))
+    return p
+
+
+def reg_workspace_size(p):
+    b = ctypes.c_size_t()
+    _chk(lib().reg_workspace_size(ctypes.byref(p), ctypes.byref(b)), what="reg_workspace_size")
+    return b.value
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One reg_ctx over a torch-allocated workspace, bound to one stream."""
+
+    def __init__(self, params, device="cuda", stream=None):
+        self.params = params
+        self.device = torch.device(device)
+        self.dtype = torch.float64 if params.prec else torch.float32
+        self.shape = tuple(params.n)
+        self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        nbytes = reg_workspace_size(params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        _chk(lib().reg_create(ctypes.byref(params), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                              _stream_ptr(stream), ctypes.byref(h)), what="reg_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().reg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ checks
+    def _t(self, t, ncomp, name):
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch.Tensor")
+        if t.device.type != "cuda":
+            raise ValueError(f"{name} must live on the GPU")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.numel() != ncomp * self.N:
+            raise ValueError(f"{name} must hold {ncomp} x {self.shape} elements, got shape {tuple(t.shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def empty(self, ncomp=1):
+        shape = self.shape if ncomp == 1 else (ncomp,) + self.shape
+        return torch.empty(shape, dtype=self.dtype, device=self.device)
+
+    # ------------------------------------------------------ entry points
+    def reg_set_beta(self, beta):
+        _chk(lib().reg_set_beta(self.handle, float(beta)), self.handle, "reg_set_beta")
+
+    def reg_set_images(self, rho_T, rho_R):
+        _chk(lib().reg_set_images(self.handle, self._t(rho_T, 1, "rho_T"), self._t(rho_R, 1, "rho_R")),
+             self.handle, "reg_set_images")
+
+    def reg_interp(self, f, D, out=None):
+        out = self.empty(1) if out is None else out
+        _chk(lib().reg_interp(self.handle, self._t(f, 1, "f"), self._t(D, 3, "D"), self._t(out, 1, "out")),
+             self.handle, "reg_interp")
+        return out
+
+    def reg_backtrace(self, v, sign=1.0, D=None):
+        D = self.empty(3) if D is None else D
+        _chk(lib().reg_backtrace(self.handle, self._t(v, 3, "v"), float(sign), self._t(D, 3, "D")), self.handle,
+             "reg_backtrace")
+        return D
+
+    def reg_deriv(self, axis, u, out=None):
+        out = self.empty(1) if out is None else out
+        _chk(lib().reg_deriv(self.handle, int(axis), self._t(u, 1, "u"), self._t(out, 1, "out")), self.handle,
+             "reg_deriv")
+        return out
+
+    def reg_grad(self, u, out=None):
+        out = self.empty(3) if out is None else out
+        _chk(lib().reg_grad(self.handle, self._t(u, 1, "u"), self._t(out, 3, "out")), self.handle, "reg_grad")
+        return out
+
+    def reg_div(self, v, out=None):
+        out = self.empty(1) if out is None else out
+        _chk(lib().reg_div(self.handle, self._t(v, 3, "v"), self._t(out, 1, "out")), self.handle, "reg_div")
+        return out
+
+    def reg_spectral(self, op, scale, v, out=None):
+        ncomp = 1 if v.dim() == 3 else v.shape[0]
+        out = self.empty(ncomp) if out is None else out
+        _chk(lib().reg_spectral(self.handle, int(op), float(scale), ncomp, self._t(v, ncomp, "v"),
+                                self._t(out, ncomp, "out")), self.handle, "reg_spectral")
+        return out
+
+    def reg_precond(self, r, z=None):
+        z = self.empty(3) if z is None else z
+        _chk(lib().reg_precond(self.handle, self._t(r, 3, "r"), self._t(z, 3, "z")), self.handle, "reg_precond")
+        return z
+
+    def reg_transport_forward(self, v, rho0, rho1=None):
+        rho1 = self.empty(1) if rho1 is None else rho1
+        _chk(lib().reg_transport_forward(self.handle, self._t(v, 3, "v"), self._t(rho0, 1, "rho0"),
+                                         self._t(rho1, 1, "rho1")), self.handle, "reg_transport_forward")
+        return rho1
+
+    def reg_transport_adjoint(self, v, lam1, lam0=None):
+        lam0 = self.empty(1) if lam0 is None else lam0
+        _chk(lib().reg_transport_adjoint(self.handle, self._t(v, 3, "v"), self._t(lam1, 1, "lam1"),
+                                         self._t(lam0, 1, "lam0")), self.handle, "reg_transport_adjoint")
+        return lam0
+
+    def reg_gradient(self, v, g=None):
+        g = self.empty(3) if g is None else g
+        J, mis, gn = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _chk(lib().reg_gradient(self.handle, self._t(v, 3, "v"), self._t(g, 3, "g"), ctypes.byref(J),
+                                ctypes.byref(mis), ctypes.byref(gn)), self.handle, "reg_gradient")
+        return g, J.value, mis.value, gn.value
+
+    def reg_objective(self, v):
+        J, mis = ctypes.c_double(), ctypes.c_double()
+        _chk(lib().reg_objective(self.handle, self._t(v, 3, "v"), ctypes.byref(J), ctypes.byref(mis)),
+             self.handle, "reg_objective")
+        return J.value, mis.value
+
+    def reg_hessian_matvec(self, vt, Hvt=None):
+        Hvt = self.empty(3) if Hvt is None else Hvt
+        _chk(lib().reg_hessian_matvec(self.handle, self._t(vt, 3, "vt"), self._t(Hvt, 3, "Hvt")), self.handle,
+             "reg_hessian_matvec")
+        return Hvt
+
+    def reg_solve(self, v=None, raise_on_error=True):
+        v = torch.zeros((3,) + self.shape, dtype=self.dtype, device=self.device) if v is None else v
+        rep = reg_report()
+        st = lib().reg_solve(self.handle, self._t(v, 3, "v"), ctypes.byref(rep))
+        if raise_on_error:
+            _chk(st, self.handle, "reg_solve")
+        return v, rep.to_dict()
+
+    def reg_deformation(self, v, u=None, want_u=True):
+        if want_u and u is None:
+            u = self.empty(3)
+        mn, mx = ctypes.c_double(), ctypes.c_double()
+        _chk(lib().reg_deformation(self.handle, self._t(v, 3, "v"), self._t(u, 3, "u") if u is not None else None,
+                                   ctypes.byref(mn), ctypes.byref(mx)), self.handle, "reg_deformation")
+        return u, mn.value, mx.value
+
+    def reg_dot(self, a, b):
+        ncomp = a.numel() // self.N
+        out = ctypes.c_double()
+        _chk(lib().reg_dot(self.handle, ncomp, self._t(a, ncomp, "a"), self._t(b, ncomp, "b"), ctypes.byref(out)),
+             self.handle, "reg_dot")
+        return out.value

@@ -1,0 +1,103 @@
+"""The C-ABI library loads without a GPU, exports every entry point that
+include/reg.h declares, lays out its structs as the header does, and rejects
+bad parameters before touching the device."""
+import ctypes
+import json
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "reg.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:reg_status|const char \*)\s*(reg_[a-z_]+)\s*\(", text, re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1608_03630_amd import reg
+
+    return reg.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_struct_layout_matches_header():
+    from paper_1608_03630_amd import reg
+
+    src = '#include <stdio.h>\n#include <stddef.h>\n#include "reg.h"\nint main(void){printf("%zu %zu %zu %zu\\n",' \
+          ' sizeof(reg_params), sizeof(reg_report), offsetof(reg_report, final_J), offsetof(reg_params, armijo_c1));' \
+          ' return 0;}\n'
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    sp, sr, ofj, ofa = map(int, out)
+    assert sp == ctypes.sizeof(reg.reg_params)
+    assert sr == ctypes.sizeof(reg.reg_report)
+    assert ofj == reg.reg_report.final_J.offset
+    assert ofa == reg.reg_params.armijo_c1.offset
+
+
+def test_default_params_are_the_papers(lib):
+    from paper_1608_03630_amd import reg
+
+    with open(os.path.join(ROOT, "tests", "golden", "paper_parameters.json")) as f:
+        gold = json.load(f)
+    p = reg.reg_default_params(32)
+    assert p.beta == gold["beta"] and p.nt == gold["nt"] and p.gtol == gold["gtol"]
+    assert p.forcing == 0 and p.isochoric == 0 and p.beta_final == 0
+
+
+def test_workspace_size_scales_with_grid(lib):
+    from paper_1608_03630_amd import reg
+
+    a = reg.reg_workspace_size(reg.reg_default_params(32))
+    b = reg.reg_workspace_size(reg.reg_default_params(64))
+    c = reg.reg_workspace_size(reg.reg_default_params(64, prec=1))
+    assert 7.5 < b / a < 8.5 and 1.9 < c / b < 2.1
+
+
+@pytest.mark.parametrize("bad", [dict(n=(30, 32, 32)), dict(n=(32, 32, 10)), dict(n=(32, 32, 6)),
+                                 dict(n=(2048, 8, 8)), dict(nt=0), dict(beta=0.0), dict(beta=-1.0),
+                                 dict(prec=2), dict(max_pcg=0), dict(gtol=-1.0)])
+def test_bad_parameters_are_rejected(lib, bad):
+    from paper_1608_03630_amd import reg
+
+    n = bad.pop("n", (32, 32, 32))
+    p = reg.reg_default_params(n, **bad)
+    with pytest.raises(reg.RegError) as e:
+        reg.reg_workspace_size(p)
+    assert e.value.status == reg.REG_EINVAL
+
+
+def test_create_rejects_null_workspace(lib):
+    from paper_1608_03630_amd import reg
+
+    p = reg.reg_default_params(32)
+    h = ctypes.c_void_p()
+    st = lib.reg_create(ctypes.byref(p), None, 1 << 30, None, ctypes.byref(h))
+    assert st == reg.REG_EINVAL and not h.value
+
+
+def test_product_package_does_not_reach_the_oracle():
+    """The product path never imports, links or loads the oracle."""
+    pkg = os.path.join(ROOT, "paper_1608_03630_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text and "liboracle" not in text, f

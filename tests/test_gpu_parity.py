@@ -1,0 +1,292 @@
+"""GPU parity: every operator of the hot path through the C ABI against the
+FP64 oracle on the same seeded inputs, in double (<= 1e-12) and single
+precision (tolerances in gpu_util.TOL), at grid sizes that span many blocks
+and end in a ragged tail (24 x 36 x 54 = 46656 points = 182.25 blocks of 256;
+54 = 2 * 3^3 exercises the radix-3 FFT passes)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_util import TOL, biharm_bound, biharm_fp32_bound, rel_l2, rounded, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+RAGGED = (24, 36, 54)
+CUBE = (32, 32, 32)
+
+
+@pytest.fixture(scope="module")
+def reg():
+    from paper_1608_03630_amd import reg as r
+
+    r.lib()
+    assert torch.cuda.is_available()
+    return r
+
+
+def make_ctx(reg, shape, prec, nt=4, **kw):
+    say(f"  [ctx] shape={shape} prec={prec} nt={nt} {kw}")
+    return reg.Context(reg.reg_default_params(shape, nt=nt, prec=prec, **kw))
+
+
+def oparams(shape, nt, beta=1e-2, iso=False, **kw):
+    return oracle.params(shape, nt, beta, isochoric=iso, **kw)
+
+
+# ------------------------------------------------------------ interpolation
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("shape", [RAGGED, CUBE])
+@pytest.mark.parametrize("cells", [2.5, 37.0])
+def test_interp(reg, prec, shape, cells):
+    ctx = make_ctx(reg, shape, prec)
+    f = rounded(synth.smooth_random_field(shape, 101, kmax=5), prec)
+    D = rounded(synth.displacement(shape, 102, max_cells=cells), prec)
+    out = to_host(ctx.reg_interp(to_dev(f, ctx), to_dev(D, ctx)))
+    ref = oracle.interp(f, D)
+    assert rel_l2(out, ref) <= TOL[("interp", prec)]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_interp_integer_shift_is_exact(reg, prec):
+    shape = RAGGED
+    ctx = make_ctx(reg, shape, prec)
+    f = rounded(np.random.default_rng(103).standard_normal(shape), prec)
+    m = (3, -5, 7)
+    D = np.stack([np.full(shape, float(x)) for x in m])
+    out = to_host(ctx.reg_interp(to_dev(f, ctx), to_dev(D, ctx)))
+    assert np.array_equal(out, np.roll(f, shift=(-m[0], -m[1], -m[2]), axis=(0, 1, 2)))
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("sign", [1.0, -1.0])
+def test_backtrace(reg, prec, sign):
+    shape = RAGGED
+    ctx = make_ctx(reg, shape, prec, nt=4)
+    v = rounded(1.5 * synth.smooth_random_field(shape, 104, kmax=3, ncomp=3), prec)
+    D = to_host(ctx.reg_backtrace(to_dev(v, ctx), sign))
+    ref = oracle.backtrace(v, 4, sign)
+    assert rel_l2(D, ref) <= TOL[("backtrace", prec)]
+
+
+# ---------------------------------------------------------------- spectral
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("shape", [RAGGED, CUBE])
+def test_derivatives(reg, prec, shape):
+    ctx = make_ctx(reg, shape, prec)
+    u = rounded(synth.smooth_random_field(shape, 105, kmax=6), prec)
+    u_dev = to_dev(u, ctx)
+    for j in range(3):
+        out = to_host(ctx.reg_deriv(j, u_dev))
+        assert rel_l2(out, oracle.deriv(u, j)) <= TOL[("spectral", prec)], j
+    g = to_host(ctx.reg_grad(u_dev))
+    assert rel_l2(g, oracle.grad(u)) <= TOL[("spectral", prec)]
+    v = rounded(synth.smooth_random_field(shape, 106, kmax=6, ncomp=3), prec)
+    d = to_host(ctx.reg_div(to_dev(v, ctx)))
+    assert rel_l2(d, oracle.div(v)) <= TOL[("spectral", prec)]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_nyquist_derivative_is_zero(reg, prec):
+    shape = CUBE
+    ctx = make_ctx(reg, shape, prec)
+    x = synth.grid(shape)
+    for j in range(3):
+        u = np.cos(shape[j] / 2 * x[j])
+        out = to_host(ctx.reg_deriv(j, to_dev(u, ctx)))
+        assert np.abs(out).max() <= (1e-13 if prec else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("shape", [RAGGED, CUBE])
+def test_even_and_projection_operators(reg, prec, shape):
+    from paper_1608_03630_amd import reg as R
+
+    ctx = make_ctx(reg, shape, prec)
+    v = rounded(synth.smooth_random_field(shape, 107, kmax=6, ncomp=3), prec)
+    vd = to_dev(v, ctx)
+    out = to_host(ctx.reg_spectral(R.SPEC_BIHARM, 0.01, vd))
+    ref = oracle.biharm(v, 0.01)
+    tol = 1e-12 if prec else biharm_fp32_bound(shape, v, ref / 0.01)
+    say(f"  biharm rel-L2 {rel_l2(out, ref):.2e} (bound {tol:.2e})")
+    assert rel_l2(out, ref) <= tol
+    out = to_host(ctx.reg_spectral(R.SPEC_INVBIHARM, 0.01, vd))
+    assert rel_l2(out, oracle.inv_biharm(v, 0.01)) <= TOL[("spectral", prec)]
+    out = to_host(ctx.reg_spectral(R.SPEC_GAUSS, 0.3, vd))
+    assert rel_l2(out, oracle.gauss(v, 0.3)) <= TOL[("spectral", prec)]
+    out = to_host(ctx.reg_spectral(R.SPEC_LERAY, 0.0, vd))
+    assert rel_l2(out, oracle.leray(v)) <= TOL[("spectral", prec)]
+    # scalar field through the single-component path
+    out = to_host(ctx.reg_spectral(R.SPEC_GAUSS, 0.2, to_dev(v[0], ctx)))
+    assert rel_l2(out, oracle.gauss(v[0], 0.2)) <= TOL[("spectral", prec)]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("iso", [False, True])
+def test_preconditioner(reg, prec, iso):
+    shape = RAGGED
+    ctx = make_ctx(reg, shape, prec, beta=3e-3, isochoric=int(iso))
+    r = rounded(synth.smooth_random_field(shape, 108, kmax=6, ncomp=3), prec)
+    z = to_host(ctx.reg_precond(to_dev(r, ctx)))
+    assert rel_l2(z, oracle.precond(r, 3e-3, iso)) <= TOL[("spectral", prec)]
+
+
+# --------------------------------------------------------------- transport
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("iso", [False, True])
+def test_transport_forward_and_adjoint(reg, prec, iso):
+    shape = RAGGED
+    nt = 6
+    ctx = make_ctx(reg, shape, prec, nt=nt, isochoric=int(iso))
+    v = synth.smooth_velocity_divfree(shape) if iso else 0.8 * synth.smooth_velocity_paper(shape)
+    v = rounded(v, prec)
+    rho0 = rounded(synth.smooth_random_field(shape, 109, kmax=4), prec)
+    P = oparams(shape, nt, iso=iso)
+    r1 = to_host(ctx.reg_transport_forward(to_dev(v, ctx), to_dev(rho0, ctx)))
+    assert rel_l2(r1, oracle.transport_forward(P, v, rho0)) <= TOL[("transport", prec)]
+    l0 = to_host(ctx.reg_transport_adjoint(to_dev(v, ctx), to_dev(rho0, ctx)))
+    assert rel_l2(l0, oracle.transport_adjoint(P, v, rho0)) <= TOL[("transport", prec)]
+
+
+# -------------------------------------------------- gradient and Hessian
+def _images(shape, prec, nt, iso):
+    case = synth.blob_case(shape, seed=1002) if iso else synth.smooth_case(shape)
+    rhoT = rounded(case["rhoT"], prec)
+    P = oparams(shape, nt, iso=iso)
+    rhoR = rounded(oracle.transport_forward(P, case["v_true"], rhoT), prec)
+    return rhoT, rhoR, case["v_true"]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("iso", [False, True])
+def test_gradient_and_hessian(reg, prec, iso):
+    shape = RAGGED
+    nt = 4
+    beta = 1e-2
+    rhoT, rhoR, vtrue = _images(shape, prec, nt, iso)
+    ctx = make_ctx(reg, shape, prec, nt=nt, beta=beta, isochoric=int(iso))
+    ctx.reg_set_images(to_dev(rhoT, ctx), to_dev(rhoR, ctx))
+    v = rounded(0.5 * vtrue if iso else 0.5 * synth.smooth_velocity_paper(shape), prec)
+    P = oparams(shape, nt, beta=beta, iso=iso)
+    g, J, mis, gn = ctx.reg_gradient(to_dev(v, ctx))
+    g = to_host(g)
+    g_ref, J_ref, mis_ref = oracle.gradient(P, rhoT, rhoR, v)
+    # Two error sources bound the gradient. (i) lam(1) = rho_R - rho(1)
+    # carries the transport error relative to the residual (factor
+    # |rho_T - rho_R| / |rho_1 - rho_R|) and g = beta lap^2 v + P b is a
+    # difference of two larger terms (factor kappa). (ii) beta lap^2 v
+    # amplifies transform round-off by |k|^4 (biharm_bound).
+    amp = max(1.0, 1.0 / max(mis_ref, 1e-300))
+    reg_part = oracle.biharm(v, beta)
+    kappa = (np.linalg.norm(reg_part) + np.linalg.norm(g_ref - reg_part)) / np.linalg.norm(g_ref)
+    tol = (1e-12 if prec else 1e-4) * amp * kappa + biharm_bound(shape, prec, beta * np.linalg.norm(v),
+                                                                  np.linalg.norm(g_ref))
+    say(f"  gradient rel-L2 {rel_l2(g, g_ref):.2e} (bound {tol:.2e}, amp {amp:.2f}, kappa {kappa:.2f})")
+    assert rel_l2(g, g_ref) <= tol
+    assert abs(J - J_ref) <= TOL[("scalar", prec)] * abs(J_ref)
+    assert abs(mis - mis_ref) <= TOL[("scalar", prec)] * abs(mis_ref)
+    h3 = np.prod([2 * np.pi / s for s in shape])
+    assert abs(gn - np.sqrt(h3 * np.sum(g_ref ** 2))) <= tol * gn
+    vt = rounded(synth.smooth_random_field(shape, 110, kmax=3, ncomp=3), prec)
+    H = to_host(ctx.reg_hessian_matvec(to_dev(vt, ctx)))
+    H_ref = oracle.hessian_matvec(P, rhoT, v, vt)
+    htol = (1e-12 if prec else 1e-4) + biharm_bound(shape, prec, beta * np.linalg.norm(vt), np.linalg.norm(H_ref))
+    say(f"  Hessian rel-L2 {rel_l2(H, H_ref):.2e} (bound {htol:.2e})")
+    assert rel_l2(H, H_ref) <= htol
+    Jo, miso = ctx.reg_objective(to_dev(v, ctx))
+    assert abs(Jo - J_ref) <= TOL[("scalar", prec)] * abs(J_ref)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_deformation(reg, prec):
+    shape = RAGGED
+    nt = 4
+    ctx = make_ctx(reg, shape, prec, nt=nt)
+    v = rounded(synth.smooth_velocity_paper(shape), prec)
+    u, dmin, dmax = ctx.reg_deformation(to_dev(v, ctx))
+    u_ref, _, mn, mx = oracle.deformation(oparams(shape, nt), v)
+    assert rel_l2(to_host(u), u_ref) <= TOL[("transport", prec)]
+    assert abs(dmin - mn) <= TOL[("det", prec)] and abs(dmax - mx) <= TOL[("det", prec)]
+
+
+# ------------------------------------------------------------------ solver
+def test_smooth_case_solve_fp64_matches_oracle(reg):
+    """32^3 smooth case in double: the same PCG iteration counts per Newton
+    step and the same velocity to 1e-9."""
+    shape = (32, 32, 32)
+    nt = 4
+    case = synth.smooth_case(shape)
+    P = oparams(shape, nt, max_newton=5)
+    rhoR = oracle.transport_forward(P, case["v_true"], case["rhoT"])
+    v_ref, rep_ref = oracle.solve(P, case["rhoT"], rhoR)
+    ctx = make_ctx(reg, shape, 1, nt=nt, max_newton=5)
+    ctx.reg_set_images(to_dev(case["rhoT"], ctx), to_dev(rhoR, ctx))
+    v, rep = ctx.reg_solve()
+    say(f"  gpu pcg={rep['pcg_iters']} oracle pcg={rep_ref['pcg_iters']} mis={rep['final_mismatch']:.6f}")
+    assert rep["pcg_iters"] == rep_ref["pcg_iters"]
+    assert rep["n_iter"] == rep_ref["n_iter"] and rep["stop_reason"] == rep_ref["stop_reason"]
+    assert rel_l2(to_host(v), v_ref) <= 1e-9
+    assert np.allclose(rep["J"], rep_ref["J"], rtol=1e-10, atol=0)
+
+
+def test_blob_case_solve_fp32_tracks_oracle(reg):
+    """Isochoric blob case at 32^3 in single precision with double
+    reductions: outer iterations within one of the FP64 oracle and the final
+    mismatch within 1% of it."""
+    shape = (32, 32, 32)
+    nt = 8
+    case = synth.blob_case(shape)
+    P = oparams(shape, nt, beta=1e-3, iso=True, max_newton=10)
+    rhoR = oracle.transport_forward(P, case["v_true"], case["rhoT"])
+    v_ref, rep_ref = oracle.solve(P, case["rhoT"], rhoR)
+    ctx = make_ctx(reg, shape, 0, nt=nt, beta=1e-3, isochoric=1, max_newton=10)
+    ctx.reg_set_images(to_dev(case["rhoT"], ctx), to_dev(rhoR, ctx))
+    v, rep = ctx.reg_solve()
+    say(f"  gpu its={rep['n_iter']} mis={rep['final_mismatch']:.5f} oracle its={rep_ref['n_iter']} "
+        f"mis={rep_ref['final_mismatch']:.5f}")
+    assert abs(rep["n_iter"] - rep_ref["n_iter"]) <= 1
+    assert abs(rep["final_mismatch"] - rep_ref["final_mismatch"]) <= 0.01 * rep_ref["final_mismatch"]
+
+
+# ------------------------------------------------------------ error paths
+def test_host_side_checks_and_status(reg):
+    shape = (16, 16, 16)
+    ctx = make_ctx(reg, shape, 0)
+    v = torch.zeros((3,) + shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(TypeError):
+        ctx.reg_backtrace(v)
+    with pytest.raises(ValueError):
+        ctx.reg_interp(torch.zeros(shape, device="cuda"), torch.zeros((2,) + shape, device="cuda"))
+    with pytest.raises(reg.RegError) as e:
+        ctx.reg_hessian_matvec(torch.zeros((3,) + shape, device="cuda"))
+    assert e.value.status == reg.REG_EINVAL
+    with pytest.raises(reg.RegError) as e:
+        ctx.reg_gradient(torch.zeros((3,) + shape, device="cuda"))
+    assert e.value.status == reg.REG_EINVAL
+
+
+def test_line_search_failure_keeps_velocity(reg):
+    shape = (16, 16, 16)
+    case = synth.smooth_case(shape)
+    ctx = make_ctx(reg, shape, 0, nt=4, max_ls=0)
+    ctx.reg_set_images(to_dev(case["rhoT"], ctx), to_dev(np.roll(case["rhoT"], 2, axis=0), ctx))
+    v0 = to_dev(0.01 * synth.smooth_velocity_paper(shape), ctx)
+    v = v0.clone()
+    v, rep = ctx.reg_solve(v, raise_on_error=False)
+    assert rep["status"] == reg.REG_ELINESEARCH
+    assert torch.equal(v, v0)
+
+
+def test_repeatable_bitwise(reg):
+    """Gathers write each point once and reductions use a fixed order, so two
+    identical calls agree bit for bit."""
+    shape = RAGGED
+    rhoT, rhoR, vtrue = _images(shape, 0, 4, False)
+    ctx = make_ctx(reg, shape, 0, nt=4)
+    ctx.reg_set_images(to_dev(rhoT, ctx), to_dev(rhoR, ctx))
+    v = to_dev(0.3 * synth.smooth_velocity_paper(shape), ctx)
+    g1, J1, _, _ = ctx.reg_gradient(v)
+    g1 = g1.clone()
+    g2, J2, _, _ = ctx.reg_gradient(v)
+    assert J1 == J2 and torch.equal(g1, g2)
