@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Time-to-solution of Gauss-Newton-Krylov diffeomorphic registration at 256^3
+on one MI355X, plus interpolation throughput and the roofline of the dominant
+kernel.
+
+Workload (synthetic; it stands in for the paper's 256x300x256 brain images,
+which are not available): a 256^3 phantom of six nested seeded ellipsoids
+with intensities from {0.1, ..., 1.0}, Gaussian-smoothed with sigma = 2 voxels
+on the GPU; the reference is the phantom transported on the GPU by a seeded
+smooth compressible velocity (|k| <= 8, max displacement 8 voxels). Solver:
+FP32 fields with FP64 reductions, nt = 16, H2 regularisation, beta
+continuation 1e-1 -> 1e-4 (factor 10), Gauss-Newton-PCG with the spectral
+preconditioner, stopping at relative mismatch <= 1e-2 (or relative gradient
+1e-2 on the last level).
+
+One step = one full solve from v = 0 with the images already in device
+memory. Output: one JSON line on stdout.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per grid point and launch of each transport kernel family
+# in single precision (what the method must move)
+BYTES_PER_POINT = {
+    "interp": 20.0,     # D (3 x 4) + gathered field 4 + out 4
+    "backtrace": 24.0,  # v (3 x 4) + D out (3 x 4)
+    "adjoint": 64.0,    # D 12, lam 4, div v 4, (div v)(X) 4, grad rho 12, b 12 in; lam 4, b 12 out
+    "incstate": 44.0,   # D 12, q 4, vt 12, grad rho 12 in; q 4 out (+12 for b on the last step)
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(reg, torch, n, seed=1003):
+    import numpy as np
+
+    import synth
+
+    shape = (n, n, n)
+    t0 = time.time()
+    case = synth.phantom_case(shape, seed)
+    log(f"[bench] phantom and velocity generated on the host in {time.time() - t0:.1f} s")
+    params = reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=1e-4, beta_factor=0.1,
+                                    gtol=1e-2, mismatch_tol=1e-2, max_newton=50, max_pcg=100, max_ls=20)
+    ctx = reg.Context(params)
+    labels = torch.from_numpy(case["labels"].astype(np.float32)).cuda()
+    rhoT = ctx.reg_spectral(reg.SPEC_GAUSS, case["sigma"], labels)
+    v_true = torch.from_numpy(case["v_true"]).cuda()
+    rhoR = ctx.reg_transport_forward(v_true, rhoT)
+    ctx.reg_set_images(rhoT, rhoR)
+    torch.cuda.synchronize()
+    return ctx, rhoT, rhoR, v_true
+
+
+def warm_small(reg, torch):
+    """One 64^3 solve so that every kernel has been loaded and run."""
+    import numpy as np
+
+    import synth
+
+    shape = (64, 64, 64)
+    case = synth.phantom_case(shape, 7)
+    ctx = reg.Context(reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=1e-3, gtol=1e-2,
+                                             mismatch_tol=1e-2, max_newton=5))
+    labels = torch.from_numpy(case["labels"].astype(np.float32)).cuda()
+    rhoT = ctx.reg_spectral(reg.SPEC_GAUSS, case["sigma"], labels)
+    rhoR = ctx.reg_transport_forward(torch.from_numpy(case["v_true"]).cuda(), rhoT)
+    ctx.reg_set_images(rhoT, rhoR)
+    ctx.reg_solve()
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def cpu_baseline(counts, n):
+    """The FP64 oracle, as it stands, on a bounded sample: one reduced
+    gradient, one Gauss-Newton matvec and one objective of the same workload
+    at 128^3 (nt = 16), scaled by the grid-size ratio (n/128)^3 and by the
+    number of gradients, matvecs and objectives of the GPU solve."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    m = 128
+    shape = (m, m, m)
+    case = synth.phantom_case(shape, 1003)
+    rhoT = oracle.gauss(case["labels"], case["sigma"])
+    P = oracle.params(shape, 16, 1e-2)
+    rhoR = oracle.transport_forward(P, case["v_true"], rhoT)
+    v = 0.5 * case["v_true"]
+    t0 = time.time()
+    g, _, _ = oracle.gradient(P, rhoT, rhoR, v)
+    t1 = time.time()
+    oracle.hessian_matvec(P, rhoT, v, g)
+    t2 = time.time()
+    oracle.objective(P, rhoT, rhoR, v)
+    t3 = time.time()
+    scale = (n / m) ** 3
+    est = scale * (counts["gradients"] * (t1 - t0) + counts["matvecs"] * (t2 - t1) + counts["objectives"] * (t3 - t2))
+    return {
+        "value": est,
+        "unit": "s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": (f"FP64 oracle at 128^3, nt=16: one gradient ({t1 - t0:.2f} s), one GN matvec ({t2 - t1:.2f} s), "
+                   f"one objective ({t3 - t2:.2f} s), measured {t3 - t0:.1f} s; scaled by (n/128)^3 = {scale:g} and "
+                   f"by the GPU solve's {counts['gradients']} gradients, {counts['matvecs']} matvecs and "
+                   f"{counts['objectives']} objectives"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 is the benchmark workload)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", type=str, default=None,
+                    help="JSON file with rocprof FETCH_SIZE/WRITE_SIZE bytes per launch of the dominant kernel")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
+              "in DESIGN.md and is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1608_03630_amd import reg
+
+    reg.lib()
+    torch.cuda.set_device(0)
+    log("[bench] warming up with a 64^3 solve")
+    warm_small(reg, torch)
+    log(f"[bench] building the {args.n}^3 workload")
+    ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
+    v = torch.zeros((3,) + ctx.shape, dtype=torch.float64, device="cuda")
+    for w in range(args.warmup):
+        v.zero_()
+        _, rep = ctx.reg_solve(v)
+        log(f"[bench] warmup solve {w}: {rep['seconds_total']:.3f} s, {rep['n_iter']} GN steps, "
+            f"{rep['matvecs']} matvecs, mismatch {rep['final_mismatch']:.4f}")
+
+    torch.cuda.synchronize()
+    ctx.reg_profile(True)
+    reports = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        v.zero_()
+        _, rep = ctx.reg_solve(v)
+        reports.append(rep)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.reg_profile_read()
+    ctx.reg_profile(False)
+    for k, rep in enumerate(reports):
+        log(f"[bench] timed solve {k}: {rep['seconds_total']:.3f} s, {rep['n_iter']} GN steps "
+            f"(pcg {rep['pcg_iters']}), mismatch {rep['final_mismatch']:.4f}, stop {rep['stop_reason']}")
+    sec = (t1 - t0) / args.steps
+    N = ctx.N
+    rep = reports[-1]
+
+    # dominant transport kernel and its roofline (HIP events on the library's stream)
+    kinds = {k: prof[k] for k in BYTES_PER_POINT if prof[k][0] > 0}
+    dom = max(kinds, key=lambda k: kinds[k][1])
+    launches, ms = kinds[dom]
+    avg_ms = ms / launches
+    bpp = BYTES_PER_POINT[dom]
+    if dom == "incstate":
+        bpp += 12.0 / ctx.params.nt  # the last step of each sweep also writes b
+    bytes_per_launch = bpp * N
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if args.traffic and os.path.exists(args.traffic):
+        with open(args.traffic) as f:
+            t = json.load(f)
+        if t.get("kernel_family") == dom and t.get("n") == args.n:
+            traffic = t.get("bytes_per_launch")
+    interp_n, interp_ms = prof["interp"]
+    gpts = N / (interp_ms / interp_n * 1e-3) / 1e9 if interp_n else None
+    interp_gbs = BYTES_PER_POINT["interp"] * N / (interp_ms / interp_n * 1e-3) / 1e9 if interp_n else None
+
+    out = {
+        "metric": "256^3 time-to-solution at rel. mismatch 1e-2; interp Gpts/s + HBM GB/s",
+        "value": sec,
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.n}^3 smoothed ellipsoid phantom (seed 1003) warped by a seeded |k|<=8 velocity, "
+                        "nt=16, H2, beta 1e-1 -> 1e-4, FP32 fields + FP64 reductions, GN-PCG, stop at "
+                        "rel. mismatch 1e-2",
+            "grid": [args.n] * 3,
+            "nt": 16,
+        },
+        "final_mismatch": rep["final_mismatch"],
+        "stop_reason": ["gradient tolerance", "mismatch", "step limit"][rep["stop_reason"]],
+        "gn_steps": rep["n_iter"],
+        "matvecs": rep["matvecs"],
+        "pcg_iters": rep["pcg_iters"],
+        "interp_gpts_s": gpts,
+        "interp_gb_s": interp_gbs,
+        "kernel_ms": {k: {"launches": n_, "avg_ms": (t_ / n_ if n_ else None)} for k, (n_, t_) in prof.items()},
+        "roofline": {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_point": bpp,
+            "avg_launch_ms": avg_ms,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(rep, args.n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -14,9 +14,16 @@
  *  - Grid: n[0] x n[1] x n[2] points x_i = 2*pi*i/n (section III-B1); arrays
  *    are C-order [n0][n1][n2], x3 fastest. A vector field is three such
  *    arrays back to back ([3][n0][n1][n2]).
- *  - Element type: float when params.prec == 0, double when prec == 1. Every
- *    field pointer is a DEVICE pointer on the device that was current at
- *    reg_create, contiguous, aligned to its element size.
+ *  - Element types. Image-space fields (images, rho, lam, f, D, u, the
+ *    outputs of reg_interp/reg_deriv/reg_grad/reg_div/reg_spectral) are float
+ *    when params.prec == 0 and double when prec == 1. Velocity-space vectors
+ *    (every argument named v, vt, g, Hvt, r, z, v_inout, and reg_dot's
+ *    operands) are double in both modes: the H2 regulariser multiplies the
+ *    representation error of v by |k|^4, which single precision cannot
+ *    absorb on fine grids, so v, the gradient, the Krylov vectors and the 3D
+ *    spectral operators on them are kept in double while the transport runs
+ *    in the field type. Every pointer is a DEVICE pointer on the device that
+ *    was current at reg_create, contiguous and aligned to its element size.
  *  - Semi-Lagrangian points are stored as displacements in cell units,
  *    D = (X - x)/h per axis, in the same element type.
  *  - Ownership: the caller owns every buffer it passes, including the
@@ -135,20 +142,23 @@ reg_status reg_backtrace(reg_ctx *ctx, const void *v, double sign, void *D);
  * (Nyquist dropped) (section III-B1 and the line-FFT remark of III-C1). */
 reg_status reg_deriv(reg_ctx *ctx, int axis, const void *u, void *du);
 
-/* g = grad u (vector field) and d = div v (scalar), spectral as above. */
+/* g = grad u (field-type vector) and d = div w (w a field-type vector),
+ * spectral as above. */
 reg_status reg_grad(reg_ctx *ctx, const void *u, void *g);
-reg_status reg_div(reg_ctx *ctx, const void *v, void *d);
+reg_status reg_div(reg_ctx *ctx, const void *w, void *d);
 
-/* Even and projection operators on vector fields by 3D real FFTs:
- *  op 0: out = scale * lap^2 v            (symbol scale*|k|^4)
- *  op 1: out = (scale * lap^2)^-1 v       (identity on the k = 0 mode)
+/* Even and projection operators on field-type data x by 3D real FFTs in the
+ * field type:
+ *  op 0: out = scale * lap^2 x            (symbol scale*|k|^4)
+ *  op 1: out = (scale * lap^2)^-1 x       (identity on the k = 0 mode)
  *  op 2: out = Gaussian filter of width scale (radians), exp(-scale^2 |k|^2/2)
- *  op 3: out = P v, P = I - grad lap^-1 div (Leray; eq. (4))
- * ncomp is 1 or 3 (op 3 needs 3). out may alias v. */
-reg_status reg_spectral(reg_ctx *ctx, int op, double scale, int ncomp, const void *v, void *out);
+ *  op 3: out = P x, P = I - grad lap^-1 div (Leray; eq. (4))
+ * ncomp is 1 or 3 (op 3 needs 3). out may alias x. */
+reg_status reg_spectral(reg_ctx *ctx, int op, double scale, int ncomp, const void *x, void *out);
 
 /* Spectral preconditioner of section III-A: z^ = r^/(beta |k|^4) for k != 0,
- * z^_0 = r^_0, followed by P when isochoric. z may alias r. */
+ * z^_0 = r^_0, followed by P when isochoric (double precision throughout).
+ * z may alias r. */
 reg_status reg_precond(reg_ctx *ctx, const void *r, void *z);
 
 /* ------------------------------------------------------ transport solves */
@@ -190,8 +200,35 @@ reg_status reg_solve(reg_ctx *ctx, void *v_inout, reg_report *rep);
  * u_or_null receives u (vector field) when not NULL. Synchronises. */
 reg_status reg_deformation(reg_ctx *ctx, const void *v, void *u_or_null, double *detmin, double *detmax);
 
-/* <a, b> over ncomp components in double precision (h1 h2 h3 weights). */
+/* <a, b> of two velocity-space (double) vectors of ncomp components each
+ * (h1 h2 h3 weights). */
 reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double *out);
+
+/* ------------------------------------------------------------- profiling */
+
+/* Kernel families timed by the profiler. */
+typedef enum {
+    REG_K_INTERP = 0,     /* interpolation / state step: reads D (3 fields), gathers f, writes out  */
+    REG_K_BACKTRACE = 1,  /* RK2 departure points                                                    */
+    REG_K_ADJOINT = 2,    /* adjoint / incremental-adjoint step with the b accumulation              */
+    REG_K_INCSTATE = 3,   /* fused incremental-state step                                            */
+    REG_K_DEFORM = 4,     /* deformation-map step                                                    */
+    REG_K_DERIV = 5,      /* line-FFT derivative passes                                              */
+    REG_K_FFT3D = 6,      /* 3D real transform passes                                                */
+    REG_K_SYMBOL = 7,     /* pointwise spectral symbols                                              */
+    REG_K_REDUCE = 8,     /* double-precision reductions                                             */
+    REG_K_VECTOR = 9,     /* vector updates and copies                                               */
+    REG_K_COUNT = 10
+} reg_kernel_kind;
+
+/* enable = 1 clears the counters and starts timing every kernel launch of
+ * the context with a pair of HIP events on its stream; 0 stops. Timing adds
+ * two event records per launch. */
+reg_status reg_profile(reg_ctx *ctx, int enable);
+
+/* Launch count and summed GPU milliseconds of one kernel family since
+ * profiling was enabled (synchronises the stream). */
+reg_status reg_profile_read(reg_ctx *ctx, int kind, int64_t *launches, double *ms);
 
 #ifdef __cplusplus
 }

@@ -162,6 +162,12 @@ __global__ __launch_bounds__(kThreads) void k_copy(long n, const T *__restrict__
     if (i < n) y[i] = x[i];
 }
 
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kThreads) void k_convert(long n, const Ti *__restrict__ x, To *__restrict__ y) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = To(x[i]);
+}
+
 inline unsigned nb(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -217,6 +223,14 @@ hipError_t launch_copy(long n, const T *x, T *y, hipStream_t s) {
     hipLaunchKernelGGL(k_copy<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, x, y);
     return hipGetLastError();
 }
+
+template <typename Ti, typename To>
+hipError_t launch_convert(long n, const Ti *x, To *y, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<Ti, To>), dim3(nb(n)), dim3(kThreads), 0, s, n, x, y);
+    return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(long, const double *, float *, hipStream_t);
+template hipError_t launch_convert<float, double>(long, const float *, double *, hipStream_t);
 
 #define REGK_BLAS_INST(T)                                                                                          \
     template hipError_t launch_dot_partials<T>(const T *, const T *, long, int, double *, hipStream_t);            \

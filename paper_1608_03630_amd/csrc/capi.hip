@@ -5,6 +5,15 @@
 // operation runs in the kernels of interp.hip, fft.hip and blas.hip; the host
 // reads back double-precision scalars (inner products, objective, norms)
 // where the Newton-Krylov iteration branches on them.
+//
+// Precision: image-space fields (images, state and adjoint histories, grad
+// rho, departure points, b) use the field type T of params.prec; the
+// velocity-space vectors (v, g, the PCG vectors) are always double and the 3D
+// spectral operators that act on them (lap^2, its inverse, P, the gradient
+// and matvec assembly) run in double. The H2 regulariser multiplies the
+// representation error of v by |k|^4 (up to (n sqrt(3)/2)^4, about 2.4e9 on
+// a 256^3 grid), which single precision cannot absorb; the transport, whose
+// data are smooth images, runs in T.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -59,11 +68,24 @@ struct reg_ctx {
     double beta = 0;
 
     // workspace views
-    void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec, *vcur;
-    void *g_, *sdir, *r, *z, *p, *q, *vtrial, *u0, *u1, *du, *H;
-    void *tw[3];
+    void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec;
+    void *vf, *vtf;                                            // velocity copies in the field type
+    void *vcur, *g_, *sdir, *r, *z, *p, *q, *vtrial;          // velocity space, double
+    void *u0, *u1, *du, *H;
+    void *tw32[3], *tw64[3];
     double *dpart, *dpart2, *dres;
     double *hres = nullptr;  // pinned host mirror of dres
+
+    // profiler: event pairs around launches, resolved after stream syncs
+    struct ProfRec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_free;
+    std::vector<ProfRec> ev_pending;
+    double prof_ms[REG_K_COUNT] = {0};
+    int64_t prof_n[REG_K_COUNT] = {0};
 
     bool have_images = false;
     bool have_state = false;  // plans, history, grad rho and div v at vcur
@@ -88,6 +110,60 @@ reg_status hipfail(reg_ctx *ctx, hipError_t e, const char *what) {
         hipError_t e_ = (expr);                                   \
         if (e_ != hipSuccess) return hipfail((ctx), e_, #expr);  \
     } while (0)
+
+// Adds the elapsed times of completed event pairs to the counters (the
+// stream has been synchronised by the caller).
+void prof_resolve(reg_ctx *ctx) {
+    for (auto &r : ctx->ev_pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            ctx->prof_ms[r.kind] += ms;
+            ctx->prof_n[r.kind] += 1;
+        } else {
+            (void)hipGetLastError();
+        }
+        ctx->ev_free.push_back(r.a);
+        ctx->ev_free.push_back(r.b);
+    }
+    ctx->ev_pending.clear();
+}
+
+hipEvent_t take_event(reg_ctx *ctx) {
+    if (ctx->ev_free.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return e;
+    }
+    hipEvent_t e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    return e;
+}
+
+// Runs one launcher; with profiling on, brackets it with two events.
+template <class F>
+hipError_t timed(reg_ctx *ctx, int kind, F &&launch) {
+    if (!ctx->prof_on) return launch();
+    if (ctx->ev_pending.size() >= 8192) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return e;
+        prof_resolve(ctx);
+    }
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, ctx->stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, ctx->stream);
+    if (e != hipSuccess) return e;
+    ctx->ev_pending.push_back({a, b, kind});
+    return hipSuccess;
+}
+
+#define KL(ctx, kind, expr) timed((ctx), (kind), [&]() { return (expr); })
 
 #define STCHK(expr)                     \
     do {                                \
@@ -153,19 +229,25 @@ size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->lam[0] = L.take(E * N);
     c->lam[1] = L.take(E * N);
     c->bvec = L.take(E * 3 * N);
-    c->vcur = L.take(E * 3 * N);
-    c->g_ = L.take(E * 3 * N);
-    c->sdir = L.take(E * 3 * N);
-    c->r = L.take(E * 3 * N);
-    c->z = L.take(E * 3 * N);
-    c->p = L.take(E * 3 * N);
-    c->q = L.take(E * 3 * N);
-    c->vtrial = L.take(E * 3 * N);
+    c->vf = L.take(E * 3 * N);
+    c->vtf = L.take(E * 3 * N);
+    const size_t D8 = sizeof(double);
+    c->vcur = L.take(D8 * 3 * N);
+    c->g_ = L.take(D8 * 3 * N);
+    c->sdir = L.take(D8 * 3 * N);
+    c->r = L.take(D8 * 3 * N);
+    c->z = L.take(D8 * 3 * N);
+    c->p = L.take(D8 * 3 * N);
+    c->q = L.take(D8 * 3 * N);
+    c->vtrial = L.take(D8 * 3 * N);
     c->u0 = L.take(E * 3 * N);
     c->u1 = L.take(E * 3 * N);
     c->du = L.take(E * 9 * N);
-    c->H = L.take(2 * E * 6 * Nh);
-    for (int j = 0; j < 3; j++) c->tw[j] = L.take(2 * E * p->n[j]);
+    c->H = L.take(2 * D8 * 6 * Nh);
+    for (int j = 0; j < 3; j++) {
+        c->tw32[j] = L.take(2 * sizeof(float) * p->n[j]);
+        c->tw64[j] = L.take(2 * D8 * p->n[j]);
+    }
     c->dpart = (double *)L.take(sizeof(double) * regk::RED_BLOCKS);
     c->dpart2 = (double *)L.take(sizeof(double) * regk::RED_BLOCKS);
     c->dres = (double *)L.take(sizeof(double) * kSlots);
@@ -194,24 +276,44 @@ template <typename T> const T *CV(const void *p) { return static_cast<const T *>
 
 double h3(const reg_ctx *c) { return (kTwoPi / c->g.n1) * (kTwoPi / c->g.n2) * (kTwoPi / c->g.n3); }
 
+// velocity (double) -> field type copy
+template <typename T>
+hipError_t to_field(reg_ctx *ctx, const void *src, void *dst, long n) {
+    if (sizeof(T) == sizeof(double))
+        return regk::launch_copy<double>(n, CV<double>(src), V<double>(dst), ctx->stream);
+    return regk::launch_convert<double, float>(n, CV<double>(src), V<float>(dst), ctx->stream);
+}
+
 // reads kSlots doubles back (synchronises)
 reg_status fetch(reg_ctx *ctx, int nslots) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (!ctx->ev_pending.empty()) prof_resolve(ctx);
     return REG_OK;
 }
 
 // dres[slot] = scale * reduction
 template <typename T>
 reg_status reduce(reg_ctx *ctx, const void *a, const void *b, long n, int mode, double scale, int slot) {
-    HIPCHK(ctx, regk::launch_dot_partials<T>(CV<T>(a), CV<T>(b ? b : a), n, mode, ctx->dpart, ctx->stream));
-    HIPCHK(ctx, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_dot_partials<T>(CV<T>(a), CV<T>(b ? b : a), n, mode, ctx->dpart, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream)));
     return REG_OK;
 }
 
 template <typename T>
+reg_status plan(reg_ctx *ctx, const void *v, double sign, void *D);
+
+// public backtrace: v is a velocity-space double vector
+template <typename T>
+reg_status backtrace_impl(reg_ctx *ctx, const void *v, double sign, void *D) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * ctx->N)));
+    return plan<T>(ctx, ctx->vf, sign, D);
+}
+
+// departure points from vf (field type)
+template <typename T>
 reg_status plan(reg_ctx *ctx, const void *v, double sign, void *D) {
-    HIPCHK(ctx, regk::launch_backtrace<T>(ctx->g, CV<T>(v), sign / ctx->P.nt, V<T>(D), ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_BACKTRACE, regk::launch_backtrace<T>(ctx->g, CV<T>(v), sign / ctx->P.nt, V<T>(D), ctx->stream)));
     ctx->interps += 3;
     return REG_OK;
 }
@@ -220,10 +322,10 @@ reg_status plan(reg_ctx *ctx, const void *v, double sign, void *D) {
 template <typename T>
 reg_status state_solve(reg_ctx *ctx, const void *Df, const void *rho0, void *hist) {
     const long N = ctx->N;
-    if (rho0 != hist) HIPCHK(ctx, regk::launch_copy<T>(N, CV<T>(rho0), V<T>(hist), ctx->stream));
+    if (rho0 != hist) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(N, CV<T>(rho0), V<T>(hist), ctx->stream)));
     for (int k = 0; k < ctx->P.nt; k++)
-        HIPCHK(ctx, regk::launch_interp<T>(ctx->g, V<T>(hist) + k * N, CV<T>(Df), V<T>(hist) + (k + 1) * N,
-                                           ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, V<T>(hist) + k * N, CV<T>(Df), V<T>(hist) + (k + 1) * N,
+                                           ctx->stream)));
     ctx->interps += ctx->P.nt;
     return REG_OK;
 }
@@ -233,7 +335,7 @@ template <typename T>
 reg_status divergence(reg_ctx *ctx, const void *v, void *d) {
     const long N = ctx->N;
     for (int j = 0; j < 3; j++)
-        HIPCHK(ctx, regk::spec_deriv<T>(ctx->spec, j, CV<T>(v) + j * N, N, V<T>(d), N, j > 0, 1, ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(v) + j * N, N, V<T>(d), N, j > 0, 1, ctx->stream)));
     return REG_OK;
 }
 
@@ -242,19 +344,21 @@ template <typename T>
 reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
     const long N = ctx->N;
     for (int j = 0; j < 3; j++)
-        HIPCHK(ctx, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream)));
     return REG_OK;
 }
 
 // out = IFFT(beta |k|^4 x^ + [P] y^); also leaves sum w |k|^4 |x^|^2 partials
 // in dpart2 when want_reg
+// (x and out are velocity-space doubles, y is a field-type vector; the
+// transforms run in double)
 template <typename T>
 reg_status assemble(reg_ctx *ctx, const void *x, const void *y, void *out, bool want_reg) {
-    HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(x), 3, 0, ctx->stream));
-    if (want_reg) HIPCHK(ctx, regk::spec_biharm_norm_partials<T>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream));
-    HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(y), 3, 3, ctx->stream));
-    HIPCHK(ctx, regk::spec_symbol<T>(ctx->spec, regk::SYM_ASSEMBLE, ctx->beta, 3, ctx->P.isochoric, ctx->stream));
-    HIPCHK(ctx, regk::spec_inverse<T>(ctx->spec, V<T>(out), 3, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(x), 3, 0, ctx->stream))));
+    if (want_reg) HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<T, double>(ctx->spec, CV<T>(y), 3, 3, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_ASSEMBLE, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(out), 3, ctx->stream))));
     return REG_OK;
 }
 
@@ -262,14 +366,14 @@ reg_status assemble(reg_ctx *ctx, const void *x, const void *y, void *out, bool 
 reg_status reg_term_to_slot(reg_ctx *ctx, int slot) {
     const double N = (double)ctx->N;
     const double scale = 0.5 * ctx->beta * kTwoPi * kTwoPi * kTwoPi / (N * N);
-    HIPCHK(ctx, regk::launch_finalize(ctx->dpart2, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart2, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream)));
     return REG_OK;
 }
 
-template <typename T>
+// v is a velocity-space double vector
 reg_status regulariser_of(reg_ctx *ctx, const void *v, int slot) {
-    HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(v), 3, 0, ctx->stream));
-    HIPCHK(ctx, regk::spec_biharm_norm_partials<T>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
     return reg_term_to_slot(ctx, slot);
 }
 
@@ -283,9 +387,9 @@ reg_status adjoint_sweep(reg_ctx *ctx, int start, const void *Da, const void *c,
     int cur = start;
     for (int k = nt - 1; k >= 0; k--) {
         const double w = (k == 0) ? 0.5 * dt : dt;
-        HIPCHK(ctx, regk::launch_adjoint_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(Da), CV<T>(c), CV<T>(cX),
+        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(Da), CV<T>(c), CV<T>(cX),
                                                  V<T>(ctx->grho) + (long)k * 3 * N, V<T>(b), V<T>(ctx->lam[1 - cur]),
-                                                 dt, w, ctx->stream));
+                                                 dt, w, ctx->stream)));
         cur = 1 - cur;
     }
     ctx->interps += nt;
@@ -293,13 +397,14 @@ reg_status adjoint_sweep(reg_ctx *ctx, int start, const void *Da, const void *c,
 }
 
 // plan for -v, grad rho^n and div v: completes the cached state at vcur
+// (vf holds vcur in the field type)
 template <typename T>
 reg_status complete_state(reg_ctx *ctx) {
-    STCHK(plan<T>(ctx, ctx->vcur, -1.0, ctx->Da));
+    STCHK(plan<T>(ctx, ctx->vf, -1.0, ctx->Da));
     STCHK(gradient_fields<T>(ctx, ctx->histA, ctx->P.nt + 1, ctx->grho));
     if (!ctx->P.isochoric) {
-        STCHK(divergence<T>(ctx, ctx->vcur, ctx->c));
-        HIPCHK(ctx, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX), ctx->stream));
+        STCHK(divergence<T>(ctx, ctx->vf, ctx->c));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX), ctx->stream)));
         ctx->interps += 1;
     }
     ctx->have_state = true;
@@ -311,7 +416,7 @@ template <typename T>
 reg_status objective_slots(reg_ctx *ctx, const void *hist, const void *v, bool reg_done) {
     const long N = ctx->N;
     STCHK(reduce<T>(ctx, V<T>(const_cast<void *>(hist)) + (long)ctx->P.nt * N, ctx->rhoR, N, 1, h3(ctx), 1));
-    if (!reg_done) STCHK(regulariser_of<T>(ctx, v, 2));
+    if (!reg_done) STCHK(regulariser_of(ctx, v, 2));
     else STCHK(reg_term_to_slot(ctx, 2));
     return REG_OK;
 }
@@ -329,24 +434,25 @@ reg_status gradient_impl(reg_ctx *ctx, const void *v, void *g, double *J, double
                          bool reuse_trial) {
     const long N = ctx->N;
     const int nt = ctx->P.nt;
-    if (v != ctx->vcur) HIPCHK(ctx, regk::launch_copy<T>(3 * N, CV<T>(v), V<T>(ctx->vcur), ctx->stream));
+    if (v != ctx->vcur) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(3 * N, CV<double>(v), V<double>(ctx->vcur), ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, ctx->vcur, ctx->vf, 3 * N)));
     if (reuse_trial) {
         std::swap(ctx->histA, ctx->histB);
         std::swap(ctx->Df, ctx->Dt);
     } else {
-        STCHK(plan<T>(ctx, ctx->vcur, +1.0, ctx->Df));
+        STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Df));
         STCHK(state_solve<T>(ctx, ctx->Df, ctx->rhoT, ctx->histA));
     }
     STCHK(complete_state<T>(ctx));
     // adjoint from lam(1) = rho_R - rho(1), b = sum w_n lam^n grad rho^n
-    HIPCHK(ctx, regk::launch_adjoint_init<T>(ctx->g, CV<T>(ctx->rhoR), V<T>(ctx->histA) + (long)nt * N,
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_adjoint_init<T>(ctx->g, CV<T>(ctx->rhoR), V<T>(ctx->histA) + (long)nt * N,
                                              V<T>(ctx->grho) + (long)nt * 3 * N, V<T>(ctx->lam[0]), V<T>(ctx->bvec),
-                                             0.5 / nt, ctx->stream));
+                                             0.5 / nt, ctx->stream)));
     STCHK(adjoint_sweep<T>(ctx, 0, ctx->Da, ctx->P.isochoric ? nullptr : ctx->c,
                            ctx->P.isochoric ? nullptr : ctx->cX, ctx->bvec));
     STCHK(assemble<T>(ctx, ctx->vcur, ctx->bvec, g, true));
     STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vcur, true));
-    STCHK(reduce<T>(ctx, g, nullptr, 3 * N, 2, h3(ctx), 3));
+    STCHK(reduce<double>(ctx, g, nullptr, 3 * N, 2, h3(ctx), 3));
     STCHK(fetch(ctx, 4));
     scalars_to_J(ctx, J, mis);
     if (gnorm) *gnorm = std::sqrt(ctx->hres[3]);
@@ -361,15 +467,16 @@ reg_status matvec_impl(reg_ctx *ctx, const void *vt, void *Hvt) {
     const int nt = ctx->P.nt;
     const double dt = 1.0 / nt;
     // incremental state through q^n = rho~^n - dt/2 vt.grad rho^n
-    HIPCHK(ctx, regk::launch_incstate_init<T>(ctx->g, CV<T>(vt), V<T>(ctx->grho), V<T>(ctx->lam[1]), -0.5 * dt,
-                                              ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, vt, ctx->vtf, 3 * N)));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho), V<T>(ctx->lam[1]), -0.5 * dt,
+                                              ctx->stream)));
     int cur = 1;
     for (int k = 0; k < nt; k++) {
         const int last = (k == nt - 1);
-        HIPCHK(ctx, regk::launch_incstate_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(ctx->Df), CV<T>(vt),
+        HIPCHK(ctx, KL(ctx, REG_K_INCSTATE, regk::launch_incstate_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(ctx->Df), CV<T>(ctx->vtf),
                                                   V<T>(ctx->grho) + (long)(k + 1) * 3 * N, V<T>(ctx->lam[1 - cur]),
                                                   last ? -0.5 * dt : -dt, last, V<T>(ctx->bvec), 0.5 * dt,
-                                                  ctx->stream));
+                                                  ctx->stream)));
         cur = 1 - cur;
     }
     ctx->interps += nt;
@@ -380,18 +487,19 @@ reg_status matvec_impl(reg_ctx *ctx, const void *vt, void *Hvt) {
     return REG_OK;
 }
 
-template <typename T>
+// r and z are velocity-space doubles
 reg_status precond_impl(reg_ctx *ctx, const void *r, void *z) {
-    HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(r), 3, 0, ctx->stream));
-    HIPCHK(ctx, regk::spec_symbol<T>(ctx->spec, regk::SYM_PRECOND, ctx->beta, 3, ctx->P.isochoric, ctx->stream));
-    HIPCHK(ctx, regk::spec_inverse<T>(ctx->spec, V<T>(z), 3, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(r), 3, 0, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_PRECOND, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(z), 3, ctx->stream))));
     return REG_OK;
 }
 
 // J and mismatch of a trial velocity: plan into Dt, state into histB
 template <typename T>
 reg_status trial_objective(reg_ctx *ctx, const void *v, double *J, double *mis) {
-    STCHK(plan<T>(ctx, v, +1.0, ctx->Dt));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * ctx->N)));
+    STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Dt));
     STCHK(state_solve<T>(ctx, ctx->Dt, ctx->rhoT, ctx->histB));
     STCHK(objective_slots<T>(ctx, ctx->histB, v, false));
     STCHK(fetch(ctx, 3));
@@ -400,9 +508,9 @@ reg_status trial_objective(reg_ctx *ctx, const void *v, double *J, double *mis) 
     return REG_OK;
 }
 
-template <typename T>
+// inner product of two velocity-space vectors
 reg_status dot3(reg_ctx *ctx, const void *a, const void *b, double *out) {
-    STCHK(reduce<T>(ctx, a, b, 3 * ctx->N, 0, h3(ctx), 0));
+    STCHK(reduce<double>(ctx, a, b, 3 * ctx->N, 0, h3(ctx), 0));
     STCHK(fetch(ctx, 1));
     *out = ctx->hres[0];
     return REG_OK;
@@ -418,9 +526,9 @@ reg_status solve_impl(reg_ctx *ctx, void *v, reg_report *rep) {
     auto t0 = clk::now();
     const long interps0 = ctx->interps;
     if (P.isochoric) {
-        HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(v), 3, 0, ctx->stream));
-        HIPCHK(ctx, regk::spec_symbol<T>(ctx->spec, regk::SYM_LERAY, 0.0, 3, 1, ctx->stream));
-        HIPCHK(ctx, regk::spec_inverse<T>(ctx->spec, V<T>(v), 3, ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
+        HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_LERAY, 0.0, 3, 1, ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(v), 3, ctx->stream))));
     }
     const double beta_final = P.beta_final > 0 ? P.beta_final : P.beta;
     const double factor = (P.beta_factor > 0 && P.beta_factor < 1) ? P.beta_factor : 0.1;
@@ -450,54 +558,54 @@ reg_status solve_impl(reg_ctx *ctx, void *v, reg_report *rep) {
             double eta = P.forcing == 1 ? std::sqrt(ratio) : ratio;
             if (eta > 0.5) eta = 0.5;
             // truncated PCG on H s = -g
-            HIPCHK(ctx, regk::launch_fill<T>(N3, 0.0, V<T>(ctx->sdir), ctx->stream));
-            HIPCHK(ctx, regk::launch_axpby<T>(N3, -1.0, CV<T>(ctx->g_), 0.0, V<T>(ctx->r), ctx->stream));
+            HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<double>(N3, 0.0, V<double>(ctx->sdir), ctx->stream)));
+            HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_axpby<double>(N3, -1.0, CV<double>(ctx->g_), 0.0, V<double>(ctx->r), ctx->stream)));
             auto tp = clk::now();
-            STCHK(precond_impl<T>(ctx, ctx->r, ctx->z));
+            STCHK(precond_impl(ctx, ctx->r, ctx->z));
             rep->seconds_precond += secs(tp);
-            HIPCHK(ctx, regk::launch_copy<T>(N3, CV<T>(ctx->z), V<T>(ctx->p), ctx->stream));
+            HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->p), ctx->stream)));
             double rz;
-            STCHK(dot3<T>(ctx, ctx->r, ctx->z, &rz));
+            STCHK(dot3(ctx, ctx->r, ctx->z, &rz));
             int iters = 0;
             for (int i = 0; i < P.max_pcg; i++) {
                 auto tm = clk::now();
                 STCHK(matvec_impl<T>(ctx, ctx->p, ctx->q));
                 double kappa;
-                STCHK(dot3<T>(ctx, ctx->p, ctx->q, &kappa));
+                STCHK(dot3(ctx, ctx->p, ctx->q, &kappa));
                 rep->seconds_matvec += secs(tm);
                 rep->matvecs++;
                 iters = i + 1;
                 if (!std::isfinite(kappa)) return fail(ctx, REG_ENONFINITE, "non-finite curvature in PCG");
                 if (kappa <= 0) {
-                    if (i == 0) HIPCHK(ctx, regk::launch_copy<T>(N3, CV<T>(ctx->z), V<T>(ctx->sdir), ctx->stream));
+                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->sdir), ctx->stream)));
                     break;
                 }
                 const double a = rz / kappa;
-                HIPCHK(ctx, regk::launch_cg_update<T>(N3, a, CV<T>(ctx->p), CV<T>(ctx->q), V<T>(ctx->sdir),
-                                                      V<T>(ctx->r), ctx->stream));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_cg_update<double>(N3, a, CV<double>(ctx->p), CV<double>(ctx->q), V<double>(ctx->sdir),
+                                                      V<double>(ctx->r), ctx->stream)));
                 double rr;
-                STCHK(dot3<T>(ctx, ctx->r, ctx->r, &rr));
+                STCHK(dot3(ctx, ctx->r, ctx->r, &rr));
                 if (std::sqrt(rr) <= eta * gnorm) break;
                 tp = clk::now();
-                STCHK(precond_impl<T>(ctx, ctx->r, ctx->z));
+                STCHK(precond_impl(ctx, ctx->r, ctx->z));
                 rep->seconds_precond += secs(tp);
                 double rz1;
-                STCHK(dot3<T>(ctx, ctx->r, ctx->z, &rz1));
-                HIPCHK(ctx, regk::launch_xpay<T>(N3, CV<T>(ctx->z), rz1 / rz, CV<T>(ctx->p), V<T>(ctx->p),
-                                                 ctx->stream));
+                STCHK(dot3(ctx, ctx->r, ctx->z, &rz1));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(ctx->z), rz1 / rz, CV<double>(ctx->p), V<double>(ctx->p),
+                                                 ctx->stream)));
                 rz = rz1;
             }
             // Armijo backtracking
             double d;
-            STCHK(dot3<T>(ctx, ctx->g_, ctx->sdir, &d));
+            STCHK(dot3(ctx, ctx->g_, ctx->sdir, &d));
             double alpha = 1.0, Jt = 0, mist = 0;
             int trials = 0;
             bool accepted = false;
             auto to = clk::now();
             for (int l = 0; l < P.max_ls; l++) {
                 trials++;
-                HIPCHK(ctx, regk::launch_xpay<T>(N3, CV<T>(v), alpha, CV<T>(ctx->sdir), V<T>(ctx->vtrial),
-                                                 ctx->stream));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(v), alpha, CV<double>(ctx->sdir), V<double>(ctx->vtrial),
+                                                 ctx->stream)));
                 STCHK(trial_objective<T>(ctx, ctx->vtrial, &Jt, &mist));
                 rep->objectives++;
                 if (Jt <= J + P.armijo_c1 * alpha * d) {
@@ -512,7 +620,7 @@ reg_status solve_impl(reg_ctx *ctx, void *v, reg_report *rep) {
                 done = true;
                 break;
             }
-            HIPCHK(ctx, regk::launch_copy<T>(N3, CV<T>(ctx->vtrial), V<T>(v), ctx->stream));
+            HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->vtrial), V<double>(v), ctx->stream)));
             tg = clk::now();
             STCHK(gradient_impl<T>(ctx, v, ctx->g_, &J, &mis, &gnorm, true));
             rep->seconds_gradient += secs(tg);
@@ -556,23 +664,24 @@ template <typename T>
 reg_status deformation_impl(reg_ctx *ctx, const void *v, void *u_out, double *dmin, double *dmax) {
     const long N = ctx->N;
     const int nt = ctx->P.nt;
-    STCHK(plan<T>(ctx, v, +1.0, ctx->Dt));
-    HIPCHK(ctx, regk::launch_fill<T>(3 * N, 0.0, V<T>(ctx->u0), ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));
+    STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Dt));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<T>(3 * N, 0.0, V<T>(ctx->u0), ctx->stream)));
     void *ub[2] = {ctx->u0, ctx->u1};
     int cur = 0;
     for (int k = 0; k < nt; k++) {
-        HIPCHK(ctx, regk::launch_deform_step<T>(ctx->g, V<T>(ub[cur]), CV<T>(ctx->Dt), V<T>(ub[1 - cur]),
-                                                ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_DEFORM, regk::launch_deform_step<T>(ctx->g, V<T>(ub[cur]), CV<T>(ctx->Dt), V<T>(ub[1 - cur]),
+                                                ctx->stream)));
         cur = 1 - cur;
     }
     ctx->interps += 3 * nt;
     // du[a*3+b] = d_b u_a
     for (int b = 0; b < 3; b++)
-        HIPCHK(ctx, regk::spec_deriv<T>(ctx->spec, b, V<T>(ub[cur]), N, V<T>(ctx->du) + b * N, 3 * N, 0, 3,
-                                        ctx->stream));
-    HIPCHK(ctx, regk::launch_det_partials<T>(V<T>(ctx->du), N, ctx->dpart, ctx->dpart2, (T *)nullptr, ctx->stream));
-    HIPCHK(ctx, regk::launch_finalize_minmax(ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->dres, ctx->stream));
-    if (u_out) HIPCHK(ctx, regk::launch_copy<T>(3 * N, V<T>(ub[cur]), V<T>(u_out), ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, b, V<T>(ub[cur]), N, V<T>(ctx->du) + b * N, 3 * N, 0, 3,
+                                        ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_det_partials<T>(V<T>(ctx->du), N, ctx->dpart, ctx->dpart2, (T *)nullptr, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_minmax(ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->dres, ctx->stream)));
+    if (u_out) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(3 * N, V<T>(ub[cur]), V<T>(u_out), ctx->stream)));
     STCHK(fetch(ctx, 2));
     *dmin = ctx->hres[0];
     *dmax = ctx->hres[1];
@@ -582,12 +691,13 @@ reg_status deformation_impl(reg_ctx *ctx, const void *v, void *u_out, double *dm
 template <typename T>
 reg_status transport_forward_impl(reg_ctx *ctx, const void *v, const void *rho0, void *rho1) {
     const long N = ctx->N;
-    STCHK(plan<T>(ctx, v, +1.0, ctx->Dt));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));
+    STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Dt));
     // ping-pong between two slices of the scratch history, last step into rho1
     const T *src = CV<T>(rho0);
     for (int k = 0; k < ctx->P.nt; k++) {
         T *dst = (k == ctx->P.nt - 1) ? V<T>(rho1) : V<T>(ctx->histB) + (long)(k & 1) * N;
-        HIPCHK(ctx, regk::launch_interp<T>(ctx->g, src, CV<T>(ctx->Dt), dst, ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, src, CV<T>(ctx->Dt), dst, ctx->stream)));
         src = dst;
     }
     ctx->interps += ctx->P.nt;
@@ -598,19 +708,20 @@ template <typename T>
 reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1, void *lam0) {
     const long N = ctx->N;
     const int nt = ctx->P.nt;
-    STCHK(plan<T>(ctx, v, -1.0, ctx->Dt));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));
+    STCHK(plan<T>(ctx, ctx->vf, -1.0, ctx->Dt));
     const bool src = !ctx->P.isochoric;
     if (src) {
-        STCHK(divergence<T>(ctx, v, ctx->c2));
-        HIPCHK(ctx, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream));
+        STCHK(divergence<T>(ctx, ctx->vf, ctx->c2));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream)));
         ctx->interps += 1;
     }
     const T *in = CV<T>(lam1);
     for (int k = 0; k < nt; k++) {
         T *out = (k == nt - 1) ? V<T>(lam0) : V<T>(ctx->histB) + (long)(k & 1) * N;
-        HIPCHK(ctx, regk::launch_adjoint_step<T>(ctx->g, in, CV<T>(ctx->Dt), src ? CV<T>(ctx->c2) : nullptr,
+        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, in, CV<T>(ctx->Dt), src ? CV<T>(ctx->c2) : nullptr,
                                                  src ? CV<T>(ctx->cX2) : nullptr, nullptr, nullptr, out, 1.0 / nt, 0.0,
-                                                 ctx->stream));
+                                                 ctx->stream)));
         in = out;
     }
     ctx->interps += nt;
@@ -619,10 +730,10 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
 
 template <typename T>
 reg_status spectral_impl(reg_ctx *ctx, int op, double scale, int ncomp, const void *v, void *out) {
-    HIPCHK(ctx, regk::spec_forward<T>(ctx->spec, CV<T>(v), ncomp, 0, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<T, T>(ctx->spec, CV<T>(v), ncomp, 0, ctx->stream))));
     int sym = op == 0 ? regk::SYM_BIHARM : op == 1 ? regk::SYM_INVBIHARM : op == 2 ? regk::SYM_GAUSS : regk::SYM_LERAY;
-    HIPCHK(ctx, regk::spec_symbol<T>(ctx->spec, sym, scale, ncomp, 1, ctx->stream));
-    HIPCHK(ctx, regk::spec_inverse<T>(ctx->spec, V<T>(out), ncomp, ctx->stream));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<T>(ctx->spec, sym, scale, ncomp, 1, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<T, T>(ctx->spec, V<T>(out), ncomp, ctx->stream))));
     return REG_OK;
 }
 
@@ -696,36 +807,26 @@ reg_status reg_create(const reg_params *p, void *workspace, size_t bytes, void *
     }
     ctx->spec.g = ctx->g;
     ctx->spec.H = ctx->H;
-    std::vector<double> buf;
     for (int j = 0; j < 3; j++) {
         regk::make_plan(p->n[j], &ctx->spec.plan[j]);
-        ctx->spec.tw[j] = ctx->tw[j];
+        ctx->spec.tw[0][j] = ctx->tw32[j];
+        ctx->spec.tw[1][j] = ctx->tw64[j];
         const int n = p->n[j];
         // twiddles exp(-2 pi i m / n), computed in double
-        if (p->prec) {
-            buf.resize(2 * n);
-            for (int m = 0; m < n; m++) {
-                buf[2 * m] = std::cos(kTwoPi * m / n);
-                buf[2 * m + 1] = -std::sin(kTwoPi * m / n);
-            }
-            if (hipMemcpy(ctx->tw[j], buf.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
-                (void)hipGetLastError();
-                (void)hipHostFree(ctx->hres);
-                delete ctx;
-                return REG_EHIP;
-            }
-        } else {
-            std::vector<float> fb(2 * n);
-            for (int m = 0; m < n; m++) {
-                fb[2 * m] = (float)std::cos(kTwoPi * m / n);
-                fb[2 * m + 1] = (float)-std::sin(kTwoPi * m / n);
-            }
-            if (hipMemcpy(ctx->tw[j], fb.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
-                (void)hipGetLastError();
-                (void)hipHostFree(ctx->hres);
-                delete ctx;
-                return REG_EHIP;
-            }
+        std::vector<double> b64(2 * n);
+        std::vector<float> b32(2 * n);
+        for (int m = 0; m < n; m++) {
+            b64[2 * m] = std::cos(kTwoPi * m / n);
+            b64[2 * m + 1] = -std::sin(kTwoPi * m / n);
+            b32[2 * m] = (float)b64[2 * m];
+            b32[2 * m + 1] = (float)b64[2 * m + 1];
+        }
+        if (hipMemcpy(ctx->tw64[j], b64.data(), sizeof(double) * 2 * n, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(ctx->tw32[j], b32.data(), sizeof(float) * 2 * n, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipHostFree(ctx->hres);
+            delete ctx;
+            return REG_EHIP;
         }
     }
     *out = ctx;
@@ -735,6 +836,8 @@ reg_status reg_create(const reg_params *p, void *workspace, size_t bytes, void *
 reg_status reg_destroy(reg_ctx *ctx) {
     if (!ctx) return REG_EINVAL;
     (void)hipStreamSynchronize(ctx->stream);
+    prof_resolve(ctx);
+    for (hipEvent_t e : ctx->ev_free) (void)hipEventDestroy(e);
     if (ctx->hres) (void)hipHostFree(ctx->hres);
     delete ctx;
     return REG_OK;
@@ -756,12 +859,12 @@ reg_status reg_set_images(reg_ctx *ctx, const void *rho_T, const void *rho_R) {
     NEED_DEV(ctx, rho_R);
     const long N = ctx->N;
     if (ctx->P.prec) {
-        HIPCHK(ctx, regk::launch_copy<double>(N, CV<double>(rho_T), V<double>(ctx->rhoT), ctx->stream));
-        HIPCHK(ctx, regk::launch_copy<double>(N, CV<double>(rho_R), V<double>(ctx->rhoR), ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N, CV<double>(rho_T), V<double>(ctx->rhoT), ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N, CV<double>(rho_R), V<double>(ctx->rhoR), ctx->stream)));
         STCHK(reduce<double>(ctx, ctx->rhoT, ctx->rhoR, N, 1, h3(ctx), 0));
     } else {
-        HIPCHK(ctx, regk::launch_copy<float>(N, CV<float>(rho_T), V<float>(ctx->rhoT), ctx->stream));
-        HIPCHK(ctx, regk::launch_copy<float>(N, CV<float>(rho_R), V<float>(ctx->rhoR), ctx->stream));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<float>(N, CV<float>(rho_T), V<float>(ctx->rhoT), ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<float>(N, CV<float>(rho_R), V<float>(ctx->rhoR), ctx->stream)));
         STCHK(reduce<float>(ctx, ctx->rhoT, ctx->rhoR, N, 1, h3(ctx), 0));
     }
     STCHK(fetch(ctx, 1));
@@ -778,8 +881,8 @@ reg_status reg_interp(reg_ctx *ctx, const void *f, const void *D, void *out) {
     NEED_DEV(ctx, out);
     if (f == out) return fail(ctx, REG_EINVAL, "out must not alias f");
     ctx->interps++;
-    if (ctx->P.prec) HIPCHK(ctx, regk::launch_interp<double>(ctx->g, CV<double>(f), CV<double>(D), V<double>(out), ctx->stream));
-    else HIPCHK(ctx, regk::launch_interp<float>(ctx->g, CV<float>(f), CV<float>(D), V<float>(out), ctx->stream));
+    if (ctx->P.prec) HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<double>(ctx->g, CV<double>(f), CV<double>(D), V<double>(out), ctx->stream)));
+    else HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<float>(ctx->g, CV<float>(f), CV<float>(D), V<float>(out), ctx->stream)));
     return REG_OK;
 }
 
@@ -789,7 +892,7 @@ reg_status reg_backtrace(reg_ctx *ctx, const void *v, double sign, void *D) {
     NEED_DEV(ctx, D);
     if (sign != 1.0 && sign != -1.0) return fail(ctx, REG_EINVAL, "sign must be +1 or -1");
     if (v == D) return fail(ctx, REG_EINVAL, "D must not alias v");
-    return DISPATCH(ctx, plan, ctx, v, sign, D);
+    return DISPATCH(ctx, backtrace_impl, ctx, v, sign, D);
 }
 
 reg_status reg_deriv(reg_ctx *ctx, int axis, const void *u, void *du) {
@@ -798,8 +901,8 @@ reg_status reg_deriv(reg_ctx *ctx, int axis, const void *u, void *du) {
     NEED_DEV(ctx, du);
     if (axis < 0 || axis > 2) return fail(ctx, REG_EINVAL, "axis must be 0, 1 or 2");
     const long N = ctx->N;
-    if (ctx->P.prec) HIPCHK(ctx, regk::spec_deriv<double>(ctx->spec, axis, CV<double>(u), N, V<double>(du), N, 0, 1, ctx->stream));
-    else HIPCHK(ctx, regk::spec_deriv<float>(ctx->spec, axis, CV<float>(u), N, V<float>(du), N, 0, 1, ctx->stream));
+    if (ctx->P.prec) HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<double>(ctx->spec, axis, CV<double>(u), N, V<double>(du), N, 0, 1, ctx->stream)));
+    else HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<float>(ctx->spec, axis, CV<float>(u), N, V<float>(du), N, 0, 1, ctx->stream)));
     return REG_OK;
 }
 
@@ -833,7 +936,7 @@ reg_status reg_precond(reg_ctx *ctx, const void *r, void *z) {
     CTX_OK(ctx);
     NEED_DEV(ctx, r);
     NEED_DEV(ctx, z);
-    return DISPATCH(ctx, precond_impl, ctx, r, z);
+    return precond_impl(ctx, r, z);
 }
 
 reg_status reg_transport_forward(reg_ctx *ctx, const void *v, const void *rho0, void *rho1) {
@@ -903,11 +1006,34 @@ reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double
     NEED_DEV(ctx, a);
     NEED_DEV(ctx, b);
     if (!out || ncomp < 1) return fail(ctx, REG_EINVAL, "bad arguments");
-    reg_status st = ctx->P.prec ? reduce<double>(ctx, a, b, ncomp * ctx->N, 0, h3(ctx), 0)
-                                : reduce<float>(ctx, a, b, ncomp * ctx->N, 0, h3(ctx), 0);
+    reg_status st = reduce<double>(ctx, a, b, ncomp * ctx->N, 0, h3(ctx), 0);
     if (st != REG_OK) return st;
     STCHK(fetch(ctx, 1));
     *out = ctx->hres[0];
+    return REG_OK;
+}
+
+reg_status reg_profile(reg_ctx *ctx, int enable) {
+    CTX_OK(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    prof_resolve(ctx);
+    for (int k = 0; k < REG_K_COUNT; k++) {
+        if (enable) {
+            ctx->prof_ms[k] = 0;
+            ctx->prof_n[k] = 0;
+        }
+    }
+    ctx->prof_on = enable != 0;
+    return REG_OK;
+}
+
+reg_status reg_profile_read(reg_ctx *ctx, int kind, int64_t *launches, double *ms) {
+    CTX_OK(ctx);
+    if (kind < 0 || kind >= REG_K_COUNT || !launches || !ms) return fail(ctx, REG_EINVAL, "bad profile query");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    prof_resolve(ctx);
+    *launches = ctx->prof_n[kind];
+    *ms = ctx->prof_ms[kind];
     return REG_OK;
 }
 

@@ -61,20 +61,22 @@ hipError_t launch_deform_step(const Grid &g, const T *u_in, const T *Df, T *u_ou
 struct SpecCtx {
     Grid g;
     FftPlan plan[3];
-    const void *tw[3];   // per-axis twiddles exp(-2 pi i m / n_axis), element type complex T
-    void *H;             // half-spectrum buffer of up to 6 components, complex T
+    const void *tw[2][3];  // per-axis twiddles exp(-2 pi i m / n_axis): [0] float2, [1] double2
+    void *H;               // half-spectrum buffer of up to 6 complex components (sized for double)
 };
 // derivative along axis of ncomp fields u + k*in_stride into out + k*out_stride
 // (accumulate: out += d_axis u)
 template <typename T>
 hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T *out, long out_stride, int accumulate,
                       int ncomp, hipStream_t s);
-// forward 3D real FFT of ncomp fields into H components [h0, h0+ncomp)
-template <typename T>
-hipError_t spec_forward(const SpecCtx &c, const T *x, int ncomp, int h0, hipStream_t s);
-// inverse 3D FFT of H components [0, ncomp) into real fields (divides by N)
-template <typename T>
-hipError_t spec_inverse(const SpecCtx &c, T *out, int ncomp, hipStream_t s);
+// forward 3D real FFT of ncomp fields of type Tr, computed in T, into H
+// components [h0, h0+ncomp)
+template <typename Tr, typename T>
+hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStream_t s);
+// inverse 3D FFT (computed in T) of H components [0, ncomp) into real fields
+// of type Tr (divides by N)
+template <typename T, typename Tr>
+hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s);
 
 enum SymbolOp {
     SYM_BIHARM = 0,      // H_c *= a |k|^4
@@ -115,5 +117,8 @@ template <typename T>
 hipError_t launch_fill(long n, double val, T *y, hipStream_t s);
 template <typename T>
 hipError_t launch_copy(long n, const T *x, T *y, hipStream_t s);
+// y = (To) x, element by element
+template <typename Ti, typename To>
+hipError_t launch_convert(long n, const Ti *x, To *y, hipStream_t s);
 
 }  // namespace regk

@@ -265,9 +265,9 @@ __global__ __launch_bounds__(kThreads) void k_deriv_x3(Grid g, FftPlan pl, const
 
 // R2C along x3 of a pair of real lines per complex line, then split the two
 // half spectra: X_a = (Z_k + conj Z_{n-k})/2, X_b = (Z_k - conj Z_{n-k})/(2i).
-template <typename T>
+template <typename Tr, typename T>
 __global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
-                                                     const T *__restrict__ x, long in_stride, cplx_t<T> *__restrict__ H,
+                                                     const Tr *__restrict__ x, long in_stride, cplx_t<T> *__restrict__ H,
                                                      long h_stride, int L) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const c
     const long nlines = (long)g.n1 * g.n2;
     const long r0 = (long)blockIdx.x * 2 * L;
     const int leff = (int)min((long)L, (nlines - r0) / 2);
-    const T *src = x + blockIdx.y * in_stride;
+    const Tr *src = x + blockIdx.y * in_stride;
     C *dst = H + blockIdx.y * h_stride;
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
         const int j = e % n, l = e / n;
@@ -286,8 +286,8 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const c
         z.x = T(0);
         z.y = T(0);
         if (l < leff) {
-            z.x = src[(r0 + 2 * l) * n + j];
-            z.y = src[(r0 + 2 * l + 1) * n + j];
+            z.x = T(src[(r0 + 2 * l) * n + j]);
+            z.y = T(src[(r0 + 2 * l + 1) * n + j]);
         }
         A[j * pitch + l] = z;
     }
@@ -351,10 +351,10 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
 // extension for k > n/2, real parts only at k = 0 and n/2), inverse FFT,
 // scale, and store the real part to line r0+2l and the imaginary part to
 // line r0+2l+1.
-template <typename T>
+template <typename T, typename Tr>
 __global__ __launch_bounds__(kThreads) void k_c2r_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                      const cplx_t<T> *__restrict__ H, long h_stride,
-                                                     T *__restrict__ out, long out_stride, T scale, int L) {
+                                                     Tr *__restrict__ out, long out_stride, T scale, int L) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     const int pitch = L + 1;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(Grid g, FftPlan pl, const c
     const long r0 = (long)blockIdx.x * 2 * L;
     const int leff = (int)min((long)L, (nlines - r0) / 2);
     const C *src = H + blockIdx.y * h_stride;
-    T *dst = out + blockIdx.y * out_stride;
+    Tr *dst = out + blockIdx.y * out_stride;
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
         const int j = e % n, l = e / n;
         C z;
@@ -394,8 +394,8 @@ __global__ __launch_bounds__(kThreads) void k_c2r_x3(Grid g, FftPlan pl, const c
         const int j = e % n, l = e / n;
         if (l >= leff) continue;
         const C z = R[j * pitch + l];
-        dst[(r0 + 2 * l) * n + j] = scale * z.x;
-        dst[(r0 + 2 * l + 1) * n + j] = scale * z.y;
+        dst[(r0 + 2 * l) * n + j] = Tr(scale * z.x);
+        dst[(r0 + 2 * l + 1) * n + j] = Tr(scale * z.y);
     }
 }
 
@@ -521,13 +521,15 @@ int pick_lines(int n, int cap, bool padded) {
 
 // ---------------------------------------------------------------- launchers
 
+template <typename T> constexpr int tw_index() { return sizeof(T) == 8 ? 1 : 0; }
+
 template <typename T>
 hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T *out, long out_stride, int accumulate,
                       int ncomp, hipStream_t s) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
     const FftPlan &pl = c.plan[axis];
-    const C *tw = reinterpret_cast<const C *>(c.tw[axis]);
+    const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]);
     if (axis == 2) {
         const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
         const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
@@ -547,50 +549,47 @@ hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T 
 }
 
 template <typename T>
-hipError_t spec_forward(const SpecCtx &c, const T *x, int ncomp, int h0, hipStream_t s) {
+static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipStream_t s) {
+    using C = cplx_t<T>;
+    const Grid &g = c.g;
+    const int nh = g.n3h();
+    for (int k = 0; k < 2; k++) {
+        const int axis = sign < 0 ? 1 - k : k;  // forward: x2 then x1; inverse: x1 then x2
+        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
+        const int nb3 = (nh + L - 1) / L;
+        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
+        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
+                           reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]), axis, H, g.Nh(), sign, L);
+    }
+}
+
+template <typename Tr, typename T>
+hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStream_t s) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(c.H) + (long)h0 * g.Nh();
-    {
-        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
-        const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
-        hipLaunchKernelGGL(k_r2c_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
-                           reinterpret_cast<const C *>(c.tw[2]), x, g.N(), H, g.Nh(), L);
-    }
-    for (int axis = 1; axis >= 0; axis--) {
-        const int nh = g.n3h();
-        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
-        const int nb3 = (nh + L - 1) / L;
-        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
-        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
-        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
-                           reinterpret_cast<const C *>(c.tw[axis]), axis, H, g.Nh(), -1, L);
-    }
+    const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
+    const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
+    hipLaunchKernelGGL((k_r2c_x3<Tr, T>), dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
+                       reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), x, g.N(), H, g.Nh(), L);
+    c2c_passes<T>(c, H, ncomp, -1, s);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t spec_inverse(const SpecCtx &c, T *out, int ncomp, hipStream_t s) {
+template <typename T, typename Tr>
+hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(c.H);
-    for (int axis = 0; axis <= 1; axis++) {
-        const int nh = g.n3h();
-        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
-        const int nb3 = (nh + L - 1) / L;
-        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
-        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
-        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
-                           reinterpret_cast<const C *>(c.tw[axis]), axis, H, g.Nh(), +1, L);
-    }
-    {
-        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
-        const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
-        hipLaunchKernelGGL(k_c2r_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
-                           reinterpret_cast<const C *>(c.tw[2]), H, g.Nh(), out, g.N(), T(1.0 / (double)g.N()), L);
-    }
+    c2c_passes<T>(c, H, ncomp, +1, s);
+    const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
+    const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
+    hipLaunchKernelGGL((k_c2r_x3<T, Tr>), dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
+                       reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), H, g.Nh(), out, g.N(),
+                       T(1.0 / (double)g.N()), L);
     return hipGetLastError();
 }
 
@@ -614,12 +613,13 @@ hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nbl
 
 #define REGK_FFT_INST(T)                                                                                           \
     template hipError_t spec_deriv<T>(const SpecCtx &, int, const T *, long, T *, long, int, int, hipStream_t);    \
-    template hipError_t spec_forward<T>(const SpecCtx &, const T *, int, int, hipStream_t);                        \
-    template hipError_t spec_inverse<T>(const SpecCtx &, T *, int, hipStream_t);                                   \
+    template hipError_t spec_forward<T, T>(const SpecCtx &, const T *, int, int, hipStream_t);                     \
+    template hipError_t spec_inverse<T, T>(const SpecCtx &, T *, int, hipStream_t);                                \
     template hipError_t spec_symbol<T>(const SpecCtx &, int, double, int, int, hipStream_t);                       \
     template hipError_t spec_biharm_norm_partials<T>(const SpecCtx &, double *, int, hipStream_t);
 
 REGK_FFT_INST(float)
 REGK_FFT_INST(double)
+template hipError_t spec_forward<float, double>(const SpecCtx &, const float *, int, int, hipStream_t);
 
 }  // namespace regk

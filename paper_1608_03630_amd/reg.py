@@ -115,7 +115,12 @@ _SIGS = {
     "reg_solve": [_P, _P, ctypes.POINTER(reg_report)],
     "reg_deformation": [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "reg_dot": [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "reg_profile": [_P, ctypes.c_int],
+    "reg_profile_read": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
 }
+
+KERNEL_KINDS = ["interp", "backtrace", "adjoint", "incstate", "deform", "deriv", "fft3d", "symbol", "reduce",
+                "vector"]
 
 
 def lib():
@@ -170,7 +175,8 @@ class Context:
     def __init__(self, params, device="cuda", stream=None):
         self.params = params
         self.device = torch.device(device)
-        self.dtype = torch.float64 if params.prec else torch.float32
+        self.dtype = torch.float64 if params.prec else torch.float32  # image-space fields
+        self.vdtype = torch.float64  # velocity-space vectors
         self.shape = tuple(params.n)
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
         nbytes = reg_workspace_size(params)
@@ -193,22 +199,23 @@ class Context:
             pass
 
     # ------------------------------------------------------------ checks
-    def _t(self, t, ncomp, name):
+    def _t(self, t, ncomp, name, vel=False):
         if not isinstance(t, torch.Tensor):
             raise TypeError(f"{name} must be a torch.Tensor")
         if t.device.type != "cuda":
             raise ValueError(f"{name} must live on the GPU")
-        if t.dtype != self.dtype:
-            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        want = self.vdtype if vel else self.dtype
+        if t.dtype != want:
+            raise TypeError(f"{name} must be {want}, got {t.dtype}")
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
         if t.numel() != ncomp * self.N:
             raise ValueError(f"{name} must hold {ncomp} x {self.shape} elements, got shape {tuple(t.shape)}")
         return ctypes.c_void_p(t.data_ptr())
 
-    def empty(self, ncomp=1):
+    def empty(self, ncomp=1, vel=False):
         shape = self.shape if ncomp == 1 else (ncomp,) + self.shape
-        return torch.empty(shape, dtype=self.dtype, device=self.device)
+        return torch.empty(shape, dtype=self.vdtype if vel else self.dtype, device=self.device)
 
     # ------------------------------------------------------ entry points
     def reg_set_beta(self, beta):
@@ -226,7 +233,7 @@ class Context:
 
     def reg_backtrace(self, v, sign=1.0, D=None):
         D = self.empty(3) if D is None else D
-        _chk(lib().reg_backtrace(self.handle, self._t(v, 3, "v"), float(sign), self._t(D, 3, "D")), self.handle,
+        _chk(lib().reg_backtrace(self.handle, self._t(v, 3, "v", True), float(sign), self._t(D, 3, "D")), self.handle,
              "reg_backtrace")
         return D
 
@@ -254,45 +261,47 @@ class Context:
         return out
 
     def reg_precond(self, r, z=None):
-        z = self.empty(3) if z is None else z
-        _chk(lib().reg_precond(self.handle, self._t(r, 3, "r"), self._t(z, 3, "z")), self.handle, "reg_precond")
+        z = self.empty(3, True) if z is None else z
+        _chk(lib().reg_precond(self.handle, self._t(r, 3, "r", True), self._t(z, 3, "z", True)), self.handle,
+             "reg_precond")
         return z
 
     def reg_transport_forward(self, v, rho0, rho1=None):
         rho1 = self.empty(1) if rho1 is None else rho1
-        _chk(lib().reg_transport_forward(self.handle, self._t(v, 3, "v"), self._t(rho0, 1, "rho0"),
+        _chk(lib().reg_transport_forward(self.handle, self._t(v, 3, "v", True), self._t(rho0, 1, "rho0"),
                                          self._t(rho1, 1, "rho1")), self.handle, "reg_transport_forward")
         return rho1
 
     def reg_transport_adjoint(self, v, lam1, lam0=None):
         lam0 = self.empty(1) if lam0 is None else lam0
-        _chk(lib().reg_transport_adjoint(self.handle, self._t(v, 3, "v"), self._t(lam1, 1, "lam1"),
+        _chk(lib().reg_transport_adjoint(self.handle, self._t(v, 3, "v", True), self._t(lam1, 1, "lam1"),
                                          self._t(lam0, 1, "lam0")), self.handle, "reg_transport_adjoint")
         return lam0
 
     def reg_gradient(self, v, g=None):
-        g = self.empty(3) if g is None else g
+        g = self.empty(3, True) if g is None else g
         J, mis, gn = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-        _chk(lib().reg_gradient(self.handle, self._t(v, 3, "v"), self._t(g, 3, "g"), ctypes.byref(J),
+        _chk(lib().reg_gradient(self.handle, self._t(v, 3, "v", True), self._t(g, 3, "g", True), ctypes.byref(J),
                                 ctypes.byref(mis), ctypes.byref(gn)), self.handle, "reg_gradient")
         return g, J.value, mis.value, gn.value
 
     def reg_objective(self, v):
         J, mis = ctypes.c_double(), ctypes.c_double()
-        _chk(lib().reg_objective(self.handle, self._t(v, 3, "v"), ctypes.byref(J), ctypes.byref(mis)),
+        _chk(lib().reg_objective(self.handle, self._t(v, 3, "v", True), ctypes.byref(J), ctypes.byref(mis)),
              self.handle, "reg_objective")
         return J.value, mis.value
 
     def reg_hessian_matvec(self, vt, Hvt=None):
-        Hvt = self.empty(3) if Hvt is None else Hvt
-        _chk(lib().reg_hessian_matvec(self.handle, self._t(vt, 3, "vt"), self._t(Hvt, 3, "Hvt")), self.handle,
+        Hvt = self.empty(3, True) if Hvt is None else Hvt
+        _chk(lib().reg_hessian_matvec(self.handle, self._t(vt, 3, "vt", True), self._t(Hvt, 3, "Hvt", True)),
+             self.handle,
              "reg_hessian_matvec")
         return Hvt
 
     def reg_solve(self, v=None, raise_on_error=True):
-        v = torch.zeros((3,) + self.shape, dtype=self.dtype, device=self.device) if v is None else v
+        v = torch.zeros((3,) + self.shape, dtype=self.vdtype, device=self.device) if v is None else v
         rep = reg_report()
-        st = lib().reg_solve(self.handle, self._t(v, 3, "v"), ctypes.byref(rep))
+        st = lib().reg_solve(self.handle, self._t(v, 3, "v", True), ctypes.byref(rep))
         if raise_on_error:
             _chk(st, self.handle, "reg_solve")
         return v, rep.to_dict()
@@ -301,13 +310,27 @@ class Context:
         if want_u and u is None:
             u = self.empty(3)
         mn, mx = ctypes.c_double(), ctypes.c_double()
-        _chk(lib().reg_deformation(self.handle, self._t(v, 3, "v"), self._t(u, 3, "u") if u is not None else None,
+        _chk(lib().reg_deformation(self.handle, self._t(v, 3, "v", True), self._t(u, 3, "u") if u is not None else None,
                                    ctypes.byref(mn), ctypes.byref(mx)), self.handle, "reg_deformation")
         return u, mn.value, mx.value
 
     def reg_dot(self, a, b):
         ncomp = a.numel() // self.N
         out = ctypes.c_double()
-        _chk(lib().reg_dot(self.handle, ncomp, self._t(a, ncomp, "a"), self._t(b, ncomp, "b"), ctypes.byref(out)),
+        _chk(lib().reg_dot(self.handle, ncomp, self._t(a, ncomp, "a", True), self._t(b, ncomp, "b", True),
+                           ctypes.byref(out)),
              self.handle, "reg_dot")
         return out.value
+
+    def reg_profile(self, enable=True):
+        _chk(lib().reg_profile(self.handle, int(bool(enable))), self.handle, "reg_profile")
+
+    def reg_profile_read(self):
+        """{kind: (launches, gpu_ms)} for every kernel family."""
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            n, ms = ctypes.c_int64(), ctypes.c_double()
+            _chk(lib().reg_profile_read(self.handle, k, ctypes.byref(n), ctypes.byref(ms)), self.handle,
+                 "reg_profile_read")
+            out[name] = (n.value, ms.value)
+        return out

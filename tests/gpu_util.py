@@ -29,6 +29,11 @@ def to_dev(x, ctx):
     return torch.from_numpy(np.ascontiguousarray(x)).to(device=ctx.device, dtype=ctx.dtype).contiguous()
 
 
+def to_vel(x, ctx):
+    """A velocity-space tensor (always float64)."""
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device=ctx.device).contiguous()
+
+
 def to_host(t):
     torch.cuda.synchronize()
     return t.detach().to(torch.float64).cpu().numpy()
