@@ -87,6 +87,14 @@ struct reg_ctx {
     double prof_ms[REG_K_COUNT] = {0};
     int64_t prof_n[REG_K_COUNT] = {0};
 
+    // tile geometry of the LDS-staged gathers, per displacement buffer
+    struct PlanGeom {
+        const void *D = nullptr;
+        bool tiled = false;
+        regk::TileGeom tg{};
+    };
+    PlanGeom geoms[6];
+
     bool have_images = false;
     bool have_state = false;  // plans, history, grad rho and div v at vcur
     double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
@@ -276,6 +284,31 @@ template <typename T> const T *CV(const void *p) { return static_cast<const T *>
 
 double h3(const reg_ctx *c) { return (kTwoPi / c->g.n1) * (kTwoPi / c->g.n2) * (kTwoPi / c->g.n3); }
 
+const regk::TileGeom *geom_of(const reg_ctx *ctx, const void *D) {
+    for (const auto &g : ctx->geoms)
+        if (g.D == D) return g.tiled ? &g.tg : nullptr;
+    return nullptr;
+}
+
+void set_geom(reg_ctx *ctx, const void *D, bool tiled, const regk::TileGeom &tg) {
+    for (auto &g : ctx->geoms)
+        if (g.D == D) {
+            g.tiled = tiled;
+            g.tg = tg;
+            return;
+        }
+    for (auto &g : ctx->geoms)
+        if (g.D == nullptr) {
+            g.D = D;
+            g.tiled = tiled;
+            g.tg = tg;
+            return;
+        }
+    ctx->geoms[0].D = D;  // table full: reuse a slot
+    ctx->geoms[0].tiled = tiled;
+    ctx->geoms[0].tg = tg;
+}
+
 // velocity (double) -> field type copy
 template <typename T>
 hipError_t to_field(reg_ctx *ctx, const void *src, void *dst, long n) {
@@ -310,12 +343,31 @@ reg_status backtrace_impl(reg_ctx *ctx, const void *v, double sign, void *D) {
     return plan<T>(ctx, ctx->vf, sign, D);
 }
 
+// floor bounds of D over the grid -> tile geometry of the gathers that use D
+// (synchronises)
+template <typename T>
+reg_status measure_plan(reg_ctx *ctx, const void *D) {
+    const int nb = regk::RED_BLOCKS / 6;
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_floor_bounds<T>(ctx->g, CV<T>(D), ctx->dpart, nb, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_bounds(ctx->dpart, nb, ctx->dres + 8, ctx->stream)));
+    STCHK(fetch(ctx, 14));
+    double fmin[3], fmax[3];
+    for (int j = 0; j < 3; j++) {
+        fmin[j] = ctx->hres[8 + 2 * j];
+        fmax[j] = ctx->hres[8 + 2 * j + 1];
+    }
+    regk::TileGeom tg{};
+    const bool ok = regk::tile_geom(fmin, fmax, sizeof(T), &tg);
+    set_geom(ctx, D, ok, tg);
+    return REG_OK;
+}
+
 // departure points from vf (field type)
 template <typename T>
 reg_status plan(reg_ctx *ctx, const void *v, double sign, void *D) {
     HIPCHK(ctx, KL(ctx, REG_K_BACKTRACE, regk::launch_backtrace<T>(ctx->g, CV<T>(v), sign / ctx->P.nt, V<T>(D), ctx->stream)));
     ctx->interps += 3;
-    return REG_OK;
+    return measure_plan<T>(ctx, D);
 }
 
 // hist[0] = rho0, hist[n+1] = hist[n](X)
@@ -325,7 +377,7 @@ reg_status state_solve(reg_ctx *ctx, const void *Df, const void *rho0, void *his
     if (rho0 != hist) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(N, CV<T>(rho0), V<T>(hist), ctx->stream)));
     for (int k = 0; k < ctx->P.nt; k++)
         HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, V<T>(hist) + k * N, CV<T>(Df), V<T>(hist) + (k + 1) * N,
-                                           ctx->stream)));
+                                           ctx->stream, geom_of(ctx, Df))));
     ctx->interps += ctx->P.nt;
     return REG_OK;
 }
@@ -389,7 +441,7 @@ reg_status adjoint_sweep(reg_ctx *ctx, int start, const void *Da, const void *c,
         const double w = (k == 0) ? 0.5 * dt : dt;
         HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(Da), CV<T>(c), CV<T>(cX),
                                                  V<T>(ctx->grho) + (long)k * 3 * N, V<T>(b), V<T>(ctx->lam[1 - cur]),
-                                                 dt, w, ctx->stream)));
+                                                 dt, w, ctx->stream, geom_of(ctx, Da))));
         cur = 1 - cur;
     }
     ctx->interps += nt;
@@ -404,7 +456,8 @@ reg_status complete_state(reg_ctx *ctx) {
     STCHK(gradient_fields<T>(ctx, ctx->histA, ctx->P.nt + 1, ctx->grho));
     if (!ctx->P.isochoric) {
         STCHK(divergence<T>(ctx, ctx->vf, ctx->c));
-        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX), ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX), ctx->stream,
+                                                                 geom_of(ctx, ctx->Da))));
         ctx->interps += 1;
     }
     ctx->have_state = true;
@@ -476,7 +529,7 @@ reg_status matvec_impl(reg_ctx *ctx, const void *vt, void *Hvt) {
         HIPCHK(ctx, KL(ctx, REG_K_INCSTATE, regk::launch_incstate_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(ctx->Df), CV<T>(ctx->vtf),
                                                   V<T>(ctx->grho) + (long)(k + 1) * 3 * N, V<T>(ctx->lam[1 - cur]),
                                                   last ? -0.5 * dt : -dt, last, V<T>(ctx->bvec), 0.5 * dt,
-                                                  ctx->stream)));
+                                                  ctx->stream, geom_of(ctx, ctx->Df))));
         cur = 1 - cur;
     }
     ctx->interps += nt;
@@ -697,7 +750,7 @@ reg_status transport_forward_impl(reg_ctx *ctx, const void *v, const void *rho0,
     const T *src = CV<T>(rho0);
     for (int k = 0; k < ctx->P.nt; k++) {
         T *dst = (k == ctx->P.nt - 1) ? V<T>(rho1) : V<T>(ctx->histB) + (long)(k & 1) * N;
-        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, src, CV<T>(ctx->Dt), dst, ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, src, CV<T>(ctx->Dt), dst, ctx->stream, geom_of(ctx, ctx->Dt))));
         src = dst;
     }
     ctx->interps += ctx->P.nt;
@@ -713,7 +766,7 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
     const bool src = !ctx->P.isochoric;
     if (src) {
         STCHK(divergence<T>(ctx, ctx->vf, ctx->c2));
-        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream)));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream, geom_of(ctx, ctx->Dt))));
         ctx->interps += 1;
     }
     const T *in = CV<T>(lam1);
@@ -721,7 +774,7 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
         T *out = (k == nt - 1) ? V<T>(lam0) : V<T>(ctx->histB) + (long)(k & 1) * N;
         HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, in, CV<T>(ctx->Dt), src ? CV<T>(ctx->c2) : nullptr,
                                                  src ? CV<T>(ctx->cX2) : nullptr, nullptr, nullptr, out, 1.0 / nt, 0.0,
-                                                 ctx->stream)));
+                                                 ctx->stream, geom_of(ctx, ctx->Dt))));
         in = out;
     }
     ctx->interps += nt;
@@ -881,8 +934,13 @@ reg_status reg_interp(reg_ctx *ctx, const void *f, const void *D, void *out) {
     NEED_DEV(ctx, out);
     if (f == out) return fail(ctx, REG_EINVAL, "out must not alias f");
     ctx->interps++;
-    if (ctx->P.prec) HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<double>(ctx->g, CV<double>(f), CV<double>(D), V<double>(out), ctx->stream)));
-    else HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<float>(ctx->g, CV<float>(f), CV<float>(D), V<float>(out), ctx->stream)));
+    if (ctx->P.prec) {
+        STCHK(measure_plan<double>(ctx, D));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<double>(ctx->g, CV<double>(f), CV<double>(D), V<double>(out), ctx->stream, geom_of(ctx, D))));
+    } else {
+        STCHK(measure_plan<float>(ctx, D));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<float>(ctx->g, CV<float>(f), CV<float>(D), V<float>(out), ctx->stream, geom_of(ctx, D))));
+    }
     return REG_OK;
 }
 

@@ -33,16 +33,34 @@ struct FftPlan {
 bool make_plan(int n, FftPlan *p);
 
 // ------------------------------------------------------------------ interp.hip
-// Every launcher enqueues on `s` and returns the hipError_t of the launch.
+// Output tile of the LDS-staged gathers and the bounding box of its stencils.
+constexpr int kTile1 = 8, kTile2 = 8, kTile3 = 64;
+struct TileGeom {
+    int lo[3];  // floor(min D_j) - 1: box origin relative to the tile origin
+    int B[3];   // box extent per axis: tile + (floor(max D_j) - floor(min D_j)) + 3
+};
+// A box of this geometry fits the LDS budget of the tiled kernels.
+bool tile_geom(const double fmin[3], const double fmax[3], size_t elem, TileGeom *tg);
+// Per-block min and max of floor(D_j) for the three components
+// (partials[6*b + 2j] = min, [6*b + 2j + 1] = max); nblocks blocks.
 template <typename T>
-hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStream_t s);
+hipError_t launch_floor_bounds(const Grid &g, const T *D, double *partials, int nblocks, hipStream_t s);
+hipError_t launch_finalize_bounds(const double *partials, int nblocks, double *out6, hipStream_t s);
+
+// Every launcher enqueues on `s` and returns the hipError_t of the launch. A
+// non-null TileGeom selects the LDS-staged gather for displacements D whose
+// floor bounds it was built from; null selects the direct gather.
+template <typename T>
+hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStream_t s,
+                         const TileGeom *tg = nullptr);
 template <typename T>
 hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hipStream_t s);
 // adjoint-type step: lam_out = Heun step of nu with source nu*c (if c), and
 // b += wn * lam_out * grad (if b); lam_out may be null when b is set.
 template <typename T>
 hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *c, const T *cX,
-                               const T *grad, T *b, T *lam_out, double dt, double wn, hipStream_t s);
+                               const T *grad, T *b, T *lam_out, double dt, double wn, hipStream_t s,
+                               const TileGeom *tg = nullptr);
 // lam = rhoR - rho1 (or -scale*src): initial adjoint level; b = w * lam * grad
 template <typename T>
 hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, const T *grad, T *lam, T *b, double w,
@@ -51,7 +69,7 @@ hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, cons
 // lam_out = -(that) and b = w * lam_out * grad
 template <typename T>
 hipError_t launch_incstate_step(const Grid &g, const T *q_in, const T *Df, const T *vt, const T *grad, T *q_out,
-                                double cs, int last, T *b, double w, hipStream_t s);
+                                double cs, int last, T *b, double w, hipStream_t s, const TileGeom *tg = nullptr);
 template <typename T>
 hipError_t launch_incstate_init(const Grid &g, const T *vt, const T *grad, T *q, double cs, hipStream_t s);
 template <typename T>

@@ -39,6 +39,10 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// row pitch of a tile of L lines in LDS; padded tiles (transposed loads) add
+// one element per row against bank conflicts
+__host__ __device__ inline int tile_pitch(int L, bool padded) { return (padded && L > 1) ? L + 1 : L; }
+
 template <typename C>
 __device__ __forceinline__ C cmul(C a, C b) {
     C r;
@@ -70,8 +74,8 @@ __device__ __forceinline__ C cmul_si(C a, int sign) {
 }
 
 // R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4}
-template <typename T>
-__device__ __forceinline__ void butterfly(cplx_t<T> *v, int R, int sign) {
+template <typename T, int R>
+__device__ __forceinline__ void butterfly(cplx_t<T> *v, int sign) {
     using C = cplx_t<T>;
     if (R == 4) {
         const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
@@ -99,33 +103,55 @@ __device__ __forceinline__ void butterfly(cplx_t<T> *v, int R, int sign) {
     }
 }
 
-// Stockham FFT of L lines held in LDS as element (j, l) at a[j*pitch + l].
-// tw[m] = exp(-2 pi i m / n); the inverse uses the conjugate. Returns the
-// buffer that holds the result; ends with a barrier.
-template <typename T>
-__device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int L, int pitch, int sign,
-                              const cplx_t<T> *__restrict__ tw) {
+// One radix-R Stockham pass over L = 2^lgL lines, element (j, l) at
+// a[j*pitch + l]: combines R sub-transforms of length Ns into one of length
+// Ns*R. tw[m] = exp(-2 pi i m / n) (in LDS); the inverse conjugates.
+template <typename T, int R>
+__device__ __forceinline__ void fft_pass(const cplx_t<T> *a, cplx_t<T> *b, int n, int Ns, int lgL, int pitch,
+                                         int sign, const cplx_t<T> *tw) {
     using C = cplx_t<T>;
-    const int n = pl.n;
+    const int L = 1 << lgL;
+    const int nr = n / R;
+    const int tstep = n / (Ns * R);
+    const bool pow2 = (Ns & (Ns - 1)) == 0;
+    for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
+        const int l = e & (L - 1), j = e >> lgL;
+        int k, q;
+        if (pow2) {
+            k = j & (Ns - 1);
+            q = j - k;
+        } else {
+            q = (j / Ns) * Ns;
+            k = j - q;
+        }
+        C v[R];
+#pragma unroll
+        for (int r = 0; r < R; r++) v[r] = a[(j + r * nr) * pitch + l];
+#pragma unroll
+        for (int r = 1; r < R; r++) {
+            C w = tw[r * k * tstep];
+            if (sign > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+        butterfly<T, R>(v, sign);
+        const int d = q * R + k;
+#pragma unroll
+        for (int r = 0; r < R; r++) b[(d + r * Ns) * pitch + l] = v[r];
+    }
+}
+
+// Stockham FFT of 2^lgL lines held in LDS; returns the buffer that holds the
+// result (natural order); ends with a barrier.
+template <typename T>
+__device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int lgL, int pitch, int sign,
+                              const cplx_t<T> *tw) {
+    using C = cplx_t<T>;
     int Ns = 1;
     for (int ps = 0; ps < pl.npass; ps++) {
         const int R = pl.radix[ps];
-        const int nr = n / R;
-        const int tstep = n / (Ns * R);
-        for (int e = threadIdx.x; e < nr * L; e += blockDim.x) {
-            const int l = e % L, j = e / L;
-            const int k = j % Ns;
-            C v[4];
-            for (int r = 0; r < R; r++) v[r] = a[(j + r * nr) * pitch + l];
-            for (int r = 1; r < R; r++) {
-                C w = tw[r * k * tstep];
-                if (sign > 0) w.y = -w.y;
-                v[r] = cmul(v[r], w);
-            }
-            butterfly<T>(v, R, sign);
-            const int d = (j / Ns) * Ns * R + k;
-            for (int r = 0; r < R; r++) b[(d + r * Ns) * pitch + l] = v[r];
-        }
+        if (R == 4) fft_pass<T, 4>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        else if (R == 2) fft_pass<T, 2>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        else fft_pass<T, 3>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         __syncthreads();
         C *t = a;
         a = b;
@@ -135,9 +161,31 @@ __device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int
     return a;
 }
 
+template <typename T>
+__device__ __forceinline__ void stage_twiddles(cplx_t<T> *twl, const cplx_t<T> *__restrict__ tw, int n) {
+    for (int m = threadIdx.x; m < n; m += blockDim.x) twl[m] = tw[m];
+}
+
 // wavenumber of index m on an axis of length n, and its odd variant (Nyquist -> 0)
 __device__ __forceinline__ int kwave(int m, int n) { return 2 * m <= n ? m : m - n; }
 __device__ __forceinline__ int kwave_odd(int m, int n) { return 2 * m == n ? 0 : kwave(m, n); }
+
+// multiply row j of the tile by the derivative symbol i k~_j / n
+template <typename T>
+__device__ __forceinline__ void deriv_symbol(cplx_t<T> *R, int n, int lgL, int pitch) {
+    using C = cplx_t<T>;
+    const int L = 1 << lgL;
+    const T inv = T(1) / T(n);
+    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
+        const int l = e & (L - 1), j = e >> lgL;
+        const T f = T(kwave_odd(j, n)) * inv;
+        const C z = R[j * pitch + l];
+        C w;
+        w.x = -f * z.y;
+        w.y = f * z.x;
+        R[j * pitch + l] = w;
+    }
+}
 
 // ----------------------------------------------------------- derivatives
 
@@ -147,14 +195,17 @@ template <typename T>
 __global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                             int axis, const T *__restrict__ u, long in_stride,
                                                             T *__restrict__ out, long out_stride, int accumulate,
-                                                            int L) {
+                                                            int lgL) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
+    const int L = 1 << lgL;
+    const int n = pl.n;
     C *A = reinterpret_cast<C *>(smem);
-    C *B = A + (long)pl.n * L;
+    C *B = A + n * L;
+    C *twl = B + n * L;
     const int ncol = g.n3 / 2;
-    const int nb3 = (ncol + L - 1) / L;
-    const int outer = blockIdx.x / nb3, cb = blockIdx.x % nb3;
+    const int nb3 = (ncol + L - 1) >> lgL;
+    const int outer = blockIdx.x / nb3, cb = blockIdx.x - (blockIdx.x / nb3) * nb3;
     const int leff = min(L, ncol - cb * L);
     long base, stride;
     if (axis == 1) {
@@ -166,9 +217,9 @@ __global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, 
     }
     const T *src = u + blockIdx.y * in_stride;
     T *dst = out + blockIdx.y * out_stride;
-    const int n = pl.n;
+    stage_twiddles<T>(twl, tw, n);
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
+        const int l = e & (L - 1), j = e >> lgL;
         C z;
         z.x = T(0);
         z.y = T(0);
@@ -176,21 +227,12 @@ __global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, 
         A[j * L + l] = z;
     }
     __syncthreads();
-    C *R = lds_fft<T>(A, B, pl, L, L, -1, tw);
-    const T inv = T(1) / T(n);
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
-        const T f = T(kwave_odd(j, n)) * inv;
-        const C z = R[j * L + l];
-        C w;
-        w.x = -f * z.y;
-        w.y = f * z.x;
-        R[j * L + l] = w;
-    }
+    C *R = lds_fft<T>(A, B, pl, lgL, L, -1, twl);
+    deriv_symbol<T>(R, n, lgL, L);
     __syncthreads();
-    C *Q = lds_fft<T>(R, R == A ? B : A, pl, L, L, +1, tw);
+    C *Q = lds_fft<T>(R, R == A ? B : A, pl, lgL, L, +1, twl);
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
+        const int l = e & (L - 1), j = e >> lgL;
         if (l >= leff) continue;
         C *p = reinterpret_cast<C *>(dst + base + j * stride + 2 * l);
         C z = Q[j * L + l];
@@ -204,61 +246,55 @@ __global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, 
 }
 
 // Lines along the contiguous x3 axis: L complex lines, each the pair of real
-// lines (r0 + 2l, r0 + 2l + 1) with r = i1*n2 + i2.
+// lines (r0 + 2l, r0 + 2l + 1) with r = i1*n2 + i2; each wavefront moves
+// whole lines, lanes along x3.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_deriv_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                        const T *__restrict__ u, long in_stride, T *__restrict__ out,
-                                                       long out_stride, int accumulate, int L) {
+                                                       long out_stride, int accumulate, int lgL) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int pitch = L + 1;
-    C *A = reinterpret_cast<C *>(smem);
-    C *B = A + (long)pl.n * pitch;
+    const int L = 1 << lgL, pitch = tile_pitch(L, true);
     const int n = pl.n;  // == n3
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + n * pitch;
+    C *twl = B + n * pitch;
     const long nlines = (long)g.n1 * g.n2;
     const long r0 = (long)blockIdx.x * 2 * L;
     const int leff = (int)min((long)L, (nlines - r0) / 2);
     const T *src = u + blockIdx.y * in_stride;
     T *dst = out + blockIdx.y * out_stride;
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int j = e % n, l = e / n;
-        C z;
-        z.x = T(0);
-        z.y = T(0);
-        if (l < leff) {
-            z.x = src[(r0 + 2 * l) * n + j];
-            z.y = src[(r0 + 2 * l + 1) * n + j];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    stage_twiddles<T>(twl, tw, n);
+    for (int l = wave; l < L; l += nw)
+        for (int j = lane; j < n; j += 64) {
+            C z;
+            z.x = T(0);
+            z.y = T(0);
+            if (l < leff) {
+                z.x = src[(r0 + 2 * l) * n + j];
+                z.y = src[(r0 + 2 * l + 1) * n + j];
+            }
+            A[j * pitch + l] = z;
         }
-        A[j * pitch + l] = z;
-    }
     __syncthreads();
-    C *R = lds_fft<T>(A, B, pl, L, pitch, -1, tw);
-    const T inv = T(1) / T(n);
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
-        const T f = T(kwave_odd(j, n)) * inv;
-        const C z = R[j * pitch + l];
-        C w;
-        w.x = -f * z.y;
-        w.y = f * z.x;
-        R[j * pitch + l] = w;
-    }
+    C *R = lds_fft<T>(A, B, pl, lgL, pitch, -1, twl);
+    deriv_symbol<T>(R, n, lgL, pitch);
     __syncthreads();
-    C *Q = lds_fft<T>(R, R == A ? B : A, pl, L, pitch, +1, tw);
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int j = e % n, l = e / n;
-        if (l >= leff) continue;
-        const C z = Q[j * pitch + l];
-        T *p0 = dst + (r0 + 2 * l) * n + j;
-        T *p1 = dst + (r0 + 2 * l + 1) * n + j;
-        if (accumulate) {
-            *p0 += z.x;
-            *p1 += z.y;
-        } else {
-            *p0 = z.x;
-            *p1 = z.y;
+    C *Q = lds_fft<T>(R, R == A ? B : A, pl, lgL, pitch, +1, twl);
+    for (int l = wave; l < leff; l += nw)
+        for (int j = lane; j < n; j += 64) {
+            const C z = Q[j * pitch + l];
+            T *p0 = dst + (r0 + 2 * l) * n + j;
+            T *p1 = dst + (r0 + 2 * l + 1) * n + j;
+            if (accumulate) {
+                *p0 += z.x;
+                *p1 += z.y;
+            } else {
+                *p0 = z.x;
+                *p1 = z.y;
+            }
         }
-    }
 }
 
 // ------------------------------------------------------------ 3D transforms
@@ -268,58 +304,63 @@ __global__ __launch_bounds__(kThreads) void k_deriv_x3(Grid g, FftPlan pl, const
 template <typename Tr, typename T>
 __global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                      const Tr *__restrict__ x, long in_stride, cplx_t<T> *__restrict__ H,
-                                                     long h_stride, int L) {
+                                                     long h_stride, int lgL) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int pitch = L + 1;
-    C *A = reinterpret_cast<C *>(smem);
-    C *B = A + (long)pl.n * pitch;
+    const int L = 1 << lgL, pitch = tile_pitch(L, true);
     const int n = pl.n, nh = n / 2 + 1;
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + n * pitch;
+    C *twl = B + n * pitch;
     const long nlines = (long)g.n1 * g.n2;
     const long r0 = (long)blockIdx.x * 2 * L;
     const int leff = (int)min((long)L, (nlines - r0) / 2);
     const Tr *src = x + blockIdx.y * in_stride;
     C *dst = H + blockIdx.y * h_stride;
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int j = e % n, l = e / n;
-        C z;
-        z.x = T(0);
-        z.y = T(0);
-        if (l < leff) {
-            z.x = T(src[(r0 + 2 * l) * n + j]);
-            z.y = T(src[(r0 + 2 * l + 1) * n + j]);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    stage_twiddles<T>(twl, tw, n);
+    for (int l = wave; l < L; l += nw)
+        for (int j = lane; j < n; j += 64) {
+            C z;
+            z.x = T(0);
+            z.y = T(0);
+            if (l < leff) {
+                z.x = T(src[(r0 + 2 * l) * n + j]);
+                z.y = T(src[(r0 + 2 * l + 1) * n + j]);
+            }
+            A[j * pitch + l] = z;
         }
-        A[j * pitch + l] = z;
-    }
     __syncthreads();
-    C *R = lds_fft<T>(A, B, pl, L, pitch, -1, tw);
-    for (int e = threadIdx.x; e < nh * L; e += blockDim.x) {
-        const int k = e % nh, l = e / nh;
-        if (l >= leff) continue;
-        const C z = R[k * pitch + l];
-        const C zc = R[((n - k) % n) * pitch + l];
-        C xa, xb;
-        xa.x = T(0.5) * (z.x + zc.x);
-        xa.y = T(0.5) * (z.y - zc.y);
-        xb.x = T(0.5) * (z.y + zc.y);
-        xb.y = T(-0.5) * (z.x - zc.x);
-        dst[(r0 + 2 * l) * nh + k] = xa;
-        dst[(r0 + 2 * l + 1) * nh + k] = xb;
-    }
+    C *R = lds_fft<T>(A, B, pl, lgL, pitch, -1, twl);
+    for (int l = wave; l < leff; l += nw)
+        for (int k = lane; k < nh; k += 64) {
+            const C z = R[k * pitch + l];
+            const C zc = R[(k == 0 ? 0 : n - k) * pitch + l];
+            C xa, xb;
+            xa.x = T(0.5) * (z.x + zc.x);
+            xa.y = T(0.5) * (z.y - zc.y);
+            xb.x = T(0.5) * (z.y + zc.y);
+            xb.y = T(-0.5) * (z.x - zc.x);
+            dst[(r0 + 2 * l) * nh + k] = xa;
+            dst[(r0 + 2 * l + 1) * nh + k] = xb;
+        }
 }
 
 // In-place complex FFT of the half spectrum along axis 0 or 1.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                           int axis, cplx_t<T> *__restrict__ H, long h_stride, int sign,
-                                                          int L) {
+                                                          int lgL) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
+    const int L = 1 << lgL;
+    const int n = pl.n;
     C *A = reinterpret_cast<C *>(smem);
-    C *B = A + (long)pl.n * L;
+    C *B = A + n * L;
+    C *twl = B + n * L;
     const int nh = g.n3h();
-    const int nb3 = (nh + L - 1) / L;
-    const int outer = blockIdx.x / nb3, cb = blockIdx.x % nb3;
+    const int nb3 = (nh + L - 1) >> lgL;
+    const int outer = blockIdx.x / nb3, cb = blockIdx.x - (blockIdx.x / nb3) * nb3;
     const int leff = min(L, nh - cb * L);
     long base, stride;
     if (axis == 1) {
@@ -330,9 +371,9 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
         stride = (long)g.n2 * nh;
     }
     C *h = H + blockIdx.y * h_stride;
-    const int n = pl.n;
+    stage_twiddles<T>(twl, tw, n);
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
+        const int l = e & (L - 1), j = e >> lgL;
         C z;
         z.x = T(0);
         z.y = T(0);
@@ -340,9 +381,9 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
         A[j * L + l] = z;
     }
     __syncthreads();
-    C *R = lds_fft<T>(A, B, pl, L, L, sign, tw);
+    C *R = lds_fft<T>(A, B, pl, lgL, L, sign, twl);
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int l = e % L, j = e / L;
+        const int l = e & (L - 1), j = e >> lgL;
         if (l < leff) h[base + j * stride + l] = R[j * L + l];
     }
 }
@@ -354,49 +395,51 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
 template <typename T, typename Tr>
 __global__ __launch_bounds__(kThreads) void k_c2r_x3(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
                                                      const cplx_t<T> *__restrict__ H, long h_stride,
-                                                     Tr *__restrict__ out, long out_stride, T scale, int L) {
+                                                     Tr *__restrict__ out, long out_stride, T scale, int lgL) {
     using C = cplx_t<T>;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int pitch = L + 1;
-    C *A = reinterpret_cast<C *>(smem);
-    C *B = A + (long)pl.n * pitch;
+    const int L = 1 << lgL, pitch = tile_pitch(L, true);
     const int n = pl.n, nh = n / 2 + 1;
+    C *A = reinterpret_cast<C *>(smem);
+    C *B = A + n * pitch;
+    C *twl = B + n * pitch;
     const long nlines = (long)g.n1 * g.n2;
     const long r0 = (long)blockIdx.x * 2 * L;
     const int leff = (int)min((long)L, (nlines - r0) / 2);
     const C *src = H + blockIdx.y * h_stride;
     Tr *dst = out + blockIdx.y * out_stride;
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int j = e % n, l = e / n;
-        C z;
-        z.x = T(0);
-        z.y = T(0);
-        if (l < leff) {
-            if (2 * j <= n) {
-                C xa = src[(r0 + 2 * l) * nh + j], xb = src[(r0 + 2 * l + 1) * nh + j];
-                if (j == 0 || 2 * j == n) {
-                    xa.y = T(0);
-                    xb.y = T(0);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    stage_twiddles<T>(twl, tw, n);
+    for (int l = wave; l < L; l += nw)
+        for (int j = lane; j < n; j += 64) {
+            C z;
+            z.x = T(0);
+            z.y = T(0);
+            if (l < leff) {
+                if (2 * j <= n) {
+                    C xa = src[(r0 + 2 * l) * nh + j], xb = src[(r0 + 2 * l + 1) * nh + j];
+                    if (j == 0 || 2 * j == n) {
+                        xa.y = T(0);
+                        xb.y = T(0);
+                    }
+                    z.x = xa.x - xb.y;
+                    z.y = xa.y + xb.x;
+                } else {
+                    const C xa = src[(r0 + 2 * l) * nh + (n - j)], xb = src[(r0 + 2 * l + 1) * nh + (n - j)];
+                    z.x = xa.x + xb.y;
+                    z.y = xb.x - xa.y;
                 }
-                z.x = xa.x - xb.y;
-                z.y = xa.y + xb.x;
-            } else {
-                const C xa = src[(r0 + 2 * l) * nh + (n - j)], xb = src[(r0 + 2 * l + 1) * nh + (n - j)];
-                z.x = xa.x + xb.y;
-                z.y = xb.x - xa.y;
             }
+            A[j * pitch + l] = z;
         }
-        A[j * pitch + l] = z;
-    }
     __syncthreads();
-    C *R = lds_fft<T>(A, B, pl, L, pitch, +1, tw);
-    for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
-        const int j = e % n, l = e / n;
-        if (l >= leff) continue;
-        const C z = R[j * pitch + l];
-        dst[(r0 + 2 * l) * n + j] = Tr(scale * z.x);
-        dst[(r0 + 2 * l + 1) * n + j] = Tr(scale * z.y);
-    }
+    C *R = lds_fft<T>(A, B, pl, lgL, pitch, +1, twl);
+    for (int l = wave; l < leff; l += nw)
+        for (int j = lane; j < n; j += 64) {
+            const C z = R[j * pitch + l];
+            dst[(r0 + 2 * l) * n + j] = Tr(scale * z.x);
+            dst[(r0 + 2 * l + 1) * n + j] = Tr(scale * z.y);
+        }
 }
 
 // Pointwise symbols on the half spectrum [n1][n2][n3/2+1].
@@ -505,16 +548,20 @@ __global__ __launch_bounds__(kThreads) void k_biharm_norm(Grid g, const cplx_t<T
     }
 }
 
-// Lines per tile so that the two LDS buffers of n*pitch complex values fit in
-// 64 KiB; padded tiles (pitch = L + 1) lose one line.
+// log2 of the lines per tile: the largest power of two L such that the two
+// LDS buffers of n*pitch complex values plus the n twiddles fit in 64 KiB;
+// padded tiles use pitch L + 1 (pitch 1 for a single line).
 template <typename T>
-int pick_lines(int n, int cap, bool padded) {
-    const int per_buffer = 32768 / (int)sizeof(cplx_t<T>);
-    int L = per_buffer / n - (padded ? 1 : 0);
-    if (L < 1) L = 1;
-    if (L > 64) L = 64;
-    if (L > cap) L = cap;
-    return L;
+int pick_lg_lines(int n, int cap, bool padded) {
+    const long per_buffer = (65536 / (long)sizeof(cplx_t<T>) - n) / 2;
+    int lg = 0;
+    while (lg < 6 && (1 << (lg + 1)) <= cap && (long)n * tile_pitch(1 << (lg + 1), padded) <= per_buffer) lg++;
+    return lg;
+}
+
+template <typename T>
+size_t tile_lds(int n, int lg, bool padded) {
+    return (2 * (size_t)n * tile_pitch(1 << lg, padded) + n) * sizeof(cplx_t<T>);
 }
 
 }  // namespace
@@ -531,19 +578,18 @@ hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T 
     const FftPlan &pl = c.plan[axis];
     const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]);
     if (axis == 2) {
-        const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
-        const size_t lds = 2 * (size_t)pl.n * (L + 1) * sizeof(C);
-        hipLaunchKernelGGL(k_deriv_x3<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, pl, tw, u, in_stride, out,
-                           out_stride, accumulate, L);
+        const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+        const long L2 = 2L << lg;
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+        hipLaunchKernelGGL(k_deriv_x3<T>, dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(pl.n, lg, true), s, g, pl, tw,
+                           u, in_stride, out, out_stride, accumulate, lg);
     } else {
         const int ncol = g.n3 / 2;
-        const int L = pick_lines<T>(pl.n, ncol, false);
-        const int nb3 = (ncol + L - 1) / L;
+        const int lg = pick_lg_lines<T>(pl.n, ncol, false);
+        const int nb3 = (ncol + (1 << lg) - 1) >> lg;
         const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
-        const size_t lds = 2 * (size_t)pl.n * L * sizeof(C);
-        hipLaunchKernelGGL(k_deriv_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, pl, tw, axis, u,
-                           in_stride, out, out_stride, accumulate, L);
+        hipLaunchKernelGGL(k_deriv_strided<T>, dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(pl.n, lg, false), s, g,
+                           pl, tw, axis, u, in_stride, out, out_stride, accumulate, lg);
     }
     return hipGetLastError();
 }
@@ -555,12 +601,12 @@ static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipS
     const int nh = g.n3h();
     for (int k = 0; k < 2; k++) {
         const int axis = sign < 0 ? 1 - k : k;  // forward: x2 then x1; inverse: x1 then x2
-        const int L = pick_lines<T>(c.plan[axis].n, nh, false);
-        const int nb3 = (nh + L - 1) / L;
+        const int lg = pick_lg_lines<T>(c.plan[axis].n, nh, false);
+        const int nb3 = (nh + (1 << lg) - 1) >> lg;
         const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
-        const size_t lds = 2 * (size_t)c.plan[axis].n * L * sizeof(C);
-        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[axis],
-                           reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]), axis, H, g.Nh(), sign, L);
+        hipLaunchKernelGGL(k_c2c_strided<T>, dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(c.plan[axis].n, lg, false),
+                           s, g, c.plan[axis], reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]), axis, H,
+                           g.Nh(), sign, lg);
     }
 }
 
@@ -569,11 +615,11 @@ hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStr
     using C = cplx_t<T>;
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(c.H) + (long)h0 * g.Nh();
-    const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
-    const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
-    hipLaunchKernelGGL((k_r2c_x3<Tr, T>), dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
-                       reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), x, g.N(), H, g.Nh(), L);
+    const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+    const long L2 = 2L << lg;
+    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+    hipLaunchKernelGGL((k_r2c_x3<Tr, T>), dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(g.n3, lg, true), s, g,
+                       c.plan[2], reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), x, g.N(), H, g.Nh(), lg);
     c2c_passes<T>(c, H, ncomp, -1, s);
     return hipGetLastError();
 }
@@ -584,12 +630,12 @@ hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(c.H);
     c2c_passes<T>(c, H, ncomp, +1, s);
-    const int L = pick_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + 2L * L - 1) / (2L * L));
-    const size_t lds = 2 * (size_t)g.n3 * (L + 1) * sizeof(C);
-    hipLaunchKernelGGL((k_c2r_x3<T, Tr>), dim3(nb, ncomp), dim3(kThreads), lds, s, g, c.plan[2],
-                       reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), H, g.Nh(), out, g.N(),
-                       T(1.0 / (double)g.N()), L);
+    const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+    const long L2 = 2L << lg;
+    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+    hipLaunchKernelGGL((k_c2r_x3<T, Tr>), dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(g.n3, lg, true), s, g,
+                       c.plan[2], reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), H, g.Nh(), out, g.N(),
+                       T(1.0 / (double)g.N()), lg);
     return hipGetLastError();
 }
 

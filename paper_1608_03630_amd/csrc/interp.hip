@@ -7,9 +7,14 @@
 // One thread per grid point, which gathers its 4x4x4 stencil and evaluates it
 // separably (16 rows of 4 along x3, then 4 planes along x2, then x1): 64 FMA
 // instead of the 64-term product sum, and every output point is written by
-// exactly one thread (a race-free gather). Blocks are remapped so that each
-// XCD (8 per MI355X, one L2 each) receives a contiguous slab of the grid,
-// which keeps the stencil halos of neighbouring blocks in the same L2.
+// exactly one thread (a race-free gather). Each stencil row (4 consecutive x3
+// values) that does not wrap around the periodic boundary is fetched with one
+// 16-byte vector load (two for double), so a wavefront issues 16 address
+// batches per point instead of 64 — the gather is bound by how many lanes the
+// address units take per clock, not by bytes. Rows that wrap use four scalar
+// loads. Blocks are remapped so that each XCD (8 per MI355X, one L2 each)
+// receives a contiguous slab of the grid, which keeps the stencil halos of
+// neighbouring blocks in the same L2.
 #include "common.hpp"
 
 namespace regk {
@@ -29,9 +34,16 @@ __device__ __forceinline__ long xcd_block() {
     return (long)(base + t);
 }
 
+// m mod n in [0, n); displacements are mostly within one period, so the
+// division runs only for the rare far point
 __device__ __forceinline__ int wrap_idx(int m, int n) {
-    const int r = m % n;
-    return r < 0 ? r + n : r;
+    if (m < 0) m += n;
+    else if (m >= n) m -= n;
+    if ((unsigned)m >= (unsigned)n) {
+        m %= n;
+        if (m < 0) m += n;
+    }
+    return m;
 }
 
 template <typename T> __device__ __forceinline__ T flo(T x);
@@ -48,53 +60,101 @@ __device__ __forceinline__ void lagrange4(T t, T w[4]) {
     w[3] = tp1 * t * tm1 * T(1.0 / 6.0);
 }
 
-// The stencil of one departure point: wrapped element offsets per axis and
-// the per-axis weights.
+// The stencil of one departure point: wrapped element offsets along x1 and
+// x2, the first x3 index b3 of the rows (wrapped), the row length n3, and the
+// per-axis weights.
 template <typename T>
 struct Stencil {
-    int o1[4], o2[4], o3[4];
+    int o1[4], o2[4];
+    int b3, n3;
     T w1[4], w2[4], w3[4];
 };
 
+// first stencil index (m - 1 wrapped into [0, n)) and the weights of one axis
 template <typename T>
-__device__ __forceinline__ void axis_stencil(int i, T d, int n, int stride, int o[4], T w[4]) {
+__device__ __forceinline__ int axis_base(int i, T d, int n, T w[4]) {
     const T fl = flo(d);
     const T t = d - fl;  // exact
     // clamp before the conversion (NaN maps to the lower bound); the modulo
     // then keeps every stencil index inside [0, n)
     const T flc = fmin(fmax(fl, T(-1e9)), T(1e9));
-    const int base = wrap_idx(i + (int)flc - 1, n);  // |i + flc| < 2^31
+    lagrange4(t, w);
+    return wrap_idx(i + (int)flc - 1, n);  // |i + flc| < 2^31
+}
+
+__device__ __forceinline__ void axis_offsets(int base, int n, int stride, int o[4]) {
     int x = base;
 #pragma unroll
     for (int a = 0; a < 4; a++) {
         o[a] = x * stride;
         x = (x + 1 == n) ? 0 : x + 1;
     }
-    lagrange4(t, w);
 }
 
 template <typename T>
 __device__ __forceinline__ void make_stencil(const Grid &g, int i1, int i2, int i3, T d1, T d2, T d3,
                                              Stencil<T> &st) {
-    axis_stencil(i1, d1, g.n1, g.n2 * g.n3, st.o1, st.w1);
-    axis_stencil(i2, d2, g.n2, g.n3, st.o2, st.w2);
-    axis_stencil(i3, d3, g.n3, 1, st.o3, st.w3);
+    axis_offsets(axis_base(i1, d1, g.n1, st.w1), g.n1, g.n2 * g.n3, st.o1);
+    axis_offsets(axis_base(i2, d2, g.n2, st.w2), g.n2, g.n3, st.o2);
+    st.b3 = axis_base(i3, d3, g.n3, st.w3);
+    st.n3 = g.n3;
 }
+
+// 4 consecutive values of a row that does not wrap, as 16-byte loads at
+// element (not vector) alignment
+typedef float f4_unaligned __attribute__((ext_vector_type(4), aligned(4)));
+typedef double d2_unaligned __attribute__((ext_vector_type(2), aligned(8)));
+
+
+template <typename T> struct Row;
+template <> struct Row<float> {
+    f4_unaligned v;
+    __device__ __forceinline__ void load(const float *p) { v = *reinterpret_cast<const f4_unaligned *>(p); }
+    __device__ __forceinline__ float dot(const float w[4]) const { return w[0] * v.x + w[1] * v.y + w[2] * v.z + w[3] * v.w; }
+};
+template <> struct Row<double> {
+    d2_unaligned a, b;
+    __device__ __forceinline__ void load(const double *p) {
+        a = *reinterpret_cast<const d2_unaligned *>(p);
+        b = *reinterpret_cast<const d2_unaligned *>(p + 2);
+    }
+    __device__ __forceinline__ double dot(const double w[4]) const {
+        return w[0] * a.x + w[1] * a.y + w[2] * b.x + w[3] * b.y;
+    }
+};
 
 template <typename T>
 __device__ __forceinline__ T apply(const T *__restrict__ f, const Stencil<T> &st) {
     T acc = T(0);
+    if (st.b3 + 3 < st.n3) {
+        // all 16 row loads are issued before the first use, so a wavefront
+        // keeps 16 requests in flight instead of one
+        Row<T> r[16];
 #pragma unroll
-    for (int a = 0; a < 4; a++) {
-        T pa = T(0);
+        for (int a = 0; a < 4; a++)
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            const T *row = f + st.o1[a] + st.o2[b];
-            const T r = st.w3[0] * row[st.o3[0]] + st.w3[1] * row[st.o3[1]] + st.w3[2] * row[st.o3[2]] +
-                        st.w3[3] * row[st.o3[3]];
-            pa += st.w2[b] * r;
+            for (int b = 0; b < 4; b++) r[a * 4 + b].load(f + st.o1[a] + st.o2[b] + st.b3);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            T pa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; b++) pa += st.w2[b] * r[a * 4 + b].dot(st.w3);
+            acc += st.w1[a] * pa;
         }
-        acc += st.w1[a] * pa;
+    } else {
+        int o3[4];
+        axis_offsets(st.b3, st.n3, 1, o3);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            T pa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const T *row = f + st.o1[a] + st.o2[b];
+                pa += st.w2[b] * (st.w3[0] * row[o3[0]] + st.w3[1] * row[o3[1]] + st.w3[2] * row[o3[2]] +
+                                  st.w3[3] * row[o3[3]]);
+            }
+            acc += st.w1[a] * pa;
+        }
     }
     return acc;
 }
@@ -242,14 +302,249 @@ __global__ __launch_bounds__(kThreads) void k_deform_step(Grid g, const T *__res
     u_out[2 * N + p] = apply(u_in + 2 * N, st) + h3 * d3;
 }
 
+
+// ---------------------------------------------------------- LDS-staged tiles
+//
+// A workgroup owns a kTile1 x kTile2 x kTile3 tile of output points. The
+// union of their stencils is the box [tile origin + lo, + B) per axis, known
+// from the floor bounds of D over the whole field (computed once per plan).
+// The box is staged in LDS with coalesced row loads (wrapping periodically),
+// then each point reads its 64 values from LDS at local indices that need no
+// modulo; local indices are clamped to the box so that even a NaN
+// displacement cannot address outside it.
+
+constexpr int kTileLines = kTile1 * kTile2;       // x3 lines per tile
+constexpr int kWaves = kThreads / 64;             // 4 wavefronts
+constexpr int kLinesPerWave = kTileLines / kWaves;
+
+struct TileIdx {
+    int t1, t2, t3;  // tile coordinates
+};
+
+__device__ __forceinline__ TileIdx tile_of(const Grid &g) {
+    const int nt3 = (g.n3 + kTile3 - 1) / kTile3, nt2 = (g.n2 + kTile2 - 1) / kTile2;
+    const unsigned b = (unsigned)xcd_block();
+    TileIdx t;
+    t.t3 = (int)(b % nt3);
+    const unsigned r = b / nt3;
+    t.t2 = (int)(r % nt2);
+    t.t1 = (int)(r / nt2);
+    return t;
+}
+
+// stage the box of field f for tile t into box[] (row-major [B1][B2][B3])
+template <typename T>
+__device__ __forceinline__ void stage_box(const Grid &g, const TileGeom &tg, const TileIdx &t,
+                                          const T *__restrict__ f, T *box) {
+    const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int nrows = tg.B[0] * tg.B[1];
+    for (int r = wave; r < nrows; r += kWaves) {
+        const int r1 = r / tg.B[1], r2 = r - r1 * tg.B[1];
+        const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
+        const T *row = f + ((long)g1 * g.n2 + g2) * g.n3;
+        T *dst = box + r * tg.B[2];
+        for (int c = lane; c < tg.B[2]; c += 64) dst[c] = row[wrap_idx(o3 + c, g.n3)];
+    }
+}
+
+// local stencil start along one axis (clamped into the box) and the weights
+template <typename T>
+__device__ __forceinline__ int local_base(int il, T d, int lo, int B, T w[4]) {
+    const T fl = flo(d);
+    lagrange4(d - fl, w);
+    const T flc = fmin(fmax(fl, T(-1e6)), T(1e6));
+    const int l = il + (int)flc - 1 - lo;
+    return min(max(l, 0), B - 4);
+}
+
+template <typename T>
+__device__ __forceinline__ T apply_box(const T *box, const TileGeom &tg, int l1, int l2, int l3, const T w1[4],
+                                       const T w2[4], const T w3[4]) {
+    const int s2 = tg.B[2], s1 = tg.B[1] * tg.B[2];
+    const T *base = box + l1 * s1 + l2 * s2 + l3;
+    T acc = T(0);
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        T pa = T(0);
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const T *row = base + a * s1 + b * s2;
+            pa += w2[b] * (w3[0] * row[0] + w3[1] * row[1] + w3[2] * row[2] + w3[3] * row[3]);
+        }
+        acc += w1[a] * pa;
+    }
+    return acc;
+}
+
+enum TileMode { TM_INTERP = 0, TM_ADJOINT = 1, TM_INCSTATE = 2 };
+
+struct TileArgs {
+    const void *c, *cX, *grad, *vt;  // mode inputs (may be null)
+    void *b, *out;                   // b accumulator (adjoint / last incstate), output field
+    double dt, wn, cs, w;
+    int last;
+};
+
+// One kernel for the three gather-based time steps; the mode picks the
+// epilogue (see k_interp, k_adjoint_step, k_incstate_step for the formulas).
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
+                                                    const T *__restrict__ D, TileArgs args) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *box = reinterpret_cast<T *>(smem_raw);
+    const TileIdx t = tile_of(g);
+    stage_box(g, tg, t, f, box);
+    __syncthreads();
+    const long N = g.N();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int i3 = t.t3 * kTile3 + lane;
+    if (i3 >= g.n3) return;
+    const T *__restrict__ c = static_cast<const T *>(args.c);
+    const T *__restrict__ cX = static_cast<const T *>(args.cX);
+    const T *__restrict__ grad = static_cast<const T *>(args.grad);
+    const T *__restrict__ vt = static_cast<const T *>(args.vt);
+    T *__restrict__ b = static_cast<T *>(args.b);
+    T *__restrict__ out = static_cast<T *>(args.out);
+    for (int k = 0; k < kLinesPerWave; k++) {
+        const int line = wave + kWaves * k;
+        const int a1 = line / kTile2, a2 = line - a1 * kTile2;
+        const int i1 = t.t1 * kTile1 + a1, i2 = t.t2 * kTile2 + a2;
+        if (i1 >= g.n1 || i2 >= g.n2) continue;
+        const long p = ((long)i1 * g.n2 + i2) * g.n3 + i3;
+        T w1[4], w2[4], w3[4];
+        const int l1 = local_base(a1, D[p], tg.lo[0], tg.B[0], w1);
+        const int l2 = local_base(a2, D[N + p], tg.lo[1], tg.B[1], w2);
+        const int l3 = local_base(lane, D[2 * N + p], tg.lo[2], tg.B[2], w3);
+        T v = apply_box(box, tg, l1, l2, l3, w1, w2, w3);
+        if (MODE == TM_INTERP) {
+            out[p] = v;
+        } else if (MODE == TM_ADJOINT) {
+            const T dt = T(args.dt);
+            if (c) {
+                const T f0 = v * cX[p];
+                const T nus = v + dt * f0;
+                const T fs = nus * c[p];
+                v = v + T(0.5) * dt * (f0 + fs);
+            }
+            if (out) out[p] = v;
+            if (b) {
+                const T s = T(args.wn) * v;
+                b[p] += s * grad[p];
+                b[N + p] += s * grad[N + p];
+                b[2 * N + p] += s * grad[2 * N + p];
+            }
+        } else {  // TM_INCSTATE
+            const T g1 = grad[p], g2 = grad[N + p], g3 = grad[2 * N + p];
+            const T sv = vt[p] * g1 + vt[N + p] * g2 + vt[2 * N + p] * g3;
+            v = v + T(args.cs) * sv;
+            if (args.last) {
+                v = -v;
+                const T ws = T(args.w) * v;
+                b[p] = ws * g1;
+                b[N + p] = ws * g2;
+                b[2 * N + p] = ws * g3;
+            }
+            out[p] = v;
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_floor_bounds(Grid g, const T *__restrict__ D,
+                                                           double *__restrict__ partials) {
+    const long N = g.N();
+    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < N; i += (long)gridDim.x * kThreads) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            const double fl = floor((double)D[j * N + i]);
+            mn[j] = fmin(mn[j], fl);
+            mx[j] = fmax(mx[j], fl);
+        }
+    }
+    __shared__ double sm[6][kThreads / 64];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        for (int off = 32; off > 0; off >>= 1) {
+            mn[j] = fmin(mn[j], __shfl_down(mn[j], off, 64));
+            mx[j] = fmax(mx[j], __shfl_down(mx[j], off, 64));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            sm[2 * j][threadIdx.x >> 6] = mn[j];
+            sm[2 * j + 1][threadIdx.x >> 6] = mx[j];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const bool is_min = (threadIdx.x & 1) == 0;
+        double v = sm[threadIdx.x][0];
+        for (int i = 1; i < kThreads / 64; i++) v = is_min ? fmin(v, sm[threadIdx.x][i]) : fmax(v, sm[threadIdx.x][i]);
+        partials[6 * blockIdx.x + threadIdx.x] = v;
+    }
+}
+
+__global__ void k_finalize_bounds(const double *__restrict__ partials, int nblocks, double *__restrict__ out6) {
+    if (threadIdx.x < 6) {
+        const bool is_min = (threadIdx.x & 1) == 0;
+        double v = partials[threadIdx.x];
+        for (int b = 1; b < nblocks; b++) {
+            const double x = partials[6 * b + threadIdx.x];
+            v = is_min ? fmin(v, x) : fmax(v, x);
+        }
+        out6[threadIdx.x] = v;
+    }
+}
+
+inline unsigned ntiles(const Grid &g) {
+    return (unsigned)(((g.n1 + kTile1 - 1) / kTile1) * ((g.n2 + kTile2 - 1) / kTile2) *
+                      ((g.n3 + kTile3 - 1) / kTile3));
+}
+
+template <typename T, int MODE>
+hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *D, const TileArgs &a, hipStream_t s) {
+    const size_t lds = sizeof(T) * (size_t)tg.B[0] * tg.B[1] * tg.B[2];
+    hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kThreads), lds, s, g, tg, f, D, a);
+    return hipGetLastError();
+}
+
 inline unsigned nblocks(long N) { return (unsigned)((N + kThreads - 1) / kThreads); }
 
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 
+bool tile_geom(const double fmin[3], const double fmax[3], size_t elem, TileGeom *tg) {
+    const int T[3] = {kTile1, kTile2, kTile3};
+    size_t vol = elem;
+    for (int j = 0; j < 3; j++) {
+        const double span = fmax[j] - fmin[j];
+        if (!(span >= 0) || span > 64 || !(fabs(fmin[j]) < 1e6)) return false;
+        tg->lo[j] = (int)fmin[j] - 1;
+        tg->B[j] = T[j] + (int)span + 3;
+        vol *= (size_t)tg->B[j];
+    }
+    return vol <= 65536;
+}
+
 template <typename T>
-hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStream_t s) {
+hipError_t launch_floor_bounds(const Grid &g, const T *D, double *partials, int nb, hipStream_t s) {
+    hipLaunchKernelGGL(k_floor_bounds<T>, dim3(nb), dim3(kThreads), 0, s, g, D, partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_bounds(const double *partials, int nb, double *out6, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_bounds, dim3(1), dim3(64), 0, s, partials, nb, out6);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStream_t s, const TileGeom *tg) {
+    if (tg) {
+        TileArgs a{};
+        a.out = out;
+        return launch_tiled<T, TM_INTERP>(g, *tg, f, D, a, s);
+    }
     hipLaunchKernelGGL(k_interp<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, f, D, out);
     return hipGetLastError();
 }
@@ -264,7 +559,18 @@ hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hip
 
 template <typename T>
 hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *c, const T *cX, const T *grad,
-                               T *b, T *lam_out, double dt, double wn, hipStream_t s) {
+                               T *b, T *lam_out, double dt, double wn, hipStream_t s, const TileGeom *tg) {
+    if (tg) {
+        TileArgs a{};
+        a.c = c;
+        a.cX = cX;
+        a.grad = grad;
+        a.b = b;
+        a.out = lam_out;
+        a.dt = dt;
+        a.wn = wn;
+        return launch_tiled<T, TM_ADJOINT>(g, *tg, lam_in, Da, a, s);
+    }
     hipLaunchKernelGGL(k_adjoint_step<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, lam_in, Da, c, cX, grad, b,
                        lam_out, T(dt), T(wn));
     return hipGetLastError();
@@ -280,7 +586,18 @@ hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, cons
 
 template <typename T>
 hipError_t launch_incstate_step(const Grid &g, const T *q_in, const T *Df, const T *vt, const T *grad, T *q_out,
-                                double cs, int last, T *b, double w, hipStream_t s) {
+                                double cs, int last, T *b, double w, hipStream_t s, const TileGeom *tg) {
+    if (tg) {
+        TileArgs a{};
+        a.vt = vt;
+        a.grad = grad;
+        a.b = b;
+        a.out = q_out;
+        a.cs = cs;
+        a.w = w;
+        a.last = last;
+        return launch_tiled<T, TM_INCSTATE>(g, *tg, q_in, Df, a, s);
+    }
     hipLaunchKernelGGL(k_incstate_step<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, q_in, Df, vt, grad, q_out,
                        T(cs), last, b, T(w));
     return hipGetLastError();
@@ -301,14 +618,15 @@ hipError_t launch_deform_step(const Grid &g, const T *u_in, const T *Df, T *u_ou
 }
 
 #define REGK_INST(T)                                                                                                 \
-    template hipError_t launch_interp<T>(const Grid &, const T *, const T *, T *, hipStream_t);                      \
+    template hipError_t launch_interp<T>(const Grid &, const T *, const T *, T *, hipStream_t, const TileGeom *);    \
+    template hipError_t launch_floor_bounds<T>(const Grid &, const T *, double *, int, hipStream_t);                 \
     template hipError_t launch_backtrace<T>(const Grid &, const T *, double, T *, hipStream_t);                      \
     template hipError_t launch_adjoint_step<T>(const Grid &, const T *, const T *, const T *, const T *, const T *,  \
-                                               T *, T *, double, double, hipStream_t);                               \
+                                               T *, T *, double, double, hipStream_t, const TileGeom *);             \
     template hipError_t launch_adjoint_init<T>(const Grid &, const T *, const T *, const T *, T *, T *, double,      \
                                                hipStream_t);                                                         \
     template hipError_t launch_incstate_step<T>(const Grid &, const T *, const T *, const T *, const T *, T *,       \
-                                                double, int, T *, double, hipStream_t);                              \
+                                                double, int, T *, double, hipStream_t, const TileGeom *);            \
     template hipError_t launch_incstate_init<T>(const Grid &, const T *, const T *, T *, double, hipStream_t);       \
     template hipError_t launch_deform_step<T>(const Grid &, const T *, const T *, T *, hipStream_t);
 
