@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_POINT = {
     "interp": 20.0,     # D (3 x 4) + gathered field 4 + out 4
     "backtrace": 24.0,  # v (3 x 4) + D out (3 x 4)
-    "adjoint": 64.0,    # D 12, lam 4, div v 4, (div v)(X) 4, grad rho 12, b 12 in; lam 4, b 12 out
-    "incstate": 44.0,   # D 12, q 4, vt 12, grad rho 12 in; q 4 out (+12 for b on the last step)
+    "adjoint": 24.0,    # D 12, gathered lam 4, source factor gam 4 in; lam 4 out
+    "incstate": 44.0,   # D 12, gathered q 4, vt 12, grad rho 12 in; q 4 out
 }
 
 
@@ -175,8 +175,6 @@ def main():
     launches, ms = kinds[dom]
     avg_ms = ms / launches
     bpp = BYTES_PER_POINT[dom]
-    if dom == "incstate":
-        bpp += 12.0 / ctx.params.nt  # the last step of each sweep also writes b
     bytes_per_launch = bpp * N
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None

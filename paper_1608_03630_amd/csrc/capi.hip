@@ -69,6 +69,8 @@ struct reg_ctx {
 
     // workspace views
     void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec;
+    void *lamh;        // adjoint levels lam^0..lam^nt
+    void *gam, *gam2;  // Heun factor of the adjoint source (cached plan, scratch plan)
     void *vf, *vtf;                                            // velocity copies in the field type
     void *vcur, *g_, *sdir, *r, *z, *p, *q, *vtrial;          // velocity space, double
     void *u0, *u1, *du, *H;
@@ -236,6 +238,9 @@ size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->cX2 = L.take(E * N);
     c->lam[0] = L.take(E * N);
     c->lam[1] = L.take(E * N);
+    c->lamh = L.take(E * N * nt1);
+    c->gam = L.take(E * N);
+    c->gam2 = L.take(E * N);
     c->bvec = L.take(E * 3 * N);
     c->vf = L.take(E * 3 * N);
     c->vtf = L.take(E * 3 * N);
@@ -429,22 +434,18 @@ reg_status regulariser_of(reg_ctx *ctx, const void *v, int slot) {
     return reg_term_to_slot(ctx, slot);
 }
 
-// Backward adjoint-type sweep from lam^nt in lam[start] with b initialised at
-// nt: lam^n for n = nt-1..0 and b += w_n lam^n grad rho^n.
+// Backward adjoint-type sweep: lamh[nt] holds lam^nt; writes lam^n for
+// n = nt-1..0, then b = sum_n w_n lam^n grad rho^n in one pass.
 template <typename T>
-reg_status adjoint_sweep(reg_ctx *ctx, int start, const void *Da, const void *c, const void *cX, void *b) {
+reg_status adjoint_sweep(reg_ctx *ctx, const void *Da, const void *gam, void *b) {
     const long N = ctx->N;
     const int nt = ctx->P.nt;
-    const double dt = 1.0 / nt;
-    int cur = start;
-    for (int k = nt - 1; k >= 0; k--) {
-        const double w = (k == 0) ? 0.5 * dt : dt;
-        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(Da), CV<T>(c), CV<T>(cX),
-                                                 V<T>(ctx->grho) + (long)k * 3 * N, V<T>(b), V<T>(ctx->lam[1 - cur]),
-                                                 dt, w, ctx->stream, geom_of(ctx, Da))));
-        cur = 1 - cur;
-    }
+    for (int k = nt - 1; k >= 0; k--)
+        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, V<T>(ctx->lamh) + (long)(k + 1) * N, CV<T>(Da),
+                                                 CV<T>(gam), V<T>(ctx->lamh) + (long)k * N, ctx->stream,
+                                                 geom_of(ctx, Da))));
     ctx->interps += nt;
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, CV<T>(ctx->lamh), CV<T>(ctx->grho), V<T>(b), ctx->stream)));
     return REG_OK;
 }
 
@@ -459,6 +460,8 @@ reg_status complete_state(reg_ctx *ctx) {
         HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX), ctx->stream,
                                                                  geom_of(ctx, ctx->Da))));
         ctx->interps += 1;
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_gamma<T>(ctx->N, CV<T>(ctx->c), CV<T>(ctx->cX), V<T>(ctx->gam),
+                                                                1.0 / ctx->P.nt, ctx->stream)));
     }
     ctx->have_state = true;
     return REG_OK;
@@ -498,11 +501,9 @@ reg_status gradient_impl(reg_ctx *ctx, const void *v, void *g, double *J, double
     }
     STCHK(complete_state<T>(ctx));
     // adjoint from lam(1) = rho_R - rho(1), b = sum w_n lam^n grad rho^n
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_adjoint_init<T>(ctx->g, CV<T>(ctx->rhoR), V<T>(ctx->histA) + (long)nt * N,
-                                             V<T>(ctx->grho) + (long)nt * 3 * N, V<T>(ctx->lam[0]), V<T>(ctx->bvec),
-                                             0.5 / nt, ctx->stream)));
-    STCHK(adjoint_sweep<T>(ctx, 0, ctx->Da, ctx->P.isochoric ? nullptr : ctx->c,
-                           ctx->P.isochoric ? nullptr : ctx->cX, ctx->bvec));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_adjoint_init<T>(N, CV<T>(ctx->rhoR), V<T>(ctx->histA) + (long)nt * N,
+                                                                   V<T>(ctx->lamh) + (long)nt * N, ctx->stream)));
+    STCHK(adjoint_sweep<T>(ctx, ctx->Da, ctx->P.isochoric ? nullptr : ctx->gam, ctx->bvec));
     STCHK(assemble<T>(ctx, ctx->vcur, ctx->bvec, g, true));
     STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vcur, true));
     STCHK(reduce<double>(ctx, g, nullptr, 3 * N, 2, h3(ctx), 3));
@@ -526,16 +527,15 @@ reg_status matvec_impl(reg_ctx *ctx, const void *vt, void *Hvt) {
     int cur = 1;
     for (int k = 0; k < nt; k++) {
         const int last = (k == nt - 1);
+        T *dst = last ? V<T>(ctx->lamh) + (long)nt * N : V<T>(ctx->lam[1 - cur]);
         HIPCHK(ctx, KL(ctx, REG_K_INCSTATE, regk::launch_incstate_step<T>(ctx->g, V<T>(ctx->lam[cur]), CV<T>(ctx->Df), CV<T>(ctx->vtf),
-                                                  V<T>(ctx->grho) + (long)(k + 1) * 3 * N, V<T>(ctx->lam[1 - cur]),
-                                                  last ? -0.5 * dt : -dt, last, V<T>(ctx->bvec), 0.5 * dt,
-                                                  ctx->stream, geom_of(ctx, ctx->Df))));
+                                                  V<T>(ctx->grho) + (long)(k + 1) * 3 * N, dst,
+                                                  last ? -0.5 * dt : -dt, last, ctx->stream, geom_of(ctx, ctx->Df))));
         cur = 1 - cur;
     }
     ctx->interps += nt;
-    // lam~^nt now sits in lam[cur]
-    STCHK(adjoint_sweep<T>(ctx, cur, ctx->Da, ctx->P.isochoric ? nullptr : ctx->c,
-                           ctx->P.isochoric ? nullptr : ctx->cX, ctx->bvec));
+    // lam~(1) = -rho~(1) now sits in lamh[nt]
+    STCHK(adjoint_sweep<T>(ctx, ctx->Da, ctx->P.isochoric ? nullptr : ctx->gam, ctx->bvec));
     STCHK(assemble<T>(ctx, vt, ctx->bvec, Hvt, false));
     return REG_OK;
 }
@@ -769,12 +769,14 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
         HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream, geom_of(ctx, ctx->Dt))));
         ctx->interps += 1;
     }
+    if (src)
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_gamma<T>(N, CV<T>(ctx->c2), CV<T>(ctx->cX2), V<T>(ctx->gam2), 1.0 / nt,
+                                                                ctx->stream)));
     const T *in = CV<T>(lam1);
     for (int k = 0; k < nt; k++) {
         T *out = (k == nt - 1) ? V<T>(lam0) : V<T>(ctx->histB) + (long)(k & 1) * N;
-        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, in, CV<T>(ctx->Dt), src ? CV<T>(ctx->c2) : nullptr,
-                                                 src ? CV<T>(ctx->cX2) : nullptr, nullptr, nullptr, out, 1.0 / nt, 0.0,
-                                                 ctx->stream, geom_of(ctx, ctx->Dt))));
+        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, in, CV<T>(ctx->Dt), src ? CV<T>(ctx->gam2) : nullptr,
+                                                                        out, ctx->stream, geom_of(ctx, ctx->Dt))));
         in = out;
     }
     ctx->interps += nt;

@@ -55,21 +55,24 @@ hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStrea
                          const TileGeom *tg = nullptr);
 template <typename T>
 hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hipStream_t s);
-// adjoint-type step: lam_out = Heun step of nu with source nu*c (if c), and
-// b += wn * lam_out * grad (if b); lam_out may be null when b is set.
+// adjoint-type step: lam_out = lam_in(X) * gam (gam = null: pure interpolation)
 template <typename T>
-hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *c, const T *cX,
-                               const T *grad, T *b, T *lam_out, double dt, double wn, hipStream_t s,
+hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *gam, T *lam_out, hipStream_t s,
                                const TileGeom *tg = nullptr);
-// lam = rhoR - rho1 (or -scale*src): initial adjoint level; b = w * lam * grad
+// gam = 1 + dt/2 (cX + c) + dt^2/2 cX c: the Heun factor of the adjoint source
 template <typename T>
-hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, const T *grad, T *lam, T *b, double w,
-                               hipStream_t s);
+hipError_t launch_gamma(long N, const T *c, const T *cX, T *gam, double dt, hipStream_t s);
+// b = sum_n w_n lam^n grad^n (trapezoid weights) from nt+1 stored levels
+template <typename T>
+hipError_t launch_b_assemble(long N, int nt, const T *lam, const T *grad, T *b, hipStream_t s);
+// lam = rhoR - rho1
+template <typename T>
+hipError_t launch_adjoint_init(long N, const T *rhoR, const T *rho1, T *lam, hipStream_t s);
 // incremental state: q_out = interp(q_in, Df) + cs * (vt . grad); with last,
-// lam_out = -(that) and b = w * lam_out * grad
+// q_out = -(that) = lam~(1)
 template <typename T>
 hipError_t launch_incstate_step(const Grid &g, const T *q_in, const T *Df, const T *vt, const T *grad, T *q_out,
-                                double cs, int last, T *b, double w, hipStream_t s, const TileGeom *tg = nullptr);
+                                double cs, int last, hipStream_t s, const TileGeom *tg = nullptr);
 template <typename T>
 hipError_t launch_incstate_init(const Grid &g, const T *vt, const T *grad, T *q, double cs, hipStream_t s);
 template <typename T>

@@ -210,72 +210,77 @@ __global__ __launch_bounds__(kThreads) void k_backtrace(Grid g, const T *__restr
 
 // One backward (tau) step of d_tau nu + (-v).grad nu = nu c with eq. (7):
 // nu0 = nu(X), f0 = nu0 c(X), nu* = nu0 + dt f0, f* = nu* c(x),
-// nu_new = nu0 + dt/2 (f0 + f*); then b += wn nu_new grad.
+// nu_new = nu0 + dt/2 (f0 + f*). The source is linear in nu, so the step is
+// nu_new = nu(X) * gam(x) with gam = 1 + dt/2 (c(X) + c) + dt^2/2 c(X) c,
+// formed once per plan (k_gamma); gam = null when div v = 0.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_adjoint_step(Grid g, const T *__restrict__ lam_in,
-                                                           const T *__restrict__ Da, const T *__restrict__ c,
-                                                           const T *__restrict__ cX, const T *__restrict__ grad,
-                                                           T *__restrict__ b, T *__restrict__ lam_out, T dt, T wn) {
+                                                           const T *__restrict__ Da, const T *__restrict__ gam,
+                                                           T *__restrict__ lam_out) {
     PointIdx pi;
     if (!point_of(g, pi)) return;
     const long N = g.N(), p = pi.p;
     Stencil<T> st;
     make_stencil(g, pi.i1, pi.i2, pi.i3, Da[p], Da[N + p], Da[2 * N + p], st);
     T lam = apply(lam_in, st);
-    if (c) {
-        const T f0 = lam * cX[p];
-        const T nus = lam + dt * f0;
-        const T fs = nus * c[p];
-        lam = lam + T(0.5) * dt * (f0 + fs);
+    if (gam) lam *= gam[p];
+    lam_out[p] = lam;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_gamma(long N, const T *__restrict__ c, const T *__restrict__ cX,
+                                                    T *__restrict__ gam, T dt) {
+    const long p = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= N) return;
+    const T a = cX[p], b = c[p];
+    gam[p] = T(1) + T(0.5) * dt * (a + b) + T(0.5) * dt * dt * a * b;
+}
+
+// b = sum_n w_n lam^n grad rho^n over the stored levels (trapezoid weights
+// dt/2 at both ends, dt inside); pointwise in x, so one streaming pass
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_b_assemble(long N, int nt, const T *__restrict__ lam,
+                                                         const T *__restrict__ grad, T *__restrict__ b) {
+    const long p = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= N) return;
+    const T dt = T(1) / T(nt);
+    T b1 = T(0), b2 = T(0), b3 = T(0);
+    for (int k = 0; k <= nt; k++) {
+        const T w = (k == 0 || k == nt) ? T(0.5) * dt : dt;
+        const T s = w * lam[(long)k * N + p];
+        const T *gk = grad + (long)k * 3 * N;
+        b1 += s * gk[p];
+        b2 += s * gk[N + p];
+        b3 += s * gk[2 * N + p];
     }
-    if (lam_out) lam_out[p] = lam;
-    if (b) {
-        const T s = wn * lam;
-        b[p] += s * grad[p];
-        b[N + p] += s * grad[N + p];
-        b[2 * N + p] += s * grad[2 * N + p];
-    }
+    b[p] = b1;
+    b[N + p] = b2;
+    b[2 * N + p] = b3;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_adjoint_init(long N, const T *__restrict__ rhoR,
-                                                           const T *__restrict__ rho1, const T *__restrict__ grad,
-                                                           T *__restrict__ lam, T *__restrict__ b, T w) {
+                                                           const T *__restrict__ rho1, T *__restrict__ lam) {
     const long p = (long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= N) return;
-    const T l = rhoR[p] - rho1[p];
-    lam[p] = l;
-    if (b) {
-        const T s = w * l;
-        b[p] = s * grad[p];
-        b[N + p] = s * grad[N + p];
-        b[2 * N + p] = s * grad[2 * N + p];
-    }
+    lam[p] = rhoR[p] - rho1[p];
 }
 
 // q_out = q_in(X) + cs * (vt . grad rho^{n+1}); the last step writes
-// lam~ = -(that) and starts b~ = w lam~ grad rho^{nt}.
+// lam~(1) = -(that), the start of the incremental adjoint.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_incstate_step(Grid g, const T *__restrict__ q_in,
                                                             const T *__restrict__ Df, const T *__restrict__ vt,
                                                             const T *__restrict__ grad, T *__restrict__ q_out, T cs,
-                                                            int last, T *__restrict__ b, T w) {
+                                                            int last) {
     PointIdx pi;
     if (!point_of(g, pi)) return;
     const long N = g.N(), p = pi.p;
     Stencil<T> st;
     make_stencil(g, pi.i1, pi.i2, pi.i3, Df[p], Df[N + p], Df[2 * N + p], st);
-    const T g1 = grad[p], g2 = grad[N + p], g3 = grad[2 * N + p];
-    const T s = vt[p] * g1 + vt[N + p] * g2 + vt[2 * N + p] * g3;
-    T q = apply(q_in, st) + cs * s;
-    if (last) {
-        q = -q;
-        const T ws = w * q;
-        b[p] = ws * g1;
-        b[N + p] = ws * g2;
-        b[2 * N + p] = ws * g3;
-    }
-    q_out[p] = q;
+    const T s = vt[p] * grad[p] + vt[N + p] * grad[N + p] + vt[2 * N + p] * grad[2 * N + p];
+    const T q = apply(q_in, st) + cs * s;
+    q_out[p] = last ? -q : q;
 }
 
 template <typename T>
@@ -332,19 +337,45 @@ __device__ __forceinline__ TileIdx tile_of(const Grid &g) {
     return t;
 }
 
-// stage the box of field f for tile t into box[] (row-major [B1][B2][B3])
+// stage the box of field f for tile t into box[] (row-major [B1][B2][B3]).
+// Rows are taken kStageRows at a time per wavefront and every value of the
+// batch is requested before the first LDS store, so that each wavefront keeps
+// up to kStageRows * 3 loads in flight (B3 <= 64 + 3 + 64 < 192).
+constexpr int kStageRows = 4;
+
 template <typename T>
 __device__ __forceinline__ void stage_box(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                           const T *__restrict__ f, T *box) {
     const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nrows = tg.B[0] * tg.B[1];
-    for (int r = wave; r < nrows; r += kWaves) {
-        const int r1 = r / tg.B[1], r2 = r - r1 * tg.B[1];
-        const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
-        const T *row = f + ((long)g1 * g.n2 + g2) * g.n3;
-        T *dst = box + r * tg.B[2];
-        for (int c = lane; c < tg.B[2]; c += 64) dst[c] = row[wrap_idx(o3 + c, g.n3)];
+    const int nrows = tg.B[0] * tg.B[1], B3 = tg.B[2];
+    int gc[3];
+#pragma unroll
+    for (int h = 0; h < 3; h++) gc[h] = wrap_idx(o3 + lane + 64 * h, g.n3);
+    for (int r0 = wave; r0 < nrows; r0 += kStageRows * kWaves) {
+        T vals[kStageRows][3];
+#pragma unroll
+        for (int u = 0; u < kStageRows; u++) {
+            const int r = r0 + u * kWaves;
+            if (r < nrows) {
+                const int r1 = r / tg.B[1], r2 = r - r1 * tg.B[1];
+                const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
+                const T *row = f + ((long)g1 * g.n2 + g2) * g.n3;
+#pragma unroll
+                for (int h = 0; h < 3; h++)
+                    if (lane + 64 * h < B3) vals[u][h] = row[gc[h]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kStageRows; u++) {
+            const int r = r0 + u * kWaves;
+            if (r < nrows) {
+                T *dst = box + r * B3;
+#pragma unroll
+                for (int h = 0; h < 3; h++)
+                    if (lane + 64 * h < B3) dst[lane + 64 * h] = vals[u][h];
+            }
+        }
     }
 }
 
@@ -380,72 +411,203 @@ __device__ __forceinline__ T apply_box(const T *box, const TileGeom &tg, int l1,
 enum TileMode { TM_INTERP = 0, TM_ADJOINT = 1, TM_INCSTATE = 2 };
 
 struct TileArgs {
-    const void *c, *cX, *grad, *vt;  // mode inputs (may be null)
-    void *b, *out;                   // b accumulator (adjoint / last incstate), output field
-    double dt, wn, cs, w;
+    const void *gam, *grad, *vt;  // mode inputs (may be null)
+    void *out;                    // output field
+    double cs;
     int last;
 };
 
 // One kernel for the three gather-based time steps; the mode picks the
 // epilogue (see k_interp, k_adjoint_step, k_incstate_step for the formulas).
+// Each thread owns kLinesPerWave points (one per x3 line it visits); their
+// displacements are loaded before the box is staged so that those HBM reads
+// overlap the staging, and each point's epilogue operands are requested
+// before its 64 LDS reads.
 template <typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
                                                     const T *__restrict__ D, TileArgs args) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *box = reinterpret_cast<T *>(smem_raw);
     const TileIdx t = tile_of(g);
-    stage_box(g, tg, t, f, box);
-    __syncthreads();
     const long N = g.N();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i3 = t.t3 * kTile3 + lane;
-    if (i3 >= g.n3) return;
-    const T *__restrict__ c = static_cast<const T *>(args.c);
-    const T *__restrict__ cX = static_cast<const T *>(args.cX);
-    const T *__restrict__ grad = static_cast<const T *>(args.grad);
-    const T *__restrict__ vt = static_cast<const T *>(args.vt);
-    T *__restrict__ b = static_cast<T *>(args.b);
-    T *__restrict__ out = static_cast<T *>(args.out);
+    const bool col_ok = i3 < g.n3;
+    T dd[kLinesPerWave][3];
+    long pp[kLinesPerWave];
+#pragma unroll
     for (int k = 0; k < kLinesPerWave; k++) {
         const int line = wave + kWaves * k;
         const int a1 = line / kTile2, a2 = line - a1 * kTile2;
         const int i1 = t.t1 * kTile1 + a1, i2 = t.t2 * kTile2 + a2;
-        if (i1 >= g.n1 || i2 >= g.n2) continue;
-        const long p = ((long)i1 * g.n2 + i2) * g.n3 + i3;
+        const bool ok = col_ok && i1 < g.n1 && i2 < g.n2;
+        const long p = ok ? ((long)i1 * g.n2 + i2) * g.n3 + i3 : -1;
+        pp[k] = p;
+        dd[k][0] = ok ? D[p] : T(0);
+        dd[k][1] = ok ? D[N + p] : T(0);
+        dd[k][2] = ok ? D[2 * N + p] : T(0);
+    }
+    stage_box(g, tg, t, f, box);
+    __syncthreads();
+    if (!col_ok) return;
+    const T *__restrict__ gam = static_cast<const T *>(args.gam);
+    const T *__restrict__ grad = static_cast<const T *>(args.grad);
+    const T *__restrict__ vt = static_cast<const T *>(args.vt);
+    T *__restrict__ out = static_cast<T *>(args.out);
+#pragma unroll
+    for (int k = 0; k < kLinesPerWave; k++) {
+        const long p = pp[k];
+        if (p < 0) continue;
+        const int line = wave + kWaves * k;
+        const int a1 = line / kTile2, a2 = line - a1 * kTile2;
+        T e0 = T(1), sv = T(0);
+        if (MODE == TM_ADJOINT) {
+            if (gam) e0 = gam[p];
+        } else if (MODE == TM_INCSTATE) {
+            sv = vt[p] * grad[p] + vt[N + p] * grad[N + p] + vt[2 * N + p] * grad[2 * N + p];
+        }
         T w1[4], w2[4], w3[4];
-        const int l1 = local_base(a1, D[p], tg.lo[0], tg.B[0], w1);
-        const int l2 = local_base(a2, D[N + p], tg.lo[1], tg.B[1], w2);
-        const int l3 = local_base(lane, D[2 * N + p], tg.lo[2], tg.B[2], w3);
+        const int l1 = local_base(a1, dd[k][0], tg.lo[0], tg.B[0], w1);
+        const int l2 = local_base(a2, dd[k][1], tg.lo[1], tg.B[1], w2);
+        const int l3 = local_base(lane, dd[k][2], tg.lo[2], tg.B[2], w3);
         T v = apply_box(box, tg, l1, l2, l3, w1, w2, w3);
         if (MODE == TM_INTERP) {
             out[p] = v;
         } else if (MODE == TM_ADJOINT) {
-            const T dt = T(args.dt);
-            if (c) {
-                const T f0 = v * cX[p];
-                const T nus = v + dt * f0;
-                const T fs = nus * c[p];
-                v = v + T(0.5) * dt * (f0 + fs);
-            }
-            if (out) out[p] = v;
-            if (b) {
-                const T s = T(args.wn) * v;
-                b[p] += s * grad[p];
-                b[N + p] += s * grad[N + p];
-                b[2 * N + p] += s * grad[2 * N + p];
-            }
+            out[p] = v * e0;
         } else {  // TM_INCSTATE
-            const T g1 = grad[p], g2 = grad[N + p], g3 = grad[2 * N + p];
-            const T sv = vt[p] * g1 + vt[N + p] * g2 + vt[2 * N + p] * g3;
             v = v + T(args.cs) * sv;
-            if (args.last) {
-                v = -v;
-                const T ws = T(args.w) * v;
-                b[p] = ws * g1;
-                b[N + p] = ws * g2;
-                b[2 * N + p] = ws * g3;
+            out[p] = args.last ? -v : v;
+        }
+    }
+}
+
+// The same three time steps with compile-time box strides: the box is stored
+// at the canonical extents kTile_j + 3 + S (any floor span <= S fits), so the
+// 64 LDS reads of a stencil are immediate offsets from one address, all index
+// arithmetic is 32-bit, and the per-thread point loop is fully unrolled with
+// no per-point branches (interior tiles only; the launcher sends ragged tiles
+// to k_tiled through the same grid via the `interior` test below).
+template <int S> struct Canon {
+    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S, C3 = kTile3 + 3 + S;
+    static constexpr int elems = C1 * C2 * C3;
+};
+
+template <typename T, int S>
+__device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &tg, const TileIdx &t,
+                                                const T *__restrict__ f, T *box) {
+    using K = Canon<S>;
+    const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int B2 = tg.B[1], B3 = tg.B[2];
+    const int nrows = tg.B[0] * B2;
+    const int gc0 = wrap_idx(o3 + lane, g.n3), gc1 = wrap_idx(o3 + lane + 64, g.n3);
+    const bool h1 = lane + 64 < B3;
+    for (int r0 = wave; r0 < nrows; r0 += kStageRows * kWaves) {
+        T v0[kStageRows], v1[kStageRows];
+        int dst[kStageRows];
+#pragma unroll
+        for (int u = 0; u < kStageRows; u++) {
+            const int r = r0 + u * kWaves;
+            dst[u] = -1;
+            if (r < nrows) {
+                const int r1 = r / B2, r2 = r - r1 * B2;
+                const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
+                const T *row = f + (unsigned)((g1 * g.n2 + g2) * g.n3);
+                v0[u] = row[gc0];
+                if (h1) v1[u] = row[gc1];
+                dst[u] = (r1 * K::C2 + r2) * K::C3;
             }
-            out[p] = v;
+        }
+#pragma unroll
+        for (int u = 0; u < kStageRows; u++) {
+            if (dst[u] >= 0) {
+                box[dst[u] + lane] = v0[u];
+                if (h1) box[dst[u] + lane + 64] = v1[u];
+            }
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ int canon_base(int il, T d, int lo, int B, T w[4]) {
+    const T fl = flo(d);
+    lagrange4(d - fl, w);
+    const T flc = fmin(fmax(fl, T(-1e6)), T(1e6));
+    return min(max(il + (int)flc - 1 - lo, 0), B - 4);
+}
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, const T *__restrict__ f,
+                                                          const T *__restrict__ D, TileArgs args) {
+    using K = Canon<S>;
+    __shared__ T box[K::elems];
+    const TileIdx t = tile_of(g);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const unsigned N = (unsigned)g.N();
+    const T *__restrict__ D1 = D;
+    const T *__restrict__ D2 = D + N;
+    const T *__restrict__ D3 = D + 2 * (size_t)N;
+    // interior tile: every point of the tile exists
+    const int i3 = t.t3 * kTile3 + lane;
+    const unsigned line_stride = (unsigned)g.n3;
+    const unsigned p0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3);
+    T d[kLinesPerWave][3];
+#pragma unroll
+    for (int k = 0; k < kLinesPerWave; k++) {
+        const int line = wave + kWaves * k;
+        const int a1 = line >> 3, a2 = line & 7;  // kTile2 == 8
+        const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
+        d[k][0] = D1[p];
+        d[k][1] = D2[p];
+        d[k][2] = D3[p];
+    }
+    stage_box_canon<T, S>(g, tg, t, f, box);
+    __syncthreads();
+    const T *__restrict__ gam = static_cast<const T *>(args.gam);
+    const T *__restrict__ gr1 = static_cast<const T *>(args.grad);
+    const T *__restrict__ gr2 = gr1 + N;
+    const T *__restrict__ gr3 = gr1 + 2 * (size_t)N;
+    const T *__restrict__ vt1 = static_cast<const T *>(args.vt);
+    const T *__restrict__ vt2 = vt1 + N;
+    const T *__restrict__ vt3 = vt1 + 2 * (size_t)N;
+    T *__restrict__ out = static_cast<T *>(args.out);
+    const T cs = T(args.cs);
+    const bool last = args.last != 0;
+#pragma unroll
+    for (int k = 0; k < kLinesPerWave; k++) {
+        const int line = wave + kWaves * k;
+        const int a1 = line >> 3, a2 = line & 7;
+        const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
+        T e0 = T(1), sv = T(0);
+        if (MODE == TM_ADJOINT) {
+            if (gam) e0 = gam[p];
+        } else if (MODE == TM_INCSTATE) {
+            sv = vt1[p] * gr1[p] + vt2[p] * gr2[p] + vt3[p] * gr3[p];
+        }
+        T w1[4], w2[4], w3[4];
+        const int l1 = canon_base(a1, d[k][0], tg.lo[0], tg.B[0], w1);
+        const int l2 = canon_base(a2, d[k][1], tg.lo[1], tg.B[1], w2);
+        const int l3 = canon_base(lane, d[k][2], tg.lo[2], tg.B[2], w3);
+        const T *base = box + (l1 * K::C2 + l2) * K::C3 + l3;
+        T acc = T(0);
+#pragma unroll
+        for (int a = 0; a < 4; a++) {
+            T pa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                const T *row = base + (a * K::C2 + b) * K::C3;
+                pa += w2[b] * (w3[0] * row[0] + w3[1] * row[1] + w3[2] * row[2] + w3[3] * row[3]);
+            }
+            acc += w1[a] * pa;
+        }
+        if (MODE == TM_INTERP) {
+            out[p] = acc;
+        } else if (MODE == TM_ADJOINT) {
+            out[p] = acc * e0;
+        } else {
+            const T v = acc + cs * sv;
+            out[p] = last ? -v : v;
         }
     }
 }
@@ -501,8 +663,25 @@ inline unsigned ntiles(const Grid &g) {
                       ((g.n3 + kTile3 - 1) / kTile3));
 }
 
+// largest floor span of a box
+inline int box_span(const TileGeom &tg) {
+    return max(max(tg.B[0] - kTile1, tg.B[1] - kTile2), tg.B[2] - kTile3) - 3;
+}
+
 template <typename T, int MODE>
 hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *D, const TileArgs &a, hipStream_t s) {
+    // canonical-stride kernels need whole tiles (every grid extent a multiple
+    // of the tile) and a floor span the canonical box holds
+    const bool whole = g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0;
+    const int span = box_span(tg);
+    if (whole && span <= 1 && sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 1>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f, D, a);
+        return hipGetLastError();
+    }
+    if (whole && span <= 2 && sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f, D, a);
+        return hipGetLastError();
+    }
     const size_t lds = sizeof(T) * (size_t)tg.B[0] * tg.B[1] * tg.B[2];
     hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kThreads), lds, s, g, tg, f, D, a);
     return hipGetLastError();
@@ -519,6 +698,7 @@ bool tile_geom(const double fmin[3], const double fmax[3], size_t elem, TileGeom
     size_t vol = elem;
     for (int j = 0; j < 3; j++) {
         const double span = fmax[j] - fmin[j];
+        // the staging loop covers rows of up to 192 values: B3 = 67 + span
         if (!(span >= 0) || span > 64 || !(fabs(fmin[j]) < 1e6)) return false;
         tg->lo[j] = (int)fmin[j] - 1;
         tg->B[j] = T[j] + (int)span + 3;
@@ -558,48 +738,50 @@ hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hip
 }
 
 template <typename T>
-hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *c, const T *cX, const T *grad,
-                               T *b, T *lam_out, double dt, double wn, hipStream_t s, const TileGeom *tg) {
+hipError_t launch_adjoint_step(const Grid &g, const T *lam_in, const T *Da, const T *gam, T *lam_out, hipStream_t s,
+                               const TileGeom *tg) {
     if (tg) {
         TileArgs a{};
-        a.c = c;
-        a.cX = cX;
-        a.grad = grad;
-        a.b = b;
+        a.gam = gam;
         a.out = lam_out;
-        a.dt = dt;
-        a.wn = wn;
         return launch_tiled<T, TM_ADJOINT>(g, *tg, lam_in, Da, a, s);
     }
-    hipLaunchKernelGGL(k_adjoint_step<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, lam_in, Da, c, cX, grad, b,
-                       lam_out, T(dt), T(wn));
+    hipLaunchKernelGGL(k_adjoint_step<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, lam_in, Da, gam, lam_out);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_adjoint_init(const Grid &g, const T *rhoR, const T *rho1, const T *grad, T *lam, T *b, double w,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_adjoint_init<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g.N(), rhoR, rho1, grad, lam,
-                       b, T(w));
+hipError_t launch_gamma(long N, const T *c, const T *cX, T *gam, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_gamma<T>, dim3(nblocks(N)), dim3(kThreads), 0, s, N, c, cX, gam, T(dt));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_assemble(long N, int nt, const T *lam, const T *grad, T *b, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_assemble<T>, dim3(nblocks(N)), dim3(kThreads), 0, s, N, nt, lam, grad, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_adjoint_init(long N, const T *rhoR, const T *rho1, T *lam, hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_init<T>, dim3(nblocks(N)), dim3(kThreads), 0, s, N, rhoR, rho1, lam);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_incstate_step(const Grid &g, const T *q_in, const T *Df, const T *vt, const T *grad, T *q_out,
-                                double cs, int last, T *b, double w, hipStream_t s, const TileGeom *tg) {
+                                double cs, int last, hipStream_t s, const TileGeom *tg) {
     if (tg) {
         TileArgs a{};
         a.vt = vt;
         a.grad = grad;
-        a.b = b;
         a.out = q_out;
         a.cs = cs;
-        a.w = w;
         a.last = last;
         return launch_tiled<T, TM_INCSTATE>(g, *tg, q_in, Df, a, s);
     }
     hipLaunchKernelGGL(k_incstate_step<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, q_in, Df, vt, grad, q_out,
-                       T(cs), last, b, T(w));
+                       T(cs), last);
     return hipGetLastError();
 }
 
@@ -621,12 +803,13 @@ hipError_t launch_deform_step(const Grid &g, const T *u_in, const T *Df, T *u_ou
     template hipError_t launch_interp<T>(const Grid &, const T *, const T *, T *, hipStream_t, const TileGeom *);    \
     template hipError_t launch_floor_bounds<T>(const Grid &, const T *, double *, int, hipStream_t);                 \
     template hipError_t launch_backtrace<T>(const Grid &, const T *, double, T *, hipStream_t);                      \
-    template hipError_t launch_adjoint_step<T>(const Grid &, const T *, const T *, const T *, const T *, const T *,  \
-                                               T *, T *, double, double, hipStream_t, const TileGeom *);             \
-    template hipError_t launch_adjoint_init<T>(const Grid &, const T *, const T *, const T *, T *, T *, double,      \
-                                               hipStream_t);                                                         \
+    template hipError_t launch_adjoint_step<T>(const Grid &, const T *, const T *, const T *, T *, hipStream_t,      \
+                                               const TileGeom *);                                                    \
+    template hipError_t launch_gamma<T>(long, const T *, const T *, T *, double, hipStream_t);                       \
+    template hipError_t launch_b_assemble<T>(long, int, const T *, const T *, T *, hipStream_t);                     \
+    template hipError_t launch_adjoint_init<T>(long, const T *, const T *, T *, hipStream_t);                        \
     template hipError_t launch_incstate_step<T>(const Grid &, const T *, const T *, const T *, const T *, T *,       \
-                                                double, int, T *, double, hipStream_t, const TileGeom *);            \
+                                                double, int, hipStream_t, const TileGeom *);                         \
     template hipError_t launch_incstate_init<T>(const Grid &, const T *, const T *, T *, double, hipStream_t);       \
     template hipError_t launch_deform_step<T>(const Grid &, const T *, const T *, T *, hipStream_t);
 
