@@ -125,8 +125,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 is the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic", type=str, default=None,
-                    help="JSON file with rocprof FETCH_SIZE/WRITE_SIZE bytes per launch of the dominant kernel")
+    ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
+                    help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
+                         "used only if it was taken on the current kernel sources")
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy"], default="solve",
+                    help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
+                         "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
+                         "calibration of the byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
@@ -139,8 +144,26 @@ def main():
 
     reg.lib()
     torch.cuda.set_device(0)
-    log("[bench] warming up with a 64^3 solve")
-    warm_small(reg, torch)
+    if args.mode == "copy":
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
+    if args.mode == "kernels":
+        ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
+        v = (0.5 * v_true).contiguous()
+        g, J, mis, gn = ctx.reg_gradient(v)
+        for _ in range(3):
+            ctx.reg_hessian_matvec(g)
+        torch.cuda.synchronize()
+        print(json.dumps({"mode": "kernels", "n": args.n, "J": J, "mismatch": mis}))
+        return
+    if args.warmup > 0:
+        log("[bench] warming up with a 64^3 solve")
+        warm_small(reg, torch)
     log(f"[bench] building the {args.n}^3 workload")
     ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
     v = torch.zeros((3,) + ctx.shape, dtype=torch.float64, device="cuda")
@@ -179,9 +202,11 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     if args.traffic and os.path.exists(args.traffic):
+        from paper_1608_03630_amd.profiling import source_hash
+
         with open(args.traffic) as f:
             t = json.load(f)
-        if t.get("kernel_family") == dom and t.get("n") == args.n:
+        if t.get("kernel_family") == dom and t.get("n") == args.n and t.get("source_sha") == source_hash():
             traffic = t.get("bytes_per_launch")
     interp_n, interp_ms = prof["interp"]
     gpts = N / (interp_ms / interp_n * 1e-3) / 1e9 if interp_n else None

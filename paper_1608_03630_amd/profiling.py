@@ -1,0 +1,102 @@
+"""Summaries of rocprofv3 output for the library's kernels.
+
+Turns the CSV files of
+
+    rocprofv3 --kernel-trace --stats --output-format csv -d DIR/solve -o run -- python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/fetch -o run -- python3 bench.py --mode kernels
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/write -o run -- python3 bench.py --mode kernels
+    rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/cfetch -o run -- python3 bench.py --mode copy
+    rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/cwrite -o run -- python3 bench.py --mode copy
+
+into a short markdown summary and a traffic record (bytes per launch of the
+dominant kernel, byte counters scaled by what they read for a copy of known
+size). The record carries a hash of the kernel sources so that a benchmark can
+tell when the counters no longer describe the kernel it runs.
+
+    python -m paper_1608_03630_amd.profiling DIR OUT.md TRAFFIC.json KERNEL_SUBSTRING GRID_SIZE FAMILY N
+"""
+import collections
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/interp.hip", "csrc/common.hpp"]
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _rows(path):
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def counter_per_dispatch(path, name_sub, grid_size=None):
+    vals = collections.defaultdict(list)
+    for r in _rows(path):
+        if name_sub in r["Kernel_Name"] and (grid_size is None or r["Grid_Size"] == str(grid_size)):
+            vals[r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+
+def trace_average_ns(path, name_sub, grid_size=None):
+    d = []
+    for r in _rows(path):
+        gsz = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        if name_sub in r["Kernel_Name"] and (grid_size is None or gsz == grid_size):
+            d.append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    return (sum(d) / len(d), len(d)) if d else (None, 0)
+
+
+def summarize(pdir, out_md, out_json, kernel_sub, grid_size, family, n, copy_bytes=256 * 1024 * 1024):
+    stats = _rows(os.path.join(pdir, "solve", "run_kernel_stats.csv"))
+    avg_ns, count = trace_average_ns(os.path.join(pdir, "solve", "run_kernel_trace.csv"), kernel_sub, grid_size)
+    fetch, _ = counter_per_dispatch(os.path.join(pdir, "fetch", "run_counter_collection.csv"), kernel_sub, grid_size)
+    write, _ = counter_per_dispatch(os.path.join(pdir, "write", "run_counter_collection.csv"), kernel_sub, grid_size)
+    cf, _ = counter_per_dispatch(os.path.join(pdir, "cfetch", "run_counter_collection.csv"), "copyBuffer")
+    cw, _ = counter_per_dispatch(os.path.join(pdir, "cwrite", "run_counter_collection.csv"), "copyBuffer")
+    fetch_scale = (copy_bytes / 1024.0) / cf["FETCH_SIZE"]
+    write_scale = (copy_bytes / 1024.0) / cw["WRITE_SIZE"]
+    rd = fetch["FETCH_SIZE"] * 1024.0 * fetch_scale
+    wr = write["WRITE_SIZE"] * 1024.0 * write_scale
+    rec = {
+        "kernel": kernel_sub, "kernel_family": family, "n": n, "grid_size": grid_size,
+        "bytes_read_per_launch": rd, "bytes_written_per_launch": wr, "bytes_per_launch": rd + wr,
+        "fetch_scale": fetch_scale, "write_scale": write_scale,
+        "trace_avg_ms": avg_ns / 1e6 if avg_ns else None, "trace_launches": count,
+        "source_sha": source_hash(),
+    }
+    with open(out_json, "w") as f:
+        json.dump(rec, f, indent=1)
+    lines = [f"# rocprofv3 summary: {family} kernel at {n}^3", ""]
+    lines += ["Commands (from the repository root; `DIR` is the output folder):", "", "```"]
+    lines += [l.strip() for l in __doc__.splitlines() if l.strip().startswith("rocprofv3")]
+    lines += ["```", "", f"Dominant kernel `{kernel_sub}` (grid size {grid_size}): {count} dispatches in the solve "
+              f"trace, average {avg_ns / 1e6:.4f} ms." if avg_ns else "", ""]
+    lines += [f"Byte counters per dispatch: FETCH_SIZE {fetch['FETCH_SIZE']:.0f} KiB, WRITE_SIZE "
+              f"{write['WRITE_SIZE']:.0f} KiB. A {copy_bytes // 2**20} MiB copy reads FETCH_SIZE "
+              f"{cf['FETCH_SIZE']:.0f} KiB and WRITE_SIZE {cw['WRITE_SIZE']:.0f} KiB, so the scale factors are "
+              f"{fetch_scale:.3f} (fetch) and {write_scale:.3f} (write): {rd / 1e6:.1f} MB read + {wr / 1e6:.1f} MB "
+              f"written per launch.", ""]
+    lines += ["Top kernels of the solve (`--stats`):", "", "| kernel | calls | total ms | avg us | % |", "|---|---|---|---|---|"]
+    for r in stats[:14]:
+        name = r["Name"].replace("regk::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+        lines.append(f"| `{name}` | {r['Calls']} | {int(r['TotalDurationNs']) / 1e6:.1f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.1f} |")
+    lines += ["", f"Kernel source hash: `{rec['source_sha']}`.", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+    return rec
+
+
+if __name__ == "__main__":
+    a = sys.argv[1:]
+    print(json.dumps(summarize(a[0], a[1], a[2], a[3], int(a[4]), a[5], int(a[6])), indent=1))
