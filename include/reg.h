@@ -97,6 +97,8 @@ typedef struct {
     int32_t pcg_iters[REG_MAXIT], ls_trials[REG_MAXIT];
     double final_J, final_mismatch, final_grel;
     double seconds_total;  /* host wall clock of the solve                         */
+    /* wall clock of the executor rounds in which this problem ran a matvec,
+     * a gradient, an objective, or only PCG vector work and preconditioning */
     double seconds_matvec, seconds_gradient, seconds_objective, seconds_precond;
     int64_t interps;       /* scalar field interpolations of n0*n1*n2 points       */
 } reg_report;
@@ -156,6 +158,14 @@ reg_status reg_div(reg_ctx *ctx, const void *w, void *d);
  * ncomp is 1 or 3 (op 3 needs 3). out may alias x. */
 reg_status reg_spectral(reg_ctx *ctx, int op, double scale, int ncomp, const void *x, void *out);
 
+/* Spectral resampling of field-type data between the grids of two contexts
+ * of the same precision (Fourier truncation from a finer grid or zero
+ * padding to a coarser-to-finer one; the Nyquist planes of the smaller grid
+ * are dropped; coefficients scaled by N_dst/N_src). Used for the multilevel
+ * warm start. Work is enqueued on src's stream and uses both contexts'
+ * spectral scratch. */
+reg_status reg_resample(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out);
+
 /* Spectral preconditioner of section III-A: z^ = r^/(beta |k|^4) for k != 0,
  * z^_0 = r^_0, followed by P when isochoric (double precision throughout).
  * z may alias r. */
@@ -204,6 +214,83 @@ reg_status reg_deformation(reg_ctx *ctx, const void *v, void *u_or_null, double 
  * (h1 h2 h3 weights). */
 reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double *out);
 
+/* ------------------------------------------------------------- batches */
+
+/* A batch is a set of independent registration problems, each with its own
+ * parameters and grid (mixed sizes allowed, one precision for all), solved
+ * together on one stream. The work of all problems advances in rounds: every
+ * semi-Lagrangian time step of all problems of a round goes out as one
+ * persistent launch over a work list of (problem, tile) items -- for single
+ * precision problems whose grids are whole 8x8x64 tiles and whose departure
+ * points stay within the canonical LDS box; the others use the
+ * single-problem launchers in the same round -- with the launch shape
+ * (workgroup count, XCD dealing) chosen by an autotuner that times the
+ * candidates on the first launch of each (step kind, box span, set of grid
+ * sizes) and keeps the choice for the process. Hessian matvecs are replayed
+ * from a captured HIP graph once the same problems repeat them with
+ * unchanged plans. A problem's results are those of the single-problem entry
+ * points on its own context (same kernels, same arguments). Problems are
+ * independent (no communication); this is the data-parallel mode across
+ * many image pairs. */
+typedef struct reg_batch reg_batch;
+
+/* Workspace bytes of a batch of npairs problems (per_pair[i] as for
+ * reg_workspace_size; every prec equal). */
+reg_status reg_batch_workspace_size(const reg_params *per_pair, int32_t npairs, size_t *bytes);
+
+/* Creates the batch and one context per problem over a caller-owned device
+ * workspace (256-byte aligned, reg_batch_workspace_size bytes). hip_stream
+ * is the stream of all work; NULL makes the batch create a blocking stream
+ * of its own (graphs cannot be captured on the null stream). Set each
+ * problem's images through reg_batch_ctx + reg_set_images. */
+reg_status reg_batch_create(const reg_params *per_pair, int32_t npairs, void *workspace, size_t bytes,
+                            void *hip_stream, reg_batch **out);
+
+/* Frees the batch and its contexts (not the workspace). */
+reg_status reg_batch_destroy(reg_batch *b);
+
+/* Message of the last failing batch call ("" if none). */
+const char *reg_batch_last_error(const reg_batch *b);
+
+/* The context of problem `pair` (owned by the batch; valid until
+ * reg_batch_destroy). Every single-problem entry point works on it. */
+reg_status reg_batch_ctx(reg_batch *b, int32_t pair, reg_ctx **ctx);
+
+/* Launch configuration of the batched step kernel: blocks = 0 autotunes,
+ * blocks >= 8 fixes the workgroup count; chunked = 1 deals the work list to
+ * the 8 XCDs in contiguous chunks, 0 round-robin; use_graph = 0 runs every
+ * matvec eagerly. Results do not depend on these settings. */
+reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, int32_t use_graph);
+
+/* Workgroups, dealing and tuned time (ms, 0 if fixed) of the last batched
+ * launch of a step kind: mode 0 interpolation/state, 1 adjoint,
+ * 2 incremental state. */
+reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, double *ms);
+
+/* Counters: batched step launches, graph captures, graph replays. */
+reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *graph_captures, int64_t *graph_replays);
+
+/* reg_profile / reg_profile_read over the batch: the batched launches and
+ * graph replays plus every problem's own launches. */
+reg_status reg_batch_profile(reg_batch *b, int enable);
+reg_status reg_batch_profile_read(reg_batch *b, int kind, int64_t *launches, double *ms);
+
+/* Batched forms of reg_transport_forward, reg_gradient and
+ * reg_hessian_matvec: array element i is problem i's argument (device
+ * pointers; scalars in host arrays of npairs entries, which may be NULL for
+ * J, mismatch, gnorm). Each synchronises the batch's stream. */
+reg_status reg_batch_transport_forward(reg_batch *b, const void *const *v, const void *const *rho0, void *const *rho1);
+reg_status reg_batch_gradient(reg_batch *b, const void *const *v, void *const *g, double *J, double *mismatch,
+                              double *gnorm);
+reg_status reg_batch_hessian_matvec(reg_batch *b, const void *const *vt, void *const *Hvt);
+
+/* reg_solve for every problem of the batch (section III-A per problem):
+ * v_inout[i] is problem i's initial velocity and result, reports[i] its
+ * report (an array of npairs). Returns REG_OK when every problem returned
+ * REG_OK, else the first failing problem's status (see reports[i].status;
+ * the other problems still ran to completion). Synchronises. */
+reg_status reg_batch_solve(reg_batch *b, void *const *v_inout, reg_report *reports);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel families timed by the profiler. */
@@ -218,7 +305,8 @@ typedef enum {
     REG_K_SYMBOL = 7,     /* pointwise spectral symbols                                              */
     REG_K_REDUCE = 8,     /* double-precision reductions                                             */
     REG_K_VECTOR = 9,     /* vector updates and copies                                               */
-    REG_K_COUNT = 10
+    REG_K_GRAPH = 10,     /* replays of a batch's captured Hessian-matvec graph (whole graph)         */
+    REG_K_COUNT = 11
 } reg_kernel_kind;
 
 /* enable = 1 clears the counters and starts timing every kernel launch of

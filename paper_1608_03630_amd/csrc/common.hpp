@@ -47,6 +47,31 @@ template <typename T>
 hipError_t launch_floor_bounds(const Grid &g, const T *D, double *partials, int nblocks, hipStream_t s);
 hipError_t launch_finalize_bounds(const double *partials, int nblocks, double *out6, hipStream_t s);
 
+// One pair's operands of a batched transport step (single precision): the
+// gathered field f, displacements D, mode operands, output, and the first
+// work item of its tiles in the batch's work list.
+struct PairStep {
+    Grid g;
+    TileGeom tg;
+    const void *f, *D, *gam, *grad, *vt;
+    void *out;
+    double cs;
+    int last;
+    int tile0;
+};
+enum { STEP_INTERP = 0, STEP_ADJOINT = 1, STEP_INCSTATE = 2 };
+// The single-grid launchers use the canonical LDS kernel (and the batched
+// kernel may take the grid) when the grid is whole tiles and the box span is
+// at most 2, in single precision.
+bool batchable(const Grid &g, const TileGeom &tg, int max_span);
+int batch_span(const TileGeom &tg);
+int tiles_of(const Grid &g);
+// One persistent launch of nblocks workgroups (>= 8) over all pairs' tiles
+// (float; pairs_dev sorted by tile0, total = sum of the pairs' tiles; span is
+// the largest box span of the pairs, 0..2).
+hipError_t launch_batched_step(int mode, int span, const PairStep *pairs_dev, int npairs, int total, int nblocks,
+                               int chunked, hipStream_t s);
+
 // Every launcher enqueues on `s` and returns the hipError_t of the launch. A
 // non-null TileGeom selects the LDS-staged gather for displacements D whose
 // floor bounds it was built from; null selects the direct gather.
@@ -109,6 +134,10 @@ enum SymbolOp {
 };
 template <typename T>
 hipError_t spec_symbol(const SpecCtx &c, int op, double a, int ncomp, int leray, hipStream_t s);
+// H of dst (first ncomp components) = resampled H of src (Fourier truncation
+// or zero padding, scaled by Nd/Ns)
+template <typename T>
+hipError_t spec_resample(const SpecCtx &src, const SpecCtx &dst, int ncomp, hipStream_t s);
 // partial sums over blocks of sum_k w(k3) |k|^4 |H_c|^2, c < 3 -> partials (double)
 template <typename T>
 hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s);

@@ -1,0 +1,510 @@
+// Internal state of a registration context and the host-side building
+// blocks shared by the operator entry points (capi.hip) and the
+// Gauss-Newton-Krylov driver and its batched executor (solver.hip). Host code
+// only orchestrates: every grid-sized operation runs in the kernels of
+// interp.hip, fft.hip and blas.hip; the host reads back double-precision
+// scalars (inner products, objective, norms) where the Newton-Krylov
+// iteration branches on them.
+//
+// Precision: image-space fields (images, state and adjoint histories, grad
+// rho, departure points, b) use the field type T of params.prec; the
+// velocity-space vectors (v, g, the PCG vectors) are always double and the 3D
+// spectral operators that act on them (lap^2, its inverse, P, the gradient
+// and matvec assembly) run in double. The H2 regulariser multiplies the
+// representation error of v by |k|^4 (up to (n sqrt(3)/2)^4, about 2.4e9 on
+// a 256^3 grid), which single precision cannot absorb; the transport, whose
+// data are smooth images, runs in T.
+#pragma once
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/reg.h"
+#include "common.hpp"
+
+using regk::Grid;
+
+namespace regc {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr size_t kAlign = 256;
+constexpr int kSlots = 32;  // device result slots (doubles)
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+inline bool fft_friendly(int n) {
+    if (n < 8 || n > 1024 || (n & 1)) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+// Carves the workspace: every view is kAlign-aligned. With base == nullptr it
+// only measures.
+struct Layout {
+    char *base;
+    size_t off = 0;
+    explicit Layout(char *b) : base(b) {}
+    void *take(size_t bytes) {
+        void *p = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return p;
+    }
+};
+
+// Times launches with event pairs on one stream; the pairs are resolved into
+// per-kind totals after the stream has been synchronised.
+struct Profiler {
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;
+    };
+    hipStream_t stream = nullptr;
+    bool on = false;
+    std::vector<hipEvent_t> free_;
+    std::vector<Rec> pending;
+    double ms[REG_K_COUNT] = {0};
+    int64_t n[REG_K_COUNT] = {0};
+
+    void resolve() {
+        for (auto &r : pending) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+                ms[r.kind] += t;
+                n[r.kind] += 1;
+            } else {
+                (void)hipGetLastError();
+            }
+            free_.push_back(r.a);
+            free_.push_back(r.b);
+        }
+        pending.clear();
+    }
+    hipEvent_t take() {
+        if (free_.empty()) {
+            hipEvent_t e = nullptr;
+            if (hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+            return e;
+        }
+        hipEvent_t e = free_.back();
+        free_.pop_back();
+        return e;
+    }
+    void reset() {
+        for (int k = 0; k < REG_K_COUNT; k++) {
+            ms[k] = 0;
+            n[k] = 0;
+        }
+    }
+    void release() {
+        resolve();
+        for (hipEvent_t e : free_) (void)hipEventDestroy(e);
+        free_.clear();
+    }
+};
+
+}  // namespace regc
+
+#define DISPATCH(ctx, fn, ...) ((ctx)->P.prec ? fn<double>(__VA_ARGS__) : fn<float>(__VA_ARGS__))
+
+#define CTX_OK(ctx)                                   \
+    do {                                              \
+        if (!(ctx)) return REG_EINVAL;                \
+        (ctx)->err.clear();                           \
+    } while (0)
+
+struct reg_ctx {
+    reg_params P;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Grid g{};
+    regk::SpecCtx spec{};
+    size_t esz = 4;
+    long N = 0, Nh = 0;
+    double beta = 0;
+
+    // workspace views
+    void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec;
+    void *lamh;        // adjoint levels lam^0..lam^nt
+    void *gam, *gam2;  // Heun factor of the adjoint source (cached plan, scratch plan)
+    void *vf, *vtf;                                            // velocity copies in the field type
+    void *vcur, *g_, *sdir, *r, *z, *p, *q, *vtrial;          // velocity space, double
+    void *u0, *u1, *du, *H;
+    void *tw32[3], *tw64[3];
+    double *dpart, *dpart2, *dres;
+    double *hres = nullptr;  // pinned host mirror of dres
+
+    regc::Profiler prof;  // event pairs around launches (reg_profile)
+
+    // tile geometry of the LDS-staged gathers, per displacement buffer
+    struct PlanGeom {
+        const void *D = nullptr;
+        bool tiled = false;
+        regk::TileGeom tg{};
+    };
+    PlanGeom geoms[6];
+
+    bool have_images = false;
+    bool have_state = false;  // plans, history, grad rho and div v at vcur
+    double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
+    long interps = 0;
+    int64_t epoch = 0;  // bumped whenever a plan (departure points, tile geometry) changes
+    std::string err;
+};
+
+namespace regc {
+
+inline reg_status fail(reg_ctx *ctx, reg_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+inline reg_status hipfail(reg_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, REG_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, expr)                                         \
+    do {                                                          \
+        hipError_t e_ = (expr);                                   \
+        if (e_ != hipSuccess) return hipfail((ctx), e_, #expr);  \
+    } while (0)
+
+// Runs one launcher; with profiling on, brackets it with two events.
+template <class F>
+hipError_t timed(Profiler &pr, int kind, F &&launch) {
+    if (!pr.on) return launch();
+    if (pr.pending.size() >= 8192) {
+        hipError_t e = hipStreamSynchronize(pr.stream);
+        if (e != hipSuccess) return e;
+        pr.resolve();
+    }
+    hipEvent_t a = pr.take(), b = pr.take();
+    if (!a || !b) return launch();
+    hipError_t e = hipEventRecord(a, pr.stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, pr.stream);
+    if (e != hipSuccess) return e;
+    pr.pending.push_back({a, b, kind});
+    return hipSuccess;
+}
+
+#define KL(ctx, kind, expr) timed((ctx)->prof, (kind), [&]() { return (expr); })
+
+
+#define STCHK(expr)                     \
+    do {                                \
+        reg_status s_ = (expr);         \
+        if (s_ != REG_OK) return s_;    \
+    } while (0)
+
+inline reg_status check_params(const reg_params *p, std::string *why) {
+    if (!p) {
+        *why = "params is NULL";
+        return REG_EINVAL;
+    }
+    for (int j = 0; j < 3; j++)
+        if (!fft_friendly(p->n[j])) {
+            *why = "grid size n[" + std::to_string(j) + "] = " + std::to_string(p->n[j]) +
+                   " must be even, 2^a 3^b and in [8, 1024]";
+            return REG_EINVAL;
+        }
+    if (p->nt < 1 || p->nt > 4096) {
+        *why = "nt must be in [1, 4096]";
+        return REG_EINVAL;
+    }
+    if (!(p->beta > 0) || !std::isfinite(p->beta)) {
+        *why = "beta must be positive and finite";
+        return REG_EINVAL;
+    }
+    if (p->prec != 0 && p->prec != 1) {
+        *why = "prec must be 0 (float) or 1 (double)";
+        return REG_EINVAL;
+    }
+    if (p->max_newton < 0 || p->max_pcg < 1 || p->max_ls < 0) {
+        *why = "max_newton >= 0, max_pcg >= 1 and max_ls >= 0 are required";
+        return REG_EINVAL;
+    }
+    if (!(p->gtol >= 0) || !(p->mismatch_tol >= 0)) {
+        *why = "gtol and mismatch_tol must be >= 0";
+        return REG_EINVAL;
+    }
+    return REG_OK;
+}
+
+// Lays out the workspace of a context (ctx == nullptr: size only).
+inline size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
+    const size_t E = p->prec ? 8 : 4;
+    const long N = (long)p->n[0] * p->n[1] * p->n[2];
+    const long Nh = (long)p->n[0] * p->n[1] * (p->n[2] / 2 + 1);
+    const long nt1 = p->nt + 1;
+    Layout L(base);
+    reg_ctx tmp;
+    reg_ctx *c = ctx ? ctx : &tmp;
+    c->rhoT = L.take(E * N);
+    c->rhoR = L.take(E * N);
+    c->histA = L.take(E * N * nt1);
+    c->histB = L.take(E * N * nt1);
+    c->grho = L.take(E * 3 * N * nt1);
+    c->Df = L.take(E * 3 * N);
+    c->Da = L.take(E * 3 * N);
+    c->Dt = L.take(E * 3 * N);
+    c->c = L.take(E * N);
+    c->cX = L.take(E * N);
+    c->c2 = L.take(E * N);
+    c->cX2 = L.take(E * N);
+    c->lam[0] = L.take(E * N);
+    c->lam[1] = L.take(E * N);
+    c->lamh = L.take(E * N * nt1);
+    c->gam = L.take(E * N);
+    c->gam2 = L.take(E * N);
+    c->bvec = L.take(E * 3 * N);
+    c->vf = L.take(E * 3 * N);
+    c->vtf = L.take(E * 3 * N);
+    const size_t D8 = sizeof(double);
+    c->vcur = L.take(D8 * 3 * N);
+    c->g_ = L.take(D8 * 3 * N);
+    c->sdir = L.take(D8 * 3 * N);
+    c->r = L.take(D8 * 3 * N);
+    c->z = L.take(D8 * 3 * N);
+    c->p = L.take(D8 * 3 * N);
+    c->q = L.take(D8 * 3 * N);
+    c->vtrial = L.take(D8 * 3 * N);
+    c->u0 = L.take(E * 3 * N);
+    c->u1 = L.take(E * 3 * N);
+    c->du = L.take(E * 9 * N);
+    c->H = L.take(2 * D8 * 6 * Nh);
+    for (int j = 0; j < 3; j++) {
+        c->tw32[j] = L.take(2 * sizeof(float) * p->n[j]);
+        c->tw64[j] = L.take(2 * D8 * p->n[j]);
+    }
+    c->dpart = (double *)L.take(sizeof(double) * regk::RED_BLOCKS);
+    c->dpart2 = (double *)L.take(sizeof(double) * regk::RED_BLOCKS);
+    c->dres = (double *)L.take(sizeof(double) * kSlots);
+    return L.off;
+}
+
+inline bool is_device_ptr(const void *ptr) {
+    if (!ptr) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+#define NEED_DEV(ctx, ptr)                                                                   \
+    do {                                                                                     \
+        if (!is_device_ptr(ptr)) return fail((ctx), REG_EINVAL, #ptr " is not a device pointer"); \
+    } while (0)
+
+// ------------------------------------------------------------ typed helpers
+
+template <typename T> T *V(void *p) { return static_cast<T *>(p); }
+template <typename T> const T *CV(const void *p) { return static_cast<const T *>(p); }
+
+inline double h3(const reg_ctx *c) { return (kTwoPi / c->g.n1) * (kTwoPi / c->g.n2) * (kTwoPi / c->g.n3); }
+
+inline const regk::TileGeom *geom_of(const reg_ctx *ctx, const void *D) {
+    for (const auto &g : ctx->geoms)
+        if (g.D == D) return g.tiled ? &g.tg : nullptr;
+    return nullptr;
+}
+
+inline void set_geom(reg_ctx *ctx, const void *D, bool tiled, const regk::TileGeom &tg) {
+    for (auto &g : ctx->geoms)
+        if (g.D == D) {
+            g.tiled = tiled;
+            g.tg = tg;
+            return;
+        }
+    for (auto &g : ctx->geoms)
+        if (g.D == nullptr) {
+            g.D = D;
+            g.tiled = tiled;
+            g.tg = tg;
+            return;
+        }
+    ctx->geoms[0].D = D;  // table full: reuse a slot
+    ctx->geoms[0].tiled = tiled;
+    ctx->geoms[0].tg = tg;
+}
+
+// velocity (double) -> field type copy
+template <typename T>
+hipError_t to_field(reg_ctx *ctx, const void *src, void *dst, long n) {
+    if (sizeof(T) == sizeof(double))
+        return regk::launch_copy<double>(n, CV<double>(src), V<double>(dst), ctx->stream);
+    return regk::launch_convert<double, float>(n, CV<double>(src), V<float>(dst), ctx->stream);
+}
+
+// reads kSlots doubles back (synchronises)
+inline reg_status fetch(reg_ctx *ctx, int nslots) {
+    HIPCHK(ctx, hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    if (!ctx->prof.pending.empty()) ctx->prof.resolve();
+    return REG_OK;
+}
+
+// dres[slot] = scale * reduction
+template <typename T>
+reg_status reduce(reg_ctx *ctx, const void *a, const void *b, long n, int mode, double scale, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_dot_partials<T>(CV<T>(a), CV<T>(b ? b : a), n, mode, ctx->dpart, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream)));
+    return REG_OK;
+}
+
+// Device result slots: 0 inner products, 1 mismatch numerator, 2 regulariser,
+// 3 |g|^2, 4 a second inner product, 8..13 and 16..21 the floor bounds of two
+// plans measured together.
+constexpr int kSlotPlanA = 8, kSlotPlanB = 16;
+
+// floor bounds of D over the grid into dres[slot..slot+5] (partials in `part`)
+template <typename T>
+reg_status bounds_enqueue(reg_ctx *ctx, const void *D, double *part, int slot) {
+    const int nb = regk::RED_BLOCKS / 6;
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_floor_bounds<T>(ctx->g, CV<T>(D), part, nb, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_bounds(part, nb, ctx->dres + slot, ctx->stream)));
+    return REG_OK;
+}
+
+// tile geometry of the gathers that use D, from bounds already in hres
+inline void plan_finish(reg_ctx *ctx, const void *D, int slot) {
+    double fmin[3], fmax[3];
+    for (int j = 0; j < 3; j++) {
+        fmin[j] = ctx->hres[slot + 2 * j];
+        fmax[j] = ctx->hres[slot + 2 * j + 1];
+    }
+    regk::TileGeom tg{};
+    const bool ok = regk::tile_geom(fmin, fmax, ctx->esz, &tg);
+    set_geom(ctx, D, ok, tg);
+    ctx->epoch++;
+}
+
+// departure points D of the field-type velocity vf (RK2 backtrace, sign +1
+// forward in t, -1 for the adjoint) and their floor bounds
+template <typename T>
+reg_status plan_enqueue(reg_ctx *ctx, const void *vf, double sign, void *D, double *part, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_BACKTRACE, regk::launch_backtrace<T>(ctx->g, CV<T>(vf), sign / ctx->P.nt, V<T>(D), ctx->stream)));
+    ctx->interps += 3;
+    return bounds_enqueue<T>(ctx, D, part, slot);
+}
+
+// bounds of D and its geometry (synchronises)
+template <typename T>
+reg_status measure_plan(reg_ctx *ctx, const void *D) {
+    STCHK(bounds_enqueue<T>(ctx, D, ctx->dpart, kSlotPlanA));
+    STCHK(fetch(ctx, kSlotPlanA + 6));
+    plan_finish(ctx, D, kSlotPlanA);
+    return REG_OK;
+}
+
+// departure points from vf (field type), with geometry (synchronises)
+template <typename T>
+reg_status plan(reg_ctx *ctx, const void *vf, double sign, void *D) {
+    STCHK(plan_enqueue<T>(ctx, vf, sign, D, ctx->dpart, kSlotPlanA));
+    STCHK(fetch(ctx, kSlotPlanA + 6));
+    plan_finish(ctx, D, kSlotPlanA);
+    return REG_OK;
+}
+
+// public backtrace: v is a velocity-space double vector
+template <typename T>
+reg_status backtrace_impl(reg_ctx *ctx, const void *v, double sign, void *D) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * ctx->N)));
+    return plan<T>(ctx, ctx->vf, sign, D);
+}
+
+template <typename T>
+reg_status divergence(reg_ctx *ctx, const void *v, void *d) {
+    const long N = ctx->N;
+    for (int j = 0; j < 3; j++)
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(v) + j * N, N, V<T>(d), N, j > 0, 1, ctx->stream)));
+    return REG_OK;
+}
+
+// grad of nf scalar fields u + k*N into out + k*3N
+template <typename T>
+reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
+    const long N = ctx->N;
+    for (int j = 0; j < 3; j++)
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream)));
+    return REG_OK;
+}
+
+// out = IFFT(beta |k|^4 x^ + [P] y^); also leaves sum w |k|^4 |x^|^2 partials
+// in dpart2 when want_reg
+// (x and out are velocity-space doubles, y is a field-type vector; the
+// transforms run in double)
+template <typename T>
+reg_status assemble(reg_ctx *ctx, const void *x, const void *y, void *out, bool want_reg) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(x), 3, 0, ctx->stream))));
+    if (want_reg) HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<T, double>(ctx->spec, CV<T>(y), 3, 3, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_ASSEMBLE, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(out), 3, ctx->stream))));
+    return REG_OK;
+}
+
+// the regulariser 1/2 beta ||lap v||^2 from biharmonic partials in dpart2
+inline reg_status reg_term_to_slot(reg_ctx *ctx, int slot) {
+    const double N = (double)ctx->N;
+    const double scale = 0.5 * ctx->beta * kTwoPi * kTwoPi * kTwoPi / (N * N);
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart2, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream)));
+    return REG_OK;
+}
+
+// v is a velocity-space double vector
+inline reg_status regulariser_of(reg_ctx *ctx, const void *v, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
+    return reg_term_to_slot(ctx, slot);
+}
+
+// mismatch^2 numerator (slot 1) and regulariser (slot 2) of the history in
+// hist at v
+template <typename T>
+reg_status objective_slots(reg_ctx *ctx, const void *hist, const void *v, bool reg_done) {
+    const long N = ctx->N;
+    STCHK(reduce<T>(ctx, V<T>(const_cast<void *>(hist)) + (long)ctx->P.nt * N, ctx->rhoR, N, 1, h3(ctx), 1));
+    if (!reg_done) STCHK(regulariser_of(ctx, v, 2));
+    else STCHK(reg_term_to_slot(ctx, 2));
+    return REG_OK;
+}
+
+inline void scalars_to_J(reg_ctx *ctx, double *J, double *mis) {
+    const double dd = ctx->hres[1];
+    if (J) *J = 0.5 * dd + ctx->hres[2];
+    if (mis) *mis = ctx->normTR2 > 0 ? std::sqrt(dd / ctx->normTR2) : 0.0;
+}
+
+// r and z are velocity-space doubles
+inline reg_status precond_impl(reg_ctx *ctx, const void *r, void *z) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(r), 3, 0, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_PRECOND, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(z), 3, ctx->stream))));
+    return REG_OK;
+}
+
+// inner product of two velocity-space vectors
+inline reg_status dot3(reg_ctx *ctx, const void *a, const void *b, double *out) {
+    STCHK(reduce<double>(ctx, a, b, 3 * ctx->N, 0, h3(ctx), 0));
+    STCHK(fetch(ctx, 1));
+    *out = ctx->hres[0];
+    return REG_OK;
+}
+
+using clk = std::chrono::steady_clock;
+inline double secs(clk::time_point a) { return std::chrono::duration<double>(clk::now() - a).count(); }
+
+
+}  // namespace regc

@@ -657,7 +657,53 @@ hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nbl
     return hipGetLastError();
 }
 
+// Spectral resampling between grids: destination mode (q1, q2, q3) takes the
+// source mode of the same wavenumber, scaled by Nd/Ns, when |k_j| <
+// min(ns_j, nd_j)/2 on every axis (the Nyquist planes of the smaller grid are
+// dropped), and 0 otherwise.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_resample(Grid gs, Grid gd, const cplx_t<T> *__restrict__ Hs,
+                                                       cplx_t<T> *__restrict__ Hd, int ncomp, T scale) {
+    using C = cplx_t<T>;
+    const long q = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= gd.Nh()) return;
+    const int nhd = gd.n3h(), nhs = gs.n3h();
+    const int q3 = (int)(q % nhd);
+    const long r = q / nhd;
+    const int q2 = (int)(r % gd.n2), q1 = (int)(r / gd.n2);
+    const int k1 = kwave(q1, gd.n1), k2 = kwave(q2, gd.n2), k3 = q3;
+    const bool keep = 2 * abs(k1) < min(gs.n1, gd.n1) && 2 * abs(k2) < min(gs.n2, gd.n2) &&
+                      2 * k3 < min(gs.n3, gd.n3);
+    long src = 0;
+    if (keep) {
+        const int s1 = k1 < 0 ? k1 + gs.n1 : k1, s2 = k2 < 0 ? k2 + gs.n2 : k2;
+        src = ((long)s1 * gs.n2 + s2) * nhs + k3;
+    }
+    for (int c = 0; c < ncomp; c++) {
+        C z;
+        z.x = T(0);
+        z.y = T(0);
+        if (keep) {
+            z = Hs[c * gs.Nh() + src];
+            z.x *= scale;
+            z.y *= scale;
+        }
+        Hd[c * gd.Nh() + q] = z;
+    }
+}
+
+template <typename T>
+hipError_t spec_resample(const SpecCtx &src, const SpecCtx &dst, int ncomp, hipStream_t s) {
+    using C = cplx_t<T>;
+    const unsigned nb = (unsigned)((dst.g.Nh() + kThreads - 1) / kThreads);
+    const T scale = T((double)dst.g.N() / (double)src.g.N());
+    hipLaunchKernelGGL(k_resample<T>, dim3(nb), dim3(kThreads), 0, s, src.g, dst.g,
+                       reinterpret_cast<const C *>(src.H), reinterpret_cast<C *>(dst.H), ncomp, scale);
+    return hipGetLastError();
+}
+
 #define REGK_FFT_INST(T)                                                                                           \
+    template hipError_t spec_resample<T>(const SpecCtx &, const SpecCtx &, int, hipStream_t);                     \
     template hipError_t spec_deriv<T>(const SpecCtx &, int, const T *, long, T *, long, int, int, hipStream_t);    \
     template hipError_t spec_forward<T, T>(const SpecCtx &, const T *, int, int, hipStream_t);                     \
     template hipError_t spec_inverse<T, T>(const SpecCtx &, T *, int, hipStream_t);                                \

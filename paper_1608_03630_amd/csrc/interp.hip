@@ -537,18 +537,18 @@ __device__ __forceinline__ int canon_base(int il, T d, int lo, int B, T w[4]) {
     return min(max(il + (int)flc - 1 - lo, 0), B - 4);
 }
 
+// The work of one tile t of one grid (shared by the single-grid and the
+// batched persistent kernels; `box` is the workgroup's LDS).
 template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, const T *__restrict__ f,
-                                                          const T *__restrict__ D, TileArgs args) {
+__device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, const TileIdx &t,
+                                           const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
+                                           T *box) {
     using K = Canon<S>;
-    __shared__ T box[K::elems];
-    const TileIdx t = tile_of(g);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const unsigned N = (unsigned)g.N();
     const T *__restrict__ D1 = D;
     const T *__restrict__ D2 = D + N;
     const T *__restrict__ D3 = D + 2 * (size_t)N;
-    // interior tile: every point of the tile exists
     const int i3 = t.t3 * kTile3 + lane;
     const unsigned line_stride = (unsigned)g.n3;
     const unsigned p0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3);
@@ -609,6 +609,58 @@ __global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, c
             const T v = acc + cs * sv;
             out[p] = last ? -v : v;
         }
+    }
+}
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, const T *__restrict__ f,
+                                                          const T *__restrict__ D, TileArgs args) {
+    __shared__ T box[Canon<S>::elems];
+    canon_tile<T, MODE, S>(g, tg, tile_of(g), f, D, args, box);
+}
+
+// Batched persistent variant: gridDim.x workgroups walk a work list of
+// (pair, tile) items over all pairs of a batch (pairs sorted by tile0). With
+// `chunked` the items are dealt to the XCDs in contiguous chunks, so that each
+// XCD's L2 sees neighbouring tiles of one grid; otherwise round-robin.
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
+                                                            int total, int chunked) {
+    __shared__ T box[Canon<S>::elems];
+    const int nb = gridDim.x;
+    int first = 0, end = total, stride = nb, start = blockIdx.x;
+    if (chunked) {
+        const int x = blockIdx.x % kXcds;
+        stride = nb / kXcds + (x < nb % kXcds ? 1 : 0);
+        start = blockIdx.x / kXcds;
+        const int chunk = (total + kXcds - 1) / kXcds;
+        first = x * chunk;
+        end = min(total, first + chunk);
+    }
+    for (int item = first + start; item < end; item += stride) {
+        int lo = 0, hi = npairs - 1;  // last pair with tile0 <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pairs[mid].tile0 <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        const PairStep &ps = pairs[lo];
+        const Grid g = ps.g;
+        const int b = item - ps.tile0;
+        const int nt3 = g.n3 / kTile3, nt2 = g.n2 / kTile2;
+        TileIdx t;
+        t.t3 = b % nt3;
+        t.t2 = (b / nt3) % nt2;
+        t.t1 = b / (nt3 * nt2);
+        TileArgs a;
+        a.gam = ps.gam;
+        a.grad = ps.grad;
+        a.vt = ps.vt;
+        a.out = ps.out;
+        a.cs = ps.cs;
+        a.last = ps.last;
+        canon_tile<T, MODE, S>(g, ps.tg, t, static_cast<const T *>(ps.f), static_cast<const T *>(ps.D), a, box);
+        __syncthreads();  // the next item restages the box
     }
 }
 
@@ -688,6 +740,38 @@ hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *
 }
 
 inline unsigned nblocks(long N) { return (unsigned)((N + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+bool batchable(const Grid &g, const TileGeom &tg, int max_span) {
+    return g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0 && box_span(tg) <= max_span;
+}
+
+int tiles_of(const Grid &g) { return (int)ntiles(g); }
+
+hipError_t launch_batched_step(int mode, int span, const PairStep *pairs_dev, int npairs, int total, int nblocks_grid,
+                               int chunked, hipStream_t s) {
+    // chunked dealing needs a workgroup on every XCD
+    if (npairs < 1 || total < 1 || nblocks_grid < kXcds || span < 0 || span > 2) return hipErrorInvalidValue;
+#define REGK_BATCH_LAUNCH(M, S)                                                                                    \
+    hipLaunchKernelGGL((k_batched_canon<float, M, S>), dim3(nblocks_grid), dim3(kThreads), 0, s, pairs_dev, npairs, \
+                       total, chunked)
+    if (span <= 1) {
+        if (mode == TM_INTERP) REGK_BATCH_LAUNCH(TM_INTERP, 1);
+        else if (mode == TM_ADJOINT) REGK_BATCH_LAUNCH(TM_ADJOINT, 1);
+        else REGK_BATCH_LAUNCH(TM_INCSTATE, 1);
+    } else {
+        if (mode == TM_INTERP) REGK_BATCH_LAUNCH(TM_INTERP, 2);
+        else if (mode == TM_ADJOINT) REGK_BATCH_LAUNCH(TM_ADJOINT, 2);
+        else REGK_BATCH_LAUNCH(TM_INCSTATE, 2);
+    }
+#undef REGK_BATCH_LAUNCH
+    return hipGetLastError();
+}
+
+int batch_span(const TileGeom &tg) { return box_span(tg); }
+
+namespace {
 
 }  // namespace
 

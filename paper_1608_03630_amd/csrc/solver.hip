@@ -1,0 +1,1273 @@
+// Gauss-Newton-Krylov driver of section III-A (reduced-space inexact Newton
+// with truncated PCG, the spectral preconditioner, forcing sequence, Armijo
+// backtracking and beta continuation) and the executor of its heavy
+// operations: the reduced gradient (state, adjoint, eq. (4)), the objective
+// (state) and the Gauss-Newton Hessian matvec (incremental state and
+// incremental adjoint, eqs. (5a)-(5e) without the second-order terms).
+//
+// One executor serves a single problem (reg_gradient, reg_solve, ...) and a
+// batch of independent problems of mixed sizes on one stream (reg_batch_*).
+// Every problem's solver is an explicit state machine. The executor works in
+// rounds: each active problem has queued light work (vector updates,
+// preconditioner, inner products) and at most one heavy request; the round
+// issues all heavy requests -- in a batch every semi-Lagrangian time step of
+// all problems goes out as ONE persistent launch over a (problem, tile) work
+// list -- then synchronises the stream once, and every problem reads its
+// double-precision scalars and advances to its next request. In a batch the
+// Hessian matvecs of a round are replayed from a captured HIP graph when the
+// same set of problems repeats them. Per problem, the kernels and their
+// arguments are those of the single-problem path, so a problem's result does
+// not depend on the batch it runs in.
+#include <algorithm>
+#include <functional>
+#include <map>
+#include <mutex>
+
+#include "ctx.hpp"
+
+using namespace regc;
+
+namespace {
+
+enum class Op { NONE, GRADIENT, OBJECTIVE, MATVEC, FORWARD };
+
+// A heavy operation of one problem.
+struct Request {
+    Op op = Op::NONE;
+    const void *x = nullptr;    // v (GRADIENT, OBJECTIVE, FORWARD) or vt (MATVEC), velocity space
+    void *y = nullptr;          // g (GRADIENT), Hvt (MATVEC), rho1 (FORWARD)
+    const void *aux = nullptr;  // rho0 (FORWARD)
+    bool reuse = false;         // GRADIENT: histB and Dt already hold the plan and state of x
+    bool dot = false;           // MATVEC: <vt, Hvt> into result slot 0
+};
+
+struct Item {
+    reg_ctx *ctx;
+    Request req;
+};
+
+int slots_of(const Request &r) {
+    switch (r.op) {
+    case Op::GRADIENT: return 4;
+    case Op::OBJECTIVE: return 3;
+    case Op::MATVEC: return r.dot ? 1 : 0;
+    default: return 0;
+    }
+}
+
+// ------------------------------------------------------------- autotuner
+// Launch shape of the batched step kernel (workgroup count and XCD dealing)
+// per (mode, box span, set of grid sizes), measured on first use and kept for
+// the process.
+struct TuneEntry {
+    int blocks = 0;
+    int chunked = 1;
+    double ms = 0;
+};
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+
+}  // namespace
+
+// --------------------------------------------------------------- the batch
+struct reg_batch {
+    int npairs = 0;
+    int prec = 0;
+    int nt_max = 0;
+    std::vector<reg_ctx *> ctx;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    regc::Profiler prof;
+    // device tables of PairStep: region 0 for a round's eager gradients,
+    // objectives and transports, region 1 for its eager matvecs, 2 + i for
+    // cached graph i
+    regk::PairStep *dev_tab = nullptr;
+    regk::PairStep *host_tab = nullptr;  // pinned staging, same layout
+    size_t region = 0;                   // entries per region
+    static constexpr int kGraphs = 4;
+    // launch configuration
+    int fixed_blocks = 0;  // 0: autotune
+    int fixed_chunked = 1;
+    int use_graph = 1;
+    struct GraphEntry {
+        std::vector<int64_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t used = 0;
+    };
+    GraphEntry graphs[kGraphs];
+    std::vector<int64_t> last_key;
+    uint64_t tick = 0;
+    int64_t launches = 0, captures = 0, replays = 0;
+    TuneEntry last[3];
+    std::string err;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- program
+// The GPU work of a round, built first (so that the batched step tables can
+// be uploaded in one copy) and then run, eagerly or under stream capture.
+struct Program {
+    std::vector<std::function<reg_status()>> ops;
+    std::vector<regk::PairStep> table;
+};
+
+reg_status bfail(reg_batch *b, reg_status st, const std::string &msg) {
+    if (b) b->err = msg;
+    return st;
+}
+
+int kind_of_mode(int mode) {
+    return mode == regk::STEP_INTERP ? REG_K_INTERP : mode == regk::STEP_ADJOINT ? REG_K_ADJOINT : REG_K_INCSTATE;
+}
+
+std::string tune_key(int mode, int span, const regk::PairStep *p, int n) {
+    std::vector<std::string> sizes;
+    for (int i = 0; i < n; i++)
+        sizes.push_back(std::to_string(p[i].g.n1) + "x" + std::to_string(p[i].g.n2) + "x" + std::to_string(p[i].g.n3));
+    std::sort(sizes.begin(), sizes.end());
+    std::string k = std::to_string(mode) + "/" + std::to_string(span);
+    for (auto &s : sizes) k += "/" + s;
+    return k;
+}
+
+// One batched step launch, with the launch shape from the tuner (tuning it
+// here, by timing every candidate on this very launch, when the shape is not
+// known yet and the stream is not being captured; every candidate computes
+// the same output from the same inputs).
+reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep *host, const regk::PairStep *dev,
+                          int n, int total, bool capturing) {
+    TuneEntry e;
+    bool have = false;
+    const std::string key = tune_key(mode, span, host, n);
+    if (b->fixed_blocks > 0) {
+        e.blocks = b->fixed_blocks;
+        e.chunked = b->fixed_chunked;
+        have = true;
+    } else {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            e = it->second;
+            have = true;
+        }
+    }
+    if (!have && capturing) {  // no timing under capture: a safe default
+        e.blocks = std::max(8, std::min(total, 1024));
+        e.chunked = 1;
+        have = true;
+    }
+    if (!have) {
+        std::vector<int> cand = {256, 512, 1024, 2048, 4096, total};
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+            return bfail(b, REG_EHIP, "hipEventCreate failed in the launch tuner");
+        TuneEntry best;
+        best.ms = 1e30;
+        reg_status st = REG_OK;
+        for (int chunked = 1; chunked >= 0 && st == REG_OK; chunked--) {
+            for (int c : cand) {
+                const int nb = std::max(8, std::min(c, total));
+                hipError_t he = regk::launch_batched_step(mode, span, dev, n, total, nb, chunked, b->stream);
+                if (he == hipSuccess) he = hipEventRecord(e0, b->stream);
+                if (he == hipSuccess) he = regk::launch_batched_step(mode, span, dev, n, total, nb, chunked, b->stream);
+                if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float ms = 0;
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) {
+                    st = bfail(b, REG_EHIP, std::string("launch tuner: ") + hipGetErrorString(he));
+                    break;
+                }
+                if (ms < best.ms) {
+                    best.ms = ms;
+                    best.blocks = nb;
+                    best.chunked = chunked;
+                }
+                if (c >= total) break;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != REG_OK) return st;
+        e = best;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = e;
+    }
+    hipError_t he = timed(b->prof, kind_of_mode(mode), [&]() {
+        return regk::launch_batched_step(mode, span, dev, n, total, e.blocks, e.chunked, b->stream);
+    });
+    if (he != hipSuccess) return bfail(b, REG_EHIP, std::string("batched step launch: ") + hipGetErrorString(he));
+    b->launches++;
+    b->last[mode] = e;
+    return REG_OK;
+}
+
+// Operands of one semi-Lagrangian step of one problem.
+template <typename T>
+struct StepArg {
+    reg_ctx *ctx;
+    const T *f;
+    const T *D;
+    T *out;
+    const T *gam = nullptr;
+    const T *vt = nullptr;
+    const T *grad = nullptr;
+    double cs = 0;
+    int last = 0;
+};
+
+template <typename T>
+struct Exec {
+    reg_batch *b;           // nullptr: single problems, no batched launches, no graphs
+    hipStream_t stream;
+    bool capturing = false;
+
+    Exec(reg_batch *b_, hipStream_t s) : b(b_), stream(s) {}
+
+    // queues one time step of every problem in args: a single batched launch
+    // for the problems the canonical tile kernel takes, the single-problem
+    // launchers for the rest
+    void sl_step(Program &P, int mode, const std::vector<StepArg<T>> &args, const regk::PairStep *dev_region) {
+        std::vector<regk::PairStep> items;
+        int span = 0, total = 0;
+        for (const auto &a : args) {
+            const regk::TileGeom *tg = geom_of(a.ctx, a.D);
+            const bool batch = b && sizeof(T) == 4 && tg && regk::batchable(a.ctx->g, *tg, 2);
+            if (batch) {
+                regk::PairStep ps{};
+                ps.g = a.ctx->g;
+                ps.tg = *tg;
+                ps.f = a.f;
+                ps.D = a.D;
+                ps.gam = a.gam;
+                ps.grad = a.grad;
+                ps.vt = a.vt;
+                ps.out = a.out;
+                ps.cs = a.cs;
+                ps.last = a.last;
+                ps.tile0 = total;
+                total += regk::tiles_of(a.ctx->g);
+                span = std::max(span, regk::batch_span(*tg));
+                items.push_back(ps);
+                continue;
+            }
+            const StepArg<T> c = a;
+            P.ops.push_back([c, mode, tg]() -> reg_status {
+                reg_ctx *ctx = c.ctx;
+                if (mode == regk::STEP_INTERP)
+                    HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, c.f, c.D, c.out, ctx->stream, tg)));
+                else if (mode == regk::STEP_ADJOINT)
+                    HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, c.f, c.D, c.gam, c.out, ctx->stream, tg)));
+                else
+                    HIPCHK(ctx, KL(ctx, REG_K_INCSTATE, regk::launch_incstate_step<T>(ctx->g, c.f, c.D, c.vt, c.grad, c.out, c.cs,
+                                                                                      c.last, ctx->stream, tg)));
+                return REG_OK;
+            });
+        }
+        if (items.empty()) return;
+        const size_t off = P.table.size();
+        P.table.insert(P.table.end(), items.begin(), items.end());
+        const int n = (int)items.size();
+        const regk::PairStep *dev = dev_region + off;
+        P.ops.push_back([this, mode, span, n, total, off, dev, &P]() -> reg_status {
+            return batched_launch(b, mode, span, P.table.data() + off, dev, n, total, capturing);
+        });
+    }
+
+    // ---------------------------------------------------------------- plans
+    // Phase A of a round: departure points and their floor bounds for every
+    // request that needs new plans, one synchronisation for all.
+    reg_status plans(std::vector<Item> &items) {
+        bool any = false;
+        for (auto &it : items) {
+            reg_ctx *ctx = it.ctx;
+            const long N3 = 3 * ctx->N;
+            const Request &r = it.req;
+            if (r.op == Op::GRADIENT) {
+                if (r.x != ctx->vcur)
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(r.x), V<double>(ctx->vcur), ctx->stream)));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, ctx->vcur, ctx->vf, N3)));
+                if (r.reuse) {
+                    std::swap(ctx->histA, ctx->histB);
+                    std::swap(ctx->Df, ctx->Dt);
+                    ctx->epoch++;
+                } else {
+                    STCHK(plan_enqueue<T>(ctx, ctx->vf, +1.0, ctx->Df, ctx->dpart, kSlotPlanA));
+                }
+                STCHK(plan_enqueue<T>(ctx, ctx->vf, -1.0, ctx->Da, ctx->dpart2, kSlotPlanB));
+            } else if (r.op == Op::OBJECTIVE || r.op == Op::FORWARD) {
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, r.x, ctx->vf, N3)));
+                STCHK(plan_enqueue<T>(ctx, ctx->vf, +1.0, ctx->Dt, ctx->dpart, kSlotPlanA));
+            } else {
+                continue;
+            }
+            HIPCHK(ctx, hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * (kSlotPlanB + 6), hipMemcpyDeviceToHost,
+                                       ctx->stream));
+            any = true;
+        }
+        if (!any) return REG_OK;
+        HIPCHK(items[0].ctx, hipStreamSynchronize(stream));
+        for (auto &it : items) {
+            reg_ctx *ctx = it.ctx;
+            const Request &r = it.req;
+            if (r.op == Op::GRADIENT) {
+                if (!r.reuse) plan_finish(ctx, ctx->Df, kSlotPlanA);
+                plan_finish(ctx, ctx->Da, kSlotPlanB);
+            } else if (r.op == Op::OBJECTIVE || r.op == Op::FORWARD) {
+                plan_finish(ctx, ctx->Dt, kSlotPlanA);
+            }
+        }
+        return REG_OK;
+    }
+
+    // -------------------------------------------------------------- program
+    // Phase B: the transport solves and everything after them, for the given
+    // items (plans already in place).
+    void build(Program &P, const std::vector<Item> &items, const regk::PairStep *dev_region) {
+        int ntmax = 0;
+        for (const auto &it : items) ntmax = std::max(ntmax, it.ctx->P.nt);
+        // set-up of the forward-in-time solves
+        for (const auto &it : items) {
+            reg_ctx *ctx = it.ctx;
+            const Request r = it.req;
+            const long N = ctx->N;
+            if (r.op == Op::GRADIENT && !r.reuse) {
+                P.ops.push_back([ctx]() -> reg_status {
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(ctx->N, CV<T>(ctx->rhoT), V<T>(ctx->histA), ctx->stream)));
+                    return REG_OK;
+                });
+            } else if (r.op == Op::OBJECTIVE) {
+                P.ops.push_back([ctx]() -> reg_status {
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(ctx->N, CV<T>(ctx->rhoT), V<T>(ctx->histB), ctx->stream)));
+                    return REG_OK;
+                });
+            } else if (r.op == Op::MATVEC) {
+                // incremental state through q^n = rho~^n - dt/2 vt.grad rho^n
+                const double dt = 1.0 / ctx->P.nt;
+                P.ops.push_back([ctx, r, N, dt]() -> reg_status {
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, r.x, ctx->vtf, 3 * N)));
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho),
+                                                                                    V<T>(ctx->lam[1]), -0.5 * dt, ctx->stream)));
+                    return REG_OK;
+                });
+            }
+        }
+        // forward-in-time steps: state histories (one launch per step) and
+        // incremental states (one launch per step)
+        for (int k = 0; k < ntmax; k++) {
+            std::vector<StepArg<T>> fw, inc;
+            for (const auto &it : items) {
+                reg_ctx *ctx = it.ctx;
+                const Request &r = it.req;
+                const int nt = ctx->P.nt;
+                const long N = ctx->N;
+                if (k >= nt) continue;
+                if (r.op == Op::GRADIENT && !r.reuse) {
+                    fw.push_back({ctx, CV<T>(ctx->histA) + k * N, CV<T>(ctx->Df), V<T>(ctx->histA) + (k + 1) * N});
+                } else if (r.op == Op::OBJECTIVE) {
+                    fw.push_back({ctx, CV<T>(ctx->histB) + k * N, CV<T>(ctx->Dt), V<T>(ctx->histB) + (k + 1) * N});
+                } else if (r.op == Op::FORWARD) {
+                    // ping-pong between two slices of the scratch history, last step into rho1
+                    const T *src = k == 0 ? CV<T>(r.aux) : CV<T>(ctx->histB) + (long)((k - 1) & 1) * N;
+                    T *dst = (k == nt - 1) ? V<T>(r.y) : V<T>(ctx->histB) + (long)(k & 1) * N;
+                    fw.push_back({ctx, src, CV<T>(ctx->Dt), dst});
+                } else if (r.op == Op::MATVEC) {
+                    const int last = (k == nt - 1);
+                    const double dt = 1.0 / nt;
+                    const int cur = (k & 1) ? 0 : 1;  // lam[1] holds q^0
+                    StepArg<T> a{ctx, CV<T>(ctx->lam[cur]), CV<T>(ctx->Df),
+                                 last ? V<T>(ctx->lamh) + (long)nt * N : V<T>(ctx->lam[1 - cur])};
+                    a.vt = CV<T>(ctx->vtf);
+                    a.grad = CV<T>(ctx->grho) + (long)(k + 1) * 3 * N;
+                    a.cs = last ? -0.5 * dt : -dt;
+                    a.last = last;
+                    inc.push_back(a);
+                }
+            }
+            sl_step(P, regk::STEP_INTERP, fw, dev_region);
+            sl_step(P, regk::STEP_INCSTATE, inc, dev_region);
+        }
+        // gradient: grad rho^n, div v and its Heun factor, adjoint final value
+        std::vector<StepArg<T>> cint;
+        for (const auto &it : items) {
+            if (it.req.op != Op::GRADIENT) continue;
+            reg_ctx *ctx = it.ctx;
+            P.ops.push_back([ctx]() -> reg_status {
+                STCHK(gradient_fields<T>(ctx, ctx->histA, ctx->P.nt + 1, ctx->grho));
+                if (!ctx->P.isochoric) STCHK(divergence<T>(ctx, ctx->vf, ctx->c));
+                return REG_OK;
+            });
+            if (!ctx->P.isochoric) cint.push_back({ctx, CV<T>(ctx->c), CV<T>(ctx->Da), V<T>(ctx->cX)});
+        }
+        sl_step(P, regk::STEP_INTERP, cint, dev_region);
+        for (const auto &it : items) {
+            if (it.req.op != Op::GRADIENT) continue;
+            reg_ctx *ctx = it.ctx;
+            P.ops.push_back([ctx]() -> reg_status {
+                const long N = ctx->N;
+                const int nt = ctx->P.nt;
+                if (!ctx->P.isochoric)
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_gamma<T>(N, CV<T>(ctx->c), CV<T>(ctx->cX), V<T>(ctx->gam),
+                                                                            1.0 / nt, ctx->stream)));
+                // lam(1) = rho_R - rho(1)
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_adjoint_init<T>(N, CV<T>(ctx->rhoR), CV<T>(ctx->histA) + (long)nt * N,
+                                                                               V<T>(ctx->lamh) + (long)nt * N, ctx->stream)));
+                return REG_OK;
+            });
+        }
+        // backward sweeps (adjoint and incremental adjoint, one launch per step)
+        for (int s = 0; s < ntmax; s++) {
+            std::vector<StepArg<T>> adj;
+            for (const auto &it : items) {
+                if (it.req.op != Op::GRADIENT && it.req.op != Op::MATVEC) continue;
+                reg_ctx *ctx = it.ctx;
+                const int nt = ctx->P.nt;
+                if (s >= nt) continue;
+                const int k = nt - 1 - s;
+                const long N = ctx->N;
+                StepArg<T> a{ctx, CV<T>(ctx->lamh) + (long)(k + 1) * N, CV<T>(ctx->Da), V<T>(ctx->lamh) + (long)k * N};
+                a.gam = ctx->P.isochoric ? nullptr : CV<T>(ctx->gam);
+                adj.push_back(a);
+            }
+            sl_step(P, regk::STEP_ADJOINT, adj, dev_region);
+        }
+        // b = sum_n w_n lam^n grad rho^n, assembly and scalars
+        for (const auto &it : items) {
+            reg_ctx *ctx = it.ctx;
+            const Request r = it.req;
+            P.ops.push_back([ctx, r]() -> reg_status {
+                const long N = ctx->N;
+                const int nt = ctx->P.nt;
+                if (r.op == Op::GRADIENT || r.op == Op::MATVEC)
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, CV<T>(ctx->lamh), CV<T>(ctx->grho),
+                                                                                 V<T>(ctx->bvec), ctx->stream)));
+                if (r.op == Op::GRADIENT) {
+                    STCHK(assemble<T>(ctx, ctx->vcur, ctx->bvec, r.y, true));
+                    STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vcur, true));
+                    STCHK(reduce<double>(ctx, r.y, nullptr, 3 * N, 2, h3(ctx), 3));
+                } else if (r.op == Op::OBJECTIVE) {
+                    STCHK(objective_slots<T>(ctx, ctx->histB, r.x, false));
+                } else if (r.op == Op::MATVEC) {
+                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y, false));
+                    if (r.dot) STCHK(reduce<double>(ctx, r.x, r.y, 3 * N, 0, h3(ctx), 0));
+                }
+                return REG_OK;
+            });
+        }
+    }
+
+    void count(const Item &it) {
+        reg_ctx *ctx = it.ctx;
+        const int nt = ctx->P.nt;
+        switch (it.req.op) {
+        case Op::GRADIENT: ctx->interps += (it.req.reuse ? 0 : nt) + (ctx->P.isochoric ? 0 : 1) + nt; break;
+        case Op::OBJECTIVE:
+        case Op::FORWARD: ctx->interps += nt; break;
+        case Op::MATVEC: ctx->interps += 2 * nt; break;
+        default: break;
+        }
+    }
+
+    reg_status run_ops(Program &P) {
+        for (auto &op : P.ops) STCHK(op());
+        return REG_OK;
+    }
+
+    reg_status upload(Program &P, size_t region_index) {
+        if (!b || P.table.empty()) return REG_OK;
+        if (P.table.size() > b->region) return bfail(b, REG_EINVAL, "batched step table overflow");
+        regk::PairStep *h = b->host_tab + region_index * b->region;
+        std::copy(P.table.begin(), P.table.end(), h);
+        hipError_t e = hipMemcpyAsync(b->dev_tab + region_index * b->region, h, sizeof(regk::PairStep) * P.table.size(),
+                                      hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return bfail(b, REG_EHIP, std::string("table upload: ") + hipGetErrorString(e));
+        return REG_OK;
+    }
+
+    // Matvec items through a captured graph: replayed when the same problems
+    // (same plans, operands and beta) were captured before; captured when the
+    // previous matvec round had the same key; otherwise run eagerly.
+    reg_status matvec_graph(std::vector<Item> &mv) {
+        std::vector<int64_t> key;
+        for (const auto &it : mv) {
+            key.push_back((int64_t)(intptr_t)it.ctx);
+            key.push_back(it.ctx->epoch);
+            key.push_back((int64_t)(intptr_t)it.req.x);
+            key.push_back((int64_t)(intptr_t)it.req.y);
+            key.push_back(it.req.dot);
+            int64_t bb;
+            std::memcpy(&bb, &it.ctx->beta, sizeof(bb));
+            key.push_back(bb);
+        }
+        b->tick++;
+        for (auto &g : b->graphs) {
+            if (g.exec && g.key == key) {
+                g.used = b->tick;
+                hipError_t e = timed(b->prof, REG_K_GRAPH, [&]() { return hipGraphLaunch(g.exec, stream); });
+                if (e != hipSuccess) return bfail(b, REG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+                b->replays++;
+                b->last_key = key;
+                return REG_OK;
+            }
+        }
+        const bool capture = (key == b->last_key);
+        b->last_key = key;
+        int slot = 0;
+        if (capture) {
+            for (int i = 1; i < reg_batch::kGraphs; i++)
+                if (b->graphs[i].used < b->graphs[slot].used) slot = i;
+            auto &g = b->graphs[slot];
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+            g = reg_batch::GraphEntry{};
+        }
+        const size_t region_index = capture ? 2 + slot : 1;
+        Program P;
+        build(P, mv, b->dev_tab + region_index * b->region);
+        STCHK(upload(P, region_index));
+        if (!capture) return run_ops(P);
+        // capture without event timing
+        std::vector<bool> prof_was;
+        for (auto &it : mv) {
+            prof_was.push_back(it.ctx->prof.on);
+            it.ctx->prof.on = false;
+        }
+        const bool bprof = b->prof.on;
+        b->prof.on = false;
+        capturing = true;
+        hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed);
+        reg_status st = e == hipSuccess ? run_ops(P) : bfail(b, REG_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(e));
+        hipGraph_t graph = nullptr;
+        if (e == hipSuccess) {
+            hipError_t e2 = hipStreamEndCapture(stream, &graph);
+            if (st == REG_OK && e2 != hipSuccess) st = bfail(b, REG_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e2));
+        }
+        capturing = false;
+        for (size_t i = 0; i < mv.size(); i++) mv[i].ctx->prof.on = prof_was[i];
+        b->prof.on = bprof;
+        if (st != REG_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        hipGraphExec_t exec = nullptr;
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return bfail(b, REG_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        auto &g = b->graphs[slot];
+        g.key = key;
+        g.graph = graph;
+        g.exec = exec;
+        g.used = b->tick;
+        b->captures++;
+        e = timed(b->prof, REG_K_GRAPH, [&]() { return hipGraphLaunch(exec, stream); });
+        if (e != hipSuccess) return bfail(b, REG_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+        return REG_OK;
+    }
+
+    // One round of heavy requests; scalars are copied to each problem's pinned
+    // buffer and become valid after the caller synchronises the stream.
+    reg_status round(std::vector<Item> &items) {
+        if (items.empty()) return REG_OK;
+        STCHK(plans(items));
+        std::vector<Item> eager, mv;
+        for (auto &it : items) {
+            count(it);
+            if (b && b->use_graph && it.req.op == Op::MATVEC) mv.push_back(it);
+            else eager.push_back(it);
+        }
+        if (!eager.empty()) {
+            Program P;
+            build(P, eager, b ? b->dev_tab : nullptr);
+            STCHK(upload(P, 0));
+            STCHK(run_ops(P));
+        }
+        if (!mv.empty()) STCHK(matvec_graph(mv));
+        for (auto &it : items) {
+            const int ns = slots_of(it.req);
+            if (ns > 0)
+                HIPCHK(it.ctx, hipMemcpyAsync(it.ctx->hres, it.ctx->dres, sizeof(double) * ns, hipMemcpyDeviceToHost, stream));
+        }
+        return REG_OK;
+    }
+};
+
+// ------------------------------------------------------------ the solver
+enum State {
+    S_START,
+    S_LEVEL,
+    S_LEVEL_GRAD,
+    S_NEWTON,
+    S_PCG_START,
+    S_MATVEC_DONE,
+    S_RR_DONE,
+    S_ARMIJO,
+    S_ARMIJO_D,
+    S_LS_TRY,
+    S_LS_DONE,
+    S_NEWTON_GRAD,
+    S_LEVEL_END,
+    S_FINISH,
+    S_DONE
+};
+
+// The Gauss-Newton-Krylov iteration of one problem as a state machine. Each
+// call of advance() runs host logic and queues light work until the problem
+// needs a heavy operation (req) or scalars of its queued work (wait).
+struct Solver {
+    reg_ctx *ctx = nullptr;
+    void *v = nullptr;
+    reg_report *rep = nullptr;
+    int st = S_START;
+    Request req;
+    bool wait = false;
+    reg_status status = REG_OK;
+    double beta = 0, beta_final = 0, factor = 0.1;
+    double J = 0, mis = 0, gnorm = 0, g0 = 0, eta = 0, rz = 0, d = 0, alpha = 1;
+    int k = 0, it = 0, i = 0, iters = 0, l = 0, trials = 0;
+    clk::time_point t0;
+    long interps0 = 0;
+
+    bool done() const { return st == S_DONE; }
+
+    void queue_fetch(int nslots) {
+        (void)hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream);
+        wait = true;
+    }
+
+    void finish(reg_status s) {
+        status = s;
+        st = S_FINISH;
+    }
+
+    reg_status read_gradient() {
+        scalars_to_J(ctx, &J, &mis);
+        gnorm = std::sqrt(ctx->hres[3]);
+        rep->gradients++;
+        if (!std::isfinite(ctx->hres[1]) || !std::isfinite(ctx->hres[2]) || !std::isfinite(ctx->hres[3]))
+            return fail(ctx, REG_ENONFINITE, "non-finite objective or gradient");
+        return REG_OK;
+    }
+
+    template <typename T>
+    reg_status advance() {
+        const reg_params &P = ctx->P;
+        const long N3 = 3 * ctx->N;
+        req = Request{};
+        wait = false;
+        for (;;) {
+            switch (st) {
+            case S_START: {
+                t0 = clk::now();
+                interps0 = ctx->interps;
+                if (P.isochoric) {
+                    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
+                    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_LERAY, 0.0, 3, 1, ctx->stream)));
+                    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(v), 3, ctx->stream))));
+                }
+                beta_final = P.beta_final > 0 ? P.beta_final : P.beta;
+                factor = (P.beta_factor > 0 && P.beta_factor < 1) ? P.beta_factor : 0.1;
+                beta = P.beta;
+                it = 0;
+                st = S_LEVEL;
+                break;
+            }
+            case S_LEVEL:
+                ctx->beta = beta;
+                req = Request{Op::GRADIENT, v, ctx->g_, nullptr, false, false};
+                st = S_LEVEL_GRAD;
+                return REG_OK;
+            case S_LEVEL_GRAD: {
+                reg_status s = read_gradient();
+                if (s != REG_OK) {
+                    finish(s);
+                    break;
+                }
+                g0 = gnorm;
+                rep->stop_reason = 2;
+                k = 0;
+                st = S_NEWTON;
+                break;
+            }
+            case S_NEWTON: {
+                if (k >= P.max_newton) {
+                    st = S_LEVEL_END;
+                    break;
+                }
+                if (gnorm <= P.gtol * g0) {
+                    rep->stop_reason = 0;
+                    st = S_LEVEL_END;
+                    break;
+                }
+                if (P.mismatch_tol > 0 && mis <= P.mismatch_tol) {
+                    rep->stop_reason = 1;
+                    st = S_LEVEL_END;
+                    break;
+                }
+                const double ratio = g0 > 0 ? gnorm / g0 : 0.0;
+                eta = P.forcing == 1 ? std::sqrt(ratio) : ratio;
+                if (eta > 0.5) eta = 0.5;
+                // truncated PCG on H s = -g from s = 0
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<double>(N3, 0.0, V<double>(ctx->sdir), ctx->stream)));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_axpby<double>(N3, -1.0, CV<double>(ctx->g_), 0.0, V<double>(ctx->r), ctx->stream)));
+                STCHK(precond_impl(ctx, ctx->r, ctx->z));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->p), ctx->stream)));
+                STCHK(reduce<double>(ctx, ctx->r, ctx->z, N3, 0, h3(ctx), 0));
+                queue_fetch(1);
+                st = S_PCG_START;
+                return REG_OK;
+            }
+            case S_PCG_START:
+                rz = ctx->hres[0];
+                i = 0;
+                iters = 0;
+                req = Request{Op::MATVEC, ctx->p, ctx->q, nullptr, false, true};
+                st = S_MATVEC_DONE;
+                return REG_OK;
+            case S_MATVEC_DONE: {
+                const double kappa = ctx->hres[0];
+                rep->matvecs++;
+                iters = i + 1;
+                if (!std::isfinite(kappa)) {
+                    finish(fail(ctx, REG_ENONFINITE, "non-finite curvature in PCG"));
+                    break;
+                }
+                if (kappa <= 0) {  // negative curvature: stop (steepest descent at the first iteration)
+                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->sdir), ctx->stream)));
+                    st = S_ARMIJO;
+                    break;
+                }
+                const double a = rz / kappa;
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_cg_update<double>(N3, a, CV<double>(ctx->p), CV<double>(ctx->q), V<double>(ctx->sdir),
+                                                                                 V<double>(ctx->r), ctx->stream)));
+                STCHK(reduce<double>(ctx, ctx->r, ctx->r, N3, 0, h3(ctx), 0));
+                // z and <r, z> for the next direction, queued with the residual
+                // norm so that one synchronisation serves both (unused when the
+                // forcing test below ends the iteration)
+                STCHK(precond_impl(ctx, ctx->r, ctx->z));
+                STCHK(reduce<double>(ctx, ctx->r, ctx->z, N3, 0, h3(ctx), 4));
+                queue_fetch(5);
+                st = S_RR_DONE;
+                return REG_OK;
+            }
+            case S_RR_DONE: {
+                const double rr = ctx->hres[0], rz1 = ctx->hres[4];
+                if (std::sqrt(rr) <= eta * gnorm) {
+                    st = S_ARMIJO;
+                    break;
+                }
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(ctx->z), rz1 / rz, CV<double>(ctx->p),
+                                                                            V<double>(ctx->p), ctx->stream)));
+                rz = rz1;
+                i++;
+                if (i >= P.max_pcg) {
+                    st = S_ARMIJO;
+                    break;
+                }
+                req = Request{Op::MATVEC, ctx->p, ctx->q, nullptr, false, true};
+                st = S_MATVEC_DONE;
+                return REG_OK;
+            }
+            case S_ARMIJO:
+                STCHK(reduce<double>(ctx, ctx->g_, ctx->sdir, N3, 0, h3(ctx), 0));
+                queue_fetch(1);
+                st = S_ARMIJO_D;
+                return REG_OK;
+            case S_ARMIJO_D:
+                d = ctx->hres[0];
+                alpha = 1.0;
+                l = 0;
+                trials = 0;
+                st = S_LS_TRY;
+                break;
+            case S_LS_TRY:
+                if (l >= P.max_ls) {
+                    finish(fail(ctx, REG_ELINESEARCH, "Armijo line search found no acceptable step"));
+                    break;
+                }
+                trials++;
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(v), alpha, CV<double>(ctx->sdir),
+                                                                            V<double>(ctx->vtrial), ctx->stream)));
+                req = Request{Op::OBJECTIVE, ctx->vtrial, nullptr, nullptr, false, false};
+                st = S_LS_DONE;
+                return REG_OK;
+            case S_LS_DONE: {
+                double Jt = 0, mist = 0;
+                scalars_to_J(ctx, &Jt, &mist);
+                rep->objectives++;
+                if (!std::isfinite(Jt)) {
+                    finish(fail(ctx, REG_ENONFINITE, "non-finite objective"));
+                    break;
+                }
+                if (Jt <= J + P.armijo_c1 * alpha * d) {
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->vtrial), V<double>(v), ctx->stream)));
+                    req = Request{Op::GRADIENT, v, ctx->g_, nullptr, true, false};
+                    st = S_NEWTON_GRAD;
+                    return REG_OK;
+                }
+                alpha *= 0.5;
+                l++;
+                st = S_LS_TRY;
+                break;
+            }
+            case S_NEWTON_GRAD: {
+                reg_status s = read_gradient();
+                if (s != REG_OK) {
+                    finish(s);
+                    break;
+                }
+                if (it < REG_MAXIT) {
+                    rep->J[it] = J;
+                    rep->mismatch[it] = mis;
+                    rep->grel[it] = g0 > 0 ? gnorm / g0 : 0;
+                    rep->alpha[it] = alpha;
+                    rep->beta[it] = beta;
+                    rep->pcg_iters[it] = iters;
+                    rep->ls_trials[it] = trials;
+                }
+                it++;
+                rep->stop_reason = 2;
+                k++;
+                st = S_NEWTON;
+                break;
+            }
+            case S_LEVEL_END:
+                if (rep->stop_reason == 2) {
+                    if (gnorm <= P.gtol * g0) rep->stop_reason = 0;
+                    if (P.mismatch_tol > 0 && mis <= P.mismatch_tol) rep->stop_reason = 1;
+                }
+                if (rep->stop_reason == 1 || beta <= beta_final * (1 + 1e-12)) {
+                    st = S_FINISH;
+                } else {
+                    beta *= factor;
+                    if (beta < beta_final) beta = beta_final;
+                    st = S_LEVEL;
+                }
+                break;
+            case S_FINISH:
+                ctx->beta = P.beta;
+                rep->status = status;
+                rep->n_iter = it;
+                rep->final_J = J;
+                rep->final_mismatch = mis;
+                rep->final_grel = g0 > 0 ? gnorm / g0 : 0;
+                rep->interps = ctx->interps - interps0;
+                rep->seconds_total = secs(t0);
+                st = S_DONE;
+                return REG_OK;
+            case S_DONE:
+                return REG_OK;
+            }
+        }
+    }
+};
+
+// Runs the solvers to completion in rounds (one stream synchronisation per
+// round). Returns the first HIP-level failure; per-problem outcomes are in
+// each solver's status.
+template <typename T>
+reg_status run_solvers(Exec<T> &ex, std::vector<Solver> &S) {
+    for (auto &s : S) {
+        reg_status st = s.advance<T>();
+        if (st != REG_OK) return st;
+    }
+    for (;;) {
+        std::vector<Item> items;
+        bool active = false;
+        for (auto &s : S) {
+            if (s.done()) continue;
+            active = true;
+            if (s.req.op != Op::NONE) items.push_back({s.ctx, s.req});
+        }
+        if (!active) break;
+        auto t = clk::now();
+        reg_status st = ex.round(items);
+        if (st != REG_OK) return st;
+        HIPCHK(S[0].ctx, hipStreamSynchronize(ex.stream));
+        const double dt = secs(t);
+        for (auto &s : S) {
+            if (s.done()) continue;
+            if (!s.ctx->prof.pending.empty()) s.ctx->prof.resolve();
+            switch (s.req.op) {
+            case Op::GRADIENT: s.rep->seconds_gradient += dt; break;
+            case Op::MATVEC: s.rep->seconds_matvec += dt; break;
+            case Op::OBJECTIVE: s.rep->seconds_objective += dt; break;
+            default: s.rep->seconds_precond += dt; break;
+            }
+            st = s.advance<T>();
+            if (st != REG_OK) return st;
+        }
+        if (ex.b && !ex.b->prof.pending.empty()) ex.b->prof.resolve();
+    }
+    return REG_OK;
+}
+
+// single heavy operation of one context (synchronises when it has scalars)
+template <typename T>
+reg_status single_op(reg_ctx *ctx, const Request &r) {
+    Exec<T> ex(nullptr, ctx->stream);
+    std::vector<Item> items{{ctx, r}};
+    STCHK(ex.round(items));
+    if (slots_of(r) > 0) {
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        if (!ctx->prof.pending.empty()) ctx->prof.resolve();
+    }
+    return REG_OK;
+}
+
+template <typename T>
+reg_status solve_one(reg_ctx *ctx, void *v, reg_report *rep) {
+    Exec<T> ex(nullptr, ctx->stream);
+    std::vector<Solver> S(1);
+    S[0].ctx = ctx;
+    S[0].v = v;
+    S[0].rep = rep;
+    reg_status st = run_solvers<T>(ex, S);
+    ctx->beta = ctx->P.beta;
+    if (st != REG_OK) return st;
+    return S[0].status;
+}
+
+template <typename T>
+reg_status batch_solve(reg_batch *b, void *const *v, reg_report *reps) {
+    Exec<T> ex(b, b->stream);
+    std::vector<Solver> S(b->npairs);
+    for (int i = 0; i < b->npairs; i++) {
+        S[i].ctx = b->ctx[i];
+        S[i].v = v[i];
+        S[i].rep = &reps[i];
+    }
+    reg_status st = run_solvers<T>(ex, S);
+    for (auto *c : b->ctx) c->beta = c->P.beta;
+    if (st != REG_OK) return st;
+    for (auto &s : S)
+        if (s.status != REG_OK) return bfail(b, s.status, "pair " + std::to_string(&s - S.data()) + ": " + s.ctx->err);
+    return REG_OK;
+}
+
+template <typename T>
+reg_status batch_round(reg_batch *b, std::vector<Item> &items) {
+    Exec<T> ex(b, b->stream);
+    STCHK(ex.round(items));
+    HIPCHK(items[0].ctx, hipStreamSynchronize(b->stream));
+    for (auto &it : items)
+        if (!it.ctx->prof.pending.empty()) it.ctx->prof.resolve();
+    if (!b->prof.pending.empty()) b->prof.resolve();
+    return REG_OK;
+}
+
+size_t batch_tables(const reg_params *pp, int32_t n, size_t *entries) {
+    int ntmax = 0;
+    for (int i = 0; i < n; i++) ntmax = std::max(ntmax, pp[i].nt);
+    // per region: the steps of one round (state, incremental state, div v
+    // interpolation and backward sweeps), one entry per problem each
+    *entries = (size_t)n * (3 * (size_t)ntmax + 2);
+    return align_up(sizeof(regk::PairStep) * *entries * (2 + reg_batch::kGraphs));
+}
+
+reg_status check_batch(const reg_params *pp, int32_t n, std::string *why) {
+    if (!pp || n < 1 || n > 4096) {
+        *why = "need 1 <= npairs <= 4096 parameter sets";
+        return REG_EINVAL;
+    }
+    for (int i = 0; i < n; i++) {
+        if (check_params(&pp[i], why) != REG_OK) {
+            *why = "pair " + std::to_string(i) + ": " + *why;
+            return REG_EINVAL;
+        }
+        if (pp[i].prec != pp[0].prec) {
+            *why = "every pair of a batch needs the same prec";
+            return REG_EINVAL;
+        }
+    }
+    return REG_OK;
+}
+
+#define BATCH_OK(b)                                   \
+    do {                                              \
+        if (!(b)) return REG_EINVAL;                  \
+        (b)->err.clear();                             \
+    } while (0)
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+reg_status reg_gradient(reg_ctx *ctx, const void *v, void *g, double *J, double *mismatch, double *gnorm) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, v);
+    NEED_DEV(ctx, g);
+    if (!ctx->have_images) return fail(ctx, REG_EINVAL, "reg_set_images has not been called");
+    ctx->have_state = false;
+    Request r{Op::GRADIENT, v, g, nullptr, false, false};
+    STCHK(DISPATCH(ctx, single_op, ctx, r));
+    scalars_to_J(ctx, J, mismatch);
+    if (gnorm) *gnorm = std::sqrt(ctx->hres[3]);
+    if (!std::isfinite(ctx->hres[1]) || !std::isfinite(ctx->hres[2]) || !std::isfinite(ctx->hres[3]))
+        return fail(ctx, REG_ENONFINITE, "non-finite objective or gradient");
+    ctx->have_state = true;
+    return REG_OK;
+}
+
+reg_status reg_objective(reg_ctx *ctx, const void *v, double *J, double *mismatch) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, v);
+    if (!J || !mismatch) return fail(ctx, REG_EINVAL, "J and mismatch are required");
+    if (!ctx->have_images) return fail(ctx, REG_EINVAL, "reg_set_images has not been called");
+    Request r{Op::OBJECTIVE, v, nullptr, nullptr, false, false};
+    STCHK(DISPATCH(ctx, single_op, ctx, r));
+    scalars_to_J(ctx, J, mismatch);
+    if (!std::isfinite(*J)) return fail(ctx, REG_ENONFINITE, "non-finite objective");
+    return REG_OK;
+}
+
+reg_status reg_hessian_matvec(reg_ctx *ctx, const void *vt, void *Hvt) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, vt);
+    NEED_DEV(ctx, Hvt);
+    if (!ctx->have_state) return fail(ctx, REG_EINVAL, "reg_gradient must be called first");
+    Request r{Op::MATVEC, vt, Hvt, nullptr, false, false};
+    return DISPATCH(ctx, single_op, ctx, r);
+}
+
+reg_status reg_solve(reg_ctx *ctx, void *v_inout, reg_report *rep) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, v_inout);
+    if (!ctx->have_images) return fail(ctx, REG_EINVAL, "reg_set_images has not been called");
+    reg_report local;
+    reg_report *r = rep ? rep : &local;
+    std::memset(r, 0, sizeof(*r));
+    ctx->have_state = false;
+    reg_status st = DISPATCH(ctx, solve_one, ctx, v_inout, r);
+    r->status = st;
+    return st;
+}
+
+// ------------------------------------------------------------------ batch
+
+reg_status reg_batch_workspace_size(const reg_params *per_pair, int32_t npairs, size_t *bytes) {
+    std::string why;
+    if (check_batch(per_pair, npairs, &why) != REG_OK || !bytes) return REG_EINVAL;
+    size_t total = 0, entries = 0;
+    for (int i = 0; i < npairs; i++) total += align_up(layout(&per_pair[i], nullptr, nullptr));
+    total += batch_tables(per_pair, npairs, &entries);
+    *bytes = total;
+    return REG_OK;
+}
+
+reg_status reg_batch_create(const reg_params *per_pair, int32_t npairs, void *workspace, size_t bytes,
+                            void *hip_stream, reg_batch **out) {
+    if (!out) return REG_EINVAL;
+    *out = nullptr;
+    std::string why;
+    if (check_batch(per_pair, npairs, &why) != REG_OK) {
+        std::fprintf(stderr, "reg_batch_create: %s\n", why.c_str());
+        return REG_EINVAL;
+    }
+    size_t need = 0;
+    if (reg_batch_workspace_size(per_pair, npairs, &need) != REG_OK) return REG_EINVAL;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0 || !is_device_ptr(workspace)) return REG_EINVAL;
+    if (bytes < need) return REG_ENOMEM;
+    reg_batch *b = new (std::nothrow) reg_batch();
+    if (!b) return REG_ENOMEM;
+    b->npairs = npairs;
+    b->prec = per_pair[0].prec;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        // graphs cannot be captured on the null stream: use a stream of our
+        // own (blocking, so it stays ordered with the null stream)
+        if (hipStreamCreate(&b->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            delete b;
+            return REG_EHIP;
+        }
+        b->own_stream = true;
+    }
+    b->prof.stream = b->stream;
+    char *base = (char *)workspace;
+    size_t off = 0;
+    reg_status st = REG_OK;
+    for (int i = 0; i < npairs && st == REG_OK; i++) {
+        const size_t sz = align_up(layout(&per_pair[i], nullptr, nullptr));
+        reg_ctx *c = nullptr;
+        st = reg_create(&per_pair[i], base + off, sz, b->stream, &c);
+        if (st == REG_OK) b->ctx.push_back(c);
+        off += sz;
+        b->nt_max = std::max(b->nt_max, per_pair[i].nt);
+    }
+    size_t entries = 0;
+    const size_t tab_bytes = batch_tables(per_pair, npairs, &entries);
+    b->region = entries;
+    b->dev_tab = (regk::PairStep *)(base + off);
+    if (st == REG_OK && hipHostMalloc((void **)&b->host_tab, tab_bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        st = REG_EHIP;
+    }
+    if (st != REG_OK) {
+        for (auto *c : b->ctx) reg_destroy(c);
+        if (b->host_tab) (void)hipHostFree(b->host_tab);
+        if (b->own_stream) (void)hipStreamDestroy(b->stream);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return REG_OK;
+}
+
+reg_status reg_batch_destroy(reg_batch *b) {
+    if (!b) return REG_EINVAL;
+    (void)hipStreamSynchronize(b->stream);
+    for (auto &g : b->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    for (auto *c : b->ctx) reg_destroy(c);
+    b->prof.release();
+    if (b->host_tab) (void)hipHostFree(b->host_tab);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return REG_OK;
+}
+
+const char *reg_batch_last_error(const reg_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+reg_status reg_batch_ctx(reg_batch *b, int32_t pair, reg_ctx **ctx) {
+    BATCH_OK(b);
+    if (!ctx || pair < 0 || pair >= b->npairs) return bfail(b, REG_EINVAL, "pair out of range");
+    *ctx = b->ctx[pair];
+    return REG_OK;
+}
+
+reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, int32_t use_graph) {
+    BATCH_OK(b);
+    if (blocks != 0 && blocks < 8) return bfail(b, REG_EINVAL, "blocks must be 0 (autotune) or >= 8");
+    if (chunked != 0 && chunked != 1) return bfail(b, REG_EINVAL, "chunked must be 0 or 1");
+    b->fixed_blocks = blocks;
+    b->fixed_chunked = chunked;
+    b->use_graph = use_graph != 0;
+    return REG_OK;
+}
+
+reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, double *ms) {
+    BATCH_OK(b);
+    if (mode < 0 || mode > 2 || !blocks || !chunked || !ms) return bfail(b, REG_EINVAL, "bad launch query");
+    *blocks = b->last[mode].blocks;
+    *chunked = b->last[mode].chunked;
+    *ms = b->last[mode].ms;
+    return REG_OK;
+}
+
+reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *graph_captures, int64_t *graph_replays) {
+    BATCH_OK(b);
+    if (!batched_launches || !graph_captures || !graph_replays) return bfail(b, REG_EINVAL, "bad stats query");
+    *batched_launches = b->launches;
+    *graph_captures = b->captures;
+    *graph_replays = b->replays;
+    return REG_OK;
+}
+
+reg_status reg_batch_profile(reg_batch *b, int enable) {
+    BATCH_OK(b);
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, REG_EHIP, "hipStreamSynchronize failed");
+    b->prof.resolve();
+    if (enable) b->prof.reset();
+    b->prof.on = enable != 0;
+    for (auto *c : b->ctx) STCHK(reg_profile(c, enable));
+    return REG_OK;
+}
+
+reg_status reg_batch_profile_read(reg_batch *b, int kind, int64_t *launches, double *ms) {
+    BATCH_OK(b);
+    if (kind < 0 || kind >= REG_K_COUNT || !launches || !ms) return bfail(b, REG_EINVAL, "bad profile query");
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, REG_EHIP, "hipStreamSynchronize failed");
+    b->prof.resolve();
+    *launches = b->prof.n[kind];
+    *ms = b->prof.ms[kind];
+    for (auto *c : b->ctx) {
+        int64_t n = 0;
+        double t = 0;
+        STCHK(reg_profile_read(c, kind, &n, &t));
+        *launches += n;
+        *ms += t;
+    }
+    return REG_OK;
+}
+
+#define BATCH_ARRAY(b, arr)                                                                  \
+    do {                                                                                     \
+        if (!(arr)) return bfail((b), REG_EINVAL, #arr " is NULL");                          \
+        for (int i_ = 0; i_ < (b)->npairs; i_++)                                             \
+            if (!is_device_ptr((arr)[i_]))                                                   \
+                return bfail((b), REG_EINVAL, #arr "[" + std::to_string(i_) + "] is not a device pointer"); \
+    } while (0)
+
+reg_status reg_batch_transport_forward(reg_batch *b, const void *const *v, const void *const *rho0, void *const *rho1) {
+    BATCH_OK(b);
+    BATCH_ARRAY(b, v);
+    BATCH_ARRAY(b, rho0);
+    BATCH_ARRAY(b, rho1);
+    std::vector<Item> items;
+    for (int i = 0; i < b->npairs; i++) {
+        if (rho0[i] == rho1[i]) return bfail(b, REG_EINVAL, "rho1 must not alias rho0");
+        items.push_back({b->ctx[i], Request{Op::FORWARD, v[i], rho1[i], rho0[i], false, false}});
+    }
+    return b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items);
+}
+
+reg_status reg_batch_gradient(reg_batch *b, const void *const *v, void *const *g, double *J, double *mismatch,
+                              double *gnorm) {
+    BATCH_OK(b);
+    BATCH_ARRAY(b, v);
+    BATCH_ARRAY(b, g);
+    std::vector<Item> items;
+    for (int i = 0; i < b->npairs; i++) {
+        reg_ctx *c = b->ctx[i];
+        if (!c->have_images) return bfail(b, REG_EINVAL, "pair " + std::to_string(i) + ": images not set");
+        c->have_state = false;
+        items.push_back({c, Request{Op::GRADIENT, v[i], g[i], nullptr, false, false}});
+    }
+    STCHK(b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items));
+    for (int i = 0; i < b->npairs; i++) {
+        reg_ctx *c = b->ctx[i];
+        scalars_to_J(c, J ? &J[i] : nullptr, mismatch ? &mismatch[i] : nullptr);
+        if (gnorm) gnorm[i] = std::sqrt(c->hres[3]);
+        if (!std::isfinite(c->hres[1]) || !std::isfinite(c->hres[2]) || !std::isfinite(c->hres[3]))
+            return bfail(b, REG_ENONFINITE, "pair " + std::to_string(i) + ": non-finite objective or gradient");
+        c->have_state = true;
+    }
+    return REG_OK;
+}
+
+reg_status reg_batch_hessian_matvec(reg_batch *b, const void *const *vt, void *const *Hvt) {
+    BATCH_OK(b);
+    BATCH_ARRAY(b, vt);
+    BATCH_ARRAY(b, Hvt);
+    std::vector<Item> items;
+    for (int i = 0; i < b->npairs; i++) {
+        if (!b->ctx[i]->have_state) return bfail(b, REG_EINVAL, "reg_batch_gradient must be called first");
+        items.push_back({b->ctx[i], Request{Op::MATVEC, vt[i], Hvt[i], nullptr, false, false}});
+    }
+    return b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items);
+}
+
+reg_status reg_batch_solve(reg_batch *b, void *const *v_inout, reg_report *reports) {
+    BATCH_OK(b);
+    BATCH_ARRAY(b, v_inout);
+    if (!reports) return bfail(b, REG_EINVAL, "reports is NULL");
+    for (int i = 0; i < b->npairs; i++) {
+        reg_ctx *c = b->ctx[i];
+        if (!c->have_images) return bfail(b, REG_EINVAL, "pair " + std::to_string(i) + ": images not set");
+        c->have_state = false;
+        std::memset(&reports[i], 0, sizeof(reg_report));
+    }
+    reg_status st = b->prec ? batch_solve<double>(b, v_inout, reports) : batch_solve<float>(b, v_inout, reports);
+    return st;
+}
+
+}  // extern "C"

@@ -115,12 +115,29 @@ _SIGS = {
     "reg_solve": [_P, _P, ctypes.POINTER(reg_report)],
     "reg_deformation": [_P, _P, _P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "reg_dot": [_P, ctypes.c_int, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "reg_resample": [_P, _P, ctypes.c_int, _P, _P],
     "reg_profile": [_P, ctypes.c_int],
     "reg_profile_read": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "reg_batch_workspace_size": [ctypes.POINTER(reg_params), ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "reg_batch_create": [ctypes.POINTER(reg_params), ctypes.c_int32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "reg_batch_destroy": [_P],
+    "reg_batch_ctx": [_P, ctypes.c_int32, ctypes.POINTER(_P)],
+    "reg_batch_set_launch": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "reg_batch_launch_info": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_double)],
+    "reg_batch_stats": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                        ctypes.POINTER(ctypes.c_int64)],
+    "reg_batch_profile": [_P, ctypes.c_int],
+    "reg_batch_profile_read": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)],
+    "reg_batch_transport_forward": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    "reg_batch_gradient": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
+    "reg_batch_hessian_matvec": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    "reg_batch_solve": [_P, ctypes.POINTER(_P), ctypes.POINTER(reg_report)],
 }
 
 KERNEL_KINDS = ["interp", "backtrace", "adjoint", "incstate", "deform", "deriv", "fft3d", "symbol", "reduce",
-                "vector"]
+                "vector", "graph"]
 
 
 def lib():
@@ -136,6 +153,8 @@ def lib():
             f.restype = ctypes.c_int
         L.reg_last_error.argtypes = [_P]
         L.reg_last_error.restype = ctypes.c_char_p
+        L.reg_batch_last_error.argtypes = [_P]
+        L.reg_batch_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -170,15 +189,22 @@ def _stream_ptr(stream=None):
 
 
 class Context:
-    """One reg_ctx over a torch-allocated workspace, bound to one stream."""
+    """One reg_ctx over a torch-allocated workspace, bound to one stream (or,
+    with `borrowed`, a view of a context that a Batch owns)."""
 
-    def __init__(self, params, device="cuda", stream=None):
+    def __init__(self, params, device="cuda", stream=None, borrowed=None):
         self.params = params
         self.device = torch.device(device)
         self.dtype = torch.float64 if params.prec else torch.float32  # image-space fields
         self.vdtype = torch.float64  # velocity-space vectors
         self.shape = tuple(params.n)
         self.N = self.shape[0] * self.shape[1] * self.shape[2]
+        self.owned = borrowed is None
+        if borrowed is not None:
+            self.workspace = None
+            self.stream = None
+            self.handle = borrowed
+            return
         nbytes = reg_workspace_size(params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = stream
@@ -188,9 +214,9 @@ class Context:
         self.handle = h
 
     def close(self):
-        if self.handle:
+        if self.handle and self.owned:
             lib().reg_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:
@@ -258,6 +284,14 @@ class Context:
         out = self.empty(ncomp) if out is None else out
         _chk(lib().reg_spectral(self.handle, int(op), float(scale), ncomp, self._t(v, ncomp, "v"),
                                 self._t(out, ncomp, "out")), self.handle, "reg_spectral")
+        return out
+
+    def reg_resample(self, dst, x, out=None):
+        """Spectral resampling of x (this context's grid) onto dst's grid."""
+        ncomp = 1 if x.dim() == 3 else x.shape[0]
+        out = dst.empty(ncomp) if out is None else out
+        _chk(lib().reg_resample(self.handle, dst.handle, ncomp, self._t(x, ncomp, "x"), dst._t(out, ncomp, "out")),
+             self.handle, "reg_resample")
         return out
 
     def reg_precond(self, r, z=None):
@@ -334,3 +368,138 @@ class Context:
                  "reg_profile_read")
             out[name] = (n.value, ms.value)
         return out
+
+
+# ------------------------------------------------------------------ batches
+def reg_batch_workspace_size(params_list):
+    arr = (reg_params * len(params_list))(*params_list)
+    b = ctypes.c_size_t()
+    _chk(lib().reg_batch_workspace_size(arr, len(params_list), ctypes.byref(b)), what="reg_batch_workspace_size")
+    return b.value
+
+
+def _bchk(st, b, what):
+    if st != REG_OK:
+        msg = lib().reg_batch_last_error(b).decode() if b else ""
+        raise RegError(st, f"{what}: {msg}")
+
+
+def _ptrs(ts):
+    return (_P * len(ts))(*[ctypes.c_void_p(t.data_ptr()) for t in ts])
+
+
+class Batch:
+    """A reg_batch: independent problems of mixed sizes on one stream (the
+    library's own blocking stream unless one is given). contexts[i] is a
+    borrowed Context of problem i for the single-problem entry points."""
+
+    def __init__(self, params_list, device="cuda", stream=None):
+        self.params = list(params_list)
+        self.n = len(self.params)
+        self.device = torch.device(device)
+        arr = (reg_params * self.n)(*self.params)
+        nbytes = reg_batch_workspace_size(self.params)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _chk(lib().reg_batch_create(arr, self.n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes, sp,
+                                    ctypes.byref(h)), what="reg_batch_create")
+        self.handle = h
+        self.contexts = []
+        for i, p in enumerate(self.params):
+            c = ctypes.c_void_p()
+            _bchk(lib().reg_batch_ctx(h, i, ctypes.byref(c)), h, "reg_batch_ctx")
+            self.contexts.append(Context(p, device, borrowed=c))
+
+    def close(self):
+        if self.handle:
+            for c in self.contexts:
+                c.handle = None
+            lib().reg_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vel(self, ts, name):
+        if len(ts) != self.n:
+            raise ValueError(f"{name} needs {self.n} tensors")
+        for c, t in zip(self.contexts, ts):
+            c._t(t, 3, name, True)
+        return _ptrs(ts)
+
+    def _fld(self, ts, name):
+        if len(ts) != self.n:
+            raise ValueError(f"{name} needs {self.n} tensors")
+        for c, t in zip(self.contexts, ts):
+            c._t(t, 1, name)
+        return _ptrs(ts)
+
+    def reg_set_images(self, i, rho_T, rho_R):
+        torch.cuda.synchronize()
+        self.contexts[i].reg_set_images(rho_T, rho_R)
+
+    def reg_batch_set_launch(self, blocks=0, chunked=1, use_graph=True):
+        _bchk(lib().reg_batch_set_launch(self.handle, int(blocks), int(chunked), int(bool(use_graph))), self.handle,
+              "reg_batch_set_launch")
+
+    def reg_batch_launch_info(self, mode):
+        b, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _bchk(lib().reg_batch_launch_info(self.handle, int(mode), ctypes.byref(b), ctypes.byref(c), ctypes.byref(ms)),
+              self.handle, "reg_batch_launch_info")
+        return b.value, c.value, ms.value
+
+    def reg_batch_stats(self):
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _bchk(lib().reg_batch_stats(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), self.handle,
+              "reg_batch_stats")
+        return {"batched_launches": a.value, "graph_captures": b.value, "graph_replays": c.value}
+
+    def reg_batch_profile(self, enable=True):
+        _bchk(lib().reg_batch_profile(self.handle, int(bool(enable))), self.handle, "reg_batch_profile")
+
+    def reg_batch_profile_read(self):
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            n, ms = ctypes.c_int64(), ctypes.c_double()
+            _bchk(lib().reg_batch_profile_read(self.handle, k, ctypes.byref(n), ctypes.byref(ms)), self.handle,
+                  "reg_batch_profile_read")
+            out[name] = (n.value, ms.value)
+        return out
+
+    def reg_batch_transport_forward(self, vs, rho0s, rho1s=None):
+        rho1s = [c.empty(1) for c in self.contexts] if rho1s is None else rho1s
+        pv, p0, p1 = self._vel(vs, "v"), self._fld(rho0s, "rho0"), self._fld(rho1s, "rho1")
+        torch.cuda.synchronize()
+        _bchk(lib().reg_batch_transport_forward(self.handle, pv, p0, p1), self.handle, "reg_batch_transport_forward")
+        return rho1s
+
+    def reg_batch_gradient(self, vs, gs=None):
+        gs = [c.empty(3, True) for c in self.contexts] if gs is None else gs
+        pv, pg = self._vel(vs, "v"), self._vel(gs, "g")
+        J, mis, gn = (ctypes.c_double * self.n)(), (ctypes.c_double * self.n)(), (ctypes.c_double * self.n)()
+        torch.cuda.synchronize()
+        _bchk(lib().reg_batch_gradient(self.handle, pv, pg, J, mis, gn), self.handle, "reg_batch_gradient")
+        return gs, list(J), list(mis), list(gn)
+
+    def reg_batch_hessian_matvec(self, vts, Hvts=None):
+        Hvts = [c.empty(3, True) for c in self.contexts] if Hvts is None else Hvts
+        pv, ph = self._vel(vts, "vt"), self._vel(Hvts, "Hvt")
+        torch.cuda.synchronize()
+        _bchk(lib().reg_batch_hessian_matvec(self.handle, pv, ph), self.handle, "reg_batch_hessian_matvec")
+        return Hvts
+
+    def reg_batch_solve(self, vs=None, raise_on_error=True):
+        vs = [torch.zeros((3,) + c.shape, dtype=torch.float64, device=self.device) for c in self.contexts] \
+            if vs is None else vs
+        pv = self._vel(vs, "v")
+        reps = (reg_report * self.n)()
+        torch.cuda.synchronize()
+        st = lib().reg_batch_solve(self.handle, pv, reps)
+        if raise_on_error:
+            _bchk(st, self.handle, "reg_batch_solve")
+        return vs, [r.to_dict() for r in reps]

@@ -95,6 +95,31 @@ def test_create_rejects_null_workspace(lib):
     assert st == reg.REG_EINVAL and not h.value
 
 
+def test_batch_workspace_is_the_sum_of_its_problems(lib):
+    from paper_1608_03630_amd import reg
+
+    ps = [reg.reg_default_params(n, nt=nt) for n, nt in [((64, 64, 64), 4), ((32, 48, 64), 3), ((24, 36, 54), 4)]]
+    total = reg.reg_batch_workspace_size(ps)
+    parts = sum((reg.reg_workspace_size(p) + 255) // 256 * 256 for p in ps)
+    # plus the tables of the batched step launches: a few KB
+    assert parts < total < parts + (1 << 20)
+
+
+def test_batch_rejects_mixed_precision_and_bad_problems(lib):
+    from paper_1608_03630_amd import reg
+
+    with pytest.raises(reg.RegError) as e:
+        reg.reg_batch_workspace_size([reg.reg_default_params(32), reg.reg_default_params(32, prec=1)])
+    assert e.value.status == reg.REG_EINVAL
+    with pytest.raises(reg.RegError) as e:
+        reg.reg_batch_workspace_size([reg.reg_default_params(32), reg.reg_default_params(30)])
+    assert e.value.status == reg.REG_EINVAL
+    h = ctypes.c_void_p()
+    arr = (reg.reg_params * 1)(reg.reg_default_params(32))
+    assert lib.reg_batch_create(arr, 1, None, 1 << 30, None, ctypes.byref(h)) == reg.REG_EINVAL and not h.value
+    assert lib.reg_batch_create(arr, 0, None, 1 << 30, None, ctypes.byref(h)) == reg.REG_EINVAL
+
+
 def test_product_package_does_not_reach_the_oracle():
     """The product path never imports, links or loads the oracle."""
     pkg = os.path.join(ROOT, "paper_1608_03630_amd")

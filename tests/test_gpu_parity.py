@@ -292,3 +292,13 @@ def test_repeatable_bitwise(reg):
     g1 = g1.clone()
     g2, J2, _, _ = ctx.reg_gradient(v)
     assert J1 == J2 and torch.equal(g1, g2)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+@pytest.mark.parametrize("src,dst", [(RAGGED, (16, 24, 32)), ((16, 24, 32), RAGGED), (CUBE, (64, 48, 36))])
+def test_resample(reg, prec, src, dst):
+    a = make_ctx(reg, src, prec)
+    b = make_ctx(reg, dst, prec)
+    u = rounded(synth.smooth_random_field(src, 111, kmax=9, ncomp=3), prec)
+    out = to_host(a.reg_resample(b, to_dev(u, a)))
+    assert rel_l2(out, oracle.resample(u, dst)) <= TOL[("spectral", prec)]
