@@ -220,10 +220,9 @@ reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double
  * parameters and grid (mixed sizes allowed, one precision for all), solved
  * together on one stream. The work of all problems advances in rounds: every
  * semi-Lagrangian time step of all problems of a round goes out as one
- * persistent launch over a work list of (problem, tile) items -- for single
- * precision problems whose grids are whole 8x8x64 tiles and whose departure
- * points stay within the canonical LDS box; the others use the
- * single-problem launchers in the same round -- with the launch shape
+ * persistent launch over a work list of (problem, tile) items -- every
+ * problem whose departure box fits the 64 KB LDS tile (the rare others use
+ * the single-problem direct gather in the same round) -- with the launch shape
  * (workgroup count, XCD dealing) chosen by an autotuner that times the
  * candidates on the first launch of each (step kind, box span, set of grid
  * sizes) and keeps the choice for the process. Hessian matvecs are replayed
@@ -262,10 +261,13 @@ reg_status reg_batch_ctx(reg_batch *b, int32_t pair, reg_ctx **ctx);
  * matvec eagerly. Results do not depend on these settings. */
 reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, int32_t use_graph);
 
-/* Workgroups, dealing and tuned time (ms, 0 if fixed) of the last batched
- * launch of a step kind: mode 0 interpolation/state, 1 adjoint,
- * 2 incremental state. */
-reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, double *ms);
+/* Workgroups, dealing, kernel variant and tuned time (ms, 0 if fixed) of the
+ * last batched launch of a step kind: mode 0 interpolation/state, 1 adjoint,
+ * 2 incremental state. Variant 1, 2, 4: canonical LDS box of that floor span
+ * for every problem; 0: generic box for every problem; 8: canonical for the
+ * problems that fit it, generic for the others. */
+reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
+                                 double *ms);
 
 /* Counters: batched step launches, graph captures, graph replays. */
 reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *graph_captures, int64_t *graph_replays);

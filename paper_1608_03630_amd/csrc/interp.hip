@@ -417,18 +417,17 @@ struct TileArgs {
     int last;
 };
 
-// One kernel for the three gather-based time steps; the mode picks the
-// epilogue (see k_interp, k_adjoint_step, k_incstate_step for the formulas).
-// Each thread owns kLinesPerWave points (one per x3 line it visits); their
-// displacements are loaded before the box is staged so that those HBM reads
-// overlap the staging, and each point's epilogue operands are requested
-// before its 64 LDS reads.
+// One body for the three gather-based time steps of one tile; the mode picks
+// the epilogue (see k_interp, k_adjoint_step, k_incstate_step for the
+// formulas). Each thread owns kLinesPerWave points (one per x3 line it
+// visits); their displacements are loaded before the box is staged so that
+// those HBM reads overlap the staging, and each point's epilogue operands are
+// requested before its 64 LDS reads. Ragged tiles are masked point by point;
+// every thread reaches the barrier.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
-                                                    const T *__restrict__ D, TileArgs args) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *box = reinterpret_cast<T *>(smem_raw);
-    const TileIdx t = tile_of(g);
+__device__ __forceinline__ void generic_tile(const Grid &g, const TileGeom &tg, const TileIdx &t,
+                                             const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
+                                             T *box) {
     const long N = g.N();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i3 = t.t3 * kTile3 + lane;
@@ -449,7 +448,6 @@ __global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T
     }
     stage_box(g, tg, t, f, box);
     __syncthreads();
-    if (!col_ok) return;
     const T *__restrict__ gam = static_cast<const T *>(args.gam);
     const T *__restrict__ grad = static_cast<const T *>(args.grad);
     const T *__restrict__ vt = static_cast<const T *>(args.vt);
@@ -482,12 +480,21 @@ __global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T
     }
 }
 
+template <typename T, int MODE>
+__global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
+                                                    const T *__restrict__ D, TileArgs args) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    generic_tile<T, MODE>(g, tg, tile_of(g), f, D, args, reinterpret_cast<T *>(smem_raw));
+}
+
 // The same three time steps with compile-time box strides: the box is stored
 // at the canonical extents kTile_j + 3 + S (any floor span <= S fits), so the
 // 64 LDS reads of a stencil are immediate offsets from one address, all index
 // arithmetic is 32-bit, and the per-thread point loop is fully unrolled with
 // no per-point branches (interior tiles only; the launcher sends ragged tiles
 // to k_tiled through the same grid via the `interior` test below).
+constexpr int kCanonMaxSpan = 4;  // largest canonical box: (12+S)^2 (67+S) floats <= 64 KB
+
 template <int S> struct Canon {
     static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S, C3 = kTile3 + 3 + S;
     static constexpr int elems = C1 * C2 * C3;
@@ -619,14 +626,15 @@ __global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, c
     canon_tile<T, MODE, S>(g, tg, tile_of(g), f, D, args, box);
 }
 
-// Batched persistent variant: gridDim.x workgroups walk a work list of
+// Batched persistent variants: gridDim.x workgroups walk a work list of
 // (pair, tile) items over all pairs of a batch (pairs sorted by tile0). With
 // `chunked` the items are dealt to the XCDs in contiguous chunks, so that each
-// XCD's L2 sees neighbouring tiles of one grid; otherwise round-robin.
-template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
-                                                            int total, int chunked) {
-    __shared__ T box[Canon<S>::elems];
+// XCD's L2 sees neighbouring tiles of one grid; otherwise round-robin. The
+// per-tile work is that of the single-grid kernels (same arithmetic, so a
+// pair's result does not depend on the batch).
+template <class F>
+__device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, int npairs, int total, int chunked,
+                                           F &&work) {
     const int nb = gridDim.x;
     int first = 0, end = total, stride = nb, start = blockIdx.x;
     if (chunked) {
@@ -647,7 +655,7 @@ __global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__re
         const PairStep &ps = pairs[lo];
         const Grid g = ps.g;
         const int b = item - ps.tile0;
-        const int nt3 = g.n3 / kTile3, nt2 = g.n2 / kTile2;
+        const int nt3 = (g.n3 + kTile3 - 1) / kTile3, nt2 = (g.n2 + kTile2 - 1) / kTile2;
         TileIdx t;
         t.t3 = b % nt3;
         t.t2 = (b / nt3) % nt2;
@@ -659,9 +667,38 @@ __global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__re
         a.out = ps.out;
         a.cs = ps.cs;
         a.last = ps.last;
-        canon_tile<T, MODE, S>(g, ps.tg, t, static_cast<const T *>(ps.f), static_cast<const T *>(ps.D), a, box);
+        work(g, ps.tg, t, ps.f, ps.D, a, ps.canon);
         __syncthreads();  // the next item restages the box
     }
+}
+
+template <typename T, int MODE, int S>
+__global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
+                                                            int total, int chunked) {
+    __shared__ T box[Canon<S>::elems];
+    walk_items(pairs, npairs, total, chunked,
+               [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
+                   const TileArgs &a, int) {
+                   canon_tile<T, MODE, S>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
+               });
+}
+
+// MIXED: pairs marked canonical take the canonical span-4 body, the others
+// the generic one, in one launch (dynamic LDS sized for both).
+template <typename T, int MODE, bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_batched_generic(const PairStep *__restrict__ pairs, int npairs,
+                                                              int total, int chunked) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *box = reinterpret_cast<T *>(smem_raw);
+    walk_items(pairs, npairs, total, chunked,
+               [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
+                   const TileArgs &a, int canon) {
+                   if (MIXED && canon)
+                       canon_tile<T, MODE, kCanonMaxSpan>(g, tg, t, static_cast<const T *>(f),
+                                                          static_cast<const T *>(D), a, box);
+                   else
+                       generic_tile<T, MODE>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
+               });
 }
 
 template <typename T>
@@ -734,6 +771,11 @@ hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *
         hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f, D, a);
         return hipGetLastError();
     }
+    if (whole && span <= kCanonMaxSpan && sizeof(T) == 4) {
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, kCanonMaxSpan>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f,
+                           D, a);
+        return hipGetLastError();
+    }
     const size_t lds = sizeof(T) * (size_t)tg.B[0] * tg.B[1] * tg.B[2];
     hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kThreads), lds, s, g, tg, f, D, a);
     return hipGetLastError();
@@ -743,33 +785,53 @@ inline unsigned nblocks(long N) { return (unsigned)((N + kThreads - 1) / kThread
 
 }  // namespace
 
-bool batchable(const Grid &g, const TileGeom &tg, int max_span) {
-    return g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0 && box_span(tg) <= max_span;
-}
-
-int tiles_of(const Grid &g) { return (int)ntiles(g); }
-
-hipError_t launch_batched_step(int mode, int span, const PairStep *pairs_dev, int npairs, int total, int nblocks_grid,
-                               int chunked, hipStream_t s) {
-    // chunked dealing needs a workgroup on every XCD
-    if (npairs < 1 || total < 1 || nblocks_grid < kXcds || span < 0 || span > 2) return hipErrorInvalidValue;
-#define REGK_BATCH_LAUNCH(M, S)                                                                                    \
-    hipLaunchKernelGGL((k_batched_canon<float, M, S>), dim3(nblocks_grid), dim3(kThreads), 0, s, pairs_dev, npairs, \
-                       total, chunked)
-    if (span <= 1) {
-        if (mode == TM_INTERP) REGK_BATCH_LAUNCH(TM_INTERP, 1);
-        else if (mode == TM_ADJOINT) REGK_BATCH_LAUNCH(TM_ADJOINT, 1);
-        else REGK_BATCH_LAUNCH(TM_INCSTATE, 1);
-    } else {
-        if (mode == TM_INTERP) REGK_BATCH_LAUNCH(TM_INTERP, 2);
-        else if (mode == TM_ADJOINT) REGK_BATCH_LAUNCH(TM_ADJOINT, 2);
-        else REGK_BATCH_LAUNCH(TM_INCSTATE, 2);
-    }
-#undef REGK_BATCH_LAUNCH
-    return hipGetLastError();
+bool canonical(const Grid &g, const TileGeom &tg, size_t esz) {
+    return esz == 4 && g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0 &&
+           box_span(tg) <= kCanonMaxSpan;
 }
 
 int batch_span(const TileGeom &tg) { return box_span(tg); }
+
+size_t canon_box_bytes() { return sizeof(float) * Canon<kCanonMaxSpan>::elems; }
+
+int tiles_of(const Grid &g) { return (int)ntiles(g); }
+
+template <typename T>
+hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep *pairs_dev, int npairs, int total,
+                               int nblocks_grid, int chunked, hipStream_t s) {
+    // chunked dealing needs a workgroup on every XCD
+    if (npairs < 1 || total < 1 || nblocks_grid < kXcds) return hipErrorInvalidValue;
+    const bool canon_variant = variant == 1 || variant == 2 || variant == kCanonMaxSpan;
+    if (!canon_variant && variant != 0 && variant != 8) return hipErrorInvalidValue;
+    if ((variant == 0 || variant == 8) && (lds == 0 || lds > 65536)) return hipErrorInvalidValue;
+    if (variant == 8 && lds < sizeof(T) * Canon<kCanonMaxSpan>::elems) return hipErrorInvalidValue;
+    if (variant != 0 && sizeof(T) != 4) return hipErrorInvalidValue;
+    const dim3 grid(nblocks_grid), block(kThreads);
+#define REGK_BATCH(M)                                                                                               \
+    do {                                                                                                            \
+        if (variant == 0)                                                                                           \
+            hipLaunchKernelGGL((k_batched_generic<T, M, false>), grid, block, lds, s, pairs_dev, npairs, total,     \
+                               chunked);                                                                            \
+        else if (variant == 8)                                                                                      \
+            hipLaunchKernelGGL((k_batched_generic<float, M, true>), grid, block, lds, s, pairs_dev, npairs, total,  \
+                               chunked);                                                                            \
+        else if (variant == 1)                                                                                      \
+            hipLaunchKernelGGL((k_batched_canon<float, M, 1>), grid, block, 0, s, pairs_dev, npairs, total, chunked); \
+        else if (variant == 2)                                                                                      \
+            hipLaunchKernelGGL((k_batched_canon<float, M, 2>), grid, block, 0, s, pairs_dev, npairs, total, chunked); \
+        else                                                                                                        \
+            hipLaunchKernelGGL((k_batched_canon<float, M, kCanonMaxSpan>), grid, block, 0, s, pairs_dev, npairs,    \
+                               total, chunked);                                                                     \
+    } while (0)
+    if (mode == TM_INTERP) REGK_BATCH(TM_INTERP);
+    else if (mode == TM_ADJOINT) REGK_BATCH(TM_ADJOINT);
+    else REGK_BATCH(TM_INCSTATE);
+#undef REGK_BATCH
+    return hipGetLastError();
+}
+
+template hipError_t launch_batched_step<float>(int, int, size_t, const PairStep *, int, int, int, int, hipStream_t);
+template hipError_t launch_batched_step<double>(int, int, size_t, const PairStep *, int, int, int, int, hipStream_t);
 
 namespace {
 

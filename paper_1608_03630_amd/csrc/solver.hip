@@ -100,6 +100,7 @@ struct reg_batch {
     uint64_t tick = 0;
     int64_t launches = 0, captures = 0, replays = 0;
     TuneEntry last[3];
+    int last_variant[3] = {0, 0, 0};
     std::string err;
 };
 
@@ -122,25 +123,38 @@ int kind_of_mode(int mode) {
     return mode == regk::STEP_INTERP ? REG_K_INTERP : mode == regk::STEP_ADJOINT ? REG_K_ADJOINT : REG_K_INCSTATE;
 }
 
-std::string tune_key(int mode, int span, const regk::PairStep *p, int n) {
+// One batched step launch: mode, kernel variant, dynamic LDS, table.
+struct Launch {
+    int mode = 0, variant = 0, n = 0, total = 0;
+    size_t lds = 0;
+    const regk::PairStep *dev = nullptr;
+};
+
+std::string tune_key(const Launch &L, const regk::PairStep *p, size_t esz) {
     std::vector<std::string> sizes;
-    for (int i = 0; i < n; i++)
+    for (int i = 0; i < L.n; i++)
         sizes.push_back(std::to_string(p[i].g.n1) + "x" + std::to_string(p[i].g.n2) + "x" + std::to_string(p[i].g.n3));
     std::sort(sizes.begin(), sizes.end());
-    std::string k = std::to_string(mode) + "/" + std::to_string(span);
+    // the dynamic LDS enters by occupancy class (16 KB steps), so that boxes
+    // that drift with the velocity do not trigger new tuning
+    std::string k = std::to_string(esz) + "/" + std::to_string(L.mode) + "/" + std::to_string(L.variant) + "/" +
+                    std::to_string((L.lds + 16383) / 16384);
     for (auto &s : sizes) k += "/" + s;
     return k;
 }
 
-// One batched step launch, with the launch shape from the tuner (tuning it
+// Runs a batched step launch with the launch shape from the tuner (tuning it
 // here, by timing every candidate on this very launch, when the shape is not
 // known yet and the stream is not being captured; every candidate computes
 // the same output from the same inputs).
-reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep *host, const regk::PairStep *dev,
-                          int n, int total, bool capturing) {
+template <typename T>
+reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *host, bool capturing) {
     TuneEntry e;
     bool have = false;
-    const std::string key = tune_key(mode, span, host, n);
+    const std::string key = tune_key(L, host, sizeof(T));
+    auto go = [&](int nb, int chunked) {
+        return regk::launch_batched_step<T>(L.mode, L.variant, L.lds, L.dev, L.n, L.total, nb, chunked, b->stream);
+    };
     if (b->fixed_blocks > 0) {
         e.blocks = b->fixed_blocks;
         e.chunked = b->fixed_chunked;
@@ -154,12 +168,12 @@ reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep
         }
     }
     if (!have && capturing) {  // no timing under capture: a safe default
-        e.blocks = std::max(8, std::min(total, 1024));
+        e.blocks = std::max(8, std::min(L.total, 1024));
         e.chunked = 1;
         have = true;
     }
     if (!have) {
-        std::vector<int> cand = {256, 512, 1024, 2048, 4096, total};
+        std::vector<int> cand = {256, 512, 1024, 2048, 4096, L.total};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
             return bfail(b, REG_EHIP, "hipEventCreate failed in the launch tuner");
@@ -168,10 +182,10 @@ reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep
         reg_status st = REG_OK;
         for (int chunked = 1; chunked >= 0 && st == REG_OK; chunked--) {
             for (int c : cand) {
-                const int nb = std::max(8, std::min(c, total));
-                hipError_t he = regk::launch_batched_step(mode, span, dev, n, total, nb, chunked, b->stream);
+                const int nb = std::max(8, std::min(c, L.total));
+                hipError_t he = go(nb, chunked);
                 if (he == hipSuccess) he = hipEventRecord(e0, b->stream);
-                if (he == hipSuccess) he = regk::launch_batched_step(mode, span, dev, n, total, nb, chunked, b->stream);
+                if (he == hipSuccess) he = go(nb, chunked);
                 if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
                 if (he == hipSuccess) he = hipEventSynchronize(e1);
                 float ms = 0;
@@ -185,7 +199,7 @@ reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep
                     best.blocks = nb;
                     best.chunked = chunked;
                 }
-                if (c >= total) break;
+                if (c >= L.total) break;
             }
         }
         (void)hipEventDestroy(e0);
@@ -195,12 +209,11 @@ reg_status batched_launch(reg_batch *b, int mode, int span, const regk::PairStep
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tune[key] = e;
     }
-    hipError_t he = timed(b->prof, kind_of_mode(mode), [&]() {
-        return regk::launch_batched_step(mode, span, dev, n, total, e.blocks, e.chunked, b->stream);
-    });
+    hipError_t he = timed(b->prof, kind_of_mode(L.mode), [&]() { return go(e.blocks, e.chunked); });
     if (he != hipSuccess) return bfail(b, REG_EHIP, std::string("batched step launch: ") + hipGetErrorString(he));
     b->launches++;
-    b->last[mode] = e;
+    b->last[L.mode] = e;
+    b->last_variant[L.mode] = L.variant;
     return REG_OK;
 }
 
@@ -231,11 +244,12 @@ struct Exec {
     // launchers for the rest
     void sl_step(Program &P, int mode, const std::vector<StepArg<T>> &args, const regk::PairStep *dev_region) {
         std::vector<regk::PairStep> items;
-        int span = 0, total = 0;
+        int total = 0, span = 0;
+        bool all_canon = true, any_canon = false;
+        size_t lds = 0;
         for (const auto &a : args) {
             const regk::TileGeom *tg = geom_of(a.ctx, a.D);
-            const bool batch = b && sizeof(T) == 4 && tg && regk::batchable(a.ctx->g, *tg, 2);
-            if (batch) {
+            if (b && tg) {
                 regk::PairStep ps{};
                 ps.g = a.ctx->g;
                 ps.tg = *tg;
@@ -248,11 +262,17 @@ struct Exec {
                 ps.cs = a.cs;
                 ps.last = a.last;
                 ps.tile0 = total;
+                ps.canon = regk::canonical(a.ctx->g, *tg, sizeof(T));
                 total += regk::tiles_of(a.ctx->g);
                 span = std::max(span, regk::batch_span(*tg));
+                all_canon = all_canon && ps.canon;
+                any_canon = any_canon || ps.canon;
+                lds = std::max(lds, sizeof(T) * (size_t)tg->B[0] * tg->B[1] * tg->B[2]);
                 items.push_back(ps);
                 continue;
             }
+            // no tile geometry (a box beyond the LDS) or a single problem: the
+            // single-problem launchers
             const StepArg<T> c = a;
             P.ops.push_back([c, mode, tg]() -> reg_status {
                 reg_ctx *ctx = c.ctx;
@@ -267,12 +287,28 @@ struct Exec {
             });
         }
         if (items.empty()) return;
+        // kernel variant: the canonical box of the largest span when every pair
+        // takes it, else the generic body (with the canonical one per pair when
+        // some pairs take it)
+        Launch L;
+        L.mode = mode;
+        L.n = (int)items.size();
+        L.total = total;
+        if (all_canon) {
+            L.variant = span <= 1 ? 1 : span <= 2 ? 2 : 4;
+            L.lds = 0;
+        } else if (any_canon && sizeof(T) == 4) {
+            L.variant = 8;
+            L.lds = std::max(lds, regk::canon_box_bytes());
+        } else {
+            L.variant = 0;
+            L.lds = lds;
+        }
         const size_t off = P.table.size();
         P.table.insert(P.table.end(), items.begin(), items.end());
-        const int n = (int)items.size();
-        const regk::PairStep *dev = dev_region + off;
-        P.ops.push_back([this, mode, span, n, total, off, dev, &P]() -> reg_status {
-            return batched_launch(b, mode, span, P.table.data() + off, dev, n, total, capturing);
+        L.dev = dev_region + off;
+        P.ops.push_back([this, L, off, &P]() -> reg_status {
+            return batched_launch<T>(b, L, P.table.data() + off, capturing);
         });
     }
 
@@ -1154,11 +1190,13 @@ reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, i
     return REG_OK;
 }
 
-reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, double *ms) {
+reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
+                                 double *ms) {
     BATCH_OK(b);
-    if (mode < 0 || mode > 2 || !blocks || !chunked || !ms) return bfail(b, REG_EINVAL, "bad launch query");
+    if (mode < 0 || mode > 2 || !blocks || !chunked || !variant || !ms) return bfail(b, REG_EINVAL, "bad launch query");
     *blocks = b->last[mode].blocks;
     *chunked = b->last[mode].chunked;
+    *variant = b->last_variant[mode];
     *ms = b->last[mode].ms;
     return REG_OK;
 }

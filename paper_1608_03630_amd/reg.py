@@ -124,7 +124,7 @@ _SIGS = {
     "reg_batch_ctx": [_P, ctypes.c_int32, ctypes.POINTER(_P)],
     "reg_batch_set_launch": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
     "reg_batch_launch_info": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                              ctypes.POINTER(ctypes.c_double)],
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
     "reg_batch_stats": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_int64)],
     "reg_batch_profile": [_P, ctypes.c_int],
@@ -448,10 +448,11 @@ class Batch:
               "reg_batch_set_launch")
 
     def reg_batch_launch_info(self, mode):
-        b, c, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _bchk(lib().reg_batch_launch_info(self.handle, int(mode), ctypes.byref(b), ctypes.byref(c), ctypes.byref(ms)),
-              self.handle, "reg_batch_launch_info")
-        return b.value, c.value, ms.value
+        """(workgroups, chunked, kernel variant, tuned ms) of the last batched launch of a step kind."""
+        b, c, v, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _bchk(lib().reg_batch_launch_info(self.handle, int(mode), ctypes.byref(b), ctypes.byref(c), ctypes.byref(v),
+                                          ctypes.byref(ms)), self.handle, "reg_batch_launch_info")
+        return b.value, c.value, v.value, ms.value
 
     def reg_batch_stats(self):
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

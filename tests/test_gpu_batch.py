@@ -3,9 +3,10 @@ problem's results through the batched persistent launches, the autotuned
 launch shapes and the captured matvec graphs equal, bit for bit, those of the
 single-problem entry points on a context of its own (same kernels, same
 arguments), and the batched transport matches the FP64 oracle like the single
-one. The mix holds grids in whole 8x8x64 tiles (batched kernel), a ragged
-grid (single-problem launchers inside the batch), different nt and both the
-compressible and the isochoric case."""
+one. The mix holds grids in whole 8x8x64 tiles (canonical LDS boxes), a
+ragged grid (generic box in the same launch), different nt, both the
+compressible and the isochoric case, small and multi-cell steps (canonical and
+generic boxes side by side) and both precisions."""
 import numpy as np
 import pytest
 import torch
@@ -36,7 +37,8 @@ def reg():
 
 
 def _params(reg, shape, nt, iso, **kw):
-    return reg.reg_default_params(shape, nt=nt, prec=0, beta=BETA, isochoric=iso, **kw)
+    kw.setdefault("prec", 0)
+    return reg.reg_default_params(shape, nt=nt, beta=BETA, isochoric=iso, **kw)
 
 
 @pytest.fixture(scope="module")
@@ -70,24 +72,28 @@ def _singles(reg, cases, **kw):
     return out
 
 
-def test_batch_transport_matches_single_and_oracle(reg, cases):
-    b = _batch(reg, cases)
-    vs = [to_vel(c["v"], ctx) for c, ctx in zip(cases, b.contexts)]
+# velocity scales: small steps (canonical boxes), and steps of several cells
+# per step on the larger grids (generic boxes beside canonical ones)
+@pytest.mark.parametrize("prec,scale", [(0, 0.3), (0, 4.0), (1, 0.3)])
+def test_batch_transport_matches_single_and_oracle(reg, cases, prec, scale):
+    b = _batch(reg, cases, prec=prec)
+    vs = [to_vel(scale * c["v"], ctx) for c, ctx in zip(cases, b.contexts)]
     r0 = [to_dev(c["rhoT"], ctx) for c, ctx in zip(cases, b.contexts)]
     rb = b.reg_batch_transport_forward(vs, r0)
     torch.cuda.synchronize()
     st = b.reg_batch_stats()
-    say(f"  stats {st}, interp launch {b.reg_batch_launch_info(0)}")
-    assert st["batched_launches"] > 0
-    singles = _singles(reg, cases)
+    say(f"  stats {st}, interp launch (blocks, chunked, variant, ms) {b.reg_batch_launch_info(0)}")
+    # double-precision boxes of 64-wide tiles exceed the LDS: direct gathers
+    assert (st["batched_launches"] > 0) == (prec == 0)
+    singles = _singles(reg, cases, prec=prec)
     for i, (ctx, c) in enumerate(zip(singles, cases)):
-        rs = ctx.reg_transport_forward(to_vel(c["v"], ctx), to_dev(c["rhoT"], ctx))
+        rs = ctx.reg_transport_forward(to_vel(scale * c["v"], ctx), to_dev(c["rhoT"], ctx))
         torch.cuda.synchronize()
         assert torch.equal(rb[i], rs), f"problem {i}"
-        ref = oracle.transport_forward(c["P"], c["v"], c["rhoT"])
+        ref = oracle.transport_forward(c["P"], scale * c["v"], c["rhoT"])
         err = rel_l2(to_host(rb[i]), ref)
         say(f"  problem {i} {PROBLEMS[i]}: rel-L2 vs oracle {err:.2e}")
-        assert err <= TOL[("transport", 0)]
+        assert err <= TOL[("transport", prec)]
 
 
 @pytest.mark.parametrize("blocks,chunked", [(8, 0), (8, 1), (72, 1), (4096, 0)])
@@ -100,7 +106,7 @@ def test_batch_launch_shape_does_not_change_results(reg, cases, blocks, chunked)
     fixed = b.reg_batch_transport_forward(vs, r0)
     torch.cuda.synchronize()
     info = b.reg_batch_launch_info(0)
-    say(f"  fixed launch {info}")
+    say(f"  fixed launch (blocks, chunked, variant, ms) {info}")
     assert info[0] == blocks and info[1] == chunked
     for i in range(len(PROBLEMS)):
         assert torch.equal(auto[i], fixed[i]), f"problem {i}"

@@ -48,6 +48,33 @@ def test_interp(reg, prec, shape, cells):
     assert rel_l2(out, ref) <= TOL[("interp", prec)]
 
 
+def _max_tile_span(D, tile=(8, 8, 64)):
+    """Largest floor-range of the displacement over any tile (per axis), the
+    quantity that picks the LDS kernel variant."""
+    fl = np.floor(D)
+    n = D.shape[1:]
+    worst = 0
+    for a in range(0, n[0], tile[0]):
+        for b in range(0, n[1], tile[1]):
+            for c in range(0, n[2], tile[2]):
+                blk = fl[:, a:a + tile[0], b:b + tile[1], c:c + tile[2]]
+                worst = max(worst, int((blk.max(axis=(1, 2, 3)) - blk.min(axis=(1, 2, 3))).max()))
+    return worst
+
+
+@pytest.mark.parametrize("cells", [0.4, 0.8, 1.2, 2.0, 3.0, 8.0])
+def test_interp_whole_tiles_all_box_variants(reg, cells):
+    """Grids of whole 8x8x64 tiles in single precision take the canonical LDS
+    kernels (box spans 1, 2, 4) or, beyond, the generic one; all must match."""
+    shape = (16, 24, 128)
+    ctx = make_ctx(reg, shape, 0)
+    f = rounded(synth.smooth_random_field(shape, 104, kmax=5), 0)
+    D = rounded(synth.displacement(shape, 105, max_cells=cells), 0)
+    say(f"  max floor span per tile {_max_tile_span(D)}")
+    out = to_host(ctx.reg_interp(to_dev(f, ctx), to_dev(D, ctx)))
+    assert rel_l2(out, oracle.interp(f, D)) <= TOL[("interp", 0)]
+
+
 @pytest.mark.parametrize("prec", [1, 0])
 def test_interp_integer_shift_is_exact(reg, prec):
     shape = RAGGED
