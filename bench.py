@@ -118,6 +118,123 @@ def cpu_baseline(counts, n):
     }
 
 
+# config of the batched workload: (grid, count); every pair like the 128^3
+# blob workload (FP32 fields, nt = 8, isochoric, beta = 1e-3)
+BATCH_SIZES = [(64, 8), (128, 8), (192, 6), (256, 2)]
+
+
+def run_batch(reg, torch, args):
+    """24 independent pairs of mixed sizes solved together: one persistent
+    launch per transport step, autotuned launch shapes, graph-replayed
+    matvecs. Reports pairs/s of the batched solve, per-size latency, and the
+    same pairs solved one after another on the same contexts."""
+    import numpy as np
+
+    import synth
+
+    params, shapes = [], []
+    for n, count in BATCH_SIZES:
+        for _ in range(count):
+            shapes.append((n, n, n))
+            params.append(reg.reg_default_params((n, n, n), nt=8, prec=0, beta=1e-3, isochoric=1, gtol=1e-2,
+                                                 max_newton=50, max_pcg=100, max_ls=20))
+    t0 = time.time()
+    b = reg.Batch(params)
+    vt_true, rhoT = [], []
+    for i, shape in enumerate(shapes):
+        case = synth.blob_case(shape, seed=4000 + i)
+        rhoT.append(torch.from_numpy(case["rhoT"].astype(np.float32)).cuda())
+        vt_true.append(torch.from_numpy(case["v_true"]).cuda())
+    rhoR = b.reg_batch_transport_forward(vt_true, rhoT)
+    for i in range(len(shapes)):
+        b.reg_set_images(i, rhoT[i], rhoR[i])
+    torch.cuda.synchronize()
+    log(f"[bench] batch of {len(shapes)} pairs built in {time.time() - t0:.1f} s "
+        f"(workspace {b.workspace.numel() / 2**30:.1f} GiB)")
+    vs = [torch.zeros((3,) + s, dtype=torch.float64, device="cuda") for s in shapes]
+    for w in range(args.warmup):
+        for v in vs:
+            v.zero_()
+        t = time.perf_counter()
+        _, reps = b.reg_batch_solve(vs)
+        log(f"[bench] warmup batch solve {w}: {time.perf_counter() - t:.3f} s")
+    b.reg_batch_profile(True)
+    st0 = b.reg_batch_stats()
+    times, reps = [], None
+    for k in range(args.steps):
+        for v in vs:
+            v.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, reps = b.reg_batch_solve(vs)
+        times.append(time.perf_counter() - t)
+        log(f"[bench] batch solve {k}: {times[-1]:.3f} s")
+    prof = b.reg_batch_profile_read()
+    b.reg_batch_profile(False)
+    st1 = b.reg_batch_stats()
+    sec = sum(times) / len(times)
+    per_size = {}
+    for shape, rep in zip(shapes, reps):
+        d = per_size.setdefault(f"{shape[0]}^3", {"latency_s": [], "gn_steps": [], "matvecs": [], "mismatch": []})
+        d["latency_s"].append(rep["seconds_total"])
+        d["gn_steps"].append(rep["n_iter"])
+        d["matvecs"].append(rep["matvecs"])
+        d["mismatch"].append(rep["final_mismatch"])
+    for d in per_size.values():
+        for k in list(d):
+            d[k] = {"median": float(np.median(d[k])), "mean": float(np.mean(d[k])), "max": float(np.max(d[k]))}
+    # the same pairs one after another (single-problem path, same contexts)
+    t = time.perf_counter()
+    seq = []
+    for i, c in enumerate(b.contexts):
+        vs[i].zero_()
+        _, rep = c.reg_solve(vs[i])
+        seq.append(rep["seconds_total"])
+    torch.cuda.synchronize()
+    seq_sec = time.perf_counter() - t
+    # batched step kernel throughput: the state transport of all pairs
+    b.reg_batch_profile(True)
+    b.reg_batch_transport_forward(vt_true, rhoT, rhoR)
+    p2 = b.reg_batch_profile_read()
+    b.reg_batch_profile(False)
+    pts = sum(s[0] * s[1] * s[2] for s in shapes)
+    n_int, ms_int = p2["interp"]
+    out = {
+        "metric": "batched registration throughput (24 mixed-size pairs, one persistent launch per transport step)",
+        "value": len(shapes) / sec,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "8x64^3 + 8x128^3 + 6x192^3 + 2x256^3 blob pairs (seeds 4000+i), divergence-free |k|<=4 "
+                        "velocity of max speed 0.5, nt=8, isochoric, beta=1e-3, gtol 1e-2, FP32 fields + FP64 "
+                        "reductions",
+            "pairs": len(shapes),
+            "points_per_step": pts,
+        },
+        "per_size": per_size,
+        "sequential": {"seconds": seq_sec, "pairs_per_s": len(shapes) / seq_sec},
+        "batch_speedup": seq_sec / sec,
+        "graph": {"captures": st1["graph_captures"] - st0["graph_captures"],
+                  "replays": st1["graph_replays"] - st0["graph_replays"],
+                  "batched_launches": st1["batched_launches"] - st0["batched_launches"]},
+        "launch": {m: dict(zip(("blocks", "chunked", "variant", "tuned_ms"), b.reg_batch_launch_info(i)))
+                   for i, m in enumerate(("interp", "adjoint", "incstate"))},
+        "kernel_ms": {k: {"launches": n_, "ms": t_} for k, (n_, t_) in prof.items() if n_},
+        "batched_interp": {"launches": n_int, "avg_ms": ms_int / max(n_int, 1),
+                           "gpts_s": pts * n_int / (ms_int * 1e-3) / 1e9 if ms_int else None,
+                           "gb_s": BYTES_PER_POINT["interp"] * pts * n_int / (ms_int * 1e-3) / 1e9 if ms_int else None},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,10 +245,10 @@ def main():
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
-    ap.add_argument("--mode", choices=["solve", "kernels", "copy"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch"], default="solve",
                     help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
                          "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
-                         "calibration of the byte counters")
+                         "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
@@ -151,6 +268,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"mode": "copy", "bytes_read": a.numel() * 4, "bytes_written": b.numel() * 4}))
+        return
+    if args.mode == "batch":
+        run_batch(reg, torch, args)
         return
     if args.mode == "kernels":
         ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
