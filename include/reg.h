@@ -293,6 +293,70 @@ reg_status reg_batch_hessian_matvec(reg_batch *b, const void *const *vt, void *c
  * the other problems still ran to completion). Synchronises. */
 reg_status reg_batch_solve(reg_batch *b, void *const *v_inout, reg_report *reports);
 
+/* ------------------------------------------------------ learned warm start */
+
+/* A small network proposes the initial velocity of a solve (not part of the
+ * paper, whose solver starts from v = 0 or the previous continuation level;
+ * the solver stays the judge). It is a 3-level 3D convolutional
+ * encoder-decoder on an n^3 grid (n = 64 in use): twelve 3x3x3 convolutions
+ * with circular padding (channels 2->16->16, stride-2 16->32, 32->32,
+ * stride-2 32->64, 64->64, 64->64, nearest upsampling, 64->32, concat with
+ * the 32-channel encoder level -> 32, upsampling, 32->16, concat with the
+ * 16-channel level -> 16, head 16->3), ReLU after every convolution but the
+ * head. Input channels: (rho_T, rho_R) sampled on n^3; output: v [3][n^3].
+ * The convolutions run on the matrix cores in BF16 with FP32 accumulation;
+ * parameters are FP32 masters, in this order per layer: W[cout][cin][3][3][3]
+ * (cross-correlation: y[o,p] = b[o] + sum W[o,c,a,b,d] x[c, s p + (a-1, b-1,
+ * d-1)]) then b[cout]. Training minimises the mean squared error to target
+ * velocities with Adam (beta1 0.9, beta2 0.999, eps 1e-8). */
+typedef struct reg_net reg_net;
+
+/* Number of FP32 parameters. */
+reg_status reg_net_param_count(int64_t *count);
+
+/* Device workspace of a network on an n^3 grid (n a multiple of 16, FFT
+ * friendly, 16 <= n <= 256). It includes a single-precision context on n^3
+ * used for spectral resampling in reg_warmstart. */
+reg_status reg_net_workspace_size(int32_t n, size_t *bytes);
+
+/* Creates the network over a caller-owned workspace (256-byte aligned);
+ * parameters start at zero (set them with reg_net_set_params). */
+reg_status reg_net_create(int32_t n, void *workspace, size_t bytes, void *hip_stream, reg_net **out);
+reg_status reg_net_destroy(reg_net *net);
+const char *reg_net_last_error(const reg_net *net);
+
+/* Copies the parameters in from / out to a device array of
+ * reg_net_param_count floats. Setting them resets the Adam moments. */
+reg_status reg_net_set_params(reg_net *net, const float *params);
+reg_status reg_net_get_params(reg_net *net, float *params);
+
+/* v [3][n^3] (device, float) = network(rho_T, rho_R), images float n^3. */
+reg_status reg_net_forward(reg_net *net, const float *rho_T, const float *rho_R, float *v);
+
+/* After reg_net_forward: the output of convolution `layer` (0..11, after its
+ * ReLU) as float [cout][m^3] on that layer's grid m (device). */
+reg_status reg_net_activation(reg_net *net, int32_t layer, float *out);
+
+/* Loss 1/(3 n^3) ||v - target||^2 of one sample and its gradient with
+ * respect to every parameter (device float array, param_count entries).
+ * Synchronises. */
+reg_status reg_net_loss_grad(reg_net *net, const float *rho_T, const float *rho_R, const float *target, float *grad,
+                             double *loss);
+
+/* One Adam step on the mean loss over `batch` samples (host arrays of device
+ * pointers to float n^3 images and [3][n^3] targets); returns the mean loss
+ * before the step. Synchronises. */
+reg_status reg_net_train_step(reg_net *net, int32_t batch, const float *const *rho_T, const float *const *rho_R,
+                              const float *const *target, double lr, double *loss);
+
+/* Warm start of a single-precision context with images set: its images are
+ * resampled spectrally to the network grid, the network proposes v, v is
+ * resampled to the context's grid (double, velocity space) and projected
+ * when isochoric, and the proposal is kept only if min det(grad y1) > 0
+ * (reg_deformation); otherwise v_out = 0 and *used_fallback = 1. detmin (may
+ * be NULL) receives min det(grad y1) of the proposal. Synchronises. */
+reg_status reg_warmstart(reg_ctx *ctx, reg_net *net, void *v_out, int32_t *used_fallback, double *detmin);
+
 /* ------------------------------------------------------------- profiling */
 
 /* Kernel families timed by the profiler. */

@@ -1,0 +1,466 @@
+// Kernels of the learned warm-start network: a 3-level 3D convolutional
+// encoder-decoder (16/32/64 channels, 3x3x3 kernels, circular padding, skip
+// concatenation) that maps the template and reference images on a 64^3 grid
+// to an initial velocity. Not part of the paper's method: its Gauss-Newton
+// solve starts from v = 0 (or the previous continuation level); this network
+// only proposes the starting point and the solver stays the judge.
+//
+// Convolutions are implicit GEMMs on the matrix cores: for 16 output points
+// (M) x 16 output channels (N), the K dimension runs over (tap, input
+// channel) in chunks of 16 with v_mfma_f32_16x16x16_bf16 (BF16 operands,
+// FP32 accumulation). Activations and activation gradients are BF16,
+// channel-last ([point][channel], x3 fastest over points); weights are FP32
+// masters with BF16 copies in the two layouts the forward and the
+// backward-data GEMMs read. Lane layout of the MFMA (16x16x16, 64 lanes):
+// lane l holds A[l%16][4(l/16)+i], B[4(l/16)+i][l%16] and
+// D[4(l/16)+i][l%16], i = 0..3.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "net.hpp"
+
+namespace regn {
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ int wrap(int x, int n) {
+    x %= n;
+    return x < 0 ? x + n : x;
+}
+
+// source point of output point (i, j, k) for tap offsets (d1, d2, d3); -1
+// when the tap does not reach a source point (odd parity in CONV_BWD2)
+template <int MODE>
+__device__ __forceinline__ int source(int i, int j, int k, int d1, int d2, int d3, int n_out, int n_in) {
+    if (MODE == CONV_FWD1) return (wrap(i + d1, n_in) * n_in + wrap(j + d2, n_in)) * n_in + wrap(k + d3, n_in);
+    if (MODE == CONV_BWD1) return (wrap(i - d1, n_in) * n_in + wrap(j - d2, n_in)) * n_in + wrap(k - d3, n_in);
+    if (MODE == CONV_FWD2)
+        return (wrap(2 * i + d1, n_in) * n_in + wrap(2 * j + d2, n_in)) * n_in + wrap(2 * k + d3, n_in);
+    // CONV_BWD2: fine output grid, coarse input grid
+    const int y1 = wrap(i - d1, n_out), y2 = wrap(j - d2, n_out), y3 = wrap(k - d3, n_out);
+    if ((y1 | y2 | y3) & 1) return -1;
+    return ((y1 >> 1) * n_in + (y2 >> 1)) * n_in + (y3 >> 1);
+}
+
+// One wavefront: 16 consecutive output points x NB*16 output channels.
+template <int MODE, int NB>
+__global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int p0 = (blockIdx.x * (kThreads / 64) + wave) * 16;
+    const long P = (long)a.n_out * a.n_out * a.n_out;
+    if (p0 >= P) return;  // whole wavefronts only (P is a multiple of 16)
+    const int g = lane >> 4, r = lane & 15;
+    // coordinates of this lane's A-row point
+    const int pa = p0 + r;
+    const int n = a.n_out;
+    const int ai = pa / (n * n), aj = (pa / n) % n, ak = pa % n;
+    v4f acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const uint16_t *__restrict__ in = a.in;
+    const uint16_t *__restrict__ W = a.w;
+    const int ccin = a.cin >> 4;
+    for (int t = 0; t < 27; t++) {
+        const int d1 = t / 9 - 1, d2 = (t / 3) % 3 - 1, d3 = t % 3 - 1;
+        const int q = source<MODE>(ai, aj, ak, d1, d2, d3, a.n_out, a.n_in);
+        const uint16_t *src = in + (long)(q < 0 ? 0 : q) * a.in_cs + 4 * g;
+        const uint16_t *wt = W + ((long)t * a.cout + r) * a.cin + 4 * g;
+        for (int c = 0; c < ccin; c++) {
+            v4s av = q < 0 ? v4s{0, 0, 0, 0} : *reinterpret_cast<const v4s *>(src + 16 * c);
+#pragma unroll
+            for (int b = 0; b < NB; b++) {
+                const v4s bv = *reinterpret_cast<const v4s *>(wt + (long)b * 16 * a.cin + 16 * c);
+                acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[b], 0, 0, 0);
+            }
+        }
+    }
+    // epilogue: lane holds D[4g+i][r] = (point p0+4g+i, channel b*16+r)
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int co = b * 16 + r;
+        const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const long p = p0 + 4 * g + i;
+            float v = acc[b][i] + bias;
+            if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
+            if (a.relu) v = fmaxf(v, 0.f);
+            if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
+            if (a.out_f32) {
+                if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
+            } else {
+                a.out[p * a.out_cs + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// Weight gradient partials: one workgroup per (point chunk, tap) forms
+// sum_p dz[p][co] x[src(p, t)][ci] over its points for every (co, ci) tile.
+// A = dz^T (co x p), B = x_src (p x ci), staged through LDS in slices of
+// kSlice points.
+constexpr int kSlice = 64;
+constexpr int kChunkSlices = 8;  // points per workgroup = 512
+
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
+    __shared__ uint16_t sdz[kSlice * 64];
+    __shared__ uint16_t sx[kSlice * 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int t = blockIdx.y;
+    const int d1 = t / 9 - 1, d2 = (t / 3) % 3 - 1, d3 = t % 3 - 1;
+    const int n = a.n_out;
+    const long P = (long)n * n * n;
+    const int cb = a.cout >> 4, ib = a.cin >> 4;
+    const int tiles = cb * ib;  // <= 16: at most 4 per wavefront
+    v4f acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
+    const long base = (long)blockIdx.x * kSlice * kChunkSlices;
+    for (int sl = 0; sl < kChunkSlices; sl++) {
+        const long s0 = base + (long)sl * kSlice;
+        if (s0 >= P) break;
+        // stage dz[s0 .. s0+kSlice)[0..cout) and x[src][0..cin)
+        for (int e = threadIdx.x; e < kSlice * a.cout; e += kThreads) {
+            const int pp = e / a.cout, c = e - pp * a.cout;
+            sdz[pp * a.cout + c] = a.dz[(s0 + pp) * a.dz_cs + c];
+        }
+        for (int e = threadIdx.x; e < kSlice * a.cin; e += kThreads) {
+            const int pp = e / a.cin, c = e - pp * a.cin;
+            const long p = s0 + pp;
+            const int i = (int)(p / ((long)n * n)), j = (int)((p / n) % n), k = (int)(p % n);
+            const int q = source<MODE>(i, j, k, d1, d2, d3, a.n_out, a.n_in);
+            sx[pp * a.cin + c] = a.x[(long)q * a.x_cs + c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int tile = wave + 4 * u;
+            if (tile >= tiles) continue;
+            const int co0 = (tile / ib) * 16, ci0 = (tile % ib) * 16;
+            for (int kk = 0; kk < kSlice; kk += 16) {
+                v4s av, bv;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int pp = kk + 4 * g + i;
+                    av[i] = (short)sdz[pp * a.cout + co0 + r];
+                    bv[i] = (short)sx[pp * a.cin + ci0 + r];
+                }
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[u], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // partials[chunk][t][co][ci]
+    float *out = a.partials + ((long)blockIdx.x * 27 + t) * a.cout * a.cin;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        const int tile = wave + 4 * u;
+        if (tile >= tiles) continue;
+        const int co0 = (tile / ib) * 16, ci0 = (tile % ib) * 16;
+#pragma unroll
+        for (int i = 0; i < 4; i++) out[(co0 + 4 * g + i) * a.cin + ci0 + r] = acc[u][i];
+    }
+}
+
+// dW[co][ci][t] += scale * sum over chunks (fixed order); real channels only
+__global__ __launch_bounds__(kThreads) void k_wgrad_reduce(const float *__restrict__ partials, int chunks, int cout,
+                                                           int cin, int cout_real, int cin_real, float scale,
+                                                           float *__restrict__ dW) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;  // over cout_real * cin_real * 27
+    if (e >= cout_real * cin_real * 27) return;
+    const int t = e % 27, ci = (e / 27) % cin_real, co = e / (27 * cin_real);
+    const long stride = 27L * cout * cin;
+    const float *p = partials + ((long)t * cout + co) * cin + ci;
+    float s = 0.f;
+    for (int c = 0; c < chunks; c++) s += p[c * stride];
+    dW[e] += scale * s;
+}
+
+// db[co] += scale * sum_p dz[p][co] (one workgroup per channel, fixed order)
+__global__ __launch_bounds__(kThreads) void k_bias_grad(const uint16_t *__restrict__ dz, int dz_cs, long P,
+                                                        float scale, float *__restrict__ db) {
+    const int co = blockIdx.x;
+    float s = 0.f;
+    for (long p = threadIdx.x; p < P; p += kThreads) s += bf2f(dz[p * dz_cs + co]);
+    __shared__ float sm[kThreads];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[co] += scale * sm[0];
+}
+
+// fine[q][c] = coarse[q/2][c] (nearest upsampling by 2 per axis)
+__global__ __launch_bounds__(kThreads) void k_up2(const uint16_t *__restrict__ x, int n_coarse, int C,
+                                                  uint16_t *__restrict__ y) {
+    const int nf = 2 * n_coarse;
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    const long total = (long)nf * nf * nf * C;
+    if (e >= total) return;
+    const int c = (int)(e % C);
+    const long q = e / C;
+    const int k = (int)(q % nf), j = (int)((q / nf) % nf), i = (int)(q / ((long)nf * nf));
+    y[e] = x[(((long)(i >> 1) * n_coarse + (j >> 1)) * n_coarse + (k >> 1)) * C + c];
+}
+
+// dz[p][c] = (sum of the 8 children of p in dy) * (mask[p][c] > 0)
+__global__ __launch_bounds__(kThreads) void k_up2_bwd(const uint16_t *__restrict__ dy, int n_coarse, int C,
+                                                      const uint16_t *__restrict__ mask, int mask_cs,
+                                                      uint16_t *__restrict__ dz) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    const long total = (long)n_coarse * n_coarse * n_coarse * C;
+    if (e >= total) return;
+    const int c = (int)(e % C);
+    const long p = e / C;
+    const int nf = 2 * n_coarse;
+    const int k = (int)(p % n_coarse), j = (int)((p / n_coarse) % n_coarse), i = (int)(p / ((long)n_coarse * n_coarse));
+    float s = 0.f;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int d = 0; d < 2; d++)
+                s += bf2f(dy[(((long)(2 * i + a) * nf + (2 * j + b)) * nf + (2 * k + d)) * C + c]);
+    if (!(bf2f(mask[p * mask_cs + c]) > 0.f)) s = 0.f;
+    dz[e] = f2bf(s);
+}
+
+// dz[p][c] = src[p][c] * (mask[p][c] > 0) for a channel slice
+__global__ __launch_bounds__(kThreads) void k_mask(const uint16_t *__restrict__ src, int src_cs, long P, int C,
+                                                   const uint16_t *__restrict__ mask, int mask_cs,
+                                                   uint16_t *__restrict__ dz) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= P * C) return;
+    const int c = (int)(e % C);
+    const long p = e / C;
+    dz[e] = bf2f(mask[p * mask_cs + c]) > 0.f ? src[p * src_cs + c] : (uint16_t)0;
+}
+
+// network input: [p][16] with channels (rho_T, rho_R, 0, ...)
+__global__ __launch_bounds__(kThreads) void k_pack_input(const float *__restrict__ a, const float *__restrict__ b,
+                                                         long P, uint16_t *__restrict__ x) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= P * 16) return;
+    const int c = (int)(e & 15);
+    const long p = e >> 4;
+    x[e] = c == 0 ? f2bf(a[p]) : c == 1 ? f2bf(b[p]) : (uint16_t)0;
+}
+
+// MSE: per-block partial sums of (v - t)^2 (double) and the head's
+// pre-activation gradient dz[p][16] = 2 (v - t) / numel (channels >= 3 zero)
+__global__ __launch_bounds__(kThreads) void k_mse(const float *__restrict__ v, const float *__restrict__ tgt, long P,
+                                                  double *__restrict__ partials, uint16_t *__restrict__ dz) {
+    const long p = (long)blockIdx.x * kThreads + threadIdx.x;
+    double s = 0.0;
+    if (p < P) {
+        const float scale = 2.f / (3.f * (float)P);
+        for (int c = 0; c < 16; c++) {
+            float gval = 0.f;
+            if (c < 3) {
+                const float r = v[c * P + p] - tgt[c * P + p];
+                s += (double)r * r;
+                gval = scale * r;
+            }
+            dz[p * 16 + c] = f2bf(gval);
+        }
+    }
+    __shared__ double sm[kThreads];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
+__global__ void k_sum(const double *__restrict__ partials, int n, double scale, double *__restrict__ out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s += partials[i];
+        *out += scale * s;
+    }
+}
+
+// Adam with bias-corrected moments, FP32
+__global__ __launch_bounds__(kThreads) void k_adam(long n, float *__restrict__ w, const float *__restrict__ g,
+                                                   float *__restrict__ m, float *__restrict__ s, float lr, float b1,
+                                                   float b2, float eps, float c1, float c2) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    const float gr = g[e];
+    const float mi = b1 * m[e] + (1.f - b1) * gr;
+    const float si = b2 * s[e] + (1.f - b2) * gr * gr;
+    m[e] = mi;
+    s[e] = si;
+    w[e] -= lr * (mi / c1) / (sqrtf(si / c2) + eps);
+}
+
+// BF16 weight copies: fwd[t][co_pad][ci_pad] and bwd[t][ci_pad][co_pad] from
+// the master W[co][ci][t] (zero padding)
+__global__ __launch_bounds__(kThreads) void k_pack_weights(const float *__restrict__ W, int cout, int cin, int cout_pad,
+                                                           int cin_pad, uint16_t *__restrict__ fwd,
+                                                           uint16_t *__restrict__ bwd) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    if (e >= 27 * cout_pad * cin_pad) return;
+    const int ci = e % cin_pad, co = (e / cin_pad) % cout_pad, t = e / (cin_pad * cout_pad);
+    const uint16_t v = (co < cout && ci < cin) ? f2bf(W[((long)co * cin + ci) * 27 + t]) : (uint16_t)0;
+    fwd[e] = v;
+    bwd[((long)t * cin_pad + ci) * cout_pad + co] = v;
+}
+
+// out[c][p] = x[p][c] for c < C (BF16 channel-last to FP32 channel-first)
+__global__ __launch_bounds__(kThreads) void k_unpack(const uint16_t *__restrict__ x, int cs, int C, long P,
+                                                     float *__restrict__ out) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= P * C) return;
+    const long p = e % P;
+    const int c = (int)(e / P);
+    out[e] = bf2f(x[p * cs + c]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_f32(long n, float v, float *__restrict__ x) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) x[e] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale_f32(long n, float s, float *__restrict__ x) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) x[e] *= s;
+}
+
+inline unsigned blocks(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
+    const long P = (long)a.n_out * a.n_out * a.n_out;
+    if (P % 16 || a.cin % 16 || a.cout % 16 || a.cout > 64 || a.cin > 64 || a.in_cs % 4) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((P / 16 + 3) / 4);
+    const int NB = a.cout / 16;
+#define REGN_CONV(M)                                                                                  \
+    do {                                                                                              \
+        if (NB == 1) hipLaunchKernelGGL((k_conv<M, 1>), dim3(nb), dim3(kThreads), 0, s, a);          \
+        else if (NB == 2) hipLaunchKernelGGL((k_conv<M, 2>), dim3(nb), dim3(kThreads), 0, s, a);     \
+        else if (NB == 4) hipLaunchKernelGGL((k_conv<M, 4>), dim3(nb), dim3(kThreads), 0, s, a);     \
+        else return hipErrorInvalidValue;                                                             \
+    } while (0)
+    switch (mode) {
+    case CONV_FWD1: REGN_CONV(CONV_FWD1); break;
+    case CONV_FWD2: REGN_CONV(CONV_FWD2); break;
+    case CONV_BWD1: REGN_CONV(CONV_BWD1); break;
+    case CONV_BWD2: REGN_CONV(CONV_BWD2); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef REGN_CONV
+    return hipGetLastError();
+}
+
+int wgrad_chunks(int n_out) {
+    const long P = (long)n_out * n_out * n_out;
+    const long per = (long)kSlice * kChunkSlices;
+    return (int)((P + per - 1) / per);
+}
+
+hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {
+    const long P = (long)a.n_out * a.n_out * a.n_out;
+    if (P % kSlice || a.cin % 16 || a.cout % 16 || a.cin > 64 || a.cout > 64) return hipErrorInvalidValue;
+    const dim3 grid(wgrad_chunks(a.n_out), 27);
+    if (mode == CONV_FWD1) hipLaunchKernelGGL(k_wgrad<CONV_FWD1>, grid, dim3(kThreads), 0, s, a);
+    else if (mode == CONV_FWD2) hipLaunchKernelGGL(k_wgrad<CONV_FWD2>, grid, dim3(kThreads), 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_wgrad_reduce(const float *partials, int chunks, int cout, int cin, int cout_real, int cin_real,
+                               float scale, float *dW, hipStream_t s) {
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((long)cout_real * cin_real * 27)), dim3(kThreads), 0, s, partials,
+                       chunks, cout, cin, cout_real, cin_real, scale, dW);
+    return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const uint16_t *dz, int dz_cs, long P, int cout_real, float scale, float *db,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_bias_grad, dim3(cout_real), dim3(kThreads), 0, s, dz, dz_cs, P, scale, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2(const uint16_t *x, int n_coarse, int C, uint16_t *y, hipStream_t s) {
+    const long total = 8L * n_coarse * n_coarse * n_coarse * C;
+    hipLaunchKernelGGL(k_up2, dim3(blocks(total)), dim3(kThreads), 0, s, x, n_coarse, C, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_up2_bwd(const uint16_t *dy, int n_coarse, int C, const uint16_t *mask, int mask_cs, uint16_t *dz,
+                          hipStream_t s) {
+    const long total = (long)n_coarse * n_coarse * n_coarse * C;
+    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks(total)), dim3(kThreads), 0, s, dy, n_coarse, C, mask, mask_cs, dz);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask(const uint16_t *src, int src_cs, long P, int C, const uint16_t *mask, int mask_cs, uint16_t *dz,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_mask, dim3(blocks(P * C)), dim3(kThreads), 0, s, src, src_cs, P, C, mask, mask_cs, dz);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_input(const float *a, const float *b, long P, uint16_t *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_input, dim3(blocks(P * 16)), dim3(kThreads), 0, s, a, b, P, x);
+    return hipGetLastError();
+}
+
+int mse_blocks(long P) { return (int)blocks(P); }
+
+hipError_t launch_mse(const float *v, const float *tgt, long P, double *partials, double *loss_acc, double scale,
+                      uint16_t *dz, hipStream_t s) {
+    hipLaunchKernelGGL(k_mse, dim3(blocks(P)), dim3(kThreads), 0, s, v, tgt, P, partials, dz);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, partials, (int)blocks(P), scale, loss_acc);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s) {
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(kThreads), 0, s, n, w, g, m, v, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights(const float *W, int cout, int cin, int cout_pad, int cin_pad, uint16_t *fwd,
+                               uint16_t *bwd, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_weights, dim3(blocks(27L * cout_pad * cin_pad)), dim3(kThreads), 0, s, W, cout, cin,
+                       cout_pad, cin_pad, fwd, bwd);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint16_t *x, int cs, int C, long P, float *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_unpack, dim3(blocks(P * C)), dim3(kThreads), 0, s, x, cs, C, P, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_f32(long n, float v, float *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(blocks(n)), dim3(kThreads), 0, s, n, v, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_f32(long n, float sc, float *x, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_f32, dim3(blocks(n)), dim3(kThreads), 0, s, n, sc, x);
+    return hipGetLastError();
+}
+
+}  // namespace regn

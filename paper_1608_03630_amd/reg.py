@@ -134,6 +134,18 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)],
     "reg_batch_hessian_matvec": [_P, ctypes.POINTER(_P), ctypes.POINTER(_P)],
     "reg_batch_solve": [_P, ctypes.POINTER(_P), ctypes.POINTER(reg_report)],
+    "reg_net_param_count": [ctypes.POINTER(ctypes.c_int64)],
+    "reg_net_workspace_size": [ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "reg_net_create": [ctypes.c_int32, _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
+    "reg_net_destroy": [_P],
+    "reg_net_set_params": [_P, _P],
+    "reg_net_get_params": [_P, _P],
+    "reg_net_forward": [_P, _P, _P, _P],
+    "reg_net_activation": [_P, ctypes.c_int32, _P],
+    "reg_net_loss_grad": [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "reg_net_train_step": [_P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
+                           ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
+    "reg_warmstart": [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
 }
 
 KERNEL_KINDS = ["interp", "backtrace", "adjoint", "incstate", "deform", "deriv", "fft3d", "symbol", "reduce",
@@ -155,6 +167,8 @@ def lib():
         L.reg_last_error.restype = ctypes.c_char_p
         L.reg_batch_last_error.argtypes = [_P]
         L.reg_batch_last_error.restype = ctypes.c_char_p
+        L.reg_net_last_error.argtypes = [_P]
+        L.reg_net_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -504,3 +518,126 @@ class Batch:
         if raise_on_error:
             _bchk(st, self.handle, "reg_batch_solve")
         return vs, [r.to_dict() for r in reps]
+
+
+# ------------------------------------------------------- learned warm start
+# (cin, cout, stride) of the network's twelve convolutions, in parameter order
+NET_LAYERS = [(2, 16, 1), (16, 16, 1), (16, 32, 2), (32, 32, 1), (32, 64, 2), (64, 64, 1), (64, 64, 1),
+              (64, 32, 1), (64, 32, 1), (32, 16, 1), (32, 16, 1), (16, 3, 1)]
+NET_LAYER_GRID = [1, 1, 2, 2, 4, 4, 4, 2, 2, 1, 1, 1]  # output grid = n // this
+
+
+def reg_net_param_count():
+    c = ctypes.c_int64()
+    _chk(lib().reg_net_param_count(ctypes.byref(c)), what="reg_net_param_count")
+    return c.value
+
+
+def _nchk(st, h, what):
+    if st != REG_OK:
+        msg = lib().reg_net_last_error(h).decode() if h else ""
+        raise RegError(st, f"{what}: {msg}")
+
+
+class Net:
+    """The warm-start network (reg_net) on an n^3 grid."""
+
+    def __init__(self, n=64, device="cuda", stream=None):
+        self.n = int(n)
+        self.device = torch.device(device)
+        self.P = self.n ** 3
+        b = ctypes.c_size_t()
+        _chk(lib().reg_net_workspace_size(self.n, ctypes.byref(b)), what="reg_net_workspace_size")
+        self.workspace = torch.empty(b.value, dtype=torch.uint8, device=self.device)
+        self.count = reg_net_param_count()
+        h = ctypes.c_void_p()
+        _chk(lib().reg_net_create(self.n, ctypes.c_void_p(self.workspace.data_ptr()), b.value, _stream_ptr(stream),
+                                  ctypes.byref(h)), what="reg_net_create")
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            lib().reg_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _f(self, t, numel, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+            raise TypeError(f"{name} must be a float32 CUDA tensor")
+        if not t.is_contiguous() or t.numel() != numel:
+            raise ValueError(f"{name} must be contiguous with {numel} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def reg_net_set_params(self, params):
+        _nchk(lib().reg_net_set_params(self.handle, self._f(params, self.count, "params")), self.handle,
+              "reg_net_set_params")
+
+    def reg_net_get_params(self):
+        out = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        _nchk(lib().reg_net_get_params(self.handle, self._f(out, self.count, "params")), self.handle,
+              "reg_net_get_params")
+        return out
+
+    def reg_net_forward(self, rhoT, rhoR, v=None):
+        v = torch.empty((3, self.n, self.n, self.n), dtype=torch.float32, device=self.device) if v is None else v
+        _nchk(lib().reg_net_forward(self.handle, self._f(rhoT, self.P, "rho_T"), self._f(rhoR, self.P, "rho_R"),
+                                    self._f(v, 3 * self.P, "v")), self.handle, "reg_net_forward")
+        return v
+
+    def reg_net_activation(self, layer):
+        cin, cout, _ = NET_LAYERS[layer]
+        m = self.n // NET_LAYER_GRID[layer]
+        out = torch.empty((cout, m, m, m), dtype=torch.float32, device=self.device)
+        _nchk(lib().reg_net_activation(self.handle, int(layer), self._f(out, out.numel(), "out")), self.handle,
+              "reg_net_activation")
+        return out
+
+    def reg_net_loss_grad(self, rhoT, rhoR, target):
+        g = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        loss = ctypes.c_double()
+        _nchk(lib().reg_net_loss_grad(self.handle, self._f(rhoT, self.P, "rho_T"), self._f(rhoR, self.P, "rho_R"),
+                                      self._f(target, 3 * self.P, "target"), self._f(g, self.count, "grad"),
+                                      ctypes.byref(loss)), self.handle, "reg_net_loss_grad")
+        return loss.value, g
+
+    def reg_net_train_step(self, rhoTs, rhoRs, targets, lr=1e-3):
+        n = len(rhoTs)
+        for t in rhoTs + rhoRs:
+            self._f(t, self.P, "image")
+        for t in targets:
+            self._f(t, 3 * self.P, "target")
+        loss = ctypes.c_double()
+        _nchk(lib().reg_net_train_step(self.handle, n, _ptrs(rhoTs), _ptrs(rhoRs), _ptrs(targets), float(lr),
+                                       ctypes.byref(loss)), self.handle, "reg_net_train_step")
+        return loss.value
+
+    def reg_warmstart(self, ctx, v=None):
+        """(v, used_fallback, detmin) for a single-precision Context with images set."""
+        v = torch.empty((3,) + ctx.shape, dtype=torch.float64, device=self.device) if v is None else v
+        fb, dmin = ctypes.c_int32(), ctypes.c_double()
+        _chk(lib().reg_warmstart(ctx.handle, self.handle, ctx._t(v, 3, "v", True), ctypes.byref(fb),
+                                 ctypes.byref(dmin)), ctx.handle, "reg_warmstart")
+        return v, bool(fb.value), dmin.value
+
+
+def net_params_to_layers(flat):
+    """Flat parameter vector (numpy) -> [(W [cout, cin, 3, 3, 3], b [cout])]."""
+    out, o = [], 0
+    for cin, cout, _ in NET_LAYERS:
+        w = flat[o:o + cout * cin * 27].reshape(cout, cin, 3, 3, 3)
+        o += cout * cin * 27
+        b = flat[o:o + cout]
+        o += cout
+        out.append((w, b))
+    return out
+
+
+def net_layers_to_params(layers):
+    import numpy as np
+
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in layers])
