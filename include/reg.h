@@ -83,6 +83,10 @@ typedef struct {
     int32_t max_ls;        /* Armijo trials per Newton step                        */
     int32_t forcing;       /* 0: eta = min(.5, r); 1: eta = min(.5, sqrt r); r = ||g||/||g0|| */
     double armijo_c1;      /* sufficient-decrease constant                         */
+    double gnorm_ref;      /* > 0: stop a level at ||g|| <= gtol * gnorm_ref instead of
+                            * gtol ||g0||, and use ||g||/gnorm_ref in the forcing term (an
+                            * absolute reference, e.g. ||g(v=0)||, so that warm and cold
+                            * starts run by the same rules); 0: ||g0||                */
 } reg_params;
 
 #define REG_MAXIT 512
@@ -122,6 +126,12 @@ const char *reg_last_error(const reg_ctx *ctx);
 
 /* Changes beta (> 0) used by reg_gradient, reg_hessian_matvec, reg_precond. */
 reg_status reg_set_beta(reg_ctx *ctx, double beta);
+
+/* Replaces the solver settings of the context (beta and its continuation,
+ * isochoric, tolerances, iteration limits, forcing, Armijo constant,
+ * gnorm_ref); n, nt and prec must equal those given to reg_create.
+ * Invalidates the cached state. */
+reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p);
 
 /* Copies rho_T and rho_R (device fields) into the context and records
  * ||rho_T - rho_R|| for the relative mismatch. Invalidates cached state. */

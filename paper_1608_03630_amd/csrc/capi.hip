@@ -205,6 +205,19 @@ reg_status reg_set_beta(reg_ctx *ctx, double beta) {
     return REG_OK;
 }
 
+reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p) {
+    CTX_OK(ctx);
+    std::string why;
+    if (check_params(p, &why) != REG_OK) return fail(ctx, REG_EINVAL, why);
+    if (p->n[0] != ctx->P.n[0] || p->n[1] != ctx->P.n[1] || p->n[2] != ctx->P.n[2] || p->nt != ctx->P.nt ||
+        p->prec != ctx->P.prec)
+        return fail(ctx, REG_EINVAL, "n, nt and prec are fixed at reg_create");
+    ctx->P = *p;
+    ctx->beta = p->beta;
+    ctx->have_state = false;
+    return REG_OK;
+}
+
 reg_status reg_set_images(reg_ctx *ctx, const void *rho_T, const void *rho_R) {
     CTX_OK(ctx);
     NEED_DEV(ctx, rho_T);
@@ -304,7 +317,9 @@ reg_status reg_precond(reg_ctx *ctx, const void *r, void *z) {
     CTX_OK(ctx);
     NEED_DEV(ctx, r);
     NEED_DEV(ctx, z);
-    return precond_impl(ctx, r, z);
+    STCHK(to_spec(ctx, r, ctx->rhat));
+    STCHK(precond_hat(ctx, ctx->rhat, ctx->zhat));
+    return from_spec(ctx, ctx->zhat, z);
 }
 
 reg_status reg_transport_forward(reg_ctx *ctx, const void *v, const void *rho0, void *rho1) {

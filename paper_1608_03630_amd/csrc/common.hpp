@@ -145,6 +145,30 @@ hipError_t spec_symbol(const SpecCtx &c, int op, double a, int ncomp, int leray,
 // or zero padding, scaled by Nd/Ns)
 template <typename T>
 hipError_t spec_resample(const SpecCtx &src, const SpecCtx &dst, int ncomp, hipStream_t s);
+// the same with explicit spectral buffers (the inverse overwrites Hin)
+template <typename Tr, typename T>
+hipError_t spec_forward_to(const SpecCtx &c, const Tr *x, int ncomp, void *Hout, hipStream_t s);
+template <typename T, typename Tr>
+hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s);
+
+// Spectral velocity vectors: [3][Nh] complex double (Nh = n1 n2 (n3/2+1)),
+// the unnormalised forward transforms of real fields.
+enum VecOp {
+    VEC_ASSEMBLE = 0,  // out = a |k|^4 x + [P] y   (y: 3 complex-T components, e.g. a transformed field)
+    VEC_PRECOND = 1,   // out = x / (a |k|^4) (x at k = 0), then [P]
+    VEC_LERAY = 2      // out = P x
+};
+// H (3 complex-T components) = vhat
+template <typename T>
+hipError_t vec_load(const SpecCtx &c, const double *vhat, void *H, hipStream_t s);
+// pointwise operator (out may alias x)
+template <typename T>
+hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, double a, int leray, double *out,
+                      hipStream_t s);
+// partials of sum w(k3) Re(a conj b) (mode 0) or sum w(k3) |k|^4 |a|^2 (mode 1)
+hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const double *b, double *partials,
+                            int nblocks, hipStream_t s);
+
 // partial sums over blocks of sum_k w(k3) |k|^4 |H_c|^2, c < 3 -> partials (double)
 template <typename T>
 hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s);

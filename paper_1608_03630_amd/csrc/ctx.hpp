@@ -135,7 +135,8 @@ struct reg_ctx {
     void *lamh;        // adjoint levels lam^0..lam^nt
     void *gam, *gam2;  // Heun factor of the adjoint source (cached plan, scratch plan)
     void *vf, *vtf;                                            // velocity copies in the field type
-    void *vcur, *g_, *sdir, *r, *z, *p, *q, *vtrial;          // velocity space, double
+    // velocity space, spectral: [3][Nh] complex double (see vec_symbol)
+    void *vhat, *ghat, *shat, *rhat, *zhat, *phat, *qhat, *vthat;
     void *u0, *u1, *du, *H;
     void *tw32[3], *tw64[3];
     double *dpart, *dpart2, *dres;
@@ -152,7 +153,7 @@ struct reg_ctx {
     PlanGeom geoms[6];
 
     bool have_images = false;
-    bool have_state = false;  // plans, history, grad rho and div v at vcur
+    bool have_state = false;  // plans, history, grad rho and div v at vhat
     double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
     long interps = 0;
     int64_t epoch = 0;  // bumped whenever a plan (departure points, tile geometry) changes
@@ -237,6 +238,10 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
         *why = "gtol and mismatch_tol must be >= 0";
         return REG_EINVAL;
     }
+    if (!(p->gnorm_ref >= 0) || !std::isfinite(p->gnorm_ref)) {
+        *why = "gnorm_ref must be >= 0 and finite";
+        return REG_EINVAL;
+    }
     return REG_OK;
 }
 
@@ -270,14 +275,15 @@ inline size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->vf = L.take(E * 3 * N);
     c->vtf = L.take(E * 3 * N);
     const size_t D8 = sizeof(double);
-    c->vcur = L.take(D8 * 3 * N);
-    c->g_ = L.take(D8 * 3 * N);
-    c->sdir = L.take(D8 * 3 * N);
-    c->r = L.take(D8 * 3 * N);
-    c->z = L.take(D8 * 3 * N);
-    c->p = L.take(D8 * 3 * N);
-    c->q = L.take(D8 * 3 * N);
-    c->vtrial = L.take(D8 * 3 * N);
+    const size_t SV = 2 * D8 * 3 * Nh;
+    c->vhat = L.take(SV);
+    c->ghat = L.take(SV);
+    c->shat = L.take(SV);
+    c->rhat = L.take(SV);
+    c->zhat = L.take(SV);
+    c->phat = L.take(SV);
+    c->qhat = L.take(SV);
+    c->vthat = L.take(SV);
     c->u0 = L.take(E * 3 * N);
     c->u1 = L.take(E * 3 * N);
     c->du = L.take(E * 9 * N);
@@ -441,17 +447,22 @@ reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
     return REG_OK;
 }
 
-// out = IFFT(beta |k|^4 x^ + [P] y^); also leaves sum w |k|^4 |x^|^2 partials
-// in dpart2 when want_reg
-// (x and out are velocity-space doubles, y is a field-type vector; the
-// transforms run in double)
-template <typename T>
-reg_status assemble(reg_ctx *ctx, const void *x, const void *y, void *out, bool want_reg) {
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(x), 3, 0, ctx->stream))));
-    if (want_reg) HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<T, double>(ctx->spec, CV<T>(y), 3, 3, ctx->stream))));
-    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_ASSEMBLE, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(out), 3, ctx->stream))));
+// ------------------------------------------- spectral velocity-space vectors
+// v, g and the Krylov vectors live on the half spectrum (vec_symbol): the
+// regulariser, the preconditioner, the Leray projection and the inner
+// products are pointwise there, and only the transport operands (v and the
+// matvec direction, in the field type) and the transport result b pass
+// through 3D transforms.
+
+// doubles in a spectral velocity vector
+inline long sv_len(const reg_ctx *c) { return 6 * c->Nh; }
+
+// dres[slot] = <a, b> (Parseval)
+inline reg_status sdot(reg_ctx *ctx, const void *a, const void *b, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::vec_dot_partials(ctx->spec, 0, CV<double>(a), CV<double>(b), ctx->dpart,
+                                                             regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
+                                                            ctx->dres + slot, ctx->stream)));
     return REG_OK;
 }
 
@@ -463,44 +474,71 @@ inline reg_status reg_term_to_slot(reg_ctx *ctx, int slot) {
     return REG_OK;
 }
 
-// v is a velocity-space double vector
-inline reg_status regulariser_of(reg_ctx *ctx, const void *v, int slot) {
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
-    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_biharm_norm_partials<double>(ctx->spec, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
-    return reg_term_to_slot(ctx, slot);
+// sum_k w |k|^4 |v^|^2 partials of a spectral vector into dpart2
+inline reg_status biharm_partials(reg_ctx *ctx, const void *vhat) {
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_dot_partials(ctx->spec, 1, CV<double>(vhat), nullptr, ctx->dpart2,
+                                                             regk::RED_BLOCKS, ctx->stream)));
+    return REG_OK;
+}
+
+// physical double vector -> spectral
+inline reg_status to_spec(reg_ctx *ctx, const void *v, void *vhat) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<double, double>(ctx->spec, CV<double>(v), 3, vhat, ctx->stream))));
+    return REG_OK;
+}
+
+// spectral -> physical double vector (through the scratch spectrum)
+inline reg_status from_spec(reg_ctx *ctx, const void *vhat, void *v) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<double>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<double, double>(ctx->spec, ctx->H, V<double>(v), 3, ctx->stream))));
+    return REG_OK;
+}
+
+// spectral -> field-type vector for the transport (transform in T)
+template <typename T>
+reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<T>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream))));
+    return REG_OK;
+}
+
+// out^ = beta |k|^4 x^ + [P] FFT(y), y a field-type vector (transformed in T)
+template <typename T>
+reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<T>(ctx->spec, regk::VEC_ASSEMBLE, CV<double>(xhat), ctx->H,
+                                                          ctx->beta, ctx->P.isochoric, V<double>(out_hat), ctx->stream)));
+    return REG_OK;
+}
+
+// z^ = M r^: inverse biharmonic (identity at k = 0), then P when isochoric
+inline reg_status precond_hat(reg_ctx *ctx, const void *rhat, void *zhat) {
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<double>(ctx->spec, regk::VEC_PRECOND, CV<double>(rhat), nullptr,
+                                                               ctx->beta, ctx->P.isochoric, V<double>(zhat), ctx->stream)));
+    return REG_OK;
+}
+
+inline reg_status leray_hat(reg_ctx *ctx, void *vhat) {
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<double>(ctx->spec, regk::VEC_LERAY, CV<double>(vhat), nullptr,
+                                                               0.0, 1, V<double>(vhat), ctx->stream)));
+    return REG_OK;
 }
 
 // mismatch^2 numerator (slot 1) and regulariser (slot 2) of the history in
-// hist at v
+// hist at the spectral velocity vhat (reg_done: its biharmonic partials are
+// already in dpart2)
 template <typename T>
-reg_status objective_slots(reg_ctx *ctx, const void *hist, const void *v, bool reg_done) {
+reg_status objective_slots(reg_ctx *ctx, const void *hist, const void *vhat, bool reg_done) {
     const long N = ctx->N;
     STCHK(reduce<T>(ctx, V<T>(const_cast<void *>(hist)) + (long)ctx->P.nt * N, ctx->rhoR, N, 1, h3(ctx), 1));
-    if (!reg_done) STCHK(regulariser_of(ctx, v, 2));
-    else STCHK(reg_term_to_slot(ctx, 2));
-    return REG_OK;
+    if (!reg_done) STCHK(biharm_partials(ctx, vhat));
+    return reg_term_to_slot(ctx, 2);
 }
 
 inline void scalars_to_J(reg_ctx *ctx, double *J, double *mis) {
     const double dd = ctx->hres[1];
     if (J) *J = 0.5 * dd + ctx->hres[2];
     if (mis) *mis = ctx->normTR2 > 0 ? std::sqrt(dd / ctx->normTR2) : 0.0;
-}
-
-// r and z are velocity-space doubles
-inline reg_status precond_impl(reg_ctx *ctx, const void *r, void *z) {
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(r), 3, 0, ctx->stream))));
-    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_PRECOND, ctx->beta, 3, ctx->P.isochoric, ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(z), 3, ctx->stream))));
-    return REG_OK;
-}
-
-// inner product of two velocity-space vectors
-inline reg_status dot3(reg_ctx *ctx, const void *a, const void *b, double *out) {
-    STCHK(reduce<double>(ctx, a, b, 3 * ctx->N, 0, h3(ctx), 0));
-    STCHK(fetch(ctx, 1));
-    *out = ctx->hres[0];
-    return REG_OK;
 }
 
 using clk = std::chrono::steady_clock;

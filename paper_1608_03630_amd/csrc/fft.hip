@@ -611,10 +611,10 @@ static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipS
 }
 
 template <typename Tr, typename T>
-hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStream_t s) {
+hipError_t spec_forward_to(const SpecCtx &c, const Tr *x, int ncomp, void *Hout, hipStream_t s) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
-    C *H = reinterpret_cast<C *>(c.H) + (long)h0 * g.Nh();
+    C *H = reinterpret_cast<C *>(Hout);
     const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
     const long L2 = 2L << lg;
     const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
@@ -624,11 +624,16 @@ hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStr
     return hipGetLastError();
 }
 
+template <typename Tr, typename T>
+hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStream_t s) {
+    return spec_forward_to<Tr, T>(c, x, ncomp, reinterpret_cast<cplx_t<T> *>(c.H) + (long)h0 * c.g.Nh(), s);
+}
+
 template <typename T, typename Tr>
-hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
+hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
-    C *H = reinterpret_cast<C *>(c.H);
+    C *H = reinterpret_cast<C *>(Hin);
     c2c_passes<T>(c, H, ncomp, +1, s);
     const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
     const long L2 = 2L << lg;
@@ -637,6 +642,11 @@ hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
                        c.plan[2], reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), H, g.Nh(), out, g.N(),
                        T(1.0 / (double)g.N()), lg);
     return hipGetLastError();
+}
+
+template <typename T, typename Tr>
+hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
+    return spec_inverse_from<T, Tr>(c, c.H, out, ncomp, s);
 }
 
 template <typename T>
@@ -655,6 +665,123 @@ hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nbl
     hipLaunchKernelGGL(k_biharm_norm<T>, dim3(nblocks), dim3(kThreads), 0, s, c.g,
                        reinterpret_cast<const C *>(c.H), c.g.Nh(), partials);
     return hipGetLastError();
+}
+
+// ------------------------------------------------ spectral velocity vectors
+// Velocity-space vectors kept on the half spectrum: three components of
+// [n1][n2][n3/2+1] complex double values, the unnormalised forward transform
+// of the real field. Inner products follow Parseval,
+// <u, w> = h1 h2 h3 / N sum_k u^(k) conj(w^(k)), with the half spectrum
+// weighted 1 on the k3 = 0 and k3 = n3/2 planes and 2 elsewhere.
+
+// H (complex T, components 0..2) = v^ (complex double)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vec_load(long n, const double2 *__restrict__ v,
+                                                       cplx_t<T> *__restrict__ H) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    const double2 z = v[e];
+    cplx_t<T> o;
+    o.x = T(z.x);
+    o.y = T(z.y);
+    H[e] = o;
+}
+
+// Pointwise operators on spectral velocity vectors:
+//  VEC_ASSEMBLE: out = a |k|^4 x + [P] y     (y complex T, promoted)
+//  VEC_PRECOND:  out = x / (a |k|^4) (x at k = 0), then [P]
+//  VEC_LERAY:    out = P x
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vec_symbol(Grid g, int op, const double2 *__restrict__ x,
+                                                         const cplx_t<T> *__restrict__ y, double a, int leray,
+                                                         double2 *__restrict__ out) {
+    const long q = (long)blockIdx.x * kThreads + threadIdx.x;
+    const long Nh = g.Nh();
+    if (q >= Nh) return;
+    const int nh = g.n3h();
+    const int m3 = (int)(q % nh);
+    const long r = q / nh;
+    const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
+    const double k1 = kwave(m1, g.n1), k2 = kwave(m2, g.n2), k3 = m3;
+    const double kk = k1 * k1 + k2 * k2 + k3 * k3;
+    const double t1 = kwave_odd(m1, g.n1), t2 = kwave_odd(m2, g.n2), t3 = (2 * m3 == g.n3 ? 0 : m3);
+    const double tt = t1 * t1 + t2 * t2 + t3 * t3;
+    double2 v[3];
+    if (op == VEC_ASSEMBLE) {
+        for (int c = 0; c < 3; c++) {
+            const cplx_t<T> z = y[c * Nh + q];
+            v[c] = make_double2((double)z.x, (double)z.y);
+        }
+    } else {
+        for (int c = 0; c < 3; c++) v[c] = x[c * Nh + q];
+        if (op == VEC_PRECOND && kk > 0.0) {
+            const double f = 1.0 / (a * kk * kk);
+            for (int c = 0; c < 3; c++) {
+                v[c].x *= f;
+                v[c].y *= f;
+            }
+        }
+    }
+    if ((leray || op == VEC_LERAY) && tt > 0.0) {
+        const double ir = 1.0 / tt;
+        const double dx = (t1 * v[0].x + t2 * v[1].x + t3 * v[2].x) * ir;
+        const double dy = (t1 * v[0].y + t2 * v[1].y + t3 * v[2].y) * ir;
+        v[0].x -= t1 * dx;
+        v[0].y -= t1 * dy;
+        v[1].x -= t2 * dx;
+        v[1].y -= t2 * dy;
+        v[2].x -= t3 * dx;
+        v[2].y -= t3 * dy;
+    }
+    if (op == VEC_ASSEMBLE) {
+        const double f = a * kk * kk;
+        for (int c = 0; c < 3; c++) {
+            const double2 z = x[c * Nh + q];
+            v[c].x = f * z.x + v[c].x;
+            v[c].y = f * z.y + v[c].y;
+        }
+    }
+    for (int c = 0; c < 3; c++) out[c * Nh + q] = v[c];
+}
+
+// Per-block partial sums of sum_c sum_k w(k3) Re(a_c conj(b_c)) (mode 0) or
+// sum_c sum_k w(k3) |k|^4 |a_c|^2 (mode 1), in a fixed order.
+__global__ __launch_bounds__(kThreads) void k_vec_dot(Grid g, int mode, const double2 *__restrict__ a,
+                                                      const double2 *__restrict__ b, double *__restrict__ partials) {
+    const long Nh = g.Nh();
+    const int nh = g.n3h();
+    double acc = 0.0;
+    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
+        const int m3 = (int)(q % nh);
+        const double w = (m3 == 0 || 2 * m3 == g.n3) ? 1.0 : 2.0;
+        double s = 0.0;
+        if (mode == 0) {
+            for (int c = 0; c < 3; c++) {
+                const double2 x = a[c * Nh + q], y = b[c * Nh + q];
+                s += x.x * y.x + x.y * y.y;
+            }
+        } else {
+            const long r = q / nh;
+            const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
+            const double k1 = kwave(m1, g.n1), k2 = kwave(m2, g.n2), k3 = m3;
+            const double kk = k1 * k1 + k2 * k2 + k3 * k3;
+            for (int c = 0; c < 3; c++) {
+                const double2 x = a[c * Nh + q];
+                s += x.x * x.x + x.y * x.y;
+            }
+            s *= kk * kk;
+        }
+        acc += w * s;
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    __shared__ double ws[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / 64; i++) t += ws[i];
+        partials[blockIdx.x] = t;
+    }
 }
 
 // Spectral resampling between grids: destination mode (q1, q2, q3) takes the
@@ -702,13 +829,43 @@ hipError_t spec_resample(const SpecCtx &src, const SpecCtx &dst, int ncomp, hipS
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t vec_load(const SpecCtx &c, const double *vhat, void *H, hipStream_t s) {
+    const long n = 3 * c.g.Nh();
+    hipLaunchKernelGGL(k_vec_load<T>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n,
+                       reinterpret_cast<const double2 *>(vhat), reinterpret_cast<cplx_t<T> *>(H));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, double a, int leray, double *out,
+                      hipStream_t s) {
+    const unsigned nb = (unsigned)((c.g.Nh() + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_vec_symbol<T>, dim3(nb), dim3(kThreads), 0, s, c.g, op,
+                       reinterpret_cast<const double2 *>(x), reinterpret_cast<const cplx_t<T> *>(y), a, leray,
+                       reinterpret_cast<double2 *>(out));
+    return hipGetLastError();
+}
+
+hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const double *b, double *partials,
+                            int nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(k_vec_dot, dim3(nblocks), dim3(kThreads), 0, s, c.g, mode,
+                       reinterpret_cast<const double2 *>(a), reinterpret_cast<const double2 *>(b ? b : a), partials);
+    return hipGetLastError();
+}
+
 #define REGK_FFT_INST(T)                                                                                           \
     template hipError_t spec_resample<T>(const SpecCtx &, const SpecCtx &, int, hipStream_t);                     \
     template hipError_t spec_deriv<T>(const SpecCtx &, int, const T *, long, T *, long, int, int, hipStream_t);    \
     template hipError_t spec_forward<T, T>(const SpecCtx &, const T *, int, int, hipStream_t);                     \
     template hipError_t spec_inverse<T, T>(const SpecCtx &, T *, int, hipStream_t);                                \
     template hipError_t spec_symbol<T>(const SpecCtx &, int, double, int, int, hipStream_t);                       \
-    template hipError_t spec_biharm_norm_partials<T>(const SpecCtx &, double *, int, hipStream_t);
+    template hipError_t spec_biharm_norm_partials<T>(const SpecCtx &, double *, int, hipStream_t);           \
+    template hipError_t spec_forward_to<T, T>(const SpecCtx &, const T *, int, void *, hipStream_t);              \
+    template hipError_t spec_inverse_from<T, T>(const SpecCtx &, void *, T *, int, hipStream_t);                  \
+    template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
+    template hipError_t vec_symbol<T>(const SpecCtx &, int, const double *, const void *, double, int, double *,  \
+                                      hipStream_t);
 
 REGK_FFT_INST(float)
 REGK_FFT_INST(double)

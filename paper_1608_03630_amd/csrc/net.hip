@@ -109,17 +109,23 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
     }
 }
 
-// Weight gradient partials: one workgroup per (point chunk, tap) forms
-// sum_p dz[p][co] x[src(p, t)][ci] over its points for every (co, ci) tile.
-// A = dz^T (co x p), B = x_src (p x ci), staged through LDS in slices of
-// kSlice points.
+// Weight gradient partials: one workgroup per (chunk of kChunk points, tap)
+// forms sum_p dz[p][co] x[src(p, t)][ci] for every (co, ci) tile with
+// v_mfma_f32_16x16x32_bf16 (K = points). Slices of kSlice points are staged
+// transposed ([channel][point], row pitch kPitch) so that each lane's 8-point
+// fragment is one 16-byte LDS read. The centre-tap workgroups also sum dz
+// over their points (bias gradient).
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
 constexpr int kSlice = 64;
-constexpr int kChunkSlices = 8;  // points per workgroup = 512
+constexpr int kChunk = 2048;
+constexpr int kPitch = kSlice + 8;  // 144-byte rows: 16-byte aligned fragments
 
 template <int MODE>
 __global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
-    __shared__ uint16_t sdz[kSlice * 64];
-    __shared__ uint16_t sx[kSlice * 64];
+    __shared__ __align__(16) uint16_t sdz[64 * kPitch];
+    __shared__ __align__(16) uint16_t sx[64 * kPitch];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int t = blockIdx.y;
@@ -128,40 +134,44 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
     const long P = (long)n * n * n;
     const int cb = a.cout >> 4, ib = a.cin >> 4;
     const int tiles = cb * ib;  // <= 16: at most 4 per wavefront
+    const int q4o = a.cout >> 2, q4i = a.cin >> 2;
     v4f acc[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
-    const long base = (long)blockIdx.x * kSlice * kChunkSlices;
-    for (int sl = 0; sl < kChunkSlices; sl++) {
+    float bsum = 0.f;
+    const long base = (long)blockIdx.x * kChunk;
+    for (int sl = 0; sl < kChunk / kSlice; sl++) {
         const long s0 = base + (long)sl * kSlice;
         if (s0 >= P) break;
-        // stage dz[s0 .. s0+kSlice)[0..cout) and x[src][0..cin)
-        for (int e = threadIdx.x; e < kSlice * a.cout; e += kThreads) {
-            const int pp = e / a.cout, c = e - pp * a.cout;
-            sdz[pp * a.cout + c] = a.dz[(s0 + pp) * a.dz_cs + c];
+        for (int e = threadIdx.x; e < kSlice * q4o; e += kThreads) {
+            const int pp = e / q4o, c = (e - pp * q4o) * 4;
+            const v4s v = *reinterpret_cast<const v4s *>(a.dz + (s0 + pp) * a.dz_cs + c);
+#pragma unroll
+            for (int i = 0; i < 4; i++) sdz[(c + i) * kPitch + pp] = (uint16_t)v[i];
         }
-        for (int e = threadIdx.x; e < kSlice * a.cin; e += kThreads) {
-            const int pp = e / a.cin, c = e - pp * a.cin;
+        for (int e = threadIdx.x; e < kSlice * q4i; e += kThreads) {
+            const int pp = e / q4i, c = (e - pp * q4i) * 4;
             const long p = s0 + pp;
-            const int i = (int)(p / ((long)n * n)), j = (int)((p / n) % n), k = (int)(p % n);
-            const int q = source<MODE>(i, j, k, d1, d2, d3, a.n_out, a.n_in);
-            sx[pp * a.cin + c] = a.x[(long)q * a.x_cs + c];
+            const int i1 = (int)(p / ((long)n * n)), i2 = (int)((p / n) % n), i3 = (int)(p % n);
+            const int q = source<MODE>(i1, i2, i3, d1, d2, d3, a.n_out, a.n_in);
+            const v4s v = *reinterpret_cast<const v4s *>(a.x + (long)q * a.x_cs + c);
+#pragma unroll
+            for (int i = 0; i < 4; i++) sx[(c + i) * kPitch + pp] = (uint16_t)v[i];
         }
         __syncthreads();
+        if (t == 13 && threadIdx.x < a.cout)
+            for (int pp = 0; pp < kSlice; pp++) bsum += bf2f(sdz[threadIdx.x * kPitch + pp]);
 #pragma unroll
         for (int u = 0; u < 4; u++) {
             const int tile = wave + 4 * u;
             if (tile >= tiles) continue;
             const int co0 = (tile / ib) * 16, ci0 = (tile % ib) * 16;
-            for (int kk = 0; kk < kSlice; kk += 16) {
-                v4s av, bv;
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int pp = kk + 4 * g + i;
-                    av[i] = (short)sdz[pp * a.cout + co0 + r];
-                    bv[i] = (short)sx[pp * a.cin + ci0 + r];
-                }
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[u], 0, 0, 0);
+            for (int kk = 0; kk < kSlice; kk += 32) {
+                const v8s av = *reinterpret_cast<const v8s *>(sdz + (co0 + r) * kPitch + kk + 8 * g);
+                const v8s bv = *reinterpret_cast<const v8s *>(sx + (ci0 + r) * kPitch + kk + 8 * g);
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av),
+                                                                 __builtin_bit_cast(v8bf, bv), acc[u], 0, 0, 0);
             }
         }
         __syncthreads();
@@ -176,36 +186,31 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; i++) out[(co0 + 4 * g + i) * a.cin + ci0 + r] = acc[u][i];
     }
+    if (t == 13 && threadIdx.x < a.cout) a.bias_partials[(long)blockIdx.x * a.cout + threadIdx.x] = bsum;
 }
 
-// dW[co][ci][t] += scale * sum over chunks (fixed order); real channels only
-__global__ __launch_bounds__(kThreads) void k_wgrad_reduce(const float *__restrict__ partials, int chunks, int cout,
-                                                           int cin, int cout_real, int cin_real, float scale,
-                                                           float *__restrict__ dW) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;  // over cout_real * cin_real * 27
-    if (e >= cout_real * cin_real * 27) return;
-    const int t = e % 27, ci = (e / 27) % cin_real, co = e / (27 * cin_real);
-    const long stride = 27L * cout * cin;
-    const float *p = partials + ((long)t * cout + co) * cin + ci;
-    float s = 0.f;
-    for (int c = 0; c < chunks; c++) s += p[c * stride];
-    dW[e] += scale * s;
-}
-
-// db[co] += scale * sum_p dz[p][co] (one workgroup per channel, fixed order)
-__global__ __launch_bounds__(kThreads) void k_bias_grad(const uint16_t *__restrict__ dz, int dz_cs, long P,
-                                                        float scale, float *__restrict__ db) {
-    const int co = blockIdx.x;
-    float s = 0.f;
-    for (long p = threadIdx.x; p < P; p += kThreads) s += bf2f(dz[p * dz_cs + co]);
-    __shared__ float sm[kThreads];
-    sm[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
-        __syncthreads();
+// dW[co][ci][t] += scale * sum over chunks and db[co] += scale * sum over
+// chunks (fixed order); real channels only. Threads run over (t, co, ci)
+// with ci fastest, so that the partial reads are coalesced.
+__global__ __launch_bounds__(kThreads) void k_wgrad_reduce(const float *__restrict__ partials,
+                                                           const float *__restrict__ bias_partials, int chunks,
+                                                           int cout, int cin, int cout_real, int cin_real, float scale,
+                                                           float *__restrict__ dW, float *__restrict__ db) {
+    const int e = blockIdx.x * kThreads + threadIdx.x;
+    const int nw = cout_real * cin_real * 27;
+    if (e < nw) {
+        const int ci = e % cin_real, co = (e / cin_real) % cout_real, t = e / (cin_real * cout_real);
+        const long stride = 27L * cout * cin;
+        const float *p = partials + ((long)t * cout + co) * cin + ci;
+        float s = 0.f;
+        for (int c = 0; c < chunks; c++) s += p[c * stride];
+        dW[((long)co * cin_real + ci) * 27 + t] += scale * s;
+    } else if (e < nw + cout_real) {
+        const int co = e - nw;
+        float s = 0.f;
+        for (int c = 0; c < chunks; c++) s += bias_partials[(long)c * cout + co];
+        db[co] += scale * s;
     }
-    if (threadIdx.x == 0) db[co] += scale * sm[0];
 }
 
 // fine[q][c] = coarse[q/2][c] (nearest upsampling by 2 per axis)
@@ -374,13 +379,13 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
 
 int wgrad_chunks(int n_out) {
     const long P = (long)n_out * n_out * n_out;
-    const long per = (long)kSlice * kChunkSlices;
-    return (int)((P + per - 1) / per);
+    return (int)((P + kChunk - 1) / kChunk);
 }
 
 hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {
     const long P = (long)a.n_out * a.n_out * a.n_out;
-    if (P % kSlice || a.cin % 16 || a.cout % 16 || a.cin > 64 || a.cout > 64) return hipErrorInvalidValue;
+    if (P % kSlice || a.cin % 16 || a.cout % 16 || a.cin > 64 || a.cout > 64 || a.x_cs % 4 || a.dz_cs % 4)
+        return hipErrorInvalidValue;
     const dim3 grid(wgrad_chunks(a.n_out), 27);
     if (mode == CONV_FWD1) hipLaunchKernelGGL(k_wgrad<CONV_FWD1>, grid, dim3(kThreads), 0, s, a);
     else if (mode == CONV_FWD2) hipLaunchKernelGGL(k_wgrad<CONV_FWD2>, grid, dim3(kThreads), 0, s, a);
@@ -388,16 +393,11 @@ hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_wgrad_reduce(const float *partials, int chunks, int cout, int cin, int cout_real, int cin_real,
-                               float scale, float *dW, hipStream_t s) {
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks((long)cout_real * cin_real * 27)), dim3(kThreads), 0, s, partials,
-                       chunks, cout, cin, cout_real, cin_real, scale, dW);
-    return hipGetLastError();
-}
-
-hipError_t launch_bias_grad(const uint16_t *dz, int dz_cs, long P, int cout_real, float scale, float *db,
-                            hipStream_t s) {
-    hipLaunchKernelGGL(k_bias_grad, dim3(cout_real), dim3(kThreads), 0, s, dz, dz_cs, P, scale, db);
+hipError_t launch_wgrad_reduce(const float *partials, const float *bias_partials, int chunks, int cout, int cin,
+                               int cout_real, int cin_real, float scale, float *dW, float *db, hipStream_t s) {
+    const long n = (long)cout_real * cin_real * 27 + cout_real;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(n)), dim3(kThreads), 0, s, partials, bias_partials, chunks, cout,
+                       cin, cout_real, cin_real, scale, dW, db);
     return hipGetLastError();
 }
 

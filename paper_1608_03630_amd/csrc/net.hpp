@@ -41,16 +41,15 @@ struct WgradArgs {
     const uint16_t *x;  // layer input [q][x_cs], cin channels
     int x_cs, cin;
     int n_in, n_out;
-    float *partials;  // [chunks][27][cout][cin]
+    float *partials;       // [chunks][27][cout][cin]
+    float *bias_partials;  // [chunks][cout]
 };
 
 hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s);
 int wgrad_chunks(int n_out);
 hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s);
-hipError_t launch_wgrad_reduce(const float *partials, int chunks, int cout, int cin, int cout_real, int cin_real,
-                               float scale, float *dW, hipStream_t s);
-hipError_t launch_bias_grad(const uint16_t *dz, int dz_cs, long P, int cout_real, float scale, float *db,
-                            hipStream_t s);
+hipError_t launch_wgrad_reduce(const float *partials, const float *bias_partials, int chunks, int cout, int cin,
+                               int cout_real, int cin_real, float scale, float *dW, float *db, hipStream_t s);
 hipError_t launch_up2(const uint16_t *x, int n_coarse, int C, uint16_t *y, hipStream_t s);
 hipError_t launch_up2_bwd(const uint16_t *dy, int n_coarse, int C, const uint16_t *mask, int mask_cs, uint16_t *dz,
                           hipStream_t s);

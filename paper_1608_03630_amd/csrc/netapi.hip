@@ -58,7 +58,7 @@ struct reg_net {
     float *v;
     // gradients
     uint16_t *dz11, *dz10, *dcat1, *dz9, *dupm2, *dz8, *dcat2, *dz7, *dupb2, *dz6, *dz5, *dz4, *dz3, *dz2, *dz1, *dz0;
-    float *partials = nullptr;
+    float *partials = nullptr, *bias_partials = nullptr;
     double *mse_part = nullptr, *loss = nullptr;
     double *hloss = nullptr;  // pinned
     int step = 0;
@@ -144,6 +144,7 @@ size_t net_layout(int n, char *base, reg_net *net) {
         part = std::max(part, (size_t)regn::wgrad_chunks(no) * 27 * pad16(kDef[l].cout) * pad16(kDef[l].cin));
     }
     t->partials = (float *)L.take(sizeof(float) * part);
+    t->bias_partials = (float *)L.take(sizeof(float) * 64 * regn::wgrad_chunks(n));
     t->mse_part = (double *)L.take(sizeof(double) * regn::mse_blocks(P1));
     t->loss = (double *)L.take(sizeof(double));
     t->rT = (float *)L.take(sizeof(float) * P1);
@@ -248,12 +249,12 @@ reg_status wgrad(reg_net *net, int l, const uint16_t *x, int x_cs, const uint16_
     a.n_out = out_grid(net, l);
     a.n_in = kDef[l].stride == 2 ? 2 * a.n_out : a.n_out;
     a.partials = net->partials;
+    a.bias_partials = net->bias_partials;
     const int mode = kDef[l].stride == 2 ? regn::CONV_FWD2 : regn::CONV_FWD1;
     NHIP(net, regn::launch_wgrad(mode, a, net->stream));
-    NHIP(net, regn::launch_wgrad_reduce(net->partials, regn::wgrad_chunks(a.n_out), a.cout, a.cin, kDef[l].cout,
-                                        kDef[l].cin, scale, net->grads + net->woff[l], net->stream));
-    const long P = (long)a.n_out * a.n_out * a.n_out;
-    NHIP(net, regn::launch_bias_grad(dz, a.dz_cs, P, kDef[l].cout, scale, net->grads + net->boff[l], net->stream));
+    NHIP(net, regn::launch_wgrad_reduce(net->partials, net->bias_partials, regn::wgrad_chunks(a.n_out), a.cout, a.cin,
+                                        kDef[l].cout, kDef[l].cin, scale, net->grads + net->woff[l],
+                                        net->grads + net->boff[l], net->stream));
     return REG_OK;
 }
 

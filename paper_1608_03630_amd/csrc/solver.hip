@@ -322,9 +322,9 @@ struct Exec {
             const long N3 = 3 * ctx->N;
             const Request &r = it.req;
             if (r.op == Op::GRADIENT) {
-                if (r.x != ctx->vcur)
-                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(r.x), V<double>(ctx->vcur), ctx->stream)));
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, ctx->vcur, ctx->vf, N3)));
+                if (r.x != ctx->vhat)
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(sv_len(ctx), CV<double>(r.x), V<double>(ctx->vhat), ctx->stream)));
+                STCHK(spec_to_field<T>(ctx, ctx->vhat, ctx->vf));
                 if (r.reuse) {
                     std::swap(ctx->histA, ctx->histB);
                     std::swap(ctx->Df, ctx->Dt);
@@ -334,7 +334,8 @@ struct Exec {
                 }
                 STCHK(plan_enqueue<T>(ctx, ctx->vf, -1.0, ctx->Da, ctx->dpart2, kSlotPlanB));
             } else if (r.op == Op::OBJECTIVE || r.op == Op::FORWARD) {
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, r.x, ctx->vf, N3)));
+                if (r.op == Op::OBJECTIVE) STCHK(spec_to_field<T>(ctx, r.x, ctx->vf));  // spectral velocity
+                else HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, r.x, ctx->vf, N3)));  // physical velocity
                 STCHK(plan_enqueue<T>(ctx, ctx->vf, +1.0, ctx->Dt, ctx->dpart, kSlotPlanA));
             } else {
                 continue;
@@ -383,7 +384,8 @@ struct Exec {
                 // incremental state through q^n = rho~^n - dt/2 vt.grad rho^n
                 const double dt = 1.0 / ctx->P.nt;
                 P.ops.push_back([ctx, r, N, dt]() -> reg_status {
-                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, r.x, ctx->vtf, 3 * N)));
+                    (void)N;
+                    STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho),
                                                                                     V<T>(ctx->lam[1]), -0.5 * dt, ctx->stream)));
                     return REG_OK;
@@ -480,14 +482,16 @@ struct Exec {
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, CV<T>(ctx->lamh), CV<T>(ctx->grho),
                                                                                  V<T>(ctx->bvec), ctx->stream)));
                 if (r.op == Op::GRADIENT) {
-                    STCHK(assemble<T>(ctx, ctx->vcur, ctx->bvec, r.y, true));
-                    STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vcur, true));
-                    STCHK(reduce<double>(ctx, r.y, nullptr, 3 * N, 2, h3(ctx), 3));
+                    // g^ = beta |k|^4 v^ + P FFT(b); J and |g|^2 by Parseval
+                    STCHK(biharm_partials(ctx, ctx->vhat));
+                    STCHK(assemble<T>(ctx, ctx->vhat, ctx->bvec, r.y));
+                    STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vhat, true));
+                    STCHK(sdot(ctx, r.y, r.y, 3));
                 } else if (r.op == Op::OBJECTIVE) {
                     STCHK(objective_slots<T>(ctx, ctx->histB, r.x, false));
                 } else if (r.op == Op::MATVEC) {
-                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y, false));
-                    if (r.dot) STCHK(reduce<double>(ctx, r.x, r.y, 3 * N, 0, h3(ctx), 0));
+                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y));
+                    if (r.dot) STCHK(sdot(ctx, r.x, r.y, 0));
                 }
                 return REG_OK;
             });
@@ -664,10 +668,15 @@ struct Solver {
     double beta = 0, beta_final = 0, factor = 0.1;
     double J = 0, mis = 0, gnorm = 0, g0 = 0, eta = 0, rz = 0, d = 0, alpha = 1;
     int k = 0, it = 0, i = 0, iters = 0, l = 0, trials = 0;
+    bool changed = false;  // an accepted step or the projection moved v
     clk::time_point t0;
     long interps0 = 0;
 
     bool done() const { return st == S_DONE; }
+
+    // reference of the gradient stopping test: the level's first gradient
+    // norm, or the caller's absolute reference
+    double gref() const { return ctx->P.gnorm_ref > 0 ? ctx->P.gnorm_ref : g0; }
 
     void queue_fetch(int nslots) {
         (void)hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream);
@@ -691,7 +700,7 @@ struct Solver {
     template <typename T>
     reg_status advance() {
         const reg_params &P = ctx->P;
-        const long N3 = 3 * ctx->N;
+        const long NV = sv_len(ctx);
         req = Request{};
         wait = false;
         for (;;) {
@@ -699,11 +708,10 @@ struct Solver {
             case S_START: {
                 t0 = clk::now();
                 interps0 = ctx->interps;
-                if (P.isochoric) {
-                    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward<double, double>(ctx->spec, CV<double>(v), 3, 0, ctx->stream))));
-                    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_LERAY, 0.0, 3, 1, ctx->stream)));
-                    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(v), 3, ctx->stream))));
-                }
+                // the iterate lives on the half spectrum until the solve ends
+                STCHK(to_spec(ctx, v, ctx->vhat));
+                if (P.isochoric) STCHK(leray_hat(ctx, ctx->vhat));
+                changed = P.isochoric != 0;
                 beta_final = P.beta_final > 0 ? P.beta_final : P.beta;
                 factor = (P.beta_factor > 0 && P.beta_factor < 1) ? P.beta_factor : 0.1;
                 beta = P.beta;
@@ -713,7 +721,7 @@ struct Solver {
             }
             case S_LEVEL:
                 ctx->beta = beta;
-                req = Request{Op::GRADIENT, v, ctx->g_, nullptr, false, false};
+                req = Request{Op::GRADIENT, ctx->vhat, ctx->ghat, nullptr, false, false};
                 st = S_LEVEL_GRAD;
                 return REG_OK;
             case S_LEVEL_GRAD: {
@@ -733,7 +741,7 @@ struct Solver {
                     st = S_LEVEL_END;
                     break;
                 }
-                if (gnorm <= P.gtol * g0) {
+                if (gnorm <= P.gtol * gref()) {
                     rep->stop_reason = 0;
                     st = S_LEVEL_END;
                     break;
@@ -743,15 +751,16 @@ struct Solver {
                     st = S_LEVEL_END;
                     break;
                 }
-                const double ratio = g0 > 0 ? gnorm / g0 : 0.0;
+                // forcing relative to the same reference as the stopping test
+                const double ratio = gref() > 0 ? gnorm / gref() : 0.0;
                 eta = P.forcing == 1 ? std::sqrt(ratio) : ratio;
                 if (eta > 0.5) eta = 0.5;
                 // truncated PCG on H s = -g from s = 0
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<double>(N3, 0.0, V<double>(ctx->sdir), ctx->stream)));
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_axpby<double>(N3, -1.0, CV<double>(ctx->g_), 0.0, V<double>(ctx->r), ctx->stream)));
-                STCHK(precond_impl(ctx, ctx->r, ctx->z));
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->p), ctx->stream)));
-                STCHK(reduce<double>(ctx, ctx->r, ctx->z, N3, 0, h3(ctx), 0));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<double>(NV, 0.0, V<double>(ctx->shat), ctx->stream)));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_axpby<double>(NV, -1.0, CV<double>(ctx->ghat), 0.0, V<double>(ctx->rhat), ctx->stream)));
+                STCHK(precond_hat(ctx, ctx->rhat, ctx->zhat));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->zhat), V<double>(ctx->phat), ctx->stream)));
+                STCHK(sdot(ctx, ctx->rhat, ctx->zhat, 0));
                 queue_fetch(1);
                 st = S_PCG_START;
                 return REG_OK;
@@ -760,7 +769,7 @@ struct Solver {
                 rz = ctx->hres[0];
                 i = 0;
                 iters = 0;
-                req = Request{Op::MATVEC, ctx->p, ctx->q, nullptr, false, true};
+                req = Request{Op::MATVEC, ctx->phat, ctx->qhat, nullptr, false, true};
                 st = S_MATVEC_DONE;
                 return REG_OK;
             case S_MATVEC_DONE: {
@@ -772,19 +781,19 @@ struct Solver {
                     break;
                 }
                 if (kappa <= 0) {  // negative curvature: stop (steepest descent at the first iteration)
-                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->z), V<double>(ctx->sdir), ctx->stream)));
+                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->zhat), V<double>(ctx->shat), ctx->stream)));
                     st = S_ARMIJO;
                     break;
                 }
                 const double a = rz / kappa;
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_cg_update<double>(N3, a, CV<double>(ctx->p), CV<double>(ctx->q), V<double>(ctx->sdir),
-                                                                                 V<double>(ctx->r), ctx->stream)));
-                STCHK(reduce<double>(ctx, ctx->r, ctx->r, N3, 0, h3(ctx), 0));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_cg_update<double>(NV, a, CV<double>(ctx->phat), CV<double>(ctx->qhat), V<double>(ctx->shat),
+                                                                                 V<double>(ctx->rhat), ctx->stream)));
+                STCHK(sdot(ctx, ctx->rhat, ctx->rhat, 0));
                 // z and <r, z> for the next direction, queued with the residual
                 // norm so that one synchronisation serves both (unused when the
                 // forcing test below ends the iteration)
-                STCHK(precond_impl(ctx, ctx->r, ctx->z));
-                STCHK(reduce<double>(ctx, ctx->r, ctx->z, N3, 0, h3(ctx), 4));
+                STCHK(precond_hat(ctx, ctx->rhat, ctx->zhat));
+                STCHK(sdot(ctx, ctx->rhat, ctx->zhat, 4));
                 queue_fetch(5);
                 st = S_RR_DONE;
                 return REG_OK;
@@ -795,20 +804,20 @@ struct Solver {
                     st = S_ARMIJO;
                     break;
                 }
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(ctx->z), rz1 / rz, CV<double>(ctx->p),
-                                                                            V<double>(ctx->p), ctx->stream)));
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(NV, CV<double>(ctx->zhat), rz1 / rz, CV<double>(ctx->phat),
+                                                                            V<double>(ctx->phat), ctx->stream)));
                 rz = rz1;
                 i++;
                 if (i >= P.max_pcg) {
                     st = S_ARMIJO;
                     break;
                 }
-                req = Request{Op::MATVEC, ctx->p, ctx->q, nullptr, false, true};
+                req = Request{Op::MATVEC, ctx->phat, ctx->qhat, nullptr, false, true};
                 st = S_MATVEC_DONE;
                 return REG_OK;
             }
             case S_ARMIJO:
-                STCHK(reduce<double>(ctx, ctx->g_, ctx->sdir, N3, 0, h3(ctx), 0));
+                STCHK(sdot(ctx, ctx->ghat, ctx->shat, 0));
                 queue_fetch(1);
                 st = S_ARMIJO_D;
                 return REG_OK;
@@ -825,9 +834,9 @@ struct Solver {
                     break;
                 }
                 trials++;
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(N3, CV<double>(v), alpha, CV<double>(ctx->sdir),
-                                                                            V<double>(ctx->vtrial), ctx->stream)));
-                req = Request{Op::OBJECTIVE, ctx->vtrial, nullptr, nullptr, false, false};
+                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(NV, CV<double>(ctx->vhat), alpha, CV<double>(ctx->shat),
+                                                                            V<double>(ctx->vthat), ctx->stream)));
+                req = Request{Op::OBJECTIVE, ctx->vthat, nullptr, nullptr, false, false};
                 st = S_LS_DONE;
                 return REG_OK;
             case S_LS_DONE: {
@@ -839,8 +848,9 @@ struct Solver {
                     break;
                 }
                 if (Jt <= J + P.armijo_c1 * alpha * d) {
-                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(N3, CV<double>(ctx->vtrial), V<double>(v), ctx->stream)));
-                    req = Request{Op::GRADIENT, v, ctx->g_, nullptr, true, false};
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->vthat), V<double>(ctx->vhat), ctx->stream)));
+                    changed = true;
+                    req = Request{Op::GRADIENT, ctx->vhat, ctx->ghat, nullptr, true, false};
                     st = S_NEWTON_GRAD;
                     return REG_OK;
                 }
@@ -872,7 +882,7 @@ struct Solver {
             }
             case S_LEVEL_END:
                 if (rep->stop_reason == 2) {
-                    if (gnorm <= P.gtol * g0) rep->stop_reason = 0;
+                    if (gnorm <= P.gtol * gref()) rep->stop_reason = 0;
                     if (P.mismatch_tol > 0 && mis <= P.mismatch_tol) rep->stop_reason = 1;
                 }
                 if (rep->stop_reason == 1 || beta <= beta_final * (1 + 1e-12)) {
@@ -884,6 +894,9 @@ struct Solver {
                 }
                 break;
             case S_FINISH:
+                // the last accepted iterate back to the caller's physical v
+                // (left untouched when nothing was accepted)
+                if (changed) STCHK(from_spec(ctx, ctx->vhat, v));
                 ctx->beta = P.beta;
                 rep->status = status;
                 rep->n_iter = it;
@@ -938,6 +951,8 @@ reg_status run_solvers(Exec<T> &ex, std::vector<Solver> &S) {
         }
         if (ex.b && !ex.b->prof.pending.empty()) ex.b->prof.resolve();
     }
+    // the last advance() of each problem queued its result transform
+    HIPCHK(S[0].ctx, hipStreamSynchronize(ex.stream));
     return REG_OK;
 }
 
@@ -1040,8 +1055,11 @@ reg_status reg_gradient(reg_ctx *ctx, const void *v, void *g, double *J, double 
     NEED_DEV(ctx, g);
     if (!ctx->have_images) return fail(ctx, REG_EINVAL, "reg_set_images has not been called");
     ctx->have_state = false;
-    Request r{Op::GRADIENT, v, g, nullptr, false, false};
+    STCHK(to_spec(ctx, v, ctx->vhat));
+    Request r{Op::GRADIENT, ctx->vhat, ctx->ghat, nullptr, false, false};
     STCHK(DISPATCH(ctx, single_op, ctx, r));
+    STCHK(from_spec(ctx, ctx->ghat, g));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     scalars_to_J(ctx, J, mismatch);
     if (gnorm) *gnorm = std::sqrt(ctx->hres[3]);
     if (!std::isfinite(ctx->hres[1]) || !std::isfinite(ctx->hres[2]) || !std::isfinite(ctx->hres[3]))
@@ -1055,7 +1073,8 @@ reg_status reg_objective(reg_ctx *ctx, const void *v, double *J, double *mismatc
     NEED_DEV(ctx, v);
     if (!J || !mismatch) return fail(ctx, REG_EINVAL, "J and mismatch are required");
     if (!ctx->have_images) return fail(ctx, REG_EINVAL, "reg_set_images has not been called");
-    Request r{Op::OBJECTIVE, v, nullptr, nullptr, false, false};
+    STCHK(to_spec(ctx, v, ctx->vthat));
+    Request r{Op::OBJECTIVE, ctx->vthat, nullptr, nullptr, false, false};
     STCHK(DISPATCH(ctx, single_op, ctx, r));
     scalars_to_J(ctx, J, mismatch);
     if (!std::isfinite(*J)) return fail(ctx, REG_ENONFINITE, "non-finite objective");
@@ -1067,8 +1086,10 @@ reg_status reg_hessian_matvec(reg_ctx *ctx, const void *vt, void *Hvt) {
     NEED_DEV(ctx, vt);
     NEED_DEV(ctx, Hvt);
     if (!ctx->have_state) return fail(ctx, REG_EINVAL, "reg_gradient must be called first");
-    Request r{Op::MATVEC, vt, Hvt, nullptr, false, false};
-    return DISPATCH(ctx, single_op, ctx, r);
+    STCHK(to_spec(ctx, vt, ctx->rhat));
+    Request r{Op::MATVEC, ctx->rhat, ctx->qhat, nullptr, false, false};
+    STCHK(DISPATCH(ctx, single_op, ctx, r));
+    return from_spec(ctx, ctx->qhat, Hvt);
 }
 
 reg_status reg_solve(reg_ctx *ctx, void *v_inout, reg_report *rep) {
@@ -1268,9 +1289,12 @@ reg_status reg_batch_gradient(reg_batch *b, const void *const *v, void *const *g
         reg_ctx *c = b->ctx[i];
         if (!c->have_images) return bfail(b, REG_EINVAL, "pair " + std::to_string(i) + ": images not set");
         c->have_state = false;
-        items.push_back({c, Request{Op::GRADIENT, v[i], g[i], nullptr, false, false}});
+        STCHK(to_spec(c, v[i], c->vhat));
+        items.push_back({c, Request{Op::GRADIENT, c->vhat, c->ghat, nullptr, false, false}});
     }
     STCHK(b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items));
+    for (int i = 0; i < b->npairs; i++) STCHK(from_spec(b->ctx[i], b->ctx[i]->ghat, g[i]));
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, REG_EHIP, "hipStreamSynchronize failed");
     for (int i = 0; i < b->npairs; i++) {
         reg_ctx *c = b->ctx[i];
         scalars_to_J(c, J ? &J[i] : nullptr, mismatch ? &mismatch[i] : nullptr);
@@ -1288,10 +1312,15 @@ reg_status reg_batch_hessian_matvec(reg_batch *b, const void *const *vt, void *c
     BATCH_ARRAY(b, Hvt);
     std::vector<Item> items;
     for (int i = 0; i < b->npairs; i++) {
-        if (!b->ctx[i]->have_state) return bfail(b, REG_EINVAL, "reg_batch_gradient must be called first");
-        items.push_back({b->ctx[i], Request{Op::MATVEC, vt[i], Hvt[i], nullptr, false, false}});
+        reg_ctx *c = b->ctx[i];
+        if (!c->have_state) return bfail(b, REG_EINVAL, "reg_batch_gradient must be called first");
+        STCHK(to_spec(c, vt[i], c->rhat));
+        items.push_back({c, Request{Op::MATVEC, c->rhat, c->qhat, nullptr, false, false}});
     }
-    return b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items);
+    STCHK(b->prec ? batch_round<double>(b, items) : batch_round<float>(b, items));
+    for (int i = 0; i < b->npairs; i++) STCHK(from_spec(b->ctx[i], b->ctx[i]->qhat, Hvt[i]));
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, REG_EHIP, "hipStreamSynchronize failed");
+    return REG_OK;
 }
 
 reg_status reg_batch_solve(reg_batch *b, void *const *v_inout, reg_report *reports) {

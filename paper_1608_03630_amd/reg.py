@@ -50,6 +50,7 @@ class reg_params(ctypes.Structure):
         ("max_ls", ctypes.c_int32),
         ("forcing", ctypes.c_int32),
         ("armijo_c1", ctypes.c_double),
+        ("gnorm_ref", ctypes.c_double),
     ]
 
 
@@ -98,6 +99,7 @@ _SIGS = {
     "reg_create": [ctypes.POINTER(reg_params), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
     "reg_destroy": [_P],
     "reg_set_beta": [_P, ctypes.c_double],
+    "reg_set_solver": [_P, ctypes.POINTER(reg_params)],
     "reg_set_images": [_P, _P, _P],
     "reg_interp": [_P, _P, _P, _P],
     "reg_backtrace": [_P, _P, ctypes.c_double, _P],
@@ -260,6 +262,10 @@ class Context:
     # ------------------------------------------------------ entry points
     def reg_set_beta(self, beta):
         _chk(lib().reg_set_beta(self.handle, float(beta)), self.handle, "reg_set_beta")
+
+    def reg_set_solver(self, params):
+        _chk(lib().reg_set_solver(self.handle, ctypes.byref(params)), self.handle, "reg_set_solver")
+        self.params = params
 
     def reg_set_images(self, rho_T, rho_R):
         _chk(lib().reg_set_images(self.handle, self._t(rho_T, 1, "rho_T"), self._t(rho_R, 1, "rho_R")),
