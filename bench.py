@@ -9,9 +9,12 @@ with intensities from {0.1, ..., 1.0}, Gaussian-smoothed with sigma = 2 voxels
 on the GPU; the reference is the phantom transported on the GPU by a seeded
 smooth compressible velocity (|k| <= 8, max displacement 8 voxels). Solver:
 FP32 fields with FP64 reductions, nt = 16, H2 regularisation, beta
-continuation 1e-1 -> 1e-4 (factor 10), Gauss-Newton-PCG with the spectral
-preconditioner, stopping at relative mismatch <= 1e-2 (or relative gradient
-1e-2 on the last level).
+continuation from 1e-1 by factors of 10, each level solved to a relative
+gradient of 1e-2, Gauss-Newton-PCG with the spectral preconditioner, stopping
+as soon as the relative mismatch is <= 1e-2. On this phantom the levels down
+to beta = 1e-4 end at mismatch 0.107, so the continuation goes on (to at most
+beta = 1e-6) until the mismatch target is met; the run to beta = 1e-4 alone is
+reported beside it.
 
 One step = one full solve from v = 0 with the images already in device
 memory. Output: one JSON line on stdout.
@@ -40,6 +43,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+METRIC_BETA_FINAL = 1e-6  # continuation floor of the time-to-mismatch run
+SCHEDULE_BETA_FINAL = 1e-4  # the 1e-1 -> 1e-4 schedule, reported beside it
+
+
+def solve_params(reg, shape, beta_final):
+    return reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=beta_final, beta_factor=0.1,
+                                  gtol=1e-2, mismatch_tol=1e-2, max_newton=50, max_pcg=100, max_ls=20)
+
+
 def make_workload(reg, torch, n, seed=1003):
     import numpy as np
 
@@ -49,9 +61,7 @@ def make_workload(reg, torch, n, seed=1003):
     t0 = time.time()
     case = synth.phantom_case(shape, seed)
     log(f"[bench] phantom and velocity generated on the host in {time.time() - t0:.1f} s")
-    params = reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=1e-4, beta_factor=0.1,
-                                    gtol=1e-2, mismatch_tol=1e-2, max_newton=50, max_pcg=100, max_ls=20)
-    ctx = reg.Context(params)
+    ctx = reg.Context(solve_params(reg, shape, METRIC_BETA_FINAL))
     labels = torch.from_numpy(case["labels"].astype(np.float32)).cuda()
     rhoT = ctx.reg_spectral(reg.SPEC_GAUSS, case["sigma"], labels)
     v_true = torch.from_numpy(case["v_true"]).cuda()
@@ -311,6 +321,16 @@ def main():
     sec = (t1 - t0) / args.steps
     N = ctx.N
     rep = reports[-1]
+    # the 1e-1 -> 1e-4 schedule alone (not timed into `value`)
+    ctx.reg_set_solver(solve_params(reg, ctx.shape, SCHEDULE_BETA_FINAL))
+    v.zero_()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    _, rep_s = ctx.reg_solve(v)
+    torch.cuda.synchronize()
+    sched = {"beta_final": SCHEDULE_BETA_FINAL, "seconds": time.perf_counter() - ts,
+             "final_mismatch": rep_s["final_mismatch"], "gn_steps": rep_s["n_iter"], "matvecs": rep_s["matvecs"]}
+    log(f"[bench] schedule to beta 1e-4: {sched['seconds']:.3f} s, mismatch {sched['final_mismatch']:.4f}")
 
     # dominant transport kernel and its roofline (HIP events on the library's stream)
     kinds = {k: prof[k] for k in BYTES_PER_POINT if prof[k][0] > 0}
@@ -347,12 +367,14 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{args.n}^3 smoothed ellipsoid phantom (seed 1003) warped by a seeded |k|<=8 velocity, "
-                        "nt=16, H2, beta 1e-1 -> 1e-4, FP32 fields + FP64 reductions, GN-PCG, stop at "
-                        "rel. mismatch 1e-2",
+                        "nt=16, H2, beta continuation from 1e-1 (x0.1 per level, each to |g|/|g0| 1e-2, floor "
+                        "1e-6), FP32 fields + FP64 reductions, GN-PCG, stop at rel. mismatch 1e-2",
             "grid": [args.n] * 3,
             "nt": 16,
         },
         "final_mismatch": rep["final_mismatch"],
+        "beta_reached": min(rep["beta"]) if rep["beta"] else None,
+        "schedule_to_1e-4": sched,
         "stop_reason": ["gradient tolerance", "mismatch", "step limit"][rep["stop_reason"]],
         "gn_steps": rep["n_iter"],
         "matvecs": rep["matvecs"],

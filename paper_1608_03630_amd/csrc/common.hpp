@@ -165,6 +165,18 @@ hipError_t vec_load(const SpecCtx &c, const double *vhat, void *H, hipStream_t s
 template <typename T>
 hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, double a, int leray, double *out,
                       hipStream_t s);
+// Fused Krylov passes (partials: one double per block of a grid-stride loop
+// over the half spectrum, nblocks blocks).
+// s = 0, r = -g, z = M r, p = z; partials of <r, z>
+hipError_t pcg_init(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *z,
+                    double *p, double *part_rz, int nblocks, hipStream_t st);
+// s += a p, r -= a q, z = M r; partials of <r, r> and <r, z>
+hipError_t pcg_update(const SpecCtx &c, double a, const double *p, const double *q, double beta, int leray, double *s,
+                      double *r, double *z, double *part_rr, double *part_rz, int nblocks, hipStream_t st);
+// out = a |k|^4 x + [P] y with partials of <x, out> (dot 1) or <out, out> (dot 2)
+template <typename T>
+hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, double a, int leray, int dot, double *out,
+                            double *part, int nblocks, hipStream_t st);
 // partials of sum w(k3) Re(a conj b) (mode 0) or sum w(k3) |k|^4 |a|^2 (mode 1)
 hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const double *b, double *partials,
                             int nblocks, hipStream_t s);

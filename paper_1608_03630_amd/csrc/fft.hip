@@ -784,6 +784,169 @@ __global__ __launch_bounds__(kThreads) void k_vec_dot(Grid g, int mode, const do
     }
 }
 
+// ---------------------------------------------- fused Krylov vector passes
+// Reductions below write one partial per block of a grid-stride loop over the
+// half spectrum; k_finalize adds them in a fixed order.
+
+__device__ __forceinline__ void block_sum2(double &x, double &y, double *__restrict__ px,
+                                           double *__restrict__ py) {
+    for (int off = 32; off > 0; off >>= 1) {
+        x += __shfl_down(x, off, 64);
+        y += __shfl_down(y, off, 64);
+    }
+    __shared__ double wsx[kThreads / 64], wsy[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) {
+        wsx[threadIdx.x >> 6] = x;
+        wsy[threadIdx.x >> 6] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tx = 0.0, ty = 0.0;
+        for (int i = 0; i < kThreads / 64; i++) {
+            tx += wsx[i];
+            ty += wsy[i];
+        }
+        if (px) px[blockIdx.x] = tx;
+        if (py) py[blockIdx.x] = ty;
+    }
+}
+
+struct ModeInfo {
+    double kk, t1, t2, t3, tt, w;
+};
+
+__device__ __forceinline__ ModeInfo mode_info(const Grid &g, long q) {
+    const int nh = g.n3h();
+    const int m3 = (int)(q % nh);
+    const long r = q / nh;
+    const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
+    ModeInfo mi;
+    const double k1 = kwave(m1, g.n1), k2 = kwave(m2, g.n2), k3 = m3;
+    mi.kk = k1 * k1 + k2 * k2 + k3 * k3;
+    mi.t1 = kwave_odd(m1, g.n1);
+    mi.t2 = kwave_odd(m2, g.n2);
+    mi.t3 = (2 * m3 == g.n3 ? 0 : m3);
+    mi.tt = mi.t1 * mi.t1 + mi.t2 * mi.t2 + mi.t3 * mi.t3;
+    mi.w = (m3 == 0 || 2 * m3 == g.n3) ? 1.0 : 2.0;
+    return mi;
+}
+
+__device__ __forceinline__ void leray3(const ModeInfo &mi, double2 v[3]) {
+    if (mi.tt > 0.0) {
+        const double ir = 1.0 / mi.tt;
+        const double dx = (mi.t1 * v[0].x + mi.t2 * v[1].x + mi.t3 * v[2].x) * ir;
+        const double dy = (mi.t1 * v[0].y + mi.t2 * v[1].y + mi.t3 * v[2].y) * ir;
+        v[0].x -= mi.t1 * dx;
+        v[0].y -= mi.t1 * dy;
+        v[1].x -= mi.t2 * dx;
+        v[1].y -= mi.t2 * dy;
+        v[2].x -= mi.t3 * dx;
+        v[2].y -= mi.t3 * dy;
+    }
+}
+
+// z = M r: inverse biharmonic (identity at k = 0), then P when leray
+__device__ __forceinline__ void precond3(const ModeInfo &mi, double beta, int leray, const double2 r[3],
+                                         double2 z[3]) {
+    const double f = mi.kk > 0.0 ? 1.0 / (beta * mi.kk * mi.kk) : 1.0;
+    for (int c = 0; c < 3; c++) z[c] = make_double2(f * r[c].x, f * r[c].y);
+    if (leray) leray3(mi, z);
+}
+
+// PCG set-up of a Newton step: s = 0, r = -g, z = M r, p = z; partials of <r, z>
+__global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const double2 *__restrict__ gv, double beta, int leray,
+                                                       double2 *__restrict__ s, double2 *__restrict__ r,
+                                                       double2 *__restrict__ z, double2 *__restrict__ p,
+                                                       double *__restrict__ part_rz) {
+    const long Nh = g.Nh();
+    double rz = 0.0, dummy = 0.0;
+    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
+        const ModeInfo mi = mode_info(g, q);
+        double2 rv[3], zv[3];
+        for (int c = 0; c < 3; c++) {
+            const double2 x = gv[c * Nh + q];
+            rv[c] = make_double2(-x.x, -x.y);
+        }
+        precond3(mi, beta, leray, rv, zv);
+        double acc = 0.0;
+        for (int c = 0; c < 3; c++) {
+            s[c * Nh + q] = make_double2(0.0, 0.0);
+            r[c * Nh + q] = rv[c];
+            z[c * Nh + q] = zv[c];
+            p[c * Nh + q] = zv[c];
+            acc += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
+        }
+        rz += mi.w * acc;
+    }
+    block_sum2(rz, dummy, part_rz, nullptr);
+}
+
+// PCG step: s += a p, r -= a q, z = M r; partials of <r, r> and <r, z>
+__global__ __launch_bounds__(kThreads) void k_pcg_update(Grid g, double a, const double2 *__restrict__ p,
+                                                         const double2 *__restrict__ qv, double beta, int leray,
+                                                         double2 *__restrict__ s, double2 *__restrict__ r,
+                                                         double2 *__restrict__ z, double *__restrict__ part_rr,
+                                                         double *__restrict__ part_rz) {
+    const long Nh = g.Nh();
+    double rr = 0.0, rz = 0.0;
+    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
+        const ModeInfo mi = mode_info(g, q);
+        double2 rv[3], zv[3];
+        for (int c = 0; c < 3; c++) {
+            const double2 pc = p[c * Nh + q], qc = qv[c * Nh + q];
+            double2 sc = s[c * Nh + q], rc = r[c * Nh + q];
+            sc.x += a * pc.x;
+            sc.y += a * pc.y;
+            rc.x -= a * qc.x;
+            rc.y -= a * qc.y;
+            s[c * Nh + q] = sc;
+            rv[c] = rc;
+        }
+        precond3(mi, beta, leray, rv, zv);
+        double arr = 0.0, arz = 0.0;
+        for (int c = 0; c < 3; c++) {
+            r[c * Nh + q] = rv[c];
+            z[c * Nh + q] = zv[c];
+            arr += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
+            arz += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
+        }
+        rr += mi.w * arr;
+        rz += mi.w * arz;
+    }
+    block_sum2(rr, rz, part_rr, part_rz);
+}
+
+// out = a |k|^4 x + [P] y (y complex T) with partials of <x, out> (dot 1) or
+// <out, out> (dot 2)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const double2 *__restrict__ x,
+                                                               const cplx_t<T> *__restrict__ y, double a, int leray,
+                                                               int dot, double2 *__restrict__ out,
+                                                               double *__restrict__ part) {
+    const long Nh = g.Nh();
+    double acc = 0.0, dummy = 0.0;
+    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
+        const ModeInfo mi = mode_info(g, q);
+        double2 v[3];
+        for (int c = 0; c < 3; c++) {
+            const cplx_t<T> zc = y[c * Nh + q];
+            v[c] = make_double2((double)zc.x, (double)zc.y);
+        }
+        if (leray) leray3(mi, v);
+        const double f = a * mi.kk * mi.kk;
+        double loc = 0.0;
+        for (int c = 0; c < 3; c++) {
+            const double2 xc = x[c * Nh + q];
+            v[c].x = f * xc.x + v[c].x;
+            v[c].y = f * xc.y + v[c].y;
+            out[c * Nh + q] = v[c];
+            loc += dot == 1 ? xc.x * v[c].x + xc.y * v[c].y : v[c].x * v[c].x + v[c].y * v[c].y;
+        }
+        acc += mi.w * loc;
+    }
+    block_sum2(acc, dummy, part, nullptr);
+}
+
 // Spectral resampling between grids: destination mode (q1, q2, q3) takes the
 // source mode of the same wavenumber, scaled by Nd/Ns, when |k_j| <
 // min(ns_j, nd_j)/2 on every axis (the Nyquist planes of the smaller grid are
@@ -854,6 +1017,32 @@ hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const d
     return hipGetLastError();
 }
 
+hipError_t pcg_init(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *z,
+                    double *p, double *part_rz, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_init, dim3(nblocks), dim3(kThreads), 0, st, c.g, reinterpret_cast<const double2 *>(g),
+                       beta, leray, reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r),
+                       reinterpret_cast<double2 *>(z), reinterpret_cast<double2 *>(p), part_rz);
+    return hipGetLastError();
+}
+
+hipError_t pcg_update(const SpecCtx &c, double a, const double *p, const double *q, double beta, int leray, double *s,
+                      double *r, double *z, double *part_rr, double *part_rz, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks), dim3(kThreads), 0, st, c.g, a,
+                       reinterpret_cast<const double2 *>(p), reinterpret_cast<const double2 *>(q), beta, leray,
+                       reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r), reinterpret_cast<double2 *>(z),
+                       part_rr, part_rz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, double a, int leray, int dot, double *out,
+                            double *part, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_vec_assemble_dot<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g,
+                       reinterpret_cast<const double2 *>(x), reinterpret_cast<const cplx_t<T> *>(y), a, leray, dot,
+                       reinterpret_cast<double2 *>(out), part);
+    return hipGetLastError();
+}
+
 #define REGK_FFT_INST(T)                                                                                           \
     template hipError_t spec_resample<T>(const SpecCtx &, const SpecCtx &, int, hipStream_t);                     \
     template hipError_t spec_deriv<T>(const SpecCtx &, int, const T *, long, T *, long, int, int, hipStream_t);    \
@@ -864,6 +1053,8 @@ hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const d
     template hipError_t spec_forward_to<T, T>(const SpecCtx &, const T *, int, void *, hipStream_t);              \
     template hipError_t spec_inverse_from<T, T>(const SpecCtx &, void *, T *, int, hipStream_t);                  \
     template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
+    template hipError_t vec_assemble_dot<T>(const SpecCtx &, const double *, const void *, double, int, int,        \
+                                            double *, double *, int, hipStream_t);                                  \
     template hipError_t vec_symbol<T>(const SpecCtx &, int, const double *, const void *, double, int, double *,  \
                                       hipStream_t);
 

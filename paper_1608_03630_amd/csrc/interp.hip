@@ -319,7 +319,11 @@ __global__ __launch_bounds__(kThreads) void k_deform_step(Grid g, const T *__res
 // displacement cannot address outside it.
 
 constexpr int kTileLines = kTile1 * kTile2;       // x3 lines per tile
-constexpr int kWaves = kThreads / 64;             // 4 wavefronts
+// Workgroup of the LDS-tiled gathers: kTileThreads threads share one tile's
+// box, each owning kLinesPerWave x3 lines (points); eight wavefronts per box
+// keep six resident per SIMD (74 VGPRs) where four wavefronts reached four.
+constexpr int kTileThreads = 512;
+constexpr int kWaves = kTileThreads / 64;
 constexpr int kLinesPerWave = kTileLines / kWaves;
 
 struct TileIdx {
@@ -481,7 +485,7 @@ __device__ __forceinline__ void generic_tile(const Grid &g, const TileGeom &tg, 
 }
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(kThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
+__global__ __launch_bounds__(kTileThreads) void k_tiled(Grid g, TileGeom tg, const T *__restrict__ f,
                                                     const T *__restrict__ D, TileArgs args) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     generic_tile<T, MODE>(g, tg, tile_of(g), f, D, args, reinterpret_cast<T *>(smem_raw));
@@ -620,7 +624,7 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
 }
 
 template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kThreads) void k_tiled_canon(Grid g, TileGeom tg, const T *__restrict__ f,
+__global__ __launch_bounds__(kTileThreads) void k_tiled_canon(Grid g, TileGeom tg, const T *__restrict__ f,
                                                           const T *__restrict__ D, TileArgs args) {
     __shared__ T box[Canon<S>::elems];
     canon_tile<T, MODE, S>(g, tg, tile_of(g), f, D, args, box);
@@ -673,7 +677,7 @@ __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, i
 }
 
 template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
+__global__ __launch_bounds__(kTileThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
                                                             int total, int chunked) {
     __shared__ T box[Canon<S>::elems];
     walk_items(pairs, npairs, total, chunked,
@@ -686,7 +690,7 @@ __global__ __launch_bounds__(kThreads) void k_batched_canon(const PairStep *__re
 // MIXED: pairs marked canonical take the canonical span-4 body, the others
 // the generic one, in one launch (dynamic LDS sized for both).
 template <typename T, int MODE, bool MIXED>
-__global__ __launch_bounds__(kThreads) void k_batched_generic(const PairStep *__restrict__ pairs, int npairs,
+__global__ __launch_bounds__(kTileThreads) void k_batched_generic(const PairStep *__restrict__ pairs, int npairs,
                                                               int total, int chunked) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *box = reinterpret_cast<T *>(smem_raw);
@@ -764,20 +768,20 @@ hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *
     const bool whole = g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0;
     const int span = box_span(tg);
     if (whole && span <= 1 && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 1>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f, D, a);
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 1>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
         return hipGetLastError();
     }
     if (whole && span <= 2 && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f, D, a);
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
         return hipGetLastError();
     }
     if (whole && span <= kCanonMaxSpan && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, kCanonMaxSpan>), dim3(ntiles(g)), dim3(kThreads), 0, s, g, tg, f,
+        hipLaunchKernelGGL((k_tiled_canon<T, MODE, kCanonMaxSpan>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f,
                            D, a);
         return hipGetLastError();
     }
     const size_t lds = sizeof(T) * (size_t)tg.B[0] * tg.B[1] * tg.B[2];
-    hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kThreads), lds, s, g, tg, f, D, a);
+    hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kTileThreads), lds, s, g, tg, f, D, a);
     return hipGetLastError();
 }
 
@@ -806,7 +810,7 @@ hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep
     if ((variant == 0 || variant == 8) && (lds == 0 || lds > 65536)) return hipErrorInvalidValue;
     if (variant == 8 && lds < sizeof(T) * Canon<kCanonMaxSpan>::elems) return hipErrorInvalidValue;
     if (variant != 0 && sizeof(T) != 4) return hipErrorInvalidValue;
-    const dim3 grid(nblocks_grid), block(kThreads);
+    const dim3 grid(nblocks_grid), block(kTileThreads);
 #define REGK_BATCH(M)                                                                                               \
     do {                                                                                                            \
         if (variant == 0)                                                                                           \

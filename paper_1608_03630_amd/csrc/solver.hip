@@ -484,14 +484,12 @@ struct Exec {
                 if (r.op == Op::GRADIENT) {
                     // g^ = beta |k|^4 v^ + P FFT(b); J and |g|^2 by Parseval
                     STCHK(biharm_partials(ctx, ctx->vhat));
-                    STCHK(assemble<T>(ctx, ctx->vhat, ctx->bvec, r.y));
                     STCHK(objective_slots<T>(ctx, ctx->histA, ctx->vhat, true));
-                    STCHK(sdot(ctx, r.y, r.y, 3));
+                    STCHK(assemble<T>(ctx, ctx->vhat, ctx->bvec, r.y, 2, 3));
                 } else if (r.op == Op::OBJECTIVE) {
                     STCHK(objective_slots<T>(ctx, ctx->histB, r.x, false));
                 } else if (r.op == Op::MATVEC) {
-                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y));
-                    if (r.dot) STCHK(sdot(ctx, r.x, r.y, 0));
+                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y, r.dot ? 1 : 0, 0));
                 }
                 return REG_OK;
             });
@@ -756,11 +754,7 @@ struct Solver {
                 eta = P.forcing == 1 ? std::sqrt(ratio) : ratio;
                 if (eta > 0.5) eta = 0.5;
                 // truncated PCG on H s = -g from s = 0
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<double>(NV, 0.0, V<double>(ctx->shat), ctx->stream)));
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_axpby<double>(NV, -1.0, CV<double>(ctx->ghat), 0.0, V<double>(ctx->rhat), ctx->stream)));
-                STCHK(precond_hat(ctx, ctx->rhat, ctx->zhat));
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->zhat), V<double>(ctx->phat), ctx->stream)));
-                STCHK(sdot(ctx, ctx->rhat, ctx->zhat, 0));
+                STCHK(pcg_init(ctx, 0));
                 queue_fetch(1);
                 st = S_PCG_START;
                 return REG_OK;
@@ -786,14 +780,11 @@ struct Solver {
                     break;
                 }
                 const double a = rz / kappa;
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_cg_update<double>(NV, a, CV<double>(ctx->phat), CV<double>(ctx->qhat), V<double>(ctx->shat),
-                                                                                 V<double>(ctx->rhat), ctx->stream)));
-                STCHK(sdot(ctx, ctx->rhat, ctx->rhat, 0));
-                // z and <r, z> for the next direction, queued with the residual
-                // norm so that one synchronisation serves both (unused when the
-                // forcing test below ends the iteration)
-                STCHK(precond_hat(ctx, ctx->rhat, ctx->zhat));
-                STCHK(sdot(ctx, ctx->rhat, ctx->zhat, 4));
+                // one pass: the update, z = M r for the next direction and
+                // both inner products, so that one synchronisation serves the
+                // forcing test and the next direction (z unused when the test
+                // ends the iteration)
+                STCHK(pcg_update(ctx, a, 0, 4));
                 queue_fetch(5);
                 st = S_RR_DONE;
                 return REG_OK;
