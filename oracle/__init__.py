@@ -40,6 +40,8 @@ class Params(ctypes.Structure):
         ("max_ls", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("armijo_c1", ctypes.c_double),
+        ("gtol_level", ctypes.c_double),
+        ("gnorm_ref", ctypes.c_double),
     ]
 
 
@@ -88,7 +90,7 @@ class Report(ctypes.Structure):
 
 
 def params(n, nt, beta, isochoric=False, beta_final=0.0, beta_factor=0.1, gtol=1e-2, mismatch_tol=0.0,
-           max_newton=50, max_pcg=100, max_ls=20, forcing=0, armijo_c1=1e-4):
+           max_newton=50, max_pcg=100, max_ls=20, forcing=0, armijo_c1=1e-4, gtol_level=0.0, gnorm_ref=0.0):
     p = Params()
     n = tuple(int(x) for x in (n if np.ndim(n) else (n, n, n)))
     p.n[:] = n
@@ -105,6 +107,8 @@ def params(n, nt, beta, isochoric=False, beta_final=0.0, beta_factor=0.1, gtol=1
     p.max_ls = int(max_ls)
     p.reserved = 0
     p.armijo_c1 = float(armijo_c1)
+    p.gtol_level = float(gtol_level)
+    p.gnorm_ref = float(gnorm_ref)
     return p
 
 

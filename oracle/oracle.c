@@ -518,6 +518,11 @@ typedef struct {
     int32_t max_newton, max_pcg, max_ls;
     int32_t reserved;
     double armijo_c1;
+    /* Continuation and stopping (section III-A leaves both to the
+     * application): gtol_level > 0 solves the levels above beta_final only
+     * to |g| <= gtol_level * ref; gnorm_ref > 0 makes ref (and the forcing
+     * ratio) absolute instead of |g0| of the level. */
+    double gtol_level, gnorm_ref;
 } oracle_params;
 
 /* everything the gradient and the Hessian need at one velocity */
@@ -819,8 +824,10 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
         gnorm = norm3(n, g);
         g0 = gnorm;
         rep->stop_reason = 2;
+        const double ref = P->gnorm_ref > 0 ? P->gnorm_ref : g0;
+        const double tol = (P->gtol_level > 0 && beta > beta_final * (1 + 1e-12)) ? P->gtol_level : P->gtol;
         for (int k = 0; k < P->max_newton; k++) {
-            if (gnorm <= P->gtol * g0) {
+            if (gnorm <= tol * ref) {
                 rep->stop_reason = 0;
                 break;
             }
@@ -828,7 +835,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
                 rep->stop_reason = 1;
                 break;
             }
-            double ratio = g0 > 0 ? gnorm / g0 : 0.0;
+            double ratio = ref > 0 ? gnorm / ref : 0.0;
             double eta = P->forcing == 1 ? sqrt(ratio) : ratio;
             if (eta > 0.5) eta = 0.5;
             /* truncated PCG on H s = -g */
@@ -907,7 +914,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
         }
         /* the loop may also end after its last step without a test */
         if (rep->stop_reason == 2) {
-            if (gnorm <= P->gtol * g0) rep->stop_reason = 0;
+            if (gnorm <= tol * ref) rep->stop_reason = 0;
             if (P->mismatch_tol > 0 && mis <= P->mismatch_tol) rep->stop_reason = 1;
         }
         st_free(&st);

@@ -89,6 +89,30 @@ def test_beta_continuation_levels(orc):
     assert rep["mismatch"][-1] < rep["mismatch"][0]
 
 
+def test_loose_intermediate_levels_and_absolute_reference(orc):
+    """gtol_level stops each level above beta_final as soon as |g| <= gtol_level
+    |g0| (and not before); the last level runs to gtol. gnorm_ref replaces
+    |g0| by an absolute reference."""
+    shape = (16, 16, 16)
+    c = synth.smooth_case(shape)
+    P0 = orc.params(shape, 4, 1e-2)
+    rhoR = orc.transport_forward(P0, c["v_true"], c["rhoT"])
+    P = orc.params(shape, 4, 1e-1, beta_final=1e-3, beta_factor=0.1, max_newton=10, gtol_level=0.3)
+    _, rep = orc.solve(P, c["rhoT"], rhoR)
+    betas, grel = np.array(rep["beta"]), np.array(rep["grel"])
+    for b in sorted(set(rep["beta"]), reverse=True):
+        g = grel[betas == b]
+        tol = 1e-2 if np.isclose(b, 1e-3) else 0.3
+        assert g[-1] <= tol and np.all(g[:-1] > tol), (b, g)
+    assert np.isclose(min(rep["beta"]), 1e-3)
+    # an absolute reference ten times |g(v=0)| is met at once: no Newton step
+    g_zero = orc.gradient(orc.params(shape, 4, 1e-1), c["rhoT"], rhoR, np.zeros((3,) + shape))[0]
+    g0 = np.sqrt(inner(g_zero, g_zero))
+    Pr = orc.params(shape, 4, 1e-1, max_newton=10, gnorm_ref=10 * g0 / 1e-2)
+    _, rep2 = orc.solve(Pr, c["rhoT"], rhoR)
+    assert rep2["n_iter"] == 0 and rep2["stop_reason"] == 0
+
+
 def test_isochoric_solve_stays_divergence_free(orc):
     shape = (16, 16, 16)
     b = synth.blob_case(shape)
