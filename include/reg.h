@@ -87,6 +87,8 @@ typedef struct {
                             * gtol ||g0||, and use ||g||/gnorm_ref in the forcing term (an
                             * absolute reference, e.g. ||g(v=0)||, so that warm and cold
                             * starts run by the same rules); 0: ||g0||                */
+    double gtol_level;     /* > 0: continuation levels above beta_final stop at
+                            * ||g|| <= gtol_level * ref (the last level uses gtol); 0: gtol */
 } reg_params;
 
 #define REG_MAXIT 512

@@ -242,6 +242,10 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
         *why = "gnorm_ref must be >= 0 and finite";
         return REG_EINVAL;
     }
+    if (!(p->gtol_level >= 0) || !std::isfinite(p->gtol_level)) {
+        *why = "gtol_level must be >= 0 and finite";
+        return REG_EINVAL;
+    }
     return REG_OK;
 }
 

@@ -675,6 +675,10 @@ struct Solver {
     // reference of the gradient stopping test: the level's first gradient
     // norm, or the caller's absolute reference
     double gref() const { return ctx->P.gnorm_ref > 0 ? ctx->P.gnorm_ref : g0; }
+    // the level's tolerance: gtol_level above beta_final when given
+    double level_tol() const {
+        return (ctx->P.gtol_level > 0 && beta > beta_final * (1 + 1e-12)) ? ctx->P.gtol_level : ctx->P.gtol;
+    }
 
     void queue_fetch(int nslots) {
         (void)hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream);
@@ -739,7 +743,7 @@ struct Solver {
                     st = S_LEVEL_END;
                     break;
                 }
-                if (gnorm <= P.gtol * gref()) {
+                if (gnorm <= level_tol() * gref()) {
                     rep->stop_reason = 0;
                     st = S_LEVEL_END;
                     break;
@@ -873,7 +877,7 @@ struct Solver {
             }
             case S_LEVEL_END:
                 if (rep->stop_reason == 2) {
-                    if (gnorm <= P.gtol * gref()) rep->stop_reason = 0;
+                    if (gnorm <= level_tol() * gref()) rep->stop_reason = 0;
                     if (P.mismatch_tol > 0 && mis <= P.mismatch_tol) rep->stop_reason = 1;
                 }
                 if (rep->stop_reason == 1 || beta <= beta_final * (1 + 1e-12)) {

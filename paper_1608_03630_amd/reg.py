@@ -51,6 +51,7 @@ class reg_params(ctypes.Structure):
         ("forcing", ctypes.c_int32),
         ("armijo_c1", ctypes.c_double),
         ("gnorm_ref", ctypes.c_double),
+        ("gtol_level", ctypes.c_double),
     ]
 
 
