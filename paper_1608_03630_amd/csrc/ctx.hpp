@@ -87,7 +87,10 @@ struct Profiler {
     hipEvent_t take() {
         if (free_.empty()) {
             hipEvent_t e = nullptr;
-            if (hipEventCreate(&e) != hipSuccess) {
+            // timing only, read after a stream synchronisation: no
+            // system-scope fence (which would write back and invalidate the
+            // caches around every timed launch)
+            if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
                 (void)hipGetLastError();
                 return nullptr;
             }

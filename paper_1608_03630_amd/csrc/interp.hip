@@ -347,39 +347,58 @@ __device__ __forceinline__ TileIdx tile_of(const Grid &g) {
 // up to kStageRows * 3 loads in flight (B3 <= 64 + 3 + 64 < 192).
 constexpr int kStageRows = 4;
 
+// Index of this thread's wavefront, in a scalar register: everything derived
+// from it (rows to stage, row addresses) is then wave-uniform scalar work.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
+// Row (r1, r2) of a B1 x B2 row grid advanced by `step` rows (r2 fastest).
+__device__ __forceinline__ void next_row(int &r1, int &r2, int step, int B2) {
+    r2 += step;
+    while (r2 >= B2) {
+        r2 -= B2;
+        r1++;
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ void stage_box(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                           const T *__restrict__ f, T *box) {
     const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int nrows = tg.B[0] * tg.B[1], B3 = tg.B[2];
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int B1 = tg.B[0], B2 = tg.B[1], B3 = tg.B[2];
     int gc[3];
 #pragma unroll
     for (int h = 0; h < 3; h++) gc[h] = wrap_idx(o3 + lane + 64 * h, g.n3);
-    for (int r0 = wave; r0 < nrows; r0 += kStageRows * kWaves) {
+    int r1 = 0, r2 = 0;
+    next_row(r1, r2, wave, B2);
+    while (r1 < B1) {
         T vals[kStageRows][3];
+        int dst[kStageRows];
+        int q1 = r1, q2 = r2;
 #pragma unroll
         for (int u = 0; u < kStageRows; u++) {
-            const int r = r0 + u * kWaves;
-            if (r < nrows) {
-                const int r1 = r / tg.B[1], r2 = r - r1 * tg.B[1];
-                const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
+            dst[u] = -1;
+            if (q1 < B1) {
+                const int g1 = wrap_idx(o1 + q1, g.n1), g2 = wrap_idx(o2 + q2, g.n2);
                 const T *row = f + ((long)g1 * g.n2 + g2) * g.n3;
 #pragma unroll
                 for (int h = 0; h < 3; h++)
                     if (lane + 64 * h < B3) vals[u][h] = row[gc[h]];
+                dst[u] = (q1 * B2 + q2) * B3;
             }
+            next_row(q1, q2, kWaves, B2);
         }
 #pragma unroll
         for (int u = 0; u < kStageRows; u++) {
-            const int r = r0 + u * kWaves;
-            if (r < nrows) {
-                T *dst = box + r * B3;
+            if (dst[u] >= 0) {
+                T *d = box + dst[u];
 #pragma unroll
                 for (int h = 0; h < 3; h++)
-                    if (lane + 64 * h < B3) dst[lane + 64 * h] = vals[u][h];
+                    if (lane + 64 * h < B3) d[lane + 64 * h] = vals[u][h];
             }
         }
+        r1 = q1;
+        r2 = q2;
     }
 }
 
@@ -433,7 +452,7 @@ __device__ __forceinline__ void generic_tile(const Grid &g, const TileGeom &tg, 
                                              const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
                                              T *box) {
     const long N = g.N();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const int i3 = t.t3 * kTile3 + lane;
     const bool col_ok = i3 < g.n3;
     T dd[kLinesPerWave][3];
@@ -509,26 +528,27 @@ __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &t
                                                 const T *__restrict__ f, T *box) {
     using K = Canon<S>;
     const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int B2 = tg.B[1], B3 = tg.B[2];
-    const int nrows = tg.B[0] * B2;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const int B1 = tg.B[0], B2 = tg.B[1], B3 = tg.B[2];
     const int gc0 = wrap_idx(o3 + lane, g.n3), gc1 = wrap_idx(o3 + lane + 64, g.n3);
     const bool h1 = lane + 64 < B3;
-    for (int r0 = wave; r0 < nrows; r0 += kStageRows * kWaves) {
+    int r1 = 0, r2 = 0;
+    next_row(r1, r2, wave, B2);
+    while (r1 < B1) {
         T v0[kStageRows], v1[kStageRows];
         int dst[kStageRows];
+        int q1 = r1, q2 = r2;
 #pragma unroll
         for (int u = 0; u < kStageRows; u++) {
-            const int r = r0 + u * kWaves;
             dst[u] = -1;
-            if (r < nrows) {
-                const int r1 = r / B2, r2 = r - r1 * B2;
-                const int g1 = wrap_idx(o1 + r1, g.n1), g2 = wrap_idx(o2 + r2, g.n2);
+            if (q1 < B1) {
+                const int g1 = wrap_idx(o1 + q1, g.n1), g2 = wrap_idx(o2 + q2, g.n2);
                 const T *row = f + (unsigned)((g1 * g.n2 + g2) * g.n3);
                 v0[u] = row[gc0];
                 if (h1) v1[u] = row[gc1];
-                dst[u] = (r1 * K::C2 + r2) * K::C3;
+                dst[u] = (q1 * K::C2 + q2) * K::C3;
             }
+            next_row(q1, q2, kWaves, B2);
         }
 #pragma unroll
         for (int u = 0; u < kStageRows; u++) {
@@ -537,6 +557,8 @@ __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &t
                 if (h1) box[dst[u] + lane + 64] = v1[u];
             }
         }
+        r1 = q1;
+        r2 = q2;
     }
 }
 
@@ -555,7 +577,7 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
                                            const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
                                            T *box) {
     using K = Canon<S>;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = wave_id(), lane = threadIdx.x & 63;
     const unsigned N = (unsigned)g.N();
     const T *__restrict__ D1 = D;
     const T *__restrict__ D2 = D + N;

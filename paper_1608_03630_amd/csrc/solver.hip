@@ -175,7 +175,8 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
     if (!have) {
         std::vector<int> cand = {256, 512, 1024, 2048, 4096, L.total};
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+            hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
             return bfail(b, REG_EHIP, "hipEventCreate failed in the launch tuner");
         TuneEntry best;
         best.ms = 1e30;
