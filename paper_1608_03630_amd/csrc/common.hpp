@@ -166,14 +166,25 @@ template <typename T>
 hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, double a, int leray, double *out,
                       hipStream_t s);
 // Fused Krylov passes (partials: one double per block of a grid-stride loop
-// over the half spectrum, nblocks blocks).
-// s = 0, r = -g, z = M r, p = z; partials of <r, z>
-hipError_t pcg_init(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *z,
-                    double *p, double *part_rz, int nblocks, hipStream_t st);
-// s += a p, r -= a q, z = M r; partials of <r, r> and <r, z>
-hipError_t pcg_update(const SpecCtx &c, double a, const double *p, const double *q, double beta, int leray, double *s,
-                      double *r, double *z, double *part_rr, double *part_rz, int nblocks, hipStream_t st);
-// out = a |k|^4 x + [P] y with partials of <x, out> (dot 1) or <out, out> (dot 2)
+// over the half spectrum, nblocks blocks). The direction p of the next
+// Hessian matvec is also written, rounded to T, into the transform buffer H,
+// so that the matvec starts with its inverse transform; z = M r is never
+// stored.
+// s = 0, r = -g, p = M r (and H = p); partials of <r, M r>
+template <typename T>
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *p,
+                     void *H, double *part_rz, int nblocks, hipStream_t st);
+// with q = a_reg |k|^4 p + [P] y (y: the transformed b~ in H, as in
+// vec_assemble_dot): s += a p, r -= a q; partials of <r, r> and <r, M r>
+template <typename T>
+hipError_t pcg_step(const SpecCtx &c, double a, const double *p, const void *y, double beta, int leray, double *s,
+                    double *r, double *part_rr, double *part_rz, int nblocks, hipStream_t st);
+// p = M r + b p (and H = p)
+template <typename T>
+hipError_t pcg_direction(const SpecCtx &c, const double *r, double b, double beta, int leray, double *p, void *H,
+                         hipStream_t st);
+// out = a |k|^4 x + [P] y with partials of <x, out> (dot 1) or <out, out> (dot 2);
+// out may be null (partials only)
 template <typename T>
 hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, double a, int leray, int dot, double *out,
                             double *part, int nblocks, hipStream_t st);

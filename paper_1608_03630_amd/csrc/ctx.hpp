@@ -509,8 +509,16 @@ reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
     return REG_OK;
 }
 
+// the same from a vector already loaded into the transform buffer
+template <typename T>
+reg_status field_from_buffer(reg_ctx *ctx, void *out) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream))));
+    return REG_OK;
+}
+
 // out^ = beta |k|^4 x^ + [P] FFT(y), y a field-type vector (transformed in
-// T); with dot = 1 (2) also dres[slot] = <x, out> (<out, out>)
+// T); with dot = 1 (2) also dres[slot] = <x, out> (<out, out>); with dot and
+// a null out_hat only the scalar (FFT(y) stays in the transform buffer)
 template <typename T>
 reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat, int dot = 0, int slot = 0) {
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
@@ -527,27 +535,39 @@ reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat
     return REG_OK;
 }
 
-// PCG set-up of a Newton step (s = 0, r = -g, z = M r, p = z) with
-// dres[slot] = <r, z>
-inline reg_status pcg_init(reg_ctx *ctx, int slot) {
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_init(ctx->spec, CV<double>(ctx->ghat), ctx->beta, ctx->P.isochoric,
-                                                     V<double>(ctx->shat), V<double>(ctx->rhat), V<double>(ctx->zhat),
-                                                     V<double>(ctx->phat), ctx->dpart, regk::RED_BLOCKS, ctx->stream)));
+// PCG set-up of a Newton step (s = 0, r = -g, p = M r, the transform buffer
+// loaded with p) with dres[slot] = <r, M r>
+template <typename T>
+reg_status pcg_start(reg_ctx *ctx, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_start<T>(ctx->spec, CV<double>(ctx->ghat), ctx->beta, ctx->P.isochoric,
+                                                         V<double>(ctx->shat), V<double>(ctx->rhat),
+                                                         V<double>(ctx->phat), ctx->H, ctx->dpart, regk::RED_BLOCKS,
+                                                         ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
                                                             ctx->dres + slot, ctx->stream)));
     return REG_OK;
 }
 
-// PCG step (s += a p, r -= a q, z = M r) with dres[slot_rr] = <r, r> and
-// dres[slot_rz] = <r, z>
-inline reg_status pcg_update(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_update(ctx->spec, a, CV<double>(ctx->phat), CV<double>(ctx->qhat),
-                                                       ctx->beta, ctx->P.isochoric, V<double>(ctx->shat),
-                                                       V<double>(ctx->rhat), V<double>(ctx->zhat), ctx->dpart,
-                                                       ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
+// PCG step after a matvec of p whose transformed b~ is still in the
+// transform buffer (s += a p, r -= a q) with dres[slot_rr] = <r, r> and
+// dres[slot_rz] = <r, M r>
+template <typename T>
+reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_step<T>(ctx->spec, a, CV<double>(ctx->phat), ctx->H, ctx->beta,
+                                                        ctx->P.isochoric, V<double>(ctx->shat), V<double>(ctx->rhat),
+                                                        ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
     const double sc = h3(ctx) / (double)ctx->N;
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, sc, ctx->dres + slot_rr, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart2, regk::RED_BLOCKS, sc, ctx->dres + slot_rz, ctx->stream)));
+    return REG_OK;
+}
+
+// next PCG direction p = M r + b p, loaded into the transform buffer
+template <typename T>
+reg_status pcg_direction(reg_ctx *ctx, double b) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_direction<T>(ctx->spec, CV<double>(ctx->rhat), b, ctx->beta,
+                                                             ctx->P.isochoric, V<double>(ctx->phat), ctx->H,
+                                                             ctx->stream)));
     return REG_OK;
 }
 

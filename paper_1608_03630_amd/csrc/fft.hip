@@ -853,11 +853,13 @@ __device__ __forceinline__ void precond3(const ModeInfo &mi, double beta, int le
     if (leray) leray3(mi, z);
 }
 
-// PCG set-up of a Newton step: s = 0, r = -g, z = M r, p = z; partials of <r, z>
-__global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const double2 *__restrict__ gv, double beta, int leray,
-                                                       double2 *__restrict__ s, double2 *__restrict__ r,
-                                                       double2 *__restrict__ z, double2 *__restrict__ p,
-                                                       double *__restrict__ part_rz) {
+// PCG set-up of a Newton step: s = 0, r = -g, p = M r (also into H);
+// partials of <r, M r>
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *__restrict__ gv, double beta, int leray,
+                                                        double2 *__restrict__ s, double2 *__restrict__ r,
+                                                        double2 *__restrict__ p, cplx_t<T> *__restrict__ H,
+                                                        double *__restrict__ part_rz) {
     const long Nh = g.Nh();
     double rz = 0.0, dummy = 0.0;
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
@@ -872,8 +874,11 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const double2 *__
         for (int c = 0; c < 3; c++) {
             s[c * Nh + q] = make_double2(0.0, 0.0);
             r[c * Nh + q] = rv[c];
-            z[c * Nh + q] = zv[c];
             p[c * Nh + q] = zv[c];
+            cplx_t<T> h;
+            h.x = T(zv[c].x);
+            h.y = T(zv[c].y);
+            H[c * Nh + q] = h;
             acc += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
         }
         rz += mi.w * acc;
@@ -881,32 +886,41 @@ __global__ __launch_bounds__(kThreads) void k_pcg_init(Grid g, const double2 *__
     block_sum2(rz, dummy, part_rz, nullptr);
 }
 
-// PCG step: s += a p, r -= a q, z = M r; partials of <r, r> and <r, z>
-__global__ __launch_bounds__(kThreads) void k_pcg_update(Grid g, double a, const double2 *__restrict__ p,
-                                                         const double2 *__restrict__ qv, double beta, int leray,
-                                                         double2 *__restrict__ s, double2 *__restrict__ r,
-                                                         double2 *__restrict__ z, double *__restrict__ part_rr,
-                                                         double *__restrict__ part_rz) {
+// PCG step: q = beta |k|^4 p + [P] y recomputed from the matvec's
+// transformed b~ (bit for bit the q of its curvature), s += a p, r -= a q;
+// partials of <r, r> and <r, M r>
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const double2 *__restrict__ p,
+                                                       const cplx_t<T> *__restrict__ y, double beta, int leray,
+                                                       double2 *__restrict__ s, double2 *__restrict__ r,
+                                                       double *__restrict__ part_rr, double *__restrict__ part_rz) {
     const long Nh = g.Nh();
     double rr = 0.0, rz = 0.0;
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
         const ModeInfo mi = mode_info(g, q);
-        double2 rv[3], zv[3];
+        double2 qv[3], rv[3], zv[3];
         for (int c = 0; c < 3; c++) {
-            const double2 pc = p[c * Nh + q], qc = qv[c * Nh + q];
+            const cplx_t<T> yc = y[c * Nh + q];
+            qv[c] = make_double2((double)yc.x, (double)yc.y);
+        }
+        if (leray) leray3(mi, qv);
+        const double f = beta * mi.kk * mi.kk;
+        for (int c = 0; c < 3; c++) {
+            const double2 pc = p[c * Nh + q];
+            qv[c].x = f * pc.x + qv[c].x;
+            qv[c].y = f * pc.y + qv[c].y;
             double2 sc = s[c * Nh + q], rc = r[c * Nh + q];
             sc.x += a * pc.x;
             sc.y += a * pc.y;
-            rc.x -= a * qc.x;
-            rc.y -= a * qc.y;
+            rc.x -= a * qv[c].x;
+            rc.y -= a * qv[c].y;
             s[c * Nh + q] = sc;
+            r[c * Nh + q] = rc;
             rv[c] = rc;
         }
         precond3(mi, beta, leray, rv, zv);
         double arr = 0.0, arz = 0.0;
         for (int c = 0; c < 3; c++) {
-            r[c * Nh + q] = rv[c];
-            z[c * Nh + q] = zv[c];
             arr += rv[c].x * rv[c].x + rv[c].y * rv[c].y;
             arz += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
         }
@@ -914,6 +928,31 @@ __global__ __launch_bounds__(kThreads) void k_pcg_update(Grid g, double a, const
         rz += mi.w * arz;
     }
     block_sum2(rr, rz, part_rr, part_rz);
+}
+
+// next direction p = M r + b p, also into H
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const double2 *__restrict__ r, double b,
+                                                            double beta, int leray, double2 *__restrict__ p,
+                                                            cplx_t<T> *__restrict__ H) {
+    const long Nh = g.Nh();
+    const long q = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= Nh) return;
+    const ModeInfo mi = mode_info(g, q);
+    double2 rv[3], zv[3];
+    for (int c = 0; c < 3; c++) rv[c] = r[c * Nh + q];
+    precond3(mi, beta, leray, rv, zv);
+    for (int c = 0; c < 3; c++) {
+        const double2 pc = p[c * Nh + q];
+        double2 o;
+        o.x = zv[c].x + b * pc.x;
+        o.y = zv[c].y + b * pc.y;
+        p[c * Nh + q] = o;
+        cplx_t<T> h;
+        h.x = T(o.x);
+        h.y = T(o.y);
+        H[c * Nh + q] = h;
+    }
 }
 
 // out = a |k|^4 x + [P] y (y complex T) with partials of <x, out> (dot 1) or
@@ -939,7 +978,7 @@ __global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const dou
             const double2 xc = x[c * Nh + q];
             v[c].x = f * xc.x + v[c].x;
             v[c].y = f * xc.y + v[c].y;
-            out[c * Nh + q] = v[c];
+            if (out) out[c * Nh + q] = v[c];
             loc += dot == 1 ? xc.x * v[c].x + xc.y * v[c].y : v[c].x * v[c].x + v[c].y * v[c].y;
         }
         acc += mi.w * loc;
@@ -1017,20 +1056,32 @@ hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const d
     return hipGetLastError();
 }
 
-hipError_t pcg_init(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *z,
-                    double *p, double *part_rz, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_init, dim3(nblocks), dim3(kThreads), 0, st, c.g, reinterpret_cast<const double2 *>(g),
-                       beta, leray, reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r),
-                       reinterpret_cast<double2 *>(z), reinterpret_cast<double2 *>(p), part_rz);
+template <typename T>
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *p,
+                     void *H, double *part_rz, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_start<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g,
+                       reinterpret_cast<const double2 *>(g), beta, leray, reinterpret_cast<double2 *>(s),
+                       reinterpret_cast<double2 *>(r), reinterpret_cast<double2 *>(p),
+                       reinterpret_cast<cplx_t<T> *>(H), part_rz);
     return hipGetLastError();
 }
 
-hipError_t pcg_update(const SpecCtx &c, double a, const double *p, const double *q, double beta, int leray, double *s,
-                      double *r, double *z, double *part_rr, double *part_rz, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_update, dim3(nblocks), dim3(kThreads), 0, st, c.g, a,
-                       reinterpret_cast<const double2 *>(p), reinterpret_cast<const double2 *>(q), beta, leray,
-                       reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r), reinterpret_cast<double2 *>(z),
-                       part_rr, part_rz);
+template <typename T>
+hipError_t pcg_step(const SpecCtx &c, double a, const double *p, const void *y, double beta, int leray, double *s,
+                    double *r, double *part_rr, double *part_rz, int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_step<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g, a,
+                       reinterpret_cast<const double2 *>(p), reinterpret_cast<const cplx_t<T> *>(y), beta, leray,
+                       reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r), part_rr, part_rz);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_direction(const SpecCtx &c, const double *r, double b, double beta, int leray, double *p, void *H,
+                         hipStream_t st) {
+    const unsigned nb = (unsigned)((c.g.Nh() + kThreads - 1) / kThreads);
+    hipLaunchKernelGGL(k_pcg_direction<T>, dim3(nb), dim3(kThreads), 0, st, c.g,
+                       reinterpret_cast<const double2 *>(r), b, beta, leray, reinterpret_cast<double2 *>(p),
+                       reinterpret_cast<cplx_t<T> *>(H));
     return hipGetLastError();
 }
 
@@ -1055,6 +1106,12 @@ hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, do
     template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
     template hipError_t vec_assemble_dot<T>(const SpecCtx &, const double *, const void *, double, int, int,        \
                                             double *, double *, int, hipStream_t);                                  \
+    template hipError_t pcg_start<T>(const SpecCtx &, const double *, double, int, double *, double *, double *,   \
+                                     void *, double *, int, hipStream_t);                                           \
+    template hipError_t pcg_step<T>(const SpecCtx &, double, const double *, const void *, double, int, double *,  \
+                                    double *, double *, double *, int, hipStream_t);                                \
+    template hipError_t pcg_direction<T>(const SpecCtx &, const double *, double, double, int, double *, void *,   \
+                                         hipStream_t);                                                              \
     template hipError_t vec_symbol<T>(const SpecCtx &, int, const double *, const void *, double, int, double *,  \
                                       hipStream_t);
 

@@ -518,8 +518,14 @@ __global__ __launch_bounds__(kTileThreads) void k_tiled(Grid g, TileGeom tg, con
 // to k_tiled through the same grid via the `interior` test below).
 constexpr int kCanonMaxSpan = 4;  // largest canonical box: (12+S)^2 (67+S) floats <= 64 KB
 
+// Row pitch C3: a multiple of 32 floats where the box still fits 64 KB. LDS
+// has 32 four-byte banks; lanes of a half-wavefront read consecutive x3
+// positions, and where the floor of D1 or D2 changes between them, some read
+// the next row. With a pitch of 0 mod 32 those lanes keep distinct banks; with
+// kTile3 + 3 + S (4 + S mod 32) they collide with the lanes of the first row.
 template <int S> struct Canon {
-    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S, C3 = kTile3 + 3 + S;
+    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S;
+    static constexpr int C3 = (S <= 2) ? (kTile3 + 3 + S + 31) / 32 * 32 : kTile3 + 3 + S;
     static constexpr int elems = C1 * C2 * C3;
 };
 

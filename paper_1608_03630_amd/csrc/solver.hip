@@ -39,6 +39,7 @@ struct Request {
     const void *aux = nullptr;  // rho0 (FORWARD)
     bool reuse = false;         // GRADIENT: histB and Dt already hold the plan and state of x
     bool dot = false;           // MATVEC: <vt, Hvt> into result slot 0
+    bool pre = false;           // MATVEC: vt is already in the transform buffer (rounded to the field type)
 };
 
 struct Item {
@@ -386,7 +387,8 @@ struct Exec {
                 const double dt = 1.0 / ctx->P.nt;
                 P.ops.push_back([ctx, r, N, dt]() -> reg_status {
                     (void)N;
-                    STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
+                    if (r.pre) STCHK(field_from_buffer<T>(ctx, ctx->vtf));
+                    else STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho),
                                                                                     V<T>(ctx->lam[1]), -0.5 * dt, ctx->stream)));
                     return REG_OK;
@@ -536,6 +538,7 @@ struct Exec {
             key.push_back((int64_t)(intptr_t)it.req.x);
             key.push_back((int64_t)(intptr_t)it.req.y);
             key.push_back(it.req.dot);
+            key.push_back(it.req.pre);
             int64_t bb;
             std::memcpy(&bb, &it.ctx->beta, sizeof(bb));
             key.push_back(bb);
@@ -759,7 +762,7 @@ struct Solver {
                 eta = P.forcing == 1 ? std::sqrt(ratio) : ratio;
                 if (eta > 0.5) eta = 0.5;
                 // truncated PCG on H s = -g from s = 0
-                STCHK(pcg_init(ctx, 0));
+                STCHK(pcg_start<T>(ctx, 0));
                 queue_fetch(1);
                 st = S_PCG_START;
                 return REG_OK;
@@ -768,7 +771,8 @@ struct Solver {
                 rz = ctx->hres[0];
                 i = 0;
                 iters = 0;
-                req = Request{Op::MATVEC, ctx->phat, ctx->qhat, nullptr, false, true};
+                // p is in the transform buffer; only the curvature <p, H p> comes back
+                req = Request{Op::MATVEC, ctx->phat, nullptr, nullptr, false, true, true};
                 st = S_MATVEC_DONE;
                 return REG_OK;
             case S_MATVEC_DONE: {
@@ -780,7 +784,8 @@ struct Solver {
                     break;
                 }
                 if (kappa <= 0) {  // negative curvature: stop (steepest descent at the first iteration)
-                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->zhat), V<double>(ctx->shat), ctx->stream)));
+                    // (p = M r at the first iteration)
+                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->phat), V<double>(ctx->shat), ctx->stream)));
                     st = S_ARMIJO;
                     break;
                 }
@@ -789,7 +794,7 @@ struct Solver {
                 // both inner products, so that one synchronisation serves the
                 // forcing test and the next direction (z unused when the test
                 // ends the iteration)
-                STCHK(pcg_update(ctx, a, 0, 4));
+                STCHK(pcg_step<T>(ctx, a, 0, 4));
                 queue_fetch(5);
                 st = S_RR_DONE;
                 return REG_OK;
@@ -800,15 +805,14 @@ struct Solver {
                     st = S_ARMIJO;
                     break;
                 }
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(NV, CV<double>(ctx->zhat), rz1 / rz, CV<double>(ctx->phat),
-                                                                            V<double>(ctx->phat), ctx->stream)));
-                rz = rz1;
                 i++;
                 if (i >= P.max_pcg) {
                     st = S_ARMIJO;
                     break;
                 }
-                req = Request{Op::MATVEC, ctx->phat, ctx->qhat, nullptr, false, true};
+                STCHK(pcg_direction<T>(ctx, rz1 / rz));
+                rz = rz1;
+                req = Request{Op::MATVEC, ctx->phat, nullptr, nullptr, false, true, true};
                 st = S_MATVEC_DONE;
                 return REG_OK;
             }
