@@ -39,6 +39,19 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Workgroups are dispatched round-robin over the 8 XCDs (one L2 each). The
+// strided line transforms below read and write 64-byte pieces of 128-byte
+// lines, the other half belonging to the neighbouring block along x3; this
+// index keeps neighbouring blocks on one XCD (XCD x takes the x-th
+// contiguous share of gridDim.x), so the line is fetched into one L2 once.
+__device__ __forceinline__ int xcd_local_block() {
+    const unsigned b = blockIdx.x, nb = gridDim.x;
+    const unsigned q = nb / 8, r = nb % 8;
+    const unsigned x = b % 8, t = b / 8;
+    const unsigned base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    return (int)(base + t);
+}
+
 // row pitch of a tile of L lines in LDS; padded tiles (transposed loads) add
 // one element per row against bank conflicts
 __host__ __device__ inline int tile_pitch(int L, bool padded) { return (padded && L > 1) ? L + 1 : L; }
@@ -205,7 +218,8 @@ __global__ __launch_bounds__(kThreads) void k_deriv_strided(Grid g, FftPlan pl, 
     C *twl = B + n * L;
     const int ncol = g.n3 / 2;
     const int nb3 = (ncol + L - 1) >> lgL;
-    const int outer = blockIdx.x / nb3, cb = blockIdx.x - (blockIdx.x / nb3) * nb3;
+    const int blk = xcd_local_block();
+    const int outer = blk / nb3, cb = blk - outer * nb3;
     const int leff = min(L, ncol - cb * L);
     long base, stride;
     if (axis == 1) {
@@ -360,7 +374,8 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
     C *twl = B + n * L;
     const int nh = g.n3h();
     const int nb3 = (nh + L - 1) >> lgL;
-    const int outer = blockIdx.x / nb3, cb = blockIdx.x - (blockIdx.x / nb3) * nb3;
+    const int blk = xcd_local_block();
+    const int outer = blk / nb3, cb = blk - outer * nb3;
     const int leff = min(L, nh - cb * L);
     long base, stride;
     if (axis == 1) {
