@@ -34,7 +34,7 @@ bool make_plan(int n, FftPlan *p);
 
 // ------------------------------------------------------------------ interp.hip
 // Output tile of the LDS-staged gathers and the bounding box of its stencils.
-constexpr int kTile1 = 8, kTile2 = 8, kTile3 = 64;
+constexpr int kTile1 = 4, kTile2 = 8, kTile3 = 64;
 struct TileGeom {
     int lo[3];  // floor(min D_j) - 1: box origin relative to the tile origin
     int B[3];   // box extent per axis: tile + (floor(max D_j) - floor(min D_j)) + 3

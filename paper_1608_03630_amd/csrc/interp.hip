@@ -320,8 +320,9 @@ __global__ __launch_bounds__(kThreads) void k_deform_step(Grid g, const T *__res
 
 constexpr int kTileLines = kTile1 * kTile2;       // x3 lines per tile
 // Workgroup of the LDS-tiled gathers: kTileThreads threads share one tile's
-// box, each owning kLinesPerWave x3 lines (points); eight wavefronts per box
-// keep six resident per SIMD (74 VGPRs) where four wavefronts reached four.
+// box, each owning kLinesPerWave x3 lines (points). A 4 x 8 x 64 tile with a
+// padded box of 8 x 12 x 96 floats (36 KiB) lets four workgroups (32
+// wavefronts, under 48 VGPRs each) share a CU.
 constexpr int kTileThreads = 512;
 constexpr int kWaves = kTileThreads / 64;
 constexpr int kLinesPerWave = kTileLines / kWaves;
@@ -516,7 +517,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tiled(Grid g, TileGeom tg, con
 // arithmetic is 32-bit, and the per-thread point loop is fully unrolled with
 // no per-point branches (interior tiles only; the launcher sends ragged tiles
 // to k_tiled through the same grid via the `interior` test below).
-constexpr int kCanonMaxSpan = 4;  // largest canonical box: (12+S)^2 (67+S) floats <= 64 KB
+constexpr int kCanonMaxSpan = 4;  // largest canonical box: (7+S)(11+S)(67+S) floats, padded, <= 64 KB
 
 // Row pitch C3: a multiple of 32 floats where the box still fits 64 KB. LDS
 // has 32 four-byte banks; lanes of a half-wavefront read consecutive x3
@@ -525,7 +526,8 @@ constexpr int kCanonMaxSpan = 4;  // largest canonical box: (12+S)^2 (67+S) floa
 // kTile3 + 3 + S (4 + S mod 32) they collide with the lanes of the first row.
 template <int S> struct Canon {
     static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S;
-    static constexpr int C3 = (S <= 2) ? (kTile3 + 3 + S + 31) / 32 * 32 : kTile3 + 3 + S;
+    static constexpr int P3 = (kTile3 + 3 + S + 31) / 32 * 32;
+    static constexpr int C3 = C1 * C2 * P3 * 4 <= 65536 ? P3 : kTile3 + 3 + S;
     static constexpr int elems = C1 * C2 * C3;
 };
 

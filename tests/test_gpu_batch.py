@@ -83,8 +83,10 @@ def test_batch_transport_matches_single_and_oracle(reg, cases, prec, scale):
     torch.cuda.synchronize()
     st = b.reg_batch_stats()
     say(f"  stats {st}, interp launch (blocks, chunked, variant, ms) {b.reg_batch_launch_info(0)}")
-    # double-precision boxes of 64-wide tiles exceed the LDS: direct gathers
-    assert (st["batched_launches"] > 0) == (prec == 0)
+    # single precision always goes through the batched persistent launch;
+    # double precision does where its boxes fit the LDS
+    if prec == 0:
+        assert st["batched_launches"] > 0
     singles = _singles(reg, cases, prec=prec)
     for i, (ctx, c) in enumerate(zip(singles, cases)):
         rs = ctx.reg_transport_forward(to_vel(scale * c["v"], ctx), to_dev(c["rhoT"], ctx))
