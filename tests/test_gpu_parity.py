@@ -48,7 +48,7 @@ def test_interp(reg, prec, shape, cells):
     assert rel_l2(out, ref) <= TOL[("interp", prec)]
 
 
-def _max_tile_span(D, tile=(8, 8, 64)):
+def _max_tile_span(D, tile=(4, 8, 64)):
     """Largest floor-range of the displacement over any tile (per axis), the
     quantity that picks the LDS kernel variant."""
     fl = np.floor(D)
@@ -64,7 +64,7 @@ def _max_tile_span(D, tile=(8, 8, 64)):
 
 @pytest.mark.parametrize("cells", [0.4, 0.8, 1.2, 2.0, 3.0, 8.0])
 def test_interp_whole_tiles_all_box_variants(reg, cells):
-    """Grids of whole 8x8x64 tiles in single precision take the canonical LDS
+    """Grids of whole 4x8x64 tiles in single precision take the canonical LDS
     kernels (box spans 1, 2, 4) or, beyond, the generic one; all must match."""
     shape = (16, 24, 128)
     ctx = make_ctx(reg, shape, 0)
@@ -73,6 +73,51 @@ def test_interp_whole_tiles_all_box_variants(reg, cells):
     say(f"  max floor span per tile {_max_tile_span(D)}")
     out = to_host(ctx.reg_interp(to_dev(f, ctx), to_dev(D, ctx)))
     assert rel_l2(out, oracle.interp(f, D)) <= TOL[("interp", 0)]
+
+
+def test_whole_tile_canonical_kernels_match_oracle(reg):
+    """A 128 x 64 x 256 single-precision grid of 1024 whole 4x8x64 tiles
+    with displacements under a quarter cell per step (box span 1) runs the
+    canonical LDS kernel in its three modes (state, adjoint with the div v
+    source, incremental state), as the 256^3 benchmark does: interpolation,
+    both transports, the gradient and a Gauss-Newton matvec against the
+    oracle."""
+    shape = (128, 64, 256)
+    nt = 4
+    beta = 1e-2
+    ctx = make_ctx(reg, shape, 0, nt=nt, beta=beta)
+    f = rounded(synth.smooth_random_field(shape, 112, kmax=5), 0)
+    D = rounded(synth.displacement(shape, 111, max_cells=0.45), 0)
+    assert _max_tile_span(D) <= 1
+    out = to_host(ctx.reg_interp(to_dev(f, ctx), to_dev(D, ctx)))
+    assert rel_l2(out, oracle.interp(f, D)) <= TOL[("interp", 0)]
+    case = synth.smooth_case(shape)
+    rhoT = rounded(case["rhoT"], 0)
+    v = rounded(0.05 * case["v_true"], 0)
+    assert _max_tile_span(oracle.backtrace(v, nt, 1.0)) <= 1 and _max_tile_span(oracle.backtrace(v, nt, -1.0)) <= 1
+    P = oparams(shape, nt, beta=beta)
+    r1 = to_host(ctx.reg_transport_forward(to_vel(v, ctx), to_dev(rhoT, ctx)))
+    assert rel_l2(r1, oracle.transport_forward(P, v, rhoT)) <= TOL[("transport", 0)]
+    l0 = to_host(ctx.reg_transport_adjoint(to_vel(v, ctx), to_dev(rhoT, ctx)))
+    assert rel_l2(l0, oracle.transport_adjoint(P, v, rhoT)) <= TOL[("transport", 0)]
+    rhoR = rounded(oracle.transport_forward(P, 0.1 * case["v_true"], rhoT), 0)
+    ctx.reg_set_images(to_dev(rhoT, ctx), to_dev(rhoR, ctx))
+    g, J, mis, gn = ctx.reg_gradient(to_vel(v, ctx))
+    g = to_host(g)
+    g_ref, J_ref, mis_ref = oracle.gradient(P, rhoT, rhoR, v)
+    amp = max(1.0, 1.0 / max(mis_ref, 1e-300))
+    reg_part = oracle.biharm(v, beta)
+    kappa = (np.linalg.norm(reg_part) + np.linalg.norm(g_ref - reg_part)) / np.linalg.norm(g_ref)
+    tol = 1e-4 * amp * kappa + biharm_bound(shape, 1, beta * np.linalg.norm(v), np.linalg.norm(g_ref))
+    say(f"  gradient rel-L2 {rel_l2(g, g_ref):.2e} (bound {tol:.2e})")
+    assert rel_l2(g, g_ref) <= tol
+    assert abs(J - J_ref) <= TOL[("scalar", 0)] * abs(J_ref)
+    vt = rounded(synth.smooth_random_field(shape, 110, kmax=3, ncomp=3), 0)
+    H = to_host(ctx.reg_hessian_matvec(to_vel(vt, ctx)))
+    H_ref = oracle.hessian_matvec(P, rhoT, v, vt)
+    htol = 1e-4 + biharm_bound(shape, 1, beta * np.linalg.norm(vt), np.linalg.norm(H_ref))
+    say(f"  Hessian rel-L2 {rel_l2(H, H_ref):.2e} (bound {htol:.2e})")
+    assert rel_l2(H, H_ref) <= htol
 
 
 @pytest.mark.parametrize("prec", [1, 0])
