@@ -275,9 +275,9 @@ reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, i
 
 /* Workgroups, dealing, kernel variant and tuned time (ms, 0 if fixed) of the
  * last batched launch of a step kind: mode 0 interpolation/state, 1 adjoint,
- * 2 incremental state. Variant 1, 2, 4: canonical LDS box of that floor span
- * for every problem; 0: generic box for every problem; 8: canonical for the
- * problems that fit it, generic for the others. */
+ * 2 incremental state. A step takes one batched launch per LDS box class of
+ * its problems: variant 1, 2, 4 for the canonical box of that floor span, 0
+ * for the generic box. */
 reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
                                  double *ms);
 

@@ -58,23 +58,20 @@ struct PairStep {
     double cs;
     int last;
     int tile0;
-    int canon;  // the pair's gathers take the canonical kernel (mixed launches)
+    int canon;  // the pair's gathers can take the canonical kernels
 };
 enum { STEP_INTERP = 0, STEP_ADJOINT = 1, STEP_INCSTATE = 2 };
 // Grids whose gathers the canonical-stride LDS kernels take (single
-// precision, whole 8x8x64 tiles, floor span of the box <= 4); any grid with a
+// precision, whole 4x8x64 tiles, floor span of the box <= 4); any grid with a
 // tile geometry can go through the generic kernels.
 bool canonical(const Grid &g, const TileGeom &tg, size_t esz);
 int batch_span(const TileGeom &tg);
 int tiles_of(const Grid &g);
-size_t canon_box_bytes();  // LDS of the largest canonical box
 // One persistent launch of nblocks workgroups (>= 8) over all pairs' tiles
 // (pairs_dev sorted by tile0, total = sum of the pairs' tiles). variant 0:
 // generic tile kernel with `lds` bytes of dynamic LDS (the largest box of the
 // pairs); variant 1, 2, 4: canonical box of that span (float only, every pair
-// canonical with span <= variant); variant 8: pairs with `canon` set take the
-// span-4 canonical body, the others the generic one (float only, lds covers
-// both).
+// canonical with span <= variant).
 template <typename T>
 hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep *pairs_dev, int npairs, int total,
                                int nblocks, int chunked, hipStream_t s);

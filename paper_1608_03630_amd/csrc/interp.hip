@@ -679,14 +679,26 @@ __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, i
         first = x * chunk;
         end = min(total, first + chunk);
     }
-    for (int item = first + start; item < end; item += stride) {
-        int lo = 0, hi = npairs - 1;  // last pair with tile0 <= item
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (pairs[mid].tile0 <= item) lo = mid;
-            else hi = mid - 1;
+    // A workgroup's items increase, so the pair that holds them (the last
+    // with tile0 <= item) only moves forward: one binary search for the first
+    // item, then a linear advance, and the pair record is read again only
+    // when the pair changes.
+    int item = first + start;
+    if (item >= end) return;
+    int lo = 0, hi = npairs - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pairs[mid].tile0 <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    PairStep ps = pairs[lo];
+    int next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 : total;
+    for (; item < end; item += stride) {
+        if (item >= next0) {
+            while (lo + 1 < npairs && pairs[lo + 1].tile0 <= item) lo++;
+            ps = pairs[lo];
+            next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 : total;
         }
-        const PairStep &ps = pairs[lo];
         const Grid g = ps.g;
         const int b = item - ps.tile0;
         const int nt3 = (g.n3 + kTile3 - 1) / kTile3, nt2 = (g.n2 + kTile2 - 1) / kTile2;
@@ -701,7 +713,7 @@ __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, i
         a.out = ps.out;
         a.cs = ps.cs;
         a.last = ps.last;
-        work(g, ps.tg, t, ps.f, ps.D, a, ps.canon);
+        work(g, ps.tg, t, ps.f, ps.D, a);
         __syncthreads();  // the next item restages the box
     }
 }
@@ -712,26 +724,21 @@ __global__ __launch_bounds__(kTileThreads) void k_batched_canon(const PairStep *
     __shared__ T box[Canon<S>::elems];
     walk_items(pairs, npairs, total, chunked,
                [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
-                   const TileArgs &a, int) {
+                   const TileArgs &a) {
                    canon_tile<T, MODE, S>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
                });
 }
 
-// MIXED: pairs marked canonical take the canonical span-4 body, the others
-// the generic one, in one launch (dynamic LDS sized for both).
-template <typename T, int MODE, bool MIXED>
+// The generic body for every pair (dynamic LDS sized for the largest box).
+template <typename T, int MODE>
 __global__ __launch_bounds__(kTileThreads) void k_batched_generic(const PairStep *__restrict__ pairs, int npairs,
                                                               int total, int chunked) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *box = reinterpret_cast<T *>(smem_raw);
     walk_items(pairs, npairs, total, chunked,
                [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
-                   const TileArgs &a, int canon) {
-                   if (MIXED && canon)
-                       canon_tile<T, MODE, kCanonMaxSpan>(g, tg, t, static_cast<const T *>(f),
-                                                          static_cast<const T *>(D), a, box);
-                   else
-                       generic_tile<T, MODE>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
+                   const TileArgs &a) {
+                   generic_tile<T, MODE>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
                });
 }
 
@@ -826,8 +833,6 @@ bool canonical(const Grid &g, const TileGeom &tg, size_t esz) {
 
 int batch_span(const TileGeom &tg) { return box_span(tg); }
 
-size_t canon_box_bytes() { return sizeof(float) * Canon<kCanonMaxSpan>::elems; }
-
 int tiles_of(const Grid &g) { return (int)ntiles(g); }
 
 template <typename T>
@@ -836,19 +841,14 @@ hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep
     // chunked dealing needs a workgroup on every XCD
     if (npairs < 1 || total < 1 || nblocks_grid < kXcds) return hipErrorInvalidValue;
     const bool canon_variant = variant == 1 || variant == 2 || variant == kCanonMaxSpan;
-    if (!canon_variant && variant != 0 && variant != 8) return hipErrorInvalidValue;
-    if ((variant == 0 || variant == 8) && (lds == 0 || lds > 65536)) return hipErrorInvalidValue;
-    if (variant == 8 && lds < sizeof(T) * Canon<kCanonMaxSpan>::elems) return hipErrorInvalidValue;
+    if (!canon_variant && variant != 0) return hipErrorInvalidValue;
+    if (variant == 0 && (lds == 0 || lds > 65536)) return hipErrorInvalidValue;
     if (variant != 0 && sizeof(T) != 4) return hipErrorInvalidValue;
     const dim3 grid(nblocks_grid), block(kTileThreads);
 #define REGK_BATCH(M)                                                                                               \
     do {                                                                                                            \
         if (variant == 0)                                                                                           \
-            hipLaunchKernelGGL((k_batched_generic<T, M, false>), grid, block, lds, s, pairs_dev, npairs, total,     \
-                               chunked);                                                                            \
-        else if (variant == 8)                                                                                      \
-            hipLaunchKernelGGL((k_batched_generic<float, M, true>), grid, block, lds, s, pairs_dev, npairs, total,  \
-                               chunked);                                                                            \
+            hipLaunchKernelGGL((k_batched_generic<T, M>), grid, block, lds, s, pairs_dev, npairs, total, chunked); \
         else if (variant == 1)                                                                                      \
             hipLaunchKernelGGL((k_batched_canon<float, M, 1>), grid, block, 0, s, pairs_dev, npairs, total, chunked); \
         else if (variant == 2)                                                                                      \

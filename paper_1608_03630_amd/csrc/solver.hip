@@ -11,9 +11,10 @@
 // rounds: each active problem has queued light work (vector updates,
 // preconditioner, inner products) and at most one heavy request; the round
 // issues all heavy requests -- in a batch every semi-Lagrangian time step of
-// all problems goes out as ONE persistent launch over a (problem, tile) work
-// list -- then synchronises the stream once, and every problem reads its
-// double-precision scalars and advances to its next request. In a batch the
+// all problems goes out as one persistent launch per LDS box class over a
+// (problem, tile) work list -- then synchronises the stream once, and every
+// problem reads its double-precision scalars and advances to its next
+// request. In a batch the
 // Hessian matvecs of a round are replayed from a captured HIP graph when the
 // same set of problems repeats them. Per problem, the kernels and their
 // arguments are those of the single-problem path, so a problem's result does
@@ -245,10 +246,14 @@ struct Exec {
     // for the problems the canonical tile kernel takes, the single-problem
     // launchers for the rest
     void sl_step(Program &P, int mode, const std::vector<StepArg<T>> &args, const regk::PairStep *dev_region) {
-        std::vector<regk::PairStep> items;
-        int total = 0, span = 0;
-        bool all_canon = true, any_canon = false;
-        size_t lds = 0;
+        // Problems are grouped by LDS box class: canonical boxes of floor span
+        // 1, 2 or 4 (classes 0..2) and the generic box (class 3). Each class
+        // takes one batched launch over its (problem, tile) work list, so that
+        // a problem with small steps keeps the small box (and four workgroups
+        // per CU) whatever the other problems need.
+        std::vector<regk::PairStep> items[4];
+        int total[4] = {0, 0, 0, 0};
+        size_t lds[4] = {0, 0, 0, 0};
         for (const auto &a : args) {
             const regk::TileGeom *tg = geom_of(a.ctx, a.D);
             if (b && tg) {
@@ -263,14 +268,13 @@ struct Exec {
                 ps.out = a.out;
                 ps.cs = a.cs;
                 ps.last = a.last;
-                ps.tile0 = total;
                 ps.canon = regk::canonical(a.ctx->g, *tg, sizeof(T));
-                total += regk::tiles_of(a.ctx->g);
-                span = std::max(span, regk::batch_span(*tg));
-                all_canon = all_canon && ps.canon;
-                any_canon = any_canon || ps.canon;
-                lds = std::max(lds, sizeof(T) * (size_t)tg->B[0] * tg->B[1] * tg->B[2]);
-                items.push_back(ps);
+                const int span = regk::batch_span(*tg);
+                const int cls = !ps.canon ? 3 : span <= 1 ? 0 : span <= 2 ? 1 : 2;
+                ps.tile0 = total[cls];
+                total[cls] += regk::tiles_of(a.ctx->g);
+                lds[cls] = std::max(lds[cls], sizeof(T) * (size_t)tg->B[0] * tg->B[1] * tg->B[2]);
+                items[cls].push_back(ps);
                 continue;
             }
             // no tile geometry (a box beyond the LDS) or a single problem: the
@@ -288,30 +292,22 @@ struct Exec {
                 return REG_OK;
             });
         }
-        if (items.empty()) return;
-        // kernel variant: the canonical box of the largest span when every pair
-        // takes it, else the generic body (with the canonical one per pair when
-        // some pairs take it)
-        Launch L;
-        L.mode = mode;
-        L.n = (int)items.size();
-        L.total = total;
-        if (all_canon) {
-            L.variant = span <= 1 ? 1 : span <= 2 ? 2 : 4;
-            L.lds = 0;
-        } else if (any_canon && sizeof(T) == 4) {
-            L.variant = 8;
-            L.lds = std::max(lds, regk::canon_box_bytes());
-        } else {
-            L.variant = 0;
-            L.lds = lds;
+        static const int kVariant[4] = {1, 2, 4, 0};
+        for (int cls = 0; cls < 4; cls++) {
+            if (items[cls].empty()) continue;
+            Launch L;
+            L.mode = mode;
+            L.n = (int)items[cls].size();
+            L.total = total[cls];
+            L.variant = kVariant[cls];
+            L.lds = cls == 3 ? lds[cls] : 0;
+            const size_t off = P.table.size();
+            P.table.insert(P.table.end(), items[cls].begin(), items[cls].end());
+            L.dev = dev_region + off;
+            P.ops.push_back([this, L, off, &P]() -> reg_status {
+                return batched_launch<T>(b, L, P.table.data() + off, capturing);
+            });
         }
-        const size_t off = P.table.size();
-        P.table.insert(P.table.end(), items.begin(), items.end());
-        L.dev = dev_region + off;
-        P.ops.push_back([this, L, off, &P]() -> reg_status {
-            return batched_launch<T>(b, L, P.table.data() + off, capturing);
-        });
     }
 
     // ---------------------------------------------------------------- plans

@@ -3,8 +3,8 @@ problem's results through the batched persistent launches, the autotuned
 launch shapes and the captured matvec graphs equal, bit for bit, those of the
 single-problem entry points on a context of its own (same kernels, same
 arguments), and the batched transport matches the FP64 oracle like the single
-one. The mix holds grids in whole 8x8x64 tiles (canonical LDS boxes), a
-ragged grid (generic box in the same launch), different nt, both the
+one. The mix holds grids in whole 4x8x64 tiles (canonical LDS boxes), a
+ragged grid (generic box, in a batched launch of its own), different nt, both the
 compressible and the isochoric case, small and multi-cell steps (canonical and
 generic boxes side by side) and both precisions."""
 import numpy as np
