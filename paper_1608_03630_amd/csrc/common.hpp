@@ -163,23 +163,36 @@ template <typename T>
 hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, double a, int leray, double *out,
                       hipStream_t s);
 // Fused Krylov passes (partials: one double per block of a grid-stride loop
-// over the half spectrum, nblocks blocks). The direction p of the next
-// Hessian matvec is also written, rounded to T, into the transform buffer H,
-// so that the matvec starts with its inverse transform; z = M r is never
-// stored.
+// over the half spectrum, nblocks blocks). The PCG vectors s, r, p are stored
+// as complex T ([3][Nh]: double with double fields, float with float
+// fields); updates are computed in double and rounded when stored. The
+// direction p of the next Hessian matvec is also written into the transform
+// buffer H (complex T), so that the matvec starts with its inverse transform;
+// z = M r is never stored.
 // s = 0, r = -g, p = M r (and H = p); partials of <r, M r>
 template <typename T>
-hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *p,
-                     void *H, double *part_rz, int nblocks, hipStream_t st);
-// with q = a_reg |k|^4 p + [P] y (y: the transformed b~ in H, as in
-// vec_assemble_dot): s += a p, r -= a q; partials of <r, r> and <r, M r>
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p, void *H,
+                     double *part_rz, int nblocks, hipStream_t st);
+// with q = beta |k|^4 p + [P] y (y: the transformed b~ in H): s += a p,
+// r -= a q; partials of <r, r> and <r, M r>
 template <typename T>
-hipError_t pcg_step(const SpecCtx &c, double a, const double *p, const void *y, double beta, int leray, double *s,
-                    double *r, double *part_rr, double *part_rz, int nblocks, hipStream_t st);
+hipError_t pcg_step(const SpecCtx &c, double a, const void *p, const void *y, double beta, int leray, void *s, void *r,
+                    double *part_rr, double *part_rz, int nblocks, hipStream_t st);
 // p = M r + b p (and H = p)
 template <typename T>
-hipError_t pcg_direction(const SpecCtx &c, const double *r, double b, double beta, int leray, double *p, void *H,
+hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, void *H,
                          hipStream_t st);
+// partials of <p, beta |k|^4 p + [P] y> for a Krylov vector p
+template <typename T>
+hipError_t krylov_curvature(const SpecCtx &c, const void *p, const void *y, double beta, int leray, double *part,
+                            int nblocks, hipStream_t st);
+// partials of sum w(k3) Re(a conj b), a a velocity vector, b a Krylov vector
+template <typename T>
+hipError_t krylov_dot_partials(const SpecCtx &c, const double *a, const void *b, double *partials, int nblocks,
+                               hipStream_t s);
+// out = x + a y, x and out velocity vectors, y a Krylov vector
+template <typename T>
+hipError_t krylov_axpy(const SpecCtx &c, const double *x, double a, const void *y, double *out, hipStream_t s);
 // out = a |k|^4 x + [P] y with partials of <x, out> (dot 1) or <out, out> (dot 2);
 // out may be null (partials only)
 template <typename T>

@@ -461,17 +461,9 @@ reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
 // matvec direction, in the field type) and the transport result b pass
 // through 3D transforms.
 
-// doubles in a spectral velocity vector
+// doubles in a spectral velocity vector (also the element count of a PCG
+// vector of complex T)
 inline long sv_len(const reg_ctx *c) { return 6 * c->Nh; }
-
-// dres[slot] = <a, b> (Parseval)
-inline reg_status sdot(reg_ctx *ctx, const void *a, const void *b, int slot) {
-    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::vec_dot_partials(ctx->spec, 0, CV<double>(a), CV<double>(b), ctx->dpart,
-                                                             regk::RED_BLOCKS, ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
-                                                            ctx->dres + slot, ctx->stream)));
-    return REG_OK;
-}
 
 // the regulariser 1/2 beta ||lap v||^2 from biharmonic partials in dpart2
 inline reg_status reg_term_to_slot(reg_ctx *ctx, int slot) {
@@ -517,8 +509,7 @@ reg_status field_from_buffer(reg_ctx *ctx, void *out) {
 }
 
 // out^ = beta |k|^4 x^ + [P] FFT(y), y a field-type vector (transformed in
-// T); with dot = 1 (2) also dres[slot] = <x, out> (<out, out>); with dot and
-// a null out_hat only the scalar (FFT(y) stays in the transform buffer)
+// T); with dot = 1 (2) also dres[slot] = <x, out> (<out, out>)
 template <typename T>
 reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat, int dot = 0, int slot = 0) {
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
@@ -535,14 +526,16 @@ reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat
     return REG_OK;
 }
 
+// The PCG vectors shat, rhat, phat hold complex T values during a solve
+// (see regk::pcg_start).
+
 // PCG set-up of a Newton step (s = 0, r = -g, p = M r, the transform buffer
 // loaded with p) with dres[slot] = <r, M r>
 template <typename T>
 reg_status pcg_start(reg_ctx *ctx, int slot) {
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_start<T>(ctx->spec, CV<double>(ctx->ghat), ctx->beta, ctx->P.isochoric,
-                                                         V<double>(ctx->shat), V<double>(ctx->rhat),
-                                                         V<double>(ctx->phat), ctx->H, ctx->dpart, regk::RED_BLOCKS,
-                                                         ctx->stream)));
+                                                         ctx->shat, ctx->rhat, ctx->phat, ctx->H, ctx->dpart,
+                                                         regk::RED_BLOCKS, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
                                                             ctx->dres + slot, ctx->stream)));
     return REG_OK;
@@ -553,9 +546,9 @@ reg_status pcg_start(reg_ctx *ctx, int slot) {
 // dres[slot_rz] = <r, M r>
 template <typename T>
 reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_step<T>(ctx->spec, a, CV<double>(ctx->phat), ctx->H, ctx->beta,
-                                                        ctx->P.isochoric, V<double>(ctx->shat), V<double>(ctx->rhat),
-                                                        ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_step<T>(ctx->spec, a, ctx->phat, ctx->H, ctx->beta, ctx->P.isochoric,
+                                                        ctx->shat, ctx->rhat, ctx->dpart, ctx->dpart2,
+                                                        regk::RED_BLOCKS, ctx->stream)));
     const double sc = h3(ctx) / (double)ctx->N;
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, sc, ctx->dres + slot_rr, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart2, regk::RED_BLOCKS, sc, ctx->dres + slot_rz, ctx->stream)));
@@ -565,9 +558,37 @@ reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
 // next PCG direction p = M r + b p, loaded into the transform buffer
 template <typename T>
 reg_status pcg_direction(reg_ctx *ctx, double b) {
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_direction<T>(ctx->spec, CV<double>(ctx->rhat), b, ctx->beta,
-                                                             ctx->P.isochoric, V<double>(ctx->phat), ctx->H,
-                                                             ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_direction<T>(ctx->spec, ctx->rhat, b, ctx->beta, ctx->P.isochoric,
+                                                             ctx->phat, ctx->H, ctx->stream)));
+    return REG_OK;
+}
+
+// dres[slot] = <a, b> for a velocity vector a and a PCG vector b
+template <typename T>
+reg_status krylov_dot(reg_ctx *ctx, const void *a, const void *b, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::krylov_dot_partials<T>(ctx->spec, CV<double>(a), b, ctx->dpart,
+                                                                   regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
+                                                            ctx->dres + slot, ctx->stream)));
+    return REG_OK;
+}
+
+// out = x + a y for velocity vectors x, out and a PCG vector y
+template <typename T>
+reg_status krylov_axpy(reg_ctx *ctx, const void *x, double a, const void *y, void *out) {
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::krylov_axpy<T>(ctx->spec, CV<double>(x), a, y, V<double>(out), ctx->stream)));
+    return REG_OK;
+}
+
+// dres[slot] = <p, beta |k|^4 p + [P] FFT(y)> for the PCG vector p, y a
+// field-type vector (FFT(y) stays in the transform buffer)
+template <typename T>
+reg_status curvature(reg_ctx *ctx, const void *p, const void *y, int slot) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
+    HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::krylov_curvature<T>(ctx->spec, p, ctx->H, ctx->beta, ctx->P.isochoric,
+                                                                ctx->dpart, regk::RED_BLOCKS, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
+                                                            ctx->dres + slot, ctx->stream)));
     return REG_OK;
 }
 

@@ -761,8 +761,9 @@ __global__ __launch_bounds__(kThreads) void k_vec_symbol(Grid g, int op, const d
 
 // Per-block partial sums of sum_c sum_k w(k3) Re(a_c conj(b_c)) (mode 0) or
 // sum_c sum_k w(k3) |k|^4 |a_c|^2 (mode 1), in a fixed order.
+template <typename B>
 __global__ __launch_bounds__(kThreads) void k_vec_dot(Grid g, int mode, const double2 *__restrict__ a,
-                                                      const double2 *__restrict__ b, double *__restrict__ partials) {
+                                                      const B *__restrict__ b, double *__restrict__ partials) {
     const long Nh = g.Nh();
     const int nh = g.n3h();
     double acc = 0.0;
@@ -772,8 +773,9 @@ __global__ __launch_bounds__(kThreads) void k_vec_dot(Grid g, int mode, const do
         double s = 0.0;
         if (mode == 0) {
             for (int c = 0; c < 3; c++) {
-                const double2 x = a[c * Nh + q], y = b[c * Nh + q];
-                s += x.x * y.x + x.y * y.y;
+                const double2 x = a[c * Nh + q];
+                const B y = b[c * Nh + q];
+                s += x.x * (double)y.x + x.y * (double)y.y;
             }
         } else {
             const long r = q / nh;
@@ -868,12 +870,28 @@ __device__ __forceinline__ void precond3(const ModeInfo &mi, double beta, int le
     if (leray) leray3(mi, z);
 }
 
+// The Krylov vectors s, r, p of the PCG are stored as complex T (double
+// with double fields, float with float fields: the matvec sees p rounded to
+// T in either case); every update is computed in double from the stored
+// values and rounded once when stored.
+template <typename T>
+__device__ __forceinline__ double2 ld2(const cplx_t<T> &z) {
+    return make_double2((double)z.x, (double)z.y);
+}
+template <typename T>
+__device__ __forceinline__ cplx_t<T> st2(double2 z) {
+    cplx_t<T> o;
+    o.x = T(z.x);
+    o.y = T(z.y);
+    return o;
+}
+
 // PCG set-up of a Newton step: s = 0, r = -g, p = M r (also into H);
 // partials of <r, M r>
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *__restrict__ gv, double beta, int leray,
-                                                        double2 *__restrict__ s, double2 *__restrict__ r,
-                                                        double2 *__restrict__ p, cplx_t<T> *__restrict__ H,
+                                                        cplx_t<T> *__restrict__ s, cplx_t<T> *__restrict__ r,
+                                                        cplx_t<T> *__restrict__ p, cplx_t<T> *__restrict__ H,
                                                         double *__restrict__ part_rz) {
     const long Nh = g.Nh();
     double rz = 0.0, dummy = 0.0;
@@ -882,18 +900,16 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *_
         double2 rv[3], zv[3];
         for (int c = 0; c < 3; c++) {
             const double2 x = gv[c * Nh + q];
-            rv[c] = make_double2(-x.x, -x.y);
+            rv[c] = ld2<T>(st2<T>(make_double2(-x.x, -x.y)));
         }
         precond3(mi, beta, leray, rv, zv);
         double acc = 0.0;
         for (int c = 0; c < 3; c++) {
-            s[c * Nh + q] = make_double2(0.0, 0.0);
-            r[c * Nh + q] = rv[c];
-            p[c * Nh + q] = zv[c];
-            cplx_t<T> h;
-            h.x = T(zv[c].x);
-            h.y = T(zv[c].y);
-            H[c * Nh + q] = h;
+            s[c * Nh + q] = st2<T>(make_double2(0.0, 0.0));
+            r[c * Nh + q] = st2<T>(rv[c]);
+            const cplx_t<T> pz = st2<T>(zv[c]);
+            p[c * Nh + q] = pz;
+            H[c * Nh + q] = pz;
             acc += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
         }
         rz += mi.w * acc;
@@ -905,33 +921,31 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *_
 // transformed b~ (bit for bit the q of its curvature), s += a p, r -= a q;
 // partials of <r, r> and <r, M r>
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const double2 *__restrict__ p,
+__global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const cplx_t<T> *__restrict__ p,
                                                        const cplx_t<T> *__restrict__ y, double beta, int leray,
-                                                       double2 *__restrict__ s, double2 *__restrict__ r,
+                                                       cplx_t<T> *__restrict__ s, cplx_t<T> *__restrict__ r,
                                                        double *__restrict__ part_rr, double *__restrict__ part_rz) {
     const long Nh = g.Nh();
     double rr = 0.0, rz = 0.0;
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
         const ModeInfo mi = mode_info(g, q);
         double2 qv[3], rv[3], zv[3];
-        for (int c = 0; c < 3; c++) {
-            const cplx_t<T> yc = y[c * Nh + q];
-            qv[c] = make_double2((double)yc.x, (double)yc.y);
-        }
+        for (int c = 0; c < 3; c++) qv[c] = ld2<T>(y[c * Nh + q]);
         if (leray) leray3(mi, qv);
         const double f = beta * mi.kk * mi.kk;
         for (int c = 0; c < 3; c++) {
-            const double2 pc = p[c * Nh + q];
+            const double2 pc = ld2<T>(p[c * Nh + q]);
             qv[c].x = f * pc.x + qv[c].x;
             qv[c].y = f * pc.y + qv[c].y;
-            double2 sc = s[c * Nh + q], rc = r[c * Nh + q];
+            double2 sc = ld2<T>(s[c * Nh + q]), rc = ld2<T>(r[c * Nh + q]);
             sc.x += a * pc.x;
             sc.y += a * pc.y;
             rc.x -= a * qv[c].x;
             rc.y -= a * qv[c].y;
-            s[c * Nh + q] = sc;
-            r[c * Nh + q] = rc;
-            rv[c] = rc;
+            s[c * Nh + q] = st2<T>(sc);
+            const cplx_t<T> rs = st2<T>(rc);
+            r[c * Nh + q] = rs;
+            rv[c] = ld2<T>(rs);
         }
         precond3(mi, beta, leray, rv, zv);
         double arr = 0.0, arz = 0.0;
@@ -947,33 +961,43 @@ __global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const d
 
 // next direction p = M r + b p, also into H
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const double2 *__restrict__ r, double b,
-                                                            double beta, int leray, double2 *__restrict__ p,
+__global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const cplx_t<T> *__restrict__ r, double b,
+                                                            double beta, int leray, cplx_t<T> *__restrict__ p,
                                                             cplx_t<T> *__restrict__ H) {
     const long Nh = g.Nh();
     const long q = (long)blockIdx.x * kThreads + threadIdx.x;
     if (q >= Nh) return;
     const ModeInfo mi = mode_info(g, q);
     double2 rv[3], zv[3];
-    for (int c = 0; c < 3; c++) rv[c] = r[c * Nh + q];
+    for (int c = 0; c < 3; c++) rv[c] = ld2<T>(r[c * Nh + q]);
     precond3(mi, beta, leray, rv, zv);
     for (int c = 0; c < 3; c++) {
-        const double2 pc = p[c * Nh + q];
+        const double2 pc = ld2<T>(p[c * Nh + q]);
         double2 o;
         o.x = zv[c].x + b * pc.x;
         o.y = zv[c].y + b * pc.y;
-        p[c * Nh + q] = o;
-        cplx_t<T> h;
-        h.x = T(o.x);
-        h.y = T(o.y);
-        H[c * Nh + q] = h;
+        const cplx_t<T> ps = st2<T>(o);
+        p[c * Nh + q] = ps;
+        H[c * Nh + q] = ps;
     }
+}
+
+// out = x + a y for a velocity vector x (complex double) and a Krylov vector
+// y (complex T)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_vec_axpy_krylov(long n, const double2 *__restrict__ x, double a,
+                                                              const cplx_t<T> *__restrict__ y,
+                                                              double2 *__restrict__ out) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= n) return;
+    const double2 xv = x[e], yv = ld2<T>(y[e]);
+    out[e] = make_double2(xv.x + a * yv.x, xv.y + a * yv.y);
 }
 
 // out = a |k|^4 x + [P] y (y complex T) with partials of <x, out> (dot 1) or
 // <out, out> (dot 2)
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const double2 *__restrict__ x,
+template <typename T, typename X>
+__global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const X *__restrict__ x,
                                                                const cplx_t<T> *__restrict__ y, double a, int leray,
                                                                int dot, double2 *__restrict__ out,
                                                                double *__restrict__ part) {
@@ -990,7 +1014,7 @@ __global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const dou
         const double f = a * mi.kk * mi.kk;
         double loc = 0.0;
         for (int c = 0; c < 3; c++) {
-            const double2 xc = x[c * Nh + q];
+            const double2 xc = make_double2((double)x[c * Nh + q].x, (double)x[c * Nh + q].y);
             v[c].x = f * xc.x + v[c].x;
             v[c].y = f * xc.y + v[c].y;
             if (out) out[c * Nh + q] = v[c];
@@ -1066,46 +1090,73 @@ hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, 
 
 hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const double *b, double *partials,
                             int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(k_vec_dot, dim3(nblocks), dim3(kThreads), 0, s, c.g, mode,
+    hipLaunchKernelGGL(k_vec_dot<double2>, dim3(nblocks), dim3(kThreads), 0, s, c.g, mode,
                        reinterpret_cast<const double2 *>(a), reinterpret_cast<const double2 *>(b ? b : a), partials);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, double *s, double *r, double *p,
-                     void *H, double *part_rz, int nblocks, hipStream_t st) {
+hipError_t krylov_dot_partials(const SpecCtx &c, const double *a, const void *b, double *partials, int nblocks,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_vec_dot<cplx_t<T>>, dim3(nblocks), dim3(kThreads), 0, s, c.g, 0,
+                       reinterpret_cast<const double2 *>(a), reinterpret_cast<const cplx_t<T> *>(b), partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t krylov_axpy(const SpecCtx &c, const double *x, double a, const void *y, double *out, hipStream_t s) {
+    const long n = 3 * c.g.Nh();
+    hipLaunchKernelGGL(k_vec_axpy_krylov<T>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n,
+                       reinterpret_cast<const double2 *>(x), a, reinterpret_cast<const cplx_t<T> *>(y),
+                       reinterpret_cast<double2 *>(out));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p, void *H,
+                     double *part_rz, int nblocks, hipStream_t st) {
+    using C = cplx_t<T>;
     hipLaunchKernelGGL(k_pcg_start<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g,
-                       reinterpret_cast<const double2 *>(g), beta, leray, reinterpret_cast<double2 *>(s),
-                       reinterpret_cast<double2 *>(r), reinterpret_cast<double2 *>(p),
-                       reinterpret_cast<cplx_t<T> *>(H), part_rz);
+                       reinterpret_cast<const double2 *>(g), beta, leray, reinterpret_cast<C *>(s),
+                       reinterpret_cast<C *>(r), reinterpret_cast<C *>(p), reinterpret_cast<C *>(H), part_rz);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t pcg_step(const SpecCtx &c, double a, const double *p, const void *y, double beta, int leray, double *s,
-                    double *r, double *part_rr, double *part_rz, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_step<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g, a,
-                       reinterpret_cast<const double2 *>(p), reinterpret_cast<const cplx_t<T> *>(y), beta, leray,
-                       reinterpret_cast<double2 *>(s), reinterpret_cast<double2 *>(r), part_rr, part_rz);
+hipError_t pcg_step(const SpecCtx &c, double a, const void *p, const void *y, double beta, int leray, void *s, void *r,
+                    double *part_rr, double *part_rz, int nblocks, hipStream_t st) {
+    using C = cplx_t<T>;
+    hipLaunchKernelGGL(k_pcg_step<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g, a, reinterpret_cast<const C *>(p),
+                       reinterpret_cast<const C *>(y), beta, leray, reinterpret_cast<C *>(s), reinterpret_cast<C *>(r),
+                       part_rr, part_rz);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t pcg_direction(const SpecCtx &c, const double *r, double b, double beta, int leray, double *p, void *H,
+hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, void *H,
                          hipStream_t st) {
+    using C = cplx_t<T>;
     const unsigned nb = (unsigned)((c.g.Nh() + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_pcg_direction<T>, dim3(nb), dim3(kThreads), 0, st, c.g,
-                       reinterpret_cast<const double2 *>(r), b, beta, leray, reinterpret_cast<double2 *>(p),
-                       reinterpret_cast<cplx_t<T> *>(H));
+    hipLaunchKernelGGL(k_pcg_direction<T>, dim3(nb), dim3(kThreads), 0, st, c.g, reinterpret_cast<const C *>(r), b,
+                       beta, leray, reinterpret_cast<C *>(p), reinterpret_cast<C *>(H));
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, double a, int leray, int dot, double *out,
                             double *part, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL(k_vec_assemble_dot<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g,
+    hipLaunchKernelGGL((k_vec_assemble_dot<T, double2>), dim3(nblocks), dim3(kThreads), 0, st, c.g,
                        reinterpret_cast<const double2 *>(x), reinterpret_cast<const cplx_t<T> *>(y), a, leray, dot,
                        reinterpret_cast<double2 *>(out), part);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t krylov_curvature(const SpecCtx &c, const void *p, const void *y, double beta, int leray, double *part,
+                            int nblocks, hipStream_t st) {
+    hipLaunchKernelGGL((k_vec_assemble_dot<T, cplx_t<T>>), dim3(nblocks), dim3(kThreads), 0, st, c.g,
+                       reinterpret_cast<const cplx_t<T> *>(p), reinterpret_cast<const cplx_t<T> *>(y), beta, leray, 1,
+                       nullptr, part);
     return hipGetLastError();
 }
 
@@ -1121,12 +1172,18 @@ hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, do
     template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
     template hipError_t vec_assemble_dot<T>(const SpecCtx &, const double *, const void *, double, int, int,        \
                                             double *, double *, int, hipStream_t);                                  \
-    template hipError_t pcg_start<T>(const SpecCtx &, const double *, double, int, double *, double *, double *,   \
-                                     void *, double *, int, hipStream_t);                                           \
-    template hipError_t pcg_step<T>(const SpecCtx &, double, const double *, const void *, double, int, double *,  \
-                                    double *, double *, double *, int, hipStream_t);                                \
-    template hipError_t pcg_direction<T>(const SpecCtx &, const double *, double, double, int, double *, void *,   \
+    template hipError_t pcg_start<T>(const SpecCtx &, const double *, double, int, void *, void *, void *, void *, \
+                                     double *, int, hipStream_t);                                                   \
+    template hipError_t pcg_step<T>(const SpecCtx &, double, const void *, const void *, double, int, void *,      \
+                                    void *, double *, double *, int, hipStream_t);                                  \
+    template hipError_t pcg_direction<T>(const SpecCtx &, const void *, double, double, int, void *, void *,       \
                                          hipStream_t);                                                              \
+    template hipError_t krylov_curvature<T>(const SpecCtx &, const void *, const void *, double, int, double *,     \
+                                            int, hipStream_t);                                                      \
+    template hipError_t krylov_dot_partials<T>(const SpecCtx &, const double *, const void *, double *, int,       \
+                                               hipStream_t);                                                        \
+    template hipError_t krylov_axpy<T>(const SpecCtx &, const double *, double, const void *, double *,            \
+                                       hipStream_t);                                                                \
     template hipError_t vec_symbol<T>(const SpecCtx &, int, const double *, const void *, double, int, double *,  \
                                       hipStream_t);
 

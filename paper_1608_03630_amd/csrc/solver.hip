@@ -488,7 +488,8 @@ struct Exec {
                 } else if (r.op == Op::OBJECTIVE) {
                     STCHK(objective_slots<T>(ctx, ctx->histB, r.x, false));
                 } else if (r.op == Op::MATVEC) {
-                    STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y, r.dot ? 1 : 0, 0));
+                    if (r.pre) STCHK(curvature<T>(ctx, r.x, ctx->bvec, 0));
+                    else STCHK(assemble<T>(ctx, r.x, ctx->bvec, r.y, r.dot ? 1 : 0, 0));
                 }
                 return REG_OK;
             });
@@ -781,7 +782,7 @@ struct Solver {
                 }
                 if (kappa <= 0) {  // negative curvature: stop (steepest descent at the first iteration)
                     // (p = M r at the first iteration)
-                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<double>(NV, CV<double>(ctx->phat), V<double>(ctx->shat), ctx->stream)));
+                    if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(NV, CV<T>(ctx->phat), V<T>(ctx->shat), ctx->stream)));
                     st = S_ARMIJO;
                     break;
                 }
@@ -813,7 +814,7 @@ struct Solver {
                 return REG_OK;
             }
             case S_ARMIJO:
-                STCHK(sdot(ctx, ctx->ghat, ctx->shat, 0));
+                STCHK(krylov_dot<T>(ctx, ctx->ghat, ctx->shat, 0));
                 queue_fetch(1);
                 st = S_ARMIJO_D;
                 return REG_OK;
@@ -830,8 +831,7 @@ struct Solver {
                     break;
                 }
                 trials++;
-                HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_xpay<double>(NV, CV<double>(ctx->vhat), alpha, CV<double>(ctx->shat),
-                                                                            V<double>(ctx->vthat), ctx->stream)));
+                STCHK(krylov_axpy<T>(ctx, ctx->vhat, alpha, ctx->shat, ctx->vthat));
                 req = Request{Op::OBJECTIVE, ctx->vthat, nullptr, nullptr, false, false};
                 st = S_LS_DONE;
                 return REG_OK;
