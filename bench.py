@@ -250,6 +250,53 @@ def run_batch(reg, torch, args):
     print(json.dumps(out), flush=True)
 
 
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix peak
+
+
+def run_net(reg, torch, args):
+    """The warm-start network's convolutions on their roofline: one forward
+    pass (one sample) and one training step (batch 8: forward, backward data,
+    weight gradients, Adam) on the 64^3 grid, seeded inputs, timed with
+    events on the stream the library runs on (torch's current stream).
+    Algorithmic FLOPs: 2 * 27 * cin * cout per output point and layer, three
+    times that per training sample."""
+    from paper_1608_03630_amd import warmstart
+
+    n = warmstart.NET_N
+    net = reg.Net(n)
+    net.reg_net_set_params(torch.from_numpy(warmstart.init_params(7)).cuda())
+    g = torch.Generator(device="cuda").manual_seed(1)
+    T = [torch.rand((n, n, n), device="cuda", generator=g) for _ in range(8)]
+    R = [torch.rand((n, n, n), device="cuda", generator=g) for _ in range(8)]
+    V = [0.01 * torch.randn((3, n, n, n), device="cuda", generator=g) for _ in range(8)]
+    flops = sum(2 * 27 * cin * cout * (n // gr) ** 3 for (cin, cout, _), gr in zip(reg.NET_LAYERS, reg.NET_LAYER_GRID))
+    for _ in range(max(1, args.warmup)):
+        net.reg_net_forward(T[0], R[0])
+        net.reg_net_train_step(T, R, V, 1e-4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10 * max(1, args.steps)
+    e0.record()
+    for _ in range(reps):
+        net.reg_net_forward(T[0], R[0])
+    e1.record()
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    e0.record()
+    for _ in range(max(1, args.steps)):
+        net.reg_net_train_step(T, R, V, 1e-4)
+    e1.record()
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / max(1, args.steps)
+    fwd_tf = flops / (fwd_ms * 1e-3) / 1e12
+    step_tf = 3 * 8 * flops / (step_ms * 1e-3) / 1e12
+    print(json.dumps({"mode": "net", "n": n, "gflop_forward": flops / 1e9, "forward_ms": fwd_ms,
+                      "forward_tflops": fwd_tf, "train_step_batch": 8, "train_step_ms": step_ms,
+                      "train_tflops": step_tf,
+                      "roofline": {"bound": "mfma", "achieved": fwd_tf, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": fwd_tf / BF16_PEAK_TFLOPS}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,10 +307,11 @@ def main():
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
-    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net"], default="solve",
                     help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
                          "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
-                         "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch")
+                         "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch; net: "
+                         "forward pass and training step of the 64^3 warm-start network against the BF16 MFMA peak")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
@@ -286,6 +334,9 @@ def main():
         return
     if args.mode == "batch":
         run_batch(reg, torch, args)
+        return
+    if args.mode == "net":
+        run_net(reg, torch, args)
         return
     if args.mode == "kernels":
         ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
