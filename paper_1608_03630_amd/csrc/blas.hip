@@ -128,29 +128,6 @@ __global__ __launch_bounds__(kThreads) void k_finalize_minmax(const double *__re
 }
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_axpby(long n, T a, const T *__restrict__ x, T b, T *__restrict__ y) {
-    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) y[i] = a * x[i] + b * y[i];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_xpay(long n, const T *__restrict__ x, T a, const T *__restrict__ y,
-                                                   T *__restrict__ z) {
-    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) z[i] = x[i] + a * y[i];
-}
-
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_cg_update(long n, T a, const T *__restrict__ p, const T *__restrict__ q,
-                                                        T *__restrict__ s, T *__restrict__ r) {
-    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (i < n) {
-        s[i] += a * p[i];
-        r[i] -= a * q[i];
-    }
-}
-
-template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fill(long n, T v, T *__restrict__ y) {
     const long i = (long)blockIdx.x * kThreads + threadIdx.x;
     if (i < n) y[i] = v;
@@ -195,24 +172,6 @@ hipError_t launch_finalize_minmax(const double *pmin, const double *pmax, int np
 }
 
 template <typename T>
-hipError_t launch_axpby(long n, double a, const T *x, double b, T *y, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpby<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(a), x, T(b), y);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_xpay(long n, const T *x, double a, const T *y, T *z, hipStream_t s) {
-    hipLaunchKernelGGL(k_xpay<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, x, T(a), y, z);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_cg_update(long n, double a, const T *p, const T *q, T *sv, T *r, hipStream_t s) {
-    hipLaunchKernelGGL(k_cg_update<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(a), p, q, sv, r);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_fill(long n, double val, T *y, hipStream_t s) {
     hipLaunchKernelGGL(k_fill<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(val), y);
     return hipGetLastError();
@@ -235,9 +194,6 @@ template hipError_t launch_convert<float, double>(long, const float *, double *,
 #define REGK_BLAS_INST(T)                                                                                          \
     template hipError_t launch_dot_partials<T>(const T *, const T *, long, int, double *, hipStream_t);            \
     template hipError_t launch_det_partials<T>(const T *, long, double *, double *, T *, hipStream_t);             \
-    template hipError_t launch_axpby<T>(long, double, const T *, double, T *, hipStream_t);                        \
-    template hipError_t launch_xpay<T>(long, const T *, double, const T *, T *, hipStream_t);                      \
-    template hipError_t launch_cg_update<T>(long, double, const T *, const T *, T *, T *, hipStream_t);            \
     template hipError_t launch_fill<T>(long, double, T *, hipStream_t);                                            \
     template hipError_t launch_copy<T>(long, const T *, T *, hipStream_t);
 

@@ -202,10 +202,6 @@ hipError_t vec_assemble_dot(const SpecCtx &c, const double *x, const void *y, do
 hipError_t vec_dot_partials(const SpecCtx &c, int mode, const double *a, const double *b, double *partials,
                             int nblocks, hipStream_t s);
 
-// partial sums over blocks of sum_k w(k3) |k|^4 |H_c|^2, c < 3 -> partials (double)
-template <typename T>
-hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s);
-
 // -------------------------------------------------------------------- blas.hip
 constexpr int RED_BLOCKS = 1024;
 constexpr int RED_THREADS = 256;
@@ -218,15 +214,6 @@ hipError_t launch_finalize(const double *partials, int nparts, double scale, dou
 template <typename T>
 hipError_t launch_det_partials(const T *du, long n, double *pmin, double *pmax, T *det_out, hipStream_t s);
 hipError_t launch_finalize_minmax(const double *pmin, const double *pmax, int nparts, double *out2, hipStream_t s);
-// y = a*x + b*y
-template <typename T>
-hipError_t launch_axpby(long n, double a, const T *x, double b, T *y, hipStream_t s);
-// z = x + a*y
-template <typename T>
-hipError_t launch_xpay(long n, const T *x, double a, const T *y, T *z, hipStream_t s);
-// s += a p; r -= a q
-template <typename T>
-hipError_t launch_cg_update(long n, double a, const T *p, const T *q, T *sv, T *r, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(long n, double val, T *y, hipStream_t s);
 template <typename T>

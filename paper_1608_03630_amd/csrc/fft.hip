@@ -531,38 +531,6 @@ __global__ __launch_bounds__(kThreads) void k_symbol(Grid g, cplx_t<T> *__restri
 // Per-block partial sums of sum_c sum_k w(k3) |k|^4 |H_c(k)|^2 with
 // w = 1 on the k3 = 0 and k3 = n3/2 planes and 2 elsewhere (the half spectrum
 // stands for both k and -k), accumulated in double.
-template <typename T>
-__global__ __launch_bounds__(kThreads) void k_biharm_norm(Grid g, const cplx_t<T> *__restrict__ H, long h_stride,
-                                                          double *__restrict__ partials) {
-    const long Nh = g.Nh();
-    const int nh = g.n3h();
-    double acc = 0.0;
-    for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
-        const int m3 = (int)(q % nh);
-        const long r = q / nh;
-        const int m2 = (int)(r % g.n2), m1 = (int)(r / g.n2);
-        const double k1 = kwave(m1, g.n1), k2 = kwave(m2, g.n2), k3 = m3;
-        const double kk = k1 * k1 + k2 * k2 + k3 * k3;
-        const double w = (m3 == 0 || 2 * m3 == g.n3) ? 1.0 : 2.0;
-        double s = 0.0;
-        for (int c = 0; c < 3; c++) {
-            const cplx_t<T> z = H[c * h_stride + q];
-            s += (double)z.x * z.x + (double)z.y * z.y;
-        }
-        acc += w * kk * kk * s;
-    }
-    // wavefront then block reduction in a fixed order
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    __shared__ double ws[kThreads / 64];
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kThreads / 64; i++) t += ws[i];
-        partials[blockIdx.x] = t;
-    }
-}
-
 // log2 of the lines per tile: the largest power of two L such that the two
 // LDS buffers of n*pitch complex values plus the n twiddles fit in 64 KiB;
 // padded tiles use pitch L + 1 (pitch 1 for a single line).
@@ -671,14 +639,6 @@ hipError_t spec_symbol(const SpecCtx &c, int op, double a, int ncomp, int leray,
     const unsigned nb = (unsigned)((g.Nh() + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_symbol<T>, dim3(nb), dim3(kThreads), 0, s, g, reinterpret_cast<C *>(c.H), g.Nh(), op, T(a),
                        ncomp, leray);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t spec_biharm_norm_partials(const SpecCtx &c, double *partials, int nblocks, hipStream_t s) {
-    using C = cplx_t<T>;
-    hipLaunchKernelGGL(k_biharm_norm<T>, dim3(nblocks), dim3(kThreads), 0, s, c.g,
-                       reinterpret_cast<const C *>(c.H), c.g.Nh(), partials);
     return hipGetLastError();
 }
 
@@ -1166,7 +1126,6 @@ hipError_t krylov_curvature(const SpecCtx &c, const void *p, const void *y, doub
     template hipError_t spec_forward<T, T>(const SpecCtx &, const T *, int, int, hipStream_t);                     \
     template hipError_t spec_inverse<T, T>(const SpecCtx &, T *, int, hipStream_t);                                \
     template hipError_t spec_symbol<T>(const SpecCtx &, int, double, int, int, hipStream_t);                       \
-    template hipError_t spec_biharm_norm_partials<T>(const SpecCtx &, double *, int, hipStream_t);           \
     template hipError_t spec_forward_to<T, T>(const SpecCtx &, const T *, int, void *, hipStream_t);              \
     template hipError_t spec_inverse_from<T, T>(const SpecCtx &, void *, T *, int, hipStream_t);                  \
     template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
