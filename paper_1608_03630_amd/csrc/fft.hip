@@ -153,12 +153,91 @@ __device__ __forceinline__ void fft_pass(const cplx_t<T> *a, cplx_t<T> *b, int n
     }
 }
 
+// 16-point DFT with kernel exp(sign 2 pi i r q / 16) in registers, natural
+// order in and out: x[4 n1 + n2] -> X[k1 + 4 k2] as 4-point DFTs over n1,
+// twiddles exp(sign 2 pi i n2 k1 / 16), 4-point DFTs over n2.
+template <typename T>
+__device__ __forceinline__ void dft16(cplx_t<T> x[16], int sign) {
+    using C = cplx_t<T>;
+    // cos and sin of 2 pi m / 16, m = 0..9
+    const T c16[10] = {T(1), T(0.92387953251128675613), T(0.70710678118654752440), T(0.38268343236508977173),
+                       T(0), T(-0.38268343236508977173), T(-0.70710678118654752440), T(-0.92387953251128675613),
+                       T(-1), T(-0.92387953251128675613)};
+    const T s16[10] = {T(0), T(0.38268343236508977173), T(0.70710678118654752440), T(0.92387953251128675613),
+                       T(1), T(0.92387953251128675613), T(0.70710678118654752440), T(0.38268343236508977173),
+                       T(0), T(-0.38268343236508977173)};
+    C y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; n2++) {
+        C v[4] = {x[n2], x[4 + n2], x[8 + n2], x[12 + n2]};
+        butterfly<T, 4>(v, sign);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; k1++) y[n2][k1] = v[k1];
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < 4; n2++)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; k1++) {
+            C w;
+            w.x = c16[n2 * k1];
+            w.y = sign > 0 ? s16[n2 * k1] : -s16[n2 * k1];
+            y[n2][k1] = cmul(y[n2][k1], w);
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; k1++) {
+        C v[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        butterfly<T, 4>(v, sign);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; k2++) x[k1 + 4 * k2] = v[k2];
+    }
+}
+
+// 256-point Stockham FFT of 2^lgL lines as two radix-16 passes, each
+// thread transforming 16 elements of one line in registers (fewer passes,
+// index computations and twiddle reads than four radix-4 passes); result in
+// a, ends with a barrier.
+template <typename T>
+__device__ cplx_t<T> *fft256_r16(cplx_t<T> *a, cplx_t<T> *b, int lgL, int pitch, int sign, const cplx_t<T> *tw) {
+    using C = cplx_t<T>;
+    const int L = 1 << lgL;
+    // Ns = 1: b[16 j + r] = DFT16(a[j + 16 r])
+    for (int e = threadIdx.x; e < 16 * L; e += blockDim.x) {
+        const int l = e & (L - 1), j = e >> lgL;
+        C v[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) v[r] = a[(j + 16 * r) * pitch + l];
+        dft16<T>(v, sign);
+#pragma unroll
+        for (int r = 0; r < 16; r++) b[(16 * j + r) * pitch + l] = v[r];
+    }
+    __syncthreads();
+    // Ns = 16: a[j + 16 r] = DFT16(b[j + 16 r] w^(r j)), w = exp(sign 2 pi i / 256)
+    for (int e = threadIdx.x; e < 16 * L; e += blockDim.x) {
+        const int l = e & (L - 1), j = e >> lgL;
+        C v[16];
+#pragma unroll
+        for (int r = 0; r < 16; r++) v[r] = b[(j + 16 * r) * pitch + l];
+#pragma unroll
+        for (int r = 1; r < 16; r++) {
+            C w = tw[r * j];
+            if (sign > 0) w.y = -w.y;
+            v[r] = cmul(v[r], w);
+        }
+        dft16<T>(v, sign);
+#pragma unroll
+        for (int r = 0; r < 16; r++) a[(j + 16 * r) * pitch + l] = v[r];
+    }
+    __syncthreads();
+    return a;
+}
+
 // Stockham FFT of 2^lgL lines held in LDS; returns the buffer that holds the
 // result (natural order); ends with a barrier.
 template <typename T>
 __device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int lgL, int pitch, int sign,
                               const cplx_t<T> *tw) {
     using C = cplx_t<T>;
+    if (pl.n == 256) return fft256_r16<T>(a, b, lgL, pitch, sign, tw);
     int Ns = 1;
     for (int ps = 0; ps < pl.npass; ps++) {
         const int R = pl.radix[ps];

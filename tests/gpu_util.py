@@ -59,6 +59,22 @@ def biharm_amp(shape):
     return float(np.sqrt(np.mean(k2 ** 4)))
 
 
+def deriv_bound(shape, prec, fields, out_ref, safety=4.0):
+    """Relative-L2 error bound of a first derivative (or a sum of them) in
+    floating point: round-off of the line transform (relative size ~u per
+    mode, white across the spectrum) is multiplied by k_j, so its norm grows
+    to u sqrt(sum_j mean_k k_j^2 |f_j|^2) for fields f_j differentiated along
+    axis j (a dict axis -> field), against the result's norm. It reaches
+    u n / sqrt(12) per axis of n points, so long lines and smooth inputs need
+    more than a fixed bar in single precision."""
+    acc = 0.0
+    for j, f in fields.items():
+        kj = np.fft.fftfreq(shape[j], 1.0 / shape[j])
+        acc += float(np.mean(kj ** 2)) * float(np.sum(np.asarray(f, dtype=np.float64) ** 2))
+    bound = safety * unit_roundoff(prec) * np.sqrt(acc) / np.linalg.norm(np.ravel(out_ref))
+    return max(TOL[("spectral", prec)], bound)
+
+
 def biharm_bound(shape, prec, scale_v_norm, out_norm, safety=4.0):
     """Relative-L2 error bound of a result that contains scale*lap^2 v.
 
