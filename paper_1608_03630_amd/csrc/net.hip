@@ -56,60 +56,105 @@ __device__ __forceinline__ int source(int i, int j, int k, int d1, int d2, int d
     return ((y1 >> 1) * n_in + (y2 >> 1)) * n_in + (y3 >> 1);
 }
 
-// One wavefront: 16 consecutive output points x NB*16 output channels.
-template <int MODE, int NB>
+// source coordinate along one axis of output coordinate i for the tap
+// offset d, or -1 where the tap does not reach a source point (the axis
+// form of source() above)
+template <int MODE>
+__device__ __forceinline__ int source_axis(int i, int d, int n_out, int n_in) {
+    if (MODE == CONV_FWD1) return wrap(i + d, n_in);
+    if (MODE == CONV_BWD1) return wrap(i - d, n_in);
+    if (MODE == CONV_FWD2) return wrap(2 * i + d, n_in);
+    const int y = wrap(i - d, n_out);  // CONV_BWD2: fine output grid, coarse input grid
+    return (y & 1) ? -1 : (y >> 1);
+}
+
+// One wavefront: MB blocks of 16 consecutive output points x NB*16 output
+// channels, starting at channel block blockIdx.y * NB (small grids split
+// the channels over gridDim.y for more wavefronts). Each weight fragment
+// feeds MB matrix products and each activation fragment NB, so a wavefront
+// issues MB + NB fragment loads for MB * NB MFMAs per (tap, channel chunk).
+template <int MODE, int NB, int MB>
 __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int p0 = (blockIdx.x * (kThreads / 64) + wave) * 16;
+    const long p0 = ((long)blockIdx.x * (kThreads / 64) + wave) * 16 * MB;
     const long P = (long)a.n_out * a.n_out * a.n_out;
-    if (p0 >= P) return;  // whole wavefronts only (P is a multiple of 16)
+    if (p0 >= P) return;  // whole wavefronts only (P is a multiple of 16 MB)
     const int g = lane >> 4, r = lane & 15;
-    // coordinates of this lane's A-row point
-    const int pa = p0 + r;
     const int n = a.n_out;
-    const int ai = pa / (n * n), aj = (pa / n) % n, ak = pa % n;
-    v4f acc[NB];
+    // this lane's A-row point in each point block: its source coordinate per
+    // axis for the offsets d = -1, 0, 1 (-1 where the tap does not reach a
+    // source point), computed once instead of per tap
+    int c1[MB][3], c2[MB][3], c3[MB][3];
 #pragma unroll
-    for (int b = 0; b < NB; b++) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < MB; m++) {
+        const long pa = p0 + 16 * m + r;
+        const int i = (int)(pa / ((long)n * n)), j = (int)((pa / n) % n), k = (int)(pa % n);
+#pragma unroll
+        for (int d = -1; d <= 1; d++) {
+            c1[m][d + 1] = source_axis<MODE>(i, d, a.n_out, a.n_in);
+            c2[m][d + 1] = source_axis<MODE>(j, d, a.n_out, a.n_in);
+            c3[m][d + 1] = source_axis<MODE>(k, d, a.n_out, a.n_in);
+        }
+    }
+    v4f acc[MB][NB];
+#pragma unroll
+    for (int m = 0; m < MB; m++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) acc[m][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const uint16_t *__restrict__ in = a.in;
     const uint16_t *__restrict__ W = a.w;
     const int ccin = a.cin >> 4;
+#pragma unroll
     for (int t = 0; t < 27; t++) {
-        const int d1 = t / 9 - 1, d2 = (t / 3) % 3 - 1, d3 = t % 3 - 1;
-        const int q = source<MODE>(ai, aj, ak, d1, d2, d3, a.n_out, a.n_in);
-        const uint16_t *src = in + (long)(q < 0 ? 0 : q) * a.in_cs + 4 * g;
-        const uint16_t *wt = W + ((long)t * a.cout + r) * a.cin + 4 * g;
+        const int e1 = t / 9, e2 = (t / 3) % 3, e3 = t % 3;
+        const uint16_t *src[MB];
+        bool ok[MB];
+#pragma unroll
+        for (int m = 0; m < MB; m++) {
+            const int x1 = c1[m][e1], x2 = c2[m][e2], x3 = c3[m][e3];
+            ok[m] = (x1 | x2 | x3) >= 0;
+            const int q = ok[m] ? (x1 * a.n_in + x2) * a.n_in + x3 : 0;
+            src[m] = in + (long)q * a.in_cs + 4 * g;
+        }
+        const uint16_t *wt = W + ((long)t * a.cout + 16 * NB * blockIdx.y + r) * a.cin + 4 * g;
         for (int c = 0; c < ccin; c++) {
-            v4s av = q < 0 ? v4s{0, 0, 0, 0} : *reinterpret_cast<const v4s *>(src + 16 * c);
+            v4s av[MB], bv[NB];
 #pragma unroll
-            for (int b = 0; b < NB; b++) {
-                const v4s bv = *reinterpret_cast<const v4s *>(wt + (long)b * 16 * a.cin + 16 * c);
-                acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[b], 0, 0, 0);
-            }
+            for (int m = 0; m < MB; m++)
+                av[m] = ok[m] ? *reinterpret_cast<const v4s *>(src[m] + 16 * c) : v4s{0, 0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < NB; b++) bv[b] = *reinterpret_cast<const v4s *>(wt + (long)b * 16 * a.cin + 16 * c);
+#pragma unroll
+            for (int m = 0; m < MB; m++)
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[m], bv[b], acc[m][b], 0, 0, 0);
         }
     }
-    // epilogue: lane holds D[4g+i][r] = (point p0+4g+i, channel b*16+r)
+    // epilogue: lane holds D[4g+i][r] = (point p0+16m+4g+i, channel b*16+r)
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        const int co = b * 16 + r;
-        const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+    for (int m = 0; m < MB; m++)
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const long p = p0 + 4 * g + i;
-            float v = acc[b][i] + bias;
-            if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
-            if (a.relu) v = fmaxf(v, 0.f);
-            if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
-            if (a.out_f32) {
-                if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
-            } else {
-                a.out[p * a.out_cs + co] = f2bf(v);
+        for (int b = 0; b < NB; b++) {
+            const int co = (NB * blockIdx.y + b) * 16 + r;
+            const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const long p = p0 + 16 * m + 4 * g + i;
+                float v = acc[m][b][i] + bias;
+                if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
+                if (a.out_f32) {
+                    if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
+                } else {
+                    a.out[p * a.out_cs + co] = f2bf(v);
+                }
             }
         }
-    }
 }
 
-// Weight gradient partials: one workgroup per (chunk of kChunk points, tap)
+// Weight gradient partials: one workgroup per (chunk of wgrad_chunk(P) points, tap)
 // forms sum_p dz[p][co] x[src(p, t)][ci] for every (co, ci) tile with
 // v_mfma_f32_16x16x32_bf16 (K = points). Slices of kSlice points are staged
 // transposed ([channel][point], row pitch kPitch) so that each lane's 8-point
@@ -119,7 +164,9 @@ typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kSlice = 64;
-constexpr int kChunk = 2048;
+// points per weight-gradient workgroup: 2048 on 64^3 and finer grids, fewer
+// on coarse ones so that they still spread over the GPU
+__host__ __device__ inline int wgrad_chunk(long P) { return P >= 262144 ? 2048 : P >= 32768 ? 512 : 128; }
 constexpr int kPitch = kSlice + 8;  // 144-byte rows: 16-byte aligned fragments
 
 template <int MODE>
@@ -139,8 +186,9 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
 #pragma unroll
     for (int u = 0; u < 4; u++) acc[u] = v4f{0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    const long base = (long)blockIdx.x * kChunk;
-    for (int sl = 0; sl < kChunk / kSlice; sl++) {
+    const int chunk = wgrad_chunk(P);
+    const long base = (long)blockIdx.x * chunk;
+    for (int sl = 0; sl < chunk / kSlice; sl++) {
         const long s0 = base + (long)sl * kSlice;
         if (s0 >= P) break;
         for (int e = threadIdx.x; e < kSlice * q4o; e += kThreads) {
@@ -356,15 +404,22 @@ inline unsigned blocks(long n) { return (unsigned)((n + kThreads - 1) / kThreads
 
 hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
     const long P = (long)a.n_out * a.n_out * a.n_out;
-    if (P % 16 || a.cin % 16 || a.cout % 16 || a.cout > 64 || a.cin > 64 || a.in_cs % 4) return hipErrorInvalidValue;
-    const unsigned nb = (unsigned)((P / 16 + 3) / 4);
+    if (P % 64 || a.cin % 16 || a.cout % 16 || a.cout > 64 || a.cin > 64 || a.in_cs % 4) return hipErrorInvalidValue;
+    // four point blocks per wavefront (64 points) and every channel block on
+    // grids of 32^3 and more; on the small grids one point block and one
+    // channel block per wavefront, the channel blocks over gridDim.y, which
+    // would otherwise leave the GPU idle
+    const bool wide = P >= 32768;
     const int NB = a.cout / 16;
+    if (NB != 1 && NB != 2 && NB != 4) return hipErrorInvalidValue;
+    const unsigned nb = (unsigned)((P / (wide ? 64 : 16) + 3) / 4);
+    const dim3 grid(nb, wide ? 1 : NB);
 #define REGN_CONV(M)                                                                                  \
     do {                                                                                              \
-        if (NB == 1) hipLaunchKernelGGL((k_conv<M, 1>), dim3(nb), dim3(kThreads), 0, s, a);          \
-        else if (NB == 2) hipLaunchKernelGGL((k_conv<M, 2>), dim3(nb), dim3(kThreads), 0, s, a);     \
-        else if (NB == 4) hipLaunchKernelGGL((k_conv<M, 4>), dim3(nb), dim3(kThreads), 0, s, a);     \
-        else return hipErrorInvalidValue;                                                             \
+        if (!wide) hipLaunchKernelGGL((k_conv<M, 1, 1>), grid, dim3(kThreads), 0, s, a);             \
+        else if (NB == 1) hipLaunchKernelGGL((k_conv<M, 1, 4>), grid, dim3(kThreads), 0, s, a);      \
+        else if (NB == 2) hipLaunchKernelGGL((k_conv<M, 2, 4>), grid, dim3(kThreads), 0, s, a);      \
+        else hipLaunchKernelGGL((k_conv<M, 4, 4>), grid, dim3(kThreads), 0, s, a);                   \
     } while (0)
     switch (mode) {
     case CONV_FWD1: REGN_CONV(CONV_FWD1); break;
@@ -379,7 +434,7 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
 
 int wgrad_chunks(int n_out) {
     const long P = (long)n_out * n_out * n_out;
-    return (int)((P + kChunk - 1) / kChunk);
+    return (int)((P + wgrad_chunk(P) - 1) / wgrad_chunk(P));
 }
 
 hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {

@@ -138,13 +138,14 @@ size_t net_layout(int n, char *base, reg_net *net) {
     t->dz2 = act(P2, 32);
     t->dz1 = act(P1, 16);
     t->dz0 = act(P1, 16);
-    size_t part = 0;
+    size_t part = 0, bpart = 0;
     for (int l = 0; l < kLayers; l++) {
         const int no = (l >= 2 && l <= 3) || l == 7 || l == 8 ? n / 2 : (l >= 4 && l <= 6) ? n / 4 : n;
         part = std::max(part, (size_t)regn::wgrad_chunks(no) * 27 * pad16(kDef[l].cout) * pad16(kDef[l].cin));
+        bpart = std::max(bpart, (size_t)regn::wgrad_chunks(no) * pad16(kDef[l].cout));
     }
     t->partials = (float *)L.take(sizeof(float) * part);
-    t->bias_partials = (float *)L.take(sizeof(float) * 64 * regn::wgrad_chunks(n));
+    t->bias_partials = (float *)L.take(sizeof(float) * bpart);
     t->mse_part = (double *)L.take(sizeof(double) * regn::mse_blocks(P1));
     t->loss = (double *)L.take(sizeof(double));
     t->rT = (float *)L.take(sizeof(float) * P1);

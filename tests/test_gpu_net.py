@@ -19,6 +19,8 @@ from oracle import net as onet
 pytestmark = pytest.mark.gpu
 
 N = 16  # network grid in these tests: levels 16^3, 8^3, 4^3
+# 32^3 levels take the kernels' four-point-block path (grids of 32^3 and more)
+SIZES = [16, 32]
 
 
 @pytest.fixture(scope="module")
@@ -49,14 +51,14 @@ def _layers(flat):
     return out
 
 
-def _setup(reg, seed=11):
+def _setup(reg, seed=11, n=N):
     layers = onet.random_params(seed)
     flat = _flat(layers)
-    net = reg.Net(N)
+    net = reg.Net(n)
     assert net.count == flat.size
     net.reg_net_set_params(torch.from_numpy(flat).cuda())
-    T = synth.smooth_random_field((N, N, N), seed + 1, kmax=4).astype(np.float32)
-    R = synth.smooth_random_field((N, N, N), seed + 2, kmax=4).astype(np.float32)
+    T = synth.smooth_random_field((n, n, n), seed + 1, kmax=4).astype(np.float32)
+    R = synth.smooth_random_field((n, n, n), seed + 2, kmax=4).astype(np.float32)
     return net, _layers(flat), T, R
 
 
@@ -64,8 +66,9 @@ def _gpu(x):
     return torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
 
 
-def test_every_layer_forward_matches_oracle(reg):
-    net, layers, T, R = _setup(reg)
+@pytest.mark.parametrize("n", SIZES)
+def test_every_layer_forward_matches_oracle(reg, n):
+    net, layers, T, R = _setup(reg, 11, n)
     net.reg_net_forward(_gpu(T), _gpu(R))
     torch.cuda.synchronize()
     act = [net.reg_net_activation(l).double().cpu().numpy() for l in range(12)]
@@ -90,9 +93,10 @@ def test_whole_forward_matches_oracle(reg):
     assert err <= 3e-2
 
 
-def test_loss_and_parameter_gradients_match_oracle(reg):
-    net, layers, T, R = _setup(reg, 31)
-    target = synth.smooth_random_field((N, N, N), 34, kmax=3, ncomp=3).astype(np.float32) * 0.1
+@pytest.mark.parametrize("n", SIZES)
+def test_loss_and_parameter_gradients_match_oracle(reg, n):
+    net, layers, T, R = _setup(reg, 31, n)
+    target = synth.smooth_random_field((n, n, n), 34, kmax=3, ncomp=3).astype(np.float32) * 0.1
     loss, g = net.reg_net_loss_grad(_gpu(T), _gpu(R), _gpu(target))
     g = _layers(g.cpu().numpy())
     Wb = [(_bf16(W), b) for W, b in layers]
