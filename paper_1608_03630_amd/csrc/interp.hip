@@ -4,16 +4,17 @@
 // kernels of the state, adjoint, incremental-state and incremental-adjoint
 // solves (eq. (7)) and of the deformation map (eq. (1)).
 //
-// One thread per grid point, which gathers its 4x4x4 stencil and evaluates it
-// separably (16 rows of 4 along x3, then 4 planes along x2, then x1): 64 FMA
-// instead of the 64-term product sum, and every output point is written by
-// exactly one thread (a race-free gather). Each stencil row (4 consecutive x3
-// values) that does not wrap around the periodic boundary is fetched with one
-// 16-byte vector load (two for double), so a wavefront issues 16 address
-// batches per point instead of 64 — the gather is bound by how many lanes the
-// address units take per clock, not by bytes. Rows that wrap use four scalar
-// loads. Blocks are remapped so that each XCD (8 per MI355X, one L2 each)
-// receives a contiguous slab of the grid, which keeps the stencil halos of
+// Every output point is computed by exactly one thread, which evaluates its
+// 4x4x4 stencil separably (16 rows of 4 along x3, then 4 planes along x2,
+// then x1): a race-free gather. Two forms:
+// * the LDS-tiled kernels (the hot path): a workgroup stages the union of
+//   its tile's stencils (a box known from the plan's floor bounds) in LDS
+//   and reads every stencil value from there (see "LDS-staged tiles");
+// * the direct gather (k_interp and friends, for displacements whose box
+//   would not fit): each stencil row that does not wrap is one 16-byte
+//   vector load (two for double), rows that wrap take four scalar loads.
+// Blocks are remapped so that each XCD (8 per MI355X, one L2 each) receives
+// a contiguous slab of the grid, which keeps the stencil halos of
 // neighbouring blocks in the same L2.
 #include "common.hpp"
 
