@@ -25,6 +25,7 @@ namespace regn {
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
@@ -154,13 +155,104 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
         }
 }
 
+// Stride-1 convolutions (forward and backward data) as an LDS-tiled implicit
+// GEMM. A workgroup owns a 4 x 4 x 16 tile of output points. For each chunk
+// of 16 input channels it stages the tile's 6 x 6 x 18 halo in LDS
+// ([halo point][16 channels], 20.7 KB) and runs all 27 taps from there: each
+// of its four wavefronts takes four x3 rows of 16 points (one MFMA row block
+// each) and NB output channel blocks starting at blockIdx.y * NB, reading per
+// tap 4 activation fragments from LDS and NB weight fragments from the cache
+// for 4 NB MFMAs.
+constexpr int kCT1 = 4, kCT2 = 4, kCT3 = 16;                      // output tile
+constexpr int kCH1 = kCT1 + 2, kCH2 = kCT2 + 2, kCH3 = kCT3 + 2;  // its halo
+constexpr int kCHalo = kCH1 * kCH2 * kCH3;                        // 648 points
+
+template <int MODE, int NB>
+__global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
+    static_assert(MODE == CONV_FWD1 || MODE == CONV_BWD1, "stride-1 modes only");
+    __shared__ __align__(16) uint16_t halo[kCHalo * 16];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int n = a.n_out;  // == a.n_in
+    const int nt3 = n / kCT3, nt2 = n / kCT2;
+    const int t3 = (int)blockIdx.x % nt3, t2 = ((int)blockIdx.x / nt3) % nt2, t1 = (int)blockIdx.x / (nt3 * nt2);
+    const int o1 = t1 * kCT1, o2 = t2 * kCT2, o3 = t3 * kCT3;
+    const int cb0 = NB * (int)blockIdx.y;  // first output channel block
+    const int sg = MODE == CONV_FWD1 ? 1 : -1;  // source = point + sg * d
+    v4f acc[4][NB];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int b = 0; b < NB; b++) acc[m][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int ccin = a.cin >> 4;
+    for (int c = 0; c < ccin; c++) {
+        // halo of channels [16c, 16c + 16): two 16-byte pieces per point
+        for (int e = threadIdx.x; e < kCHalo * 2; e += kThreads) {
+            const int hp = e >> 1, half = e & 1;
+            const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = hp / (kCH3 * kCH2);
+            const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
+            const long q = ((long)x1 * n + x2) * n + x3;
+            *reinterpret_cast<v8s *>(halo + hp * 16 + 8 * half) =
+                *reinterpret_cast<const v8s *>(a.in + q * a.in_cs + 16 * c + 8 * half);
+        }
+        __syncthreads();
+        // nine (d1, d2) rows of taps, the three d3 taps of a row unrolled
+#pragma unroll 1
+        for (int t12 = 0; t12 < 9; t12++)
+#pragma unroll
+        for (int e3 = 0; e3 < 3; e3++) {
+            const int t = 3 * t12 + e3;
+            const int d1 = t12 / 3 - 1, d2 = t12 % 3 - 1, d3 = e3 - 1;
+            v4s bv[NB];
+#pragma unroll
+            for (int b = 0; b < NB; b++)
+                bv[b] = *reinterpret_cast<const v4s *>(a.w + ((long)t * a.cout + (cb0 + b) * 16 + r) * a.cin + 16 * c +
+                                                       4 * g);
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const int pb = 4 * wave + m;  // x3 row (a1, a2) = (pb / 4, pb % 4)
+                const int h1 = pb / kCT2 + 1 + sg * d1, h2 = pb % kCT2 + 1 + sg * d2, h3 = r + 1 + sg * d3;
+                const v4s av = *reinterpret_cast<const v4s *>(halo + ((h1 * kCH2 + h2) * kCH3 + h3) * 16 + 4 * g);
+#pragma unroll
+                for (int b = 0; b < NB; b++)
+                    acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[b], acc[m][b], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // the halo is restaged for the next chunk
+    }
+    // epilogue: lane holds D[4g+i][r] = (point 4g+i of row pb, channel (cb0+b)*16+r)
+    const long P = (long)n * n * n;
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const int pb = 4 * wave + m;
+        const long prow = ((long)(o1 + pb / kCT2) * n + o2 + pb % kCT2) * n + o3;
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            const int co = (cb0 + b) * 16 + r;
+            const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const long p = prow + 4 * g + i;
+                float v = acc[m][b][i] + bias;
+                if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
+                if (a.out_f32) {
+                    if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
+                } else {
+                    a.out[p * a.out_cs + co] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
 // Weight gradient partials: one workgroup per (chunk of wgrad_chunk(P) points, tap)
 // forms sum_p dz[p][co] x[src(p, t)][ci] for every (co, ci) tile with
 // v_mfma_f32_16x16x32_bf16 (K = points). Slices of kSlice points are staged
 // transposed ([channel][point], row pitch kPitch) so that each lane's 8-point
 // fragment is one 16-byte LDS read. The centre-tap workgroups also sum dz
 // over their points (bias gradient).
-typedef short v8s __attribute__((ext_vector_type(8)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kSlice = 64;
@@ -412,6 +504,25 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
     const bool wide = P >= 32768;
     const int NB = a.cout / 16;
     if (NB != 1 && NB != 2 && NB != 4) return hipErrorInvalidValue;
+    // stride-1 layers on grids of 32^3 and more: the LDS-tiled kernel (one
+    // channel block per workgroup on 32^3, all of them on larger grids)
+    const bool tiled_ok = (mode == CONV_FWD1 || mode == CONV_BWD1) && a.n_out % kCT3 == 0 && a.in_cs % 8 == 0 &&
+                          (reinterpret_cast<uintptr_t>(a.in) & 15) == 0 && wide;
+    if (tiled_ok) {
+        const unsigned ntile = (unsigned)((a.n_out / kCT1) * (a.n_out / kCT2) * (a.n_out / kCT3));
+        const bool split = P <= 32768;
+        const dim3 grid(ntile, split ? NB : 1);
+#define REGN_TILED(M)                                                                                  \
+    do {                                                                                               \
+        if (split || NB == 1) hipLaunchKernelGGL((k_conv_tiled<M, 1>), grid, dim3(kThreads), 0, s, a); \
+        else if (NB == 2) hipLaunchKernelGGL((k_conv_tiled<M, 2>), grid, dim3(kThreads), 0, s, a);     \
+        else hipLaunchKernelGGL((k_conv_tiled<M, 4>), grid, dim3(kThreads), 0, s, a);                  \
+    } while (0)
+        if (mode == CONV_FWD1) REGN_TILED(CONV_FWD1);
+        else REGN_TILED(CONV_BWD1);
+#undef REGN_TILED
+        return hipGetLastError();
+    }
     const unsigned nb = (unsigned)((P / (wide ? 64 : 16) + 3) / 4);
     const dim3 grid(nb, wide ? 1 : NB);
 #define REGN_CONV(M)                                                                                  \
