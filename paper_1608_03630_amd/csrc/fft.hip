@@ -439,6 +439,167 @@ __global__ __launch_bounds__(kThreads) void k_r2c_x3(Grid g, FftPlan pl, const c
         }
 }
 
+// 256-point x3 transforms of 2^LG complex lines (pairs of real lines) per
+// workgroup, 16 threads per line, each holding elements j + 16 r (r = 0..15)
+// of its line in registers; the exchange between the two radix-16 passes goes
+// through LDS (line-major, rows skewed by one element per 16 against bank
+// conflicts).
+constexpr int kX3Pitch = 256 + 16;
+
+// Exchange step and second radix-16 pass shared by both x3 kernels: v holds
+// the first pass's output DFT16(a[j + 16 r]) of this thread's line; on return
+// v[r] = X[j + 16 r].
+template <typename T>
+__device__ __forceinline__ void x3_second_pass(cplx_t<T> v[16], cplx_t<T> *line_buf, int j, const cplx_t<T> *twl,
+                                               int sign) {
+    using C = cplx_t<T>;
+#pragma unroll
+    for (int r = 0; r < 16; r++) line_buf[17 * j + r] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = line_buf[j + 17 * r];
+#pragma unroll
+    for (int r = 1; r < 16; r++) {
+        C w = twl[r * j];
+        if (sign > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+    dft16<T>(v, sign);
+}
+
+// R2C along x3 (n3 = 256) of line pairs, then the split of the two half
+// spectra as in k_r2c_x3; Z_{n-k} comes from lane 16 - j of the same line.
+template <typename Tr, typename T, int LG>
+__global__ __launch_bounds__(16 << LG) void k_r2c256_x3(Grid g, const cplx_t<T> *__restrict__ tw,
+                                                        const Tr *__restrict__ x, long in_stride,
+                                                        cplx_t<T> *__restrict__ H, long h_stride) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG, n = 256, nh = 129;
+    __shared__ C buf[L * kX3Pitch];
+    __shared__ C twl[256];
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    for (int m = threadIdx.x; m < n; m += 16 << LG) twl[m] = tw[m];
+    const int j = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const bool live = l < leff;
+    const Tr *sa = x + blockIdx.y * in_stride + (r0 + 2 * l) * n;
+    const Tr *sb = sa + n;
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        v[r].x = T(0);
+        v[r].y = T(0);
+        if (live) {
+            v[r].x = T(sa[j + 16 * r]);
+            v[r].y = T(sb[j + 16 * r]);
+        }
+    }
+    dft16<T>(v, -1);
+    x3_second_pass<T>(v, buf + l * kX3Pitch, j, twl, -1);
+    const int lane = threadIdx.x & 63, partner = (lane & ~15) | ((16 - j) & 15);
+    C *da = H + blockIdx.y * h_stride + (r0 + 2 * l) * nh;
+    C *db = da + nh;
+#pragma unroll
+    for (int r = 0; r <= 8; r++) {
+        // lane 16 - j holds Z_{n-k} for k = j + 16 r in v[15 - r]; lane 0
+        // holds its own in v[(16 - r) mod 16]
+        const C give = j == 0 ? v[(16 - r) & 15] : v[15 - r];
+        C zc;
+        zc.x = __shfl(give.x, partner, 64);
+        zc.y = __shfl(give.y, partner, 64);
+        const C z = v[r];
+        const int k = j + 16 * r;
+        if (live && k < nh) {
+            C xa, xb;
+            xa.x = T(0.5) * (z.x + zc.x);
+            xa.y = T(0.5) * (z.y - zc.y);
+            xb.x = T(0.5) * (z.y + zc.y);
+            xb.y = T(-0.5) * (z.x - zc.x);
+            da[k] = xa;
+            db[k] = xb;
+        }
+    }
+}
+
+// C2R along x3 (n3 = 256): merge two half spectra into Z = X_a + i X_b as in
+// k_c2r_x3, inverse FFT, scale, real part to line r0 + 2 l, imaginary part to
+// line r0 + 2 l + 1.
+template <typename T, typename Tr, int LG>
+__global__ __launch_bounds__(16 << LG) void k_c2r256_x3(Grid g, const cplx_t<T> *__restrict__ tw,
+                                                        const cplx_t<T> *__restrict__ H, long h_stride,
+                                                        Tr *__restrict__ out, long out_stride, T scale) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG, n = 256, nh = 129;
+    __shared__ C buf[L * kX3Pitch];
+    __shared__ C twl[256];
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    for (int m = threadIdx.x; m < n; m += 16 << LG) twl[m] = tw[m];
+    const int j = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const bool live = l < leff;
+    const C *sa = H + blockIdx.y * h_stride + (r0 + 2 * l) * nh;
+    const C *sb = sa + nh;
+    // each half-spectrum value is loaded once, k = j + 16 r for r < 8 and
+    // k = n/2 by lane 0; Z_k for k > n/2 needs X_{n-k}, which lane 16 - j
+    // loaded as its r' = 15 - r (lane 0: its own r' = 16 - r)
+    C da[9], db[9];
+#pragma unroll
+    for (int r = 0; r < 9; r++) {
+        da[r].x = T(0);
+        da[r].y = T(0);
+        db[r] = da[r];
+        if (live && (r < 8 || j == 0)) {
+            da[r] = sa[j + 16 * r];
+            db[r] = sb[j + 16 * r];
+        }
+    }
+    if (j == 0) {  // k = 0 and k = n/2 are real
+        da[0].y = T(0);
+        db[0].y = T(0);
+        da[8].y = T(0);
+        db[8].y = T(0);
+    }
+    const int lane = threadIdx.x & 63, partner = (lane & ~15) | ((16 - j) & 15);
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 8; r++) {
+        v[r].x = da[r].x - db[r].y;
+        v[r].y = da[r].y + db[r].x;
+    }
+#pragma unroll
+    for (int r = 8; r < 16; r++) {
+        // selects on values (a select of the two array elements would be
+        // lowered through private memory)
+        const bool own = j == 0;
+        const C a0 = da[16 - r], a1 = da[15 - r], b0 = db[16 - r], b1 = db[15 - r];
+        C xa, xb;
+        xa.x = __shfl(own ? a0.x : a1.x, partner, 64);
+        xa.y = __shfl(own ? a0.y : a1.y, partner, 64);
+        xb.x = __shfl(own ? b0.x : b1.x, partner, 64);
+        xb.y = __shfl(own ? b0.y : b1.y, partner, 64);
+        if (r == 8 && j == 0) {  // k = n/2 itself
+            v[r].x = xa.x - xb.y;
+            v[r].y = xa.y + xb.x;
+        } else {
+            v[r].x = xa.x + xb.y;
+            v[r].y = xb.x - xa.y;
+        }
+    }
+    dft16<T>(v, +1);
+    x3_second_pass<T>(v, buf + l * kX3Pitch, j, twl, +1);
+    if (live) {
+        Tr *oa = out + blockIdx.y * out_stride + (r0 + 2 * l) * n;
+        Tr *ob = oa + n;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            oa[j + 16 * r] = Tr(scale * v[r].x);
+            ob[j + 16 * r] = Tr(scale * v[r].y);
+        }
+    }
+}
+
 // In-place complex FFT of the half spectrum along axis 0 or 1.
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, const cplx_t<T> *__restrict__ tw,
@@ -479,6 +640,64 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
     for (int e = threadIdx.x; e < n * L; e += blockDim.x) {
         const int l = e & (L - 1), j = e >> lgL;
         if (l < leff) h[base + j * stride + l] = R[j * L + l];
+    }
+}
+
+// In-place 256-point complex FFT of the half spectrum along axis 0 or 1,
+// 2^LG columns per workgroup and 16 threads per column. Each thread keeps 16
+// elements of its column in registers: the first radix-16 pass reads them
+// straight from HBM (rows j + 16 r), the second writes them straight back, and
+// only the exchange between the passes goes through LDS (one buffer, rows
+// skewed by one element per 16 against bank conflicts). Same two passes as
+// fft256_r16.
+template <typename T, int LG>
+__global__ __launch_bounds__(16 << LG) void k_c2c256_strided(Grid g, const cplx_t<T> *__restrict__ tw, int axis,
+                                                             cplx_t<T> *__restrict__ H, long h_stride, int sign) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG, kRow = L, kSkew = 1;
+    __shared__ C buf[256 * kRow + 16 * kSkew];
+    __shared__ C twl[256];
+    const int nh = g.n3h();
+    const int nb3 = (nh + L - 1) >> LG;
+    const int blk = xcd_local_block();
+    const int outer = blk / nb3, cb = blk - outer * nb3;
+    const int leff = min(L, nh - cb * L);
+    long base, stride;
+    if (axis == 1) {
+        base = (long)outer * g.n2 * nh + (long)cb * L;
+        stride = nh;
+    } else {
+        base = (long)outer * nh + (long)cb * L;
+        stride = (long)g.n2 * nh;
+    }
+    C *h = H + blockIdx.y * h_stride;
+    for (int m = threadIdx.x; m < 256; m += 16 << LG) twl[m] = tw[m];
+    const int l = threadIdx.x & (L - 1), j = threadIdx.x >> LG;
+    const bool live = l < leff;
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        v[r].x = T(0);
+        v[r].y = T(0);
+        if (live) v[r] = h[base + (long)(j + 16 * r) * stride + l];
+    }
+    dft16<T>(v, sign);
+    // row m = 16 j + r of the exchange buffer sits at m * kRow + (m >> 4) * kSkew
+#pragma unroll
+    for (int r = 0; r < 16; r++) buf[(16 * j + r) * kRow + j * kSkew + l] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = buf[(j + 16 * r) * kRow + r * kSkew + l];
+#pragma unroll
+    for (int r = 1; r < 16; r++) {
+        C w = twl[r * j];
+        if (sign > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+    dft16<T>(v, sign);
+    if (live) {
+#pragma unroll
+        for (int r = 0; r < 16; r++) h[base + (long)(j + 16 * r) * stride + l] = v[r];
     }
 }
 
@@ -663,6 +882,26 @@ static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipS
     const int nh = g.n3h();
     for (int k = 0; k < 2; k++) {
         const int axis = sign < 0 ? 1 - k : k;  // forward: x2 then x1; inverse: x1 then x2
+        if (c.plan[axis].n == 256) {
+            // 16 columns per workgroup in FP32, 8 in FP64 (32 KiB of LDS),
+            // fewer when the half spectrum is narrower
+            const int lg_max = sizeof(T) == 4 ? 4 : 3;
+            int lg = 2;
+            while (lg < lg_max && (1 << lg) < nh) lg++;
+            const int nb3 = (nh + (1 << lg) - 1) >> lg;
+            const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+            const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]);
+            if (lg == 2)
+                hipLaunchKernelGGL((k_c2c256_strided<T, 2>), dim3(nb, ncomp), dim3(64), 0, s, g, tw, axis, H, g.Nh(),
+                                   sign);
+            else if (lg == 3)
+                hipLaunchKernelGGL((k_c2c256_strided<T, 3>), dim3(nb, ncomp), dim3(128), 0, s, g, tw, axis, H, g.Nh(),
+                                   sign);
+            else
+                hipLaunchKernelGGL((k_c2c256_strided<T, sizeof(T) == 4 ? 4 : 3>), dim3(nb, ncomp),
+                                   dim3(sizeof(T) == 4 ? 256 : 128), 0, s, g, tw, axis, H, g.Nh(), sign);
+            continue;
+        }
         const int lg = pick_lg_lines<T>(c.plan[axis].n, nh, false);
         const int nb3 = (nh + (1 << lg) - 1) >> lg;
         const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
@@ -677,11 +916,20 @@ hipError_t spec_forward_to(const SpecCtx &c, const Tr *x, int ncomp, void *Hout,
     using C = cplx_t<T>;
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(Hout);
-    const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
-    const long L2 = 2L << lg;
-    const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
-    hipLaunchKernelGGL((k_r2c_x3<Tr, T>), dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(g.n3, lg, true), s, g,
-                       c.plan[2], reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), x, g.N(), H, g.Nh(), lg);
+    const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]);
+    if (g.n3 == 256) {
+        constexpr int LG = sizeof(T) == 4 ? 4 : 3;
+        const long L2 = 2L << LG;
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+        hipLaunchKernelGGL((k_r2c256_x3<Tr, T, LG>), dim3(nb, ncomp), dim3(16 << LG), 0, s, g, tw, x, g.N(), H,
+                           g.Nh());
+    } else {
+        const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
+        const long L2 = 2L << lg;
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+        hipLaunchKernelGGL((k_r2c_x3<Tr, T>), dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(g.n3, lg, true), s, g,
+                           c.plan[2], tw, x, g.N(), H, g.Nh(), lg);
+    }
     c2c_passes<T>(c, H, ncomp, -1, s);
     return hipGetLastError();
 }
@@ -697,12 +945,20 @@ hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hi
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(Hin);
     c2c_passes<T>(c, H, ncomp, +1, s);
+    const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]);
+    if (g.n3 == 256) {
+        constexpr int LG = sizeof(T) == 4 ? 4 : 3;
+        const long L2 = 2L << LG;
+        const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+        hipLaunchKernelGGL((k_c2r256_x3<T, Tr, LG>), dim3(nb, ncomp), dim3(16 << LG), 0, s, g, tw, H, g.Nh(), out,
+                           g.N(), T(1.0 / (double)g.N()));
+        return hipGetLastError();
+    }
     const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
     const long L2 = 2L << lg;
     const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
     hipLaunchKernelGGL((k_c2r_x3<T, Tr>), dim3(nb, ncomp), dim3(kThreads), tile_lds<T>(g.n3, lg, true), s, g,
-                       c.plan[2], reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]), H, g.Nh(), out, g.N(),
-                       T(1.0 / (double)g.N()), lg);
+                       c.plan[2], tw, H, g.Nh(), out, g.N(), T(1.0 / (double)g.N()), lg);
     return hipGetLastError();
 }
 

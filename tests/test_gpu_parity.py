@@ -19,6 +19,12 @@ CUBE = (32, 32, 32)
 # 256-point line transforms (the benchmark's length) along x1 and x2, and along x3
 WIDE = (256, 256, 8)
 LONG3 = (8, 16, 256)
+# 17 half-spectrum columns: the 256-point x1/x2 passes run two (FP32) or three
+# (FP64) column blocks per line, the last holding a single column
+WIDE17 = (256, 256, 32)
+# 108 line pairs along x3 = 256: the last x3 workgroup holds 12 of its 16 (FP32)
+# or 4 of its 8 (FP64) line pairs
+X3TAIL = (12, 18, 256)
 
 
 @pytest.fixture(scope="module")
@@ -180,7 +186,7 @@ def test_nyquist_derivative_is_zero(reg, prec):
 
 
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("shape", [RAGGED, CUBE, WIDE, LONG3])
+@pytest.mark.parametrize("shape", [RAGGED, CUBE, WIDE, WIDE17, LONG3, X3TAIL])
 def test_even_and_projection_operators(reg, prec, shape):
     from paper_1608_03630_amd import reg as R
 
