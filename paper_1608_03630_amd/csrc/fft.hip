@@ -1173,6 +1173,17 @@ template <typename T>
 __device__ __forceinline__ double2 ld2(const cplx_t<T> &z) {
     return make_double2((double)z.x, (double)z.y);
 }
+// streaming load (non-temporal: the Krylov passes read each value once)
+template <typename T>
+__device__ __forceinline__ double2 ld2nt(const cplx_t<T> *ptr) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 z = __builtin_nontemporal_load(reinterpret_cast<const v2 *>(ptr));
+    return make_double2((double)z.x, (double)z.y);
+}
+__device__ __forceinline__ double2 ldv_nt(const cplx_t<float> *ptr) { return ld2nt<float>(ptr); }
+__device__ __forceinline__ double2 ldv_nt(const double2 *ptr) {
+    return ld2nt<double>(reinterpret_cast<const cplx_t<double> *>(ptr));
+}
 template <typename T>
 __device__ __forceinline__ cplx_t<T> st2(double2 z) {
     cplx_t<T> o;
@@ -1225,14 +1236,14 @@ __global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const c
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
         const ModeInfo mi = mode_info(g, q);
         double2 qv[3], rv[3], zv[3];
-        for (int c = 0; c < 3; c++) qv[c] = ld2<T>(y[c * Nh + q]);
+        for (int c = 0; c < 3; c++) qv[c] = ld2nt<T>(y + c * Nh + q);
         if (leray) leray3(mi, qv);
         const double f = beta * mi.kk * mi.kk;
         for (int c = 0; c < 3; c++) {
-            const double2 pc = ld2<T>(p[c * Nh + q]);
+            const double2 pc = ld2nt<T>(p + c * Nh + q);
             qv[c].x = f * pc.x + qv[c].x;
             qv[c].y = f * pc.y + qv[c].y;
-            double2 sc = ld2<T>(s[c * Nh + q]), rc = ld2<T>(r[c * Nh + q]);
+            double2 sc = ld2nt<T>(s + c * Nh + q), rc = ld2nt<T>(r + c * Nh + q);
             sc.x += a * pc.x;
             sc.y += a * pc.y;
             rc.x -= a * qv[c].x;
@@ -1264,10 +1275,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const cplx_t
     if (q >= Nh) return;
     const ModeInfo mi = mode_info(g, q);
     double2 rv[3], zv[3];
-    for (int c = 0; c < 3; c++) rv[c] = ld2<T>(r[c * Nh + q]);
+    for (int c = 0; c < 3; c++) rv[c] = ld2nt<T>(r + c * Nh + q);
     precond3(mi, beta, leray, rv, zv);
     for (int c = 0; c < 3; c++) {
-        const double2 pc = ld2<T>(p[c * Nh + q]);
+        const double2 pc = ld2nt<T>(p + c * Nh + q);
         double2 o;
         o.x = zv[c].x + b * pc.x;
         o.y = zv[c].y + b * pc.y;
@@ -1301,15 +1312,12 @@ __global__ __launch_bounds__(kThreads) void k_vec_assemble_dot(Grid g, const X *
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
         const ModeInfo mi = mode_info(g, q);
         double2 v[3];
-        for (int c = 0; c < 3; c++) {
-            const cplx_t<T> zc = y[c * Nh + q];
-            v[c] = make_double2((double)zc.x, (double)zc.y);
-        }
+        for (int c = 0; c < 3; c++) v[c] = ld2nt<T>(y + c * Nh + q);
         if (leray) leray3(mi, v);
         const double f = a * mi.kk * mi.kk;
         double loc = 0.0;
         for (int c = 0; c < 3; c++) {
-            const double2 xc = make_double2((double)x[c * Nh + q].x, (double)x[c * Nh + q].y);
+            const double2 xc = ldv_nt(x + c * Nh + q);
             v[c].x = f * xc.x + v[c].x;
             v[c].y = f * xc.y + v[c].y;
             if (out) out[c * Nh + q] = v[c];

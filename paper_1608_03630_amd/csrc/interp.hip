@@ -248,11 +248,11 @@ __global__ __launch_bounds__(kThreads) void k_b_assemble(long N, int nt, const T
     T b1 = T(0), b2 = T(0), b3 = T(0);
     for (int k = 0; k <= nt; k++) {
         const T w = (k == 0 || k == nt) ? T(0.5) * dt : dt;
-        const T s = w * lam[(long)k * N + p];
+        const T s = w * __builtin_nontemporal_load(lam + (long)k * N + p);
         const T *gk = grad + (long)k * 3 * N;
-        b1 += s * gk[p];
-        b2 += s * gk[N + p];
-        b3 += s * gk[2 * N + p];
+        b1 += s * __builtin_nontemporal_load(gk + p);
+        b2 += s * __builtin_nontemporal_load(gk + N + p);
+        b3 += s * __builtin_nontemporal_load(gk + 2 * N + p);
     }
     b[p] = b1;
     b[N + p] = b2;
@@ -289,7 +289,9 @@ __global__ __launch_bounds__(kThreads) void k_incstate_init(long N, const T *__r
                                                             const T *__restrict__ grad, T *__restrict__ q, T cs) {
     const long p = (long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= N) return;
-    q[p] = cs * (vt[p] * grad[p] + vt[N + p] * grad[N + p] + vt[2 * N + p] * grad[2 * N + p]);
+    q[p] = cs * (__builtin_nontemporal_load(vt + p) * __builtin_nontemporal_load(grad + p) +
+                 __builtin_nontemporal_load(vt + N + p) * __builtin_nontemporal_load(grad + N + p) +
+                 __builtin_nontemporal_load(vt + 2 * N + p) * __builtin_nontemporal_load(grad + 2 * N + p));
 }
 
 // u^{n+1}_j = u^n_j(X) + h_j D_j for the three components
@@ -600,9 +602,9 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
         const int line = wave + kWaves * k;
         const int a1 = line >> 3, a2 = line & 7;  // kTile2 == 8
         const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
-        d[k][0] = D1[p];
-        d[k][1] = D2[p];
-        d[k][2] = D3[p];
+        d[k][0] = __builtin_nontemporal_load(D1 + p);
+        d[k][1] = __builtin_nontemporal_load(D2 + p);
+        d[k][2] = __builtin_nontemporal_load(D3 + p);
     }
     stage_box_canon<T, S>(g, tg, t, f, box);
     __syncthreads();
@@ -623,9 +625,11 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
         const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
         T e0 = T(1), sv = T(0);
         if (MODE == TM_ADJOINT) {
-            if (gam) e0 = gam[p];
+            if (gam) e0 = __builtin_nontemporal_load(gam + p);
         } else if (MODE == TM_INCSTATE) {
-            sv = vt1[p] * gr1[p] + vt2[p] * gr2[p] + vt3[p] * gr3[p];
+            sv = __builtin_nontemporal_load(vt1 + p) * __builtin_nontemporal_load(gr1 + p) +
+                 __builtin_nontemporal_load(vt2 + p) * __builtin_nontemporal_load(gr2 + p) +
+                 __builtin_nontemporal_load(vt3 + p) * __builtin_nontemporal_load(gr3 + p);
         }
         T w1[4], w2[4], w3[4];
         const int l1 = canon_base(a1, d[k][0], tg.lo[0], tg.B[0], w1);
