@@ -522,15 +522,24 @@ __global__ __launch_bounds__(kTileThreads) void k_tiled(Grid g, TileGeom tg, con
 // to k_tiled through the same grid via the `interior` test below).
 constexpr int kCanonMaxSpan = 4;  // largest canonical box: (7+S)(11+S)(67+S) floats, padded, <= 64 KB
 
-// Row pitch C3: a multiple of 32 floats where the box still fits 64 KB. LDS
-// has 32 four-byte banks; lanes of a half-wavefront read consecutive x3
-// positions, and where the floor of D1 or D2 changes between them, some read
-// the next row. With a pitch of 0 mod 32 those lanes keep distinct banks; with
-// kTile3 + 3 + S (4 + S mod 32) they collide with the lanes of the first row.
+// Row pitch C3. LDS has 32 four-byte banks; lanes of a half-wavefront read
+// consecutive x3 positions, and where the floor of D1 or D2 changes between
+// them, some read the next row. With a pitch of 0 mod 32 those lanes keep
+// distinct banks; with kTile3 + 3 + S (4 + S mod 32) they collide with the
+// lanes of the first row, and with 16 mod 32 only lanes 16 apart can. The
+// pitch is the multiple of 32, else of 16, else the natural one, whichever
+// first reaches the most workgroups per CU (160 KiB of LDS, at most four
+// 512-thread workgroups): 96 for span 1, 80 for spans 2 and 4.
+constexpr int kLdsPerCu = 160 * 1024;
 template <int S> struct Canon {
-    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S;
-    static constexpr int P3 = (kTile3 + 3 + S + 31) / 32 * 32;
-    static constexpr int C3 = C1 * C2 * P3 * 4 <= 65536 ? P3 : kTile3 + 3 + S;
+    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S, W = kTile3 + 3 + S;
+    static constexpr int P32 = (W + 31) / 32 * 32, P16 = (W + 15) / 16 * 16;
+    static constexpr int wg(int pitch) {
+        const int bytes = C1 * C2 * pitch * 4;
+        return bytes > 65536 ? 0 : (kLdsPerCu / bytes < 4 ? kLdsPerCu / bytes : 4);
+    }
+    static constexpr int best = wg(W) > wg(P16) ? wg(W) : wg(P16);
+    static constexpr int C3 = wg(P32) >= best ? P32 : wg(P16) >= best ? P16 : W;
     static constexpr int elems = C1 * C2 * C3;
 };
 
