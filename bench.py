@@ -47,6 +47,8 @@ def log(msg):
 METRIC_BETA_FINAL = 1e-6  # continuation floor of the time-to-mismatch run
 SCHEDULE_BETA_FINAL = 1e-4  # the 1e-1 -> 1e-4 schedule, reported beside it
 LEVEL_GTOL = 0.3  # gradient reduction of the continuation levels above the last
+PROFILE_EVERY = 13  # the timed solve brackets one launch in 13 of each family with HIP events (prime, so
+# the samples cycle through all nt = 16 steps of a transport)
 
 
 def solve_params(reg, shape, beta_final, gtol_level=LEVEL_GTOL):
@@ -360,7 +362,9 @@ def main():
             f"{rep['matvecs']} matvecs, mismatch {rep['final_mismatch']:.4f}")
 
     torch.cuda.synchronize()
-    ctx.reg_profile(True)
+    # HIP events around one launch in PROFILE_EVERY of each kernel family
+    # (an event pair leaves the GPU idle for a few microseconds)
+    ctx.reg_profile(True, every=PROFILE_EVERY)
     reports = []
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -447,7 +451,8 @@ def main():
         "pcg_iters": rep["pcg_iters"],
         "interp_gpts_s": gpts,
         "interp_gb_s": interp_gbs,
-        "kernel_ms": {k: {"launches": n_, "avg_ms": (t_ / n_ if n_ else None)} for k, (n_, t_) in prof.items()},
+        "kernel_ms": {k: {"timed_launches": n_, "avg_ms": (t_ / n_ if n_ else None)} for k, (n_, t_) in prof.items()},
+        "kernel_ms_sampling": f"HIP events around one launch in {PROFILE_EVERY} of each family",
         "roofline": {
             "kernel": dom,
             "bound": "hbm",
@@ -458,6 +463,7 @@ def main():
             "traffic": traffic,
             "bytes_per_point": bpp,
             "avg_launch_ms": avg_ms,
+            "timed_launches": launches,
         },
         "cpu_baseline": None,
     }

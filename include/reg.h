@@ -285,7 +285,8 @@ reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, in
 reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *graph_captures, int64_t *graph_replays);
 
 /* reg_profile / reg_profile_read over the batch: the batched launches and
- * graph replays plus every problem's own launches. */
+ * graph replays plus every problem's own launches (enable as in
+ * reg_profile). */
 reg_status reg_batch_profile(reg_batch *b, int enable);
 reg_status reg_batch_profile_read(reg_batch *b, int kind, int64_t *launches, double *ms);
 
@@ -387,13 +388,17 @@ typedef enum {
     REG_K_COUNT = 11
 } reg_kernel_kind;
 
-/* enable = 1 clears the counters and starts timing every kernel launch of
- * the context with a pair of HIP events on its stream; 0 stops. Timing adds
- * two event records per launch. */
+/* enable = k >= 1 clears the counters and starts timing launches of the
+ * context with a pair of HIP events on its stream: every launch for k = 1,
+ * else the first of every k launches of each kernel family. 0 stops; a
+ * negative value is REG_EINVAL. Each timed launch adds two event records,
+ * which leave the GPU idle for a few microseconds, so long runs sample
+ * (k = 16 adds well under 1% to a 256^3 solve). */
 reg_status reg_profile(reg_ctx *ctx, int enable);
 
-/* Launch count and summed GPU milliseconds of one kernel family since
- * profiling was enabled (synchronises the stream). */
+/* Number of timed launches and their summed GPU milliseconds for one
+ * kernel family since profiling was enabled (synchronises the stream); the
+ * average launch time is ms / launches. */
 reg_status reg_profile_read(reg_ctx *ctx, int kind, int64_t *launches, double *ms);
 
 #ifdef __cplusplus

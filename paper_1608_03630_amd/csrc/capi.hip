@@ -360,9 +360,13 @@ reg_status reg_dot(reg_ctx *ctx, int ncomp, const void *a, const void *b, double
 
 reg_status reg_profile(reg_ctx *ctx, int enable) {
     CTX_OK(ctx);
+    if (enable < 0) return fail(ctx, REG_EINVAL, "reg_profile: enable must be >= 0");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->prof.resolve();
-    if (enable) ctx->prof.reset();
+    if (enable) {
+        ctx->prof.reset();
+        ctx->prof.every = enable;
+    }
     ctx->prof.on = enable != 0;
     return REG_OK;
 }

@@ -60,11 +60,13 @@ struct Layout {
 // per-kind totals after the stream has been synchronised.
 struct Profiler {
     struct Rec {
-        hipEvent_t a, b;
+        hipEvent_t a, b, pre;
         int kind;
     };
     hipStream_t stream = nullptr;
     bool on = false;
+    int every = 1;                  // time one launch in `every` of each kind
+    int64_t seen[REG_K_COUNT] = {0};  // launches of each kind since enabled
     std::vector<hipEvent_t> free_;
     std::vector<Rec> pending;
     double ms[REG_K_COUNT] = {0};
@@ -81,6 +83,7 @@ struct Profiler {
             }
             free_.push_back(r.a);
             free_.push_back(r.b);
+            if (r.pre) free_.push_back(r.pre);
         }
         pending.clear();
     }
@@ -104,6 +107,7 @@ struct Profiler {
         for (int k = 0; k < REG_K_COUNT; k++) {
             ms[k] = 0;
             n[k] = 0;
+            seen[k] = 0;
         }
     }
     void release() {
@@ -180,24 +184,38 @@ inline reg_status hipfail(reg_ctx *ctx, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hipfail((ctx), e_, #expr);  \
     } while (0)
 
-// Runs one launcher; with profiling on, brackets it with two events.
+// Runs one launcher; with profiling on, brackets every `every`-th launch of
+// each kind with two events (an event pair costs a few microseconds of idle
+// GPU between launches, so a long run samples). When sampling, a third event
+// goes first: the first event after a kernel absorbs the wait for that
+// kernel, and without it the sampled times ran 5% long.
 template <class F>
 hipError_t timed(Profiler &pr, int kind, F &&launch) {
-    if (!pr.on) return launch();
+    if (!pr.on || pr.seen[kind]++ % pr.every != 0) return launch();
     if (pr.pending.size() >= 8192) {
         hipError_t e = hipStreamSynchronize(pr.stream);
         if (e != hipSuccess) return e;
         pr.resolve();
     }
     hipEvent_t a = pr.take(), b = pr.take();
-    if (!a || !b) return launch();
-    hipError_t e = hipEventRecord(a, pr.stream);
+    hipEvent_t pre = pr.every > 1 ? pr.take() : nullptr;
+    if (!a || !b || (pr.every > 1 && !pre)) {
+        for (hipEvent_t x : {a, b, pre})
+            if (x) pr.free_.push_back(x);
+        return launch();
+    }
+    hipError_t e = hipSuccess;
+    if (pre) {
+        e = hipEventRecord(pre, pr.stream);
+        if (e != hipSuccess) return e;
+    }
+    e = hipEventRecord(a, pr.stream);
     if (e != hipSuccess) return e;
     e = launch();
     if (e != hipSuccess) return e;
     e = hipEventRecord(b, pr.stream);
     if (e != hipSuccess) return e;
-    pr.pending.push_back({a, b, kind});
+    pr.pending.push_back({a, b, pre, kind});
     return hipSuccess;
 }
 

@@ -1229,9 +1229,13 @@ reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *gra
 
 reg_status reg_batch_profile(reg_batch *b, int enable) {
     BATCH_OK(b);
+    if (enable < 0) return bfail(b, REG_EINVAL, "reg_batch_profile: enable must be >= 0");
     if (hipStreamSynchronize(b->stream) != hipSuccess) return bfail(b, REG_EHIP, "hipStreamSynchronize failed");
     b->prof.resolve();
-    if (enable) b->prof.reset();
+    if (enable) {
+        b->prof.reset();
+        b->prof.every = enable;
+    }
     b->prof.on = enable != 0;
     for (auto *c : b->ctx) STCHK(reg_profile(c, enable));
     return REG_OK;

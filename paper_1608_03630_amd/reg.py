@@ -377,8 +377,10 @@ class Context:
              self.handle, "reg_dot")
         return out.value
 
-    def reg_profile(self, enable=True):
-        _chk(lib().reg_profile(self.handle, int(bool(enable))), self.handle, "reg_profile")
+    def reg_profile(self, enable=True, every=1):
+        """Start (enable) or stop timing launches; every=k times one launch in
+        k of each kernel family."""
+        _chk(lib().reg_profile(self.handle, int(every) if enable else 0), self.handle, "reg_profile")
 
     def reg_profile_read(self):
         """{kind: (launches, gpu_ms)} for every kernel family."""
@@ -481,8 +483,8 @@ class Batch:
               "reg_batch_stats")
         return {"batched_launches": a.value, "graph_captures": b.value, "graph_replays": c.value}
 
-    def reg_batch_profile(self, enable=True):
-        _bchk(lib().reg_batch_profile(self.handle, int(bool(enable))), self.handle, "reg_batch_profile")
+    def reg_batch_profile(self, enable=True, every=1):
+        _bchk(lib().reg_batch_profile(self.handle, int(every) if enable else 0), self.handle, "reg_batch_profile")
 
     def reg_batch_profile_read(self):
         out = {}

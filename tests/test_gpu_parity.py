@@ -395,6 +395,26 @@ def test_line_search_failure_keeps_velocity(reg):
     assert torch.equal(v, v0)
 
 
+def test_profile_sampling_counts_launches(reg):
+    """reg_profile(k) times the first of every k launches of each kernel
+    family: an nt-step transport makes nt adjoint-step launches."""
+    shape = (16, 16, 64)
+    nt = 6
+    ctx = make_ctx(reg, shape, 0, nt=nt, isochoric=1)
+    v = to_vel(synth.smooth_velocity_divfree(shape), ctx)
+    lam1 = to_dev(synth.smooth_random_field(shape, 110, kmax=4), ctx)
+    for every, timed in ((1, nt), (4, 2), (16, 1)):
+        ctx.reg_profile(True, every=every)
+        ctx.reg_transport_adjoint(v, lam1)
+        n, ms = ctx.reg_profile_read()["adjoint"]
+        ctx.reg_profile(False)
+        say(f"  every={every}: {n} timed adjoint launches, {ms:.3f} ms")
+        assert n == timed and ms > 0
+    with pytest.raises(reg.RegError) as e:
+        ctx.reg_profile(True, every=-1)
+    assert e.value.status == reg.REG_EINVAL
+
+
 def test_repeatable_bitwise(reg):
     """Gathers write each point once and reductions use a fixed order, so two
     identical calls agree bit for bit."""
