@@ -643,6 +643,150 @@ __global__ __launch_bounds__(kThreads) void k_c2c_strided(Grid g, FftPlan pl, co
     }
 }
 
+// Spectral derivative of 256-point lines in registers: the thread that ends
+// the forward transform with X[j + 16 r] (r = 0..15) multiplies by the
+// symbol i k~ / n and starts the inverse transform with exactly those
+// values, so forward and inverse need one LDS exchange each.
+template <typename T>
+__device__ __forceinline__ void deriv256_symbol(cplx_t<T> v[16], int j) {
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        const T f = T(kwave_odd(j + 16 * r, 256)) * T(1.0 / 256.0);
+        const T x = v[r].x;
+        v[r].x = -f * v[r].y;
+        v[r].y = f * x;
+    }
+}
+
+// Along x3 (n3 = 256): 2^LG line pairs per workgroup, 16 threads per pair,
+// the real lines r0 + 2 l and r0 + 2 l + 1 packed as one complex line (the
+// derivative is real, so it acts on both parts separately).
+template <typename T, int LG>
+__global__ __launch_bounds__(16 << LG) void k_deriv256_x3(Grid g, const cplx_t<T> *__restrict__ tw,
+                                                          const T *__restrict__ u, long in_stride,
+                                                          T *__restrict__ out, long out_stride, int accumulate) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG, n = 256;
+    __shared__ C buf[L * kX3Pitch];
+    __shared__ C twl[256];
+    const long nlines = (long)g.n1 * g.n2;
+    const long r0 = (long)blockIdx.x * 2 * L;
+    const int leff = (int)min((long)L, (nlines - r0) / 2);
+    for (int m = threadIdx.x; m < n; m += 16 << LG) twl[m] = tw[m];
+    const int j = threadIdx.x & 15, l = threadIdx.x >> 4;
+    const bool live = l < leff;
+    const T *sa = u + blockIdx.y * in_stride + (r0 + 2 * l) * n;
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        v[r].x = T(0);
+        v[r].y = T(0);
+        if (live) {
+            v[r].x = sa[j + 16 * r];
+            v[r].y = sa[n + j + 16 * r];
+        }
+    }
+    C *line_buf = buf + l * kX3Pitch;
+    dft16<T>(v, -1);
+    x3_second_pass<T>(v, line_buf, j, twl, -1);
+    deriv256_symbol<T>(v, j);
+    dft16<T>(v, +1);
+    __syncthreads();  // every thread has read the forward exchange
+    x3_second_pass<T>(v, line_buf, j, twl, +1);
+    if (live) {
+        T *oa = out + blockIdx.y * out_stride + (r0 + 2 * l) * n;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            T *pa = oa + j + 16 * r, *pb = pa + n;
+            if (accumulate) {
+                *pa += v[r].x;
+                *pb += v[r].y;
+            } else {
+                *pa = v[r].x;
+                *pb = v[r].y;
+            }
+        }
+    }
+}
+
+// Exchange and second radix-16 pass of a 256-point column transform with
+// 2^LG columns per workgroup (rows skewed by one element per 16 in LDS);
+// v holds DFT16(a[j + 16 r]) on entry and X[j + 16 r] on return.
+template <typename T, int LG>
+__device__ __forceinline__ void col_second_pass(cplx_t<T> v[16], cplx_t<T> *buf, int j, int l,
+                                                const cplx_t<T> *twl, int sign) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG;
+#pragma unroll
+    for (int r = 0; r < 16; r++) buf[(16 * j + r) * L + j + l] = v[r];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = buf[(j + 16 * r) * L + r + l];
+#pragma unroll
+    for (int r = 1; r < 16; r++) {
+        C w = twl[r * j];
+        if (sign > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+    }
+    dft16<T>(v, sign);
+}
+
+// Along x1 or x2 (that axis 256 long) of real fields: 2^LG complex columns
+// per workgroup, each the pair of adjacent x3 columns (2 c, 2 c + 1).
+template <typename T, int LG>
+__global__ __launch_bounds__(16 << LG) void k_deriv256_strided(Grid g, const cplx_t<T> *__restrict__ tw, int axis,
+                                                               const T *__restrict__ u, long in_stride,
+                                                               T *__restrict__ out, long out_stride, int accumulate) {
+    using C = cplx_t<T>;
+    constexpr int L = 1 << LG;
+    __shared__ C buf[256 * L + 16];
+    __shared__ C twl[256];
+    const int ncol = g.n3 / 2;
+    const int nb3 = (ncol + L - 1) >> LG;
+    const int blk = xcd_local_block();
+    const int outer = blk / nb3, cb = blk - outer * nb3;
+    const int leff = min(L, ncol - cb * L);
+    long base, stride;
+    if (axis == 1) {
+        base = (long)outer * g.n2 * g.n3 + 2L * cb * L;
+        stride = g.n3;
+    } else {
+        base = (long)outer * g.n3 + 2L * cb * L;
+        stride = (long)g.n2 * g.n3;
+    }
+    for (int m = threadIdx.x; m < 256; m += 16 << LG) twl[m] = tw[m];
+    const int l = threadIdx.x & (L - 1), j = threadIdx.x >> LG;
+    const bool live = l < leff;
+    const T *src = u + blockIdx.y * in_stride + base + 2 * l;
+    C v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+        v[r].x = T(0);
+        v[r].y = T(0);
+        if (live) v[r] = *reinterpret_cast<const C *>(src + (long)(j + 16 * r) * stride);
+    }
+    dft16<T>(v, -1);
+    col_second_pass<T, LG>(v, buf, j, l, twl, -1);
+    deriv256_symbol<T>(v, j);
+    dft16<T>(v, +1);
+    __syncthreads();  // every thread has read the forward exchange
+    col_second_pass<T, LG>(v, buf, j, l, twl, +1);
+    if (live) {
+        T *dst = out + blockIdx.y * out_stride + base + 2 * l;
+#pragma unroll
+        for (int r = 0; r < 16; r++) {
+            C *p = reinterpret_cast<C *>(dst + (long)(j + 16 * r) * stride);
+            C z = v[r];
+            if (accumulate) {
+                const C o = *p;
+                z.x += o.x;
+                z.y += o.y;
+            }
+            *p = z;
+        }
+    }
+}
+
 // In-place 256-point complex FFT of the half spectrum along axis 0 or 1,
 // 2^LG columns per workgroup and 16 threads per column. Each thread keeps 16
 // elements of its column in registers: the first radix-16 pass reads them
@@ -858,6 +1002,32 @@ hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T 
     const Grid &g = c.g;
     const FftPlan &pl = c.plan[axis];
     const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]);
+    if (pl.n == 256) {
+        constexpr int lg_max = sizeof(T) == 4 ? 4 : 3;
+        if (axis == 2) {
+            const long L2 = 2L << lg_max;
+            const unsigned nb = (unsigned)(((long)g.n1 * g.n2 + L2 - 1) / L2);
+            hipLaunchKernelGGL((k_deriv256_x3<T, lg_max>), dim3(nb, ncomp), dim3(16 << lg_max), 0, s, g, tw, u,
+                               in_stride, out, out_stride, accumulate);
+            return hipGetLastError();
+        }
+        // columns per workgroup: 16 in FP32 (8 in FP64), fewer for narrow x3
+        const int ncol = g.n3 / 2;
+        int lg = 2;
+        while (lg < lg_max && (1 << lg) < ncol) lg++;
+        const int nb3 = (ncol + (1 << lg) - 1) >> lg;
+        const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
+        if (lg == 2)
+            hipLaunchKernelGGL((k_deriv256_strided<T, 2>), dim3(nb, ncomp), dim3(64), 0, s, g, tw, axis, u, in_stride,
+                               out, out_stride, accumulate);
+        else if (lg == 3)
+            hipLaunchKernelGGL((k_deriv256_strided<T, 3>), dim3(nb, ncomp), dim3(128), 0, s, g, tw, axis, u,
+                               in_stride, out, out_stride, accumulate);
+        else
+            hipLaunchKernelGGL((k_deriv256_strided<T, lg_max>), dim3(nb, ncomp), dim3(16 << lg_max), 0, s, g, tw,
+                               axis, u, in_stride, out, out_stride, accumulate);
+        return hipGetLastError();
+    }
     if (axis == 2) {
         const int lg = pick_lg_lines<T>(g.n3, (int)(((long)g.n1 * g.n2) / 2), true);
         const long L2 = 2L << lg;

@@ -154,7 +154,7 @@ def test_backtrace(reg, prec, sign):
 
 # ---------------------------------------------------------------- spectral
 @pytest.mark.parametrize("prec", [1, 0])
-@pytest.mark.parametrize("shape", [RAGGED, CUBE, WIDE, LONG3])
+@pytest.mark.parametrize("shape", [RAGGED, CUBE, WIDE, WIDE17, LONG3, X3TAIL])
 def test_derivatives(reg, prec, shape):
     ctx = make_ctx(reg, shape, prec)
     u = rounded(synth.smooth_random_field(shape, 105, kmax=6), prec)
