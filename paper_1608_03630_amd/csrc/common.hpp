@@ -145,8 +145,11 @@ hipError_t spec_resample(const SpecCtx &src, const SpecCtx &dst, int ncomp, hipS
 // the same with explicit spectral buffers (the inverse overwrites Hin)
 template <typename Tr, typename T>
 hipError_t spec_forward_to(const SpecCtx &c, const Tr *x, int ncomp, void *Hout, hipStream_t s);
+// src (nullptr: Hin) is read by the first pass, so that a spectrum held
+// elsewhere is transformed without a copy into Hin
 template <typename T, typename Tr>
-hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s);
+hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s,
+                             const void *src = nullptr);
 
 // Spectral velocity vectors: [3][Nh] complex double (Nh = n1 n2 (n3/2+1)),
 // the unnormalised forward transforms of real fields.
@@ -166,22 +169,20 @@ hipError_t vec_symbol(const SpecCtx &c, int op, const double *x, const void *y, 
 // over the half spectrum, nblocks blocks). The PCG vectors s, r, p are stored
 // as complex T ([3][Nh]: double with double fields, float with float
 // fields); updates are computed in double and rounded when stored. The
-// direction p of the next Hessian matvec is also written into the transform
-// buffer H (complex T), so that the matvec starts with its inverse transform;
-// z = M r is never stored.
-// s = 0, r = -g, p = M r (and H = p); partials of <r, M r>
+// Hessian matvec of a direction p starts with the inverse transform of p
+// read in place (spec_inverse_from with src = p); z = M r is never stored.
+// s = 0, r = -g, p = M r; partials of <r, M r>
 template <typename T>
-hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p, void *H,
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p,
                      double *part_rz, int nblocks, hipStream_t st);
 // with q = beta |k|^4 p + [P] y (y: the transformed b~ in H): s += a p,
 // r -= a q; partials of <r, r> and <r, M r>
 template <typename T>
 hipError_t pcg_step(const SpecCtx &c, double a, const void *p, const void *y, double beta, int leray, void *s, void *r,
                     double *part_rr, double *part_rz, int nblocks, hipStream_t st);
-// p = M r + b p (and H = p)
+// p = M r + b p
 template <typename T>
-hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, void *H,
-                         hipStream_t st);
+hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, hipStream_t st);
 // partials of <p, beta |k|^4 p + [P] y> for a Krylov vector p
 template <typename T>
 hipError_t krylov_curvature(const SpecCtx &c, const void *p, const void *y, double beta, int leray, double *part,

@@ -519,10 +519,11 @@ reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
     return REG_OK;
 }
 
-// the same from a vector already loaded into the transform buffer
+// the same from a Krylov vector (complex T, the layout of the transform
+// buffer), read by the first inverse pass
 template <typename T>
-reg_status field_from_buffer(reg_ctx *ctx, void *out) {
-    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream))));
+reg_status field_from_krylov(reg_ctx *ctx, const void *p, void *out) {
+    HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream, p))));
     return REG_OK;
 }
 
@@ -547,12 +548,12 @@ reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat
 // The PCG vectors shat, rhat, phat hold complex T values during a solve
 // (see regk::pcg_start).
 
-// PCG set-up of a Newton step (s = 0, r = -g, p = M r, the transform buffer
-// loaded with p) with dres[slot] = <r, M r>
+// PCG set-up of a Newton step (s = 0, r = -g, p = M r) with
+// dres[slot] = <r, M r>
 template <typename T>
 reg_status pcg_start(reg_ctx *ctx, int slot) {
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_start<T>(ctx->spec, CV<double>(ctx->ghat), ctx->beta, ctx->P.isochoric,
-                                                         ctx->shat, ctx->rhat, ctx->phat, ctx->H, ctx->dpart,
+                                                         ctx->shat, ctx->rhat, ctx->phat, ctx->dpart,
                                                          regk::RED_BLOCKS, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
                                                             ctx->dres + slot, ctx->stream)));
@@ -573,11 +574,11 @@ reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
     return REG_OK;
 }
 
-// next PCG direction p = M r + b p, loaded into the transform buffer
+// next PCG direction p = M r + b p
 template <typename T>
 reg_status pcg_direction(reg_ctx *ctx, double b) {
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_direction<T>(ctx->spec, ctx->rhat, b, ctx->beta, ctx->P.isochoric,
-                                                             ctx->phat, ctx->H, ctx->stream)));
+                                                             ctx->phat, ctx->stream)));
     return REG_OK;
 }
 

@@ -787,8 +787,8 @@ __global__ __launch_bounds__(16 << LG) void k_deriv256_strided(Grid g, const cpl
     }
 }
 
-// In-place 256-point complex FFT of the half spectrum along axis 0 or 1,
-// 2^LG columns per workgroup and 16 threads per column. Each thread keeps 16
+// 256-point complex FFT of the half spectrum along axis 0 or 1 (in place, or
+// from src into H), 2^LG columns per workgroup and 16 threads per column. Each thread keeps 16
 // elements of its column in registers: the first radix-16 pass reads them
 // straight from HBM (rows j + 16 r), the second writes them straight back, and
 // only the exchange between the passes goes through LDS (one buffer, rows
@@ -796,7 +796,8 @@ __global__ __launch_bounds__(16 << LG) void k_deriv256_strided(Grid g, const cpl
 // fft256_r16.
 template <typename T, int LG>
 __global__ __launch_bounds__(16 << LG) void k_c2c256_strided(Grid g, const cplx_t<T> *__restrict__ tw, int axis,
-                                                             cplx_t<T> *__restrict__ H, long h_stride, int sign) {
+                                                             const cplx_t<T> *src, cplx_t<T> *H, long h_stride,
+                                                             int sign) {
     using C = cplx_t<T>;
     constexpr int L = 1 << LG, kRow = L, kSkew = 1;
     __shared__ C buf[256 * kRow + 16 * kSkew];
@@ -815,6 +816,7 @@ __global__ __launch_bounds__(16 << LG) void k_c2c256_strided(Grid g, const cplx_
         stride = (long)g.n2 * nh;
     }
     C *h = H + blockIdx.y * h_stride;
+    const C *hs = src + blockIdx.y * h_stride;  // == h in place
     for (int m = threadIdx.x; m < 256; m += 16 << LG) twl[m] = tw[m];
     const int l = threadIdx.x & (L - 1), j = threadIdx.x >> LG;
     const bool live = l < leff;
@@ -823,7 +825,7 @@ __global__ __launch_bounds__(16 << LG) void k_c2c256_strided(Grid g, const cplx_
     for (int r = 0; r < 16; r++) {
         v[r].x = T(0);
         v[r].y = T(0);
-        if (live) v[r] = h[base + (long)(j + 16 * r) * stride + l];
+        if (live) v[r] = hs[base + (long)(j + 16 * r) * stride + l];
     }
     dft16<T>(v, sign);
     // row m = 16 j + r of the exchange buffer sits at m * kRow + (m >> 4) * kSkew
@@ -1046,12 +1048,28 @@ hipError_t spec_deriv(const SpecCtx &c, int axis, const T *u, long in_stride, T 
 }
 
 template <typename T>
-static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipStream_t s) {
+__global__ __launch_bounds__(kThreads) void k_cplx_copy(long n, const cplx_t<T> *__restrict__ a,
+                                                        cplx_t<T> *__restrict__ b) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e < n) b[e] = a[e];
+}
+
+// the first pass reads src0 (nullptr: H itself)
+template <typename T>
+static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipStream_t s,
+                       const cplx_t<T> *src0 = nullptr) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
     const int nh = g.n3h();
     for (int k = 0; k < 2; k++) {
         const int axis = sign < 0 ? 1 - k : k;  // forward: x2 then x1; inverse: x1 then x2
+        const C *src = (k == 0 && src0) ? src0 : H;
+        if (src != H && c.plan[axis].n != 256) {
+            const long n = (long)ncomp * g.Nh();
+            hipLaunchKernelGGL(k_cplx_copy<T>, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, n,
+                               src, H);
+            src = H;
+        }
         if (c.plan[axis].n == 256) {
             // 16 columns per workgroup in FP32, 8 in FP64 (32 KiB of LDS),
             // fewer when the half spectrum is narrower
@@ -1062,14 +1080,14 @@ static void c2c_passes(const SpecCtx &c, cplx_t<T> *H, int ncomp, int sign, hipS
             const unsigned nb = (unsigned)((axis == 1 ? g.n1 : g.n2) * nb3);
             const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][axis]);
             if (lg == 2)
-                hipLaunchKernelGGL((k_c2c256_strided<T, 2>), dim3(nb, ncomp), dim3(64), 0, s, g, tw, axis, H, g.Nh(),
-                                   sign);
+                hipLaunchKernelGGL((k_c2c256_strided<T, 2>), dim3(nb, ncomp), dim3(64), 0, s, g, tw, axis, src, H,
+                                   g.Nh(), sign);
             else if (lg == 3)
-                hipLaunchKernelGGL((k_c2c256_strided<T, 3>), dim3(nb, ncomp), dim3(128), 0, s, g, tw, axis, H, g.Nh(),
-                                   sign);
+                hipLaunchKernelGGL((k_c2c256_strided<T, 3>), dim3(nb, ncomp), dim3(128), 0, s, g, tw, axis, src, H,
+                                   g.Nh(), sign);
             else
                 hipLaunchKernelGGL((k_c2c256_strided<T, sizeof(T) == 4 ? 4 : 3>), dim3(nb, ncomp),
-                                   dim3(sizeof(T) == 4 ? 256 : 128), 0, s, g, tw, axis, H, g.Nh(), sign);
+                                   dim3(sizeof(T) == 4 ? 256 : 128), 0, s, g, tw, axis, src, H, g.Nh(), sign);
             continue;
         }
         const int lg = pick_lg_lines<T>(c.plan[axis].n, nh, false);
@@ -1110,11 +1128,11 @@ hipError_t spec_forward(const SpecCtx &c, const Tr *x, int ncomp, int h0, hipStr
 }
 
 template <typename T, typename Tr>
-hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s) {
+hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hipStream_t s, const void *src) {
     using C = cplx_t<T>;
     const Grid &g = c.g;
     C *H = reinterpret_cast<C *>(Hin);
-    c2c_passes<T>(c, H, ncomp, +1, s);
+    c2c_passes<T>(c, H, ncomp, +1, s, reinterpret_cast<const C *>(src));
     const C *tw = reinterpret_cast<const C *>(c.tw[tw_index<T>()][2]);
     if (g.n3 == 256) {
         constexpr int LG = sizeof(T) == 4 ? 4 : 3;
@@ -1134,7 +1152,7 @@ hipError_t spec_inverse_from(const SpecCtx &c, void *Hin, Tr *out, int ncomp, hi
 
 template <typename T, typename Tr>
 hipError_t spec_inverse(const SpecCtx &c, Tr *out, int ncomp, hipStream_t s) {
-    return spec_inverse_from<T, Tr>(c, c.H, out, ncomp, s);
+    return spec_inverse_from<T, Tr>(c, c.H, out, ncomp, s, nullptr);
 }
 
 template <typename T>
@@ -1367,8 +1385,7 @@ __device__ __forceinline__ cplx_t<T> st2(double2 z) {
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *__restrict__ gv, double beta, int leray,
                                                         cplx_t<T> *__restrict__ s, cplx_t<T> *__restrict__ r,
-                                                        cplx_t<T> *__restrict__ p, cplx_t<T> *__restrict__ H,
-                                                        double *__restrict__ part_rz) {
+                                                        cplx_t<T> *__restrict__ p, double *__restrict__ part_rz) {
     const long Nh = g.Nh();
     double rz = 0.0, dummy = 0.0;
     for (long q = (long)blockIdx.x * kThreads + threadIdx.x; q < Nh; q += (long)gridDim.x * kThreads) {
@@ -1383,9 +1400,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start(Grid g, const double2 *_
         for (int c = 0; c < 3; c++) {
             s[c * Nh + q] = st2<T>(make_double2(0.0, 0.0));
             r[c * Nh + q] = st2<T>(rv[c]);
-            const cplx_t<T> pz = st2<T>(zv[c]);
-            p[c * Nh + q] = pz;
-            H[c * Nh + q] = pz;
+            p[c * Nh + q] = st2<T>(zv[c]);
             acc += rv[c].x * zv[c].x + rv[c].y * zv[c].y;
         }
         rz += mi.w * acc;
@@ -1435,11 +1450,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_step(Grid g, double a, const c
     block_sum2(rr, rz, part_rr, part_rz);
 }
 
-// next direction p = M r + b p, also into H
+// next direction p = M r + b p
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const cplx_t<T> *__restrict__ r, double b,
-                                                            double beta, int leray, cplx_t<T> *__restrict__ p,
-                                                            cplx_t<T> *__restrict__ H) {
+                                                            double beta, int leray, cplx_t<T> *__restrict__ p) {
     const long Nh = g.Nh();
     const long q = (long)blockIdx.x * kThreads + threadIdx.x;
     if (q >= Nh) return;
@@ -1452,9 +1466,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_direction(Grid g, const cplx_t
         double2 o;
         o.x = zv[c].x + b * pc.x;
         o.y = zv[c].y + b * pc.y;
-        const cplx_t<T> ps = st2<T>(o);
-        p[c * Nh + q] = ps;
-        H[c * Nh + q] = ps;
+        p[c * Nh + q] = st2<T>(o);
     }
 }
 
@@ -1586,12 +1598,12 @@ hipError_t krylov_axpy(const SpecCtx &c, const double *x, double a, const void *
 }
 
 template <typename T>
-hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p, void *H,
+hipError_t pcg_start(const SpecCtx &c, const double *g, double beta, int leray, void *s, void *r, void *p,
                      double *part_rz, int nblocks, hipStream_t st) {
     using C = cplx_t<T>;
     hipLaunchKernelGGL(k_pcg_start<T>, dim3(nblocks), dim3(kThreads), 0, st, c.g,
                        reinterpret_cast<const double2 *>(g), beta, leray, reinterpret_cast<C *>(s),
-                       reinterpret_cast<C *>(r), reinterpret_cast<C *>(p), reinterpret_cast<C *>(H), part_rz);
+                       reinterpret_cast<C *>(r), reinterpret_cast<C *>(p), part_rz);
     return hipGetLastError();
 }
 
@@ -1606,12 +1618,11 @@ hipError_t pcg_step(const SpecCtx &c, double a, const void *p, const void *y, do
 }
 
 template <typename T>
-hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, void *H,
-                         hipStream_t st) {
+hipError_t pcg_direction(const SpecCtx &c, const void *r, double b, double beta, int leray, void *p, hipStream_t st) {
     using C = cplx_t<T>;
     const unsigned nb = (unsigned)((c.g.Nh() + kThreads - 1) / kThreads);
     hipLaunchKernelGGL(k_pcg_direction<T>, dim3(nb), dim3(kThreads), 0, st, c.g, reinterpret_cast<const C *>(r), b,
-                       beta, leray, reinterpret_cast<C *>(p), reinterpret_cast<C *>(H));
+                       beta, leray, reinterpret_cast<C *>(p));
     return hipGetLastError();
 }
 
@@ -1640,16 +1651,15 @@ hipError_t krylov_curvature(const SpecCtx &c, const void *p, const void *y, doub
     template hipError_t spec_inverse<T, T>(const SpecCtx &, T *, int, hipStream_t);                                \
     template hipError_t spec_symbol<T>(const SpecCtx &, int, double, int, int, hipStream_t);                       \
     template hipError_t spec_forward_to<T, T>(const SpecCtx &, const T *, int, void *, hipStream_t);              \
-    template hipError_t spec_inverse_from<T, T>(const SpecCtx &, void *, T *, int, hipStream_t);                  \
+    template hipError_t spec_inverse_from<T, T>(const SpecCtx &, void *, T *, int, hipStream_t, const void *);    \
     template hipError_t vec_load<T>(const SpecCtx &, const double *, void *, hipStream_t);                         \
     template hipError_t vec_assemble_dot<T>(const SpecCtx &, const double *, const void *, double, int, int,        \
                                             double *, double *, int, hipStream_t);                                  \
-    template hipError_t pcg_start<T>(const SpecCtx &, const double *, double, int, void *, void *, void *, void *, \
+    template hipError_t pcg_start<T>(const SpecCtx &, const double *, double, int, void *, void *, void *,        \
                                      double *, int, hipStream_t);                                                   \
     template hipError_t pcg_step<T>(const SpecCtx &, double, const void *, const void *, double, int, void *,      \
                                     void *, double *, double *, int, hipStream_t);                                  \
-    template hipError_t pcg_direction<T>(const SpecCtx &, const void *, double, double, int, void *, void *,       \
-                                         hipStream_t);                                                              \
+    template hipError_t pcg_direction<T>(const SpecCtx &, const void *, double, double, int, void *, hipStream_t); \
     template hipError_t krylov_curvature<T>(const SpecCtx &, const void *, const void *, double, int, double *,     \
                                             int, hipStream_t);                                                      \
     template hipError_t krylov_dot_partials<T>(const SpecCtx &, const double *, const void *, double *, int,       \

@@ -40,7 +40,7 @@ struct Request {
     const void *aux = nullptr;  // rho0 (FORWARD)
     bool reuse = false;         // GRADIENT: histB and Dt already hold the plan and state of x
     bool dot = false;           // MATVEC: <vt, Hvt> into result slot 0
-    bool pre = false;           // MATVEC: vt is already in the transform buffer (rounded to the field type)
+    bool pre = false;           // MATVEC: x is a Krylov vector (complex field type), transformed in place
 };
 
 struct Item {
@@ -383,7 +383,7 @@ struct Exec {
                 const double dt = 1.0 / ctx->P.nt;
                 P.ops.push_back([ctx, r, N, dt]() -> reg_status {
                     (void)N;
-                    if (r.pre) STCHK(field_from_buffer<T>(ctx, ctx->vtf));
+                    if (r.pre) STCHK(field_from_krylov<T>(ctx, r.x, ctx->vtf));
                     else STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho),
                                                                                     V<T>(ctx->lam[1]), -0.5 * dt, ctx->stream)));
@@ -768,7 +768,7 @@ struct Solver {
                 rz = ctx->hres[0];
                 i = 0;
                 iters = 0;
-                // p is in the transform buffer; only the curvature <p, H p> comes back
+                // the matvec reads p in place; only the curvature <p, H p> comes back
                 req = Request{Op::MATVEC, ctx->phat, nullptr, nullptr, false, true, true};
                 st = S_MATVEC_DONE;
                 return REG_OK;
