@@ -174,7 +174,6 @@ def run_batch(reg, torch, args):
         t = time.perf_counter()
         _, reps = b.reg_batch_solve(vs)
         log(f"[bench] warmup batch solve {w}: {time.perf_counter() - t:.3f} s")
-    b.reg_batch_profile(True)
     st0 = b.reg_batch_stats()
     times, reps = [], None
     for k in range(args.steps):
@@ -185,9 +184,16 @@ def run_batch(reg, torch, args):
         _, reps = b.reg_batch_solve(vs)
         times.append(time.perf_counter() - t)
         log(f"[bench] batch solve {k}: {times[-1]:.3f} s")
+    st1 = b.reg_batch_stats()
+    # GPU time by kernel family: one more batched solve with every launch
+    # bracketed by HIP events (not timed into `value`: the events idle the GPU
+    # between launches)
+    for v in vs:
+        v.zero_()
+    b.reg_batch_profile(True)
+    b.reg_batch_solve(vs)
     prof = b.reg_batch_profile_read()
     b.reg_batch_profile(False)
-    st1 = b.reg_batch_stats()
     sec = sum(times) / len(times)
     per_size = {}
     for shape, rep in zip(shapes, reps):

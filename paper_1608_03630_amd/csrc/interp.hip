@@ -345,6 +345,13 @@ __device__ __forceinline__ TileIdx tile_of(const Grid &g) {
     return t;
 }
 
+// Global-memory view of a pointer. The tile bodies access fields through it:
+// in the batched kernels the pointers are read from the work list, and with
+// plain pointers the compiler, not knowing their address space, emitted flat
+// loads and stores, whose completion the LDS wait counter also tracks (every
+// LDS wait of the gather then waited for the streaming loads as well).
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+
 // stage the box of field f for tile t into box[] (row-major [B1][B2][B3]).
 // Rows are taken kStageRows at a time per wavefront and every value of the
 // batch is requested before the first LDS store, so that each wavefront keeps
@@ -384,7 +391,7 @@ __device__ __forceinline__ void stage_box(const Grid &g, const TileGeom &tg, con
             dst[u] = -1;
             if (q1 < B1) {
                 const int g1 = wrap_idx(o1 + q1, g.n1), g2 = wrap_idx(o2 + q2, g.n2);
-                const T *row = f + ((long)g1 * g.n2 + g2) * g.n3;
+                const gmem<T> *row = (const gmem<T> *)f + ((long)g1 * g.n2 + g2) * g.n3;
 #pragma unroll
                 for (int h = 0; h < 3; h++)
                     if (lane + 64 * h < B3) vals[u][h] = row[gc[h]];
@@ -469,16 +476,17 @@ __device__ __forceinline__ void generic_tile(const Grid &g, const TileGeom &tg, 
         const bool ok = col_ok && i1 < g.n1 && i2 < g.n2;
         const long p = ok ? ((long)i1 * g.n2 + i2) * g.n3 + i3 : -1;
         pp[k] = p;
-        dd[k][0] = ok ? D[p] : T(0);
-        dd[k][1] = ok ? D[N + p] : T(0);
-        dd[k][2] = ok ? D[2 * N + p] : T(0);
+        const gmem<T> *Dg = (const gmem<T> *)D;
+        dd[k][0] = ok ? Dg[p] : T(0);
+        dd[k][1] = ok ? Dg[N + p] : T(0);
+        dd[k][2] = ok ? Dg[2 * N + p] : T(0);
     }
     stage_box(g, tg, t, f, box);
     __syncthreads();
-    const T *__restrict__ gam = static_cast<const T *>(args.gam);
-    const T *__restrict__ grad = static_cast<const T *>(args.grad);
-    const T *__restrict__ vt = static_cast<const T *>(args.vt);
-    T *__restrict__ out = static_cast<T *>(args.out);
+    const gmem<T> *__restrict__ gam = (const gmem<T> *)args.gam;
+    const gmem<T> *__restrict__ grad = (const gmem<T> *)args.grad;
+    const gmem<T> *__restrict__ vt = (const gmem<T> *)args.vt;
+    gmem<T> *__restrict__ out = (gmem<T> *)args.out;
 #pragma unroll
     for (int k = 0; k < kLinesPerWave; k++) {
         const long p = pp[k];
@@ -563,7 +571,7 @@ __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &t
             dst[u] = -1;
             if (q1 < B1) {
                 const int g1 = wrap_idx(o1 + q1, g.n1), g2 = wrap_idx(o2 + q2, g.n2);
-                const T *row = f + (unsigned)((g1 * g.n2 + g2) * g.n3);
+                const gmem<T> *row = (const gmem<T> *)f + (unsigned)((g1 * g.n2 + g2) * g.n3);
                 v0[u] = row[gc0];
                 if (h1) v1[u] = row[gc1];
                 dst[u] = (q1 * K::C2 + q2) * K::C3;
@@ -599,9 +607,9 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     using K = Canon<S>;
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const unsigned N = (unsigned)g.N();
-    const T *__restrict__ D1 = D;
-    const T *__restrict__ D2 = D + N;
-    const T *__restrict__ D3 = D + 2 * (size_t)N;
+    const gmem<T> *__restrict__ D1 = (const gmem<T> *)D;
+    const gmem<T> *__restrict__ D2 = D1 + N;
+    const gmem<T> *__restrict__ D3 = D1 + 2 * (size_t)N;
     const int i3 = t.t3 * kTile3 + lane;
     const unsigned line_stride = (unsigned)g.n3;
     const unsigned p0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3);
@@ -617,14 +625,14 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     }
     stage_box_canon<T, S>(g, tg, t, f, box);
     __syncthreads();
-    const T *__restrict__ gam = static_cast<const T *>(args.gam);
-    const T *__restrict__ gr1 = static_cast<const T *>(args.grad);
-    const T *__restrict__ gr2 = gr1 + N;
-    const T *__restrict__ gr3 = gr1 + 2 * (size_t)N;
-    const T *__restrict__ vt1 = static_cast<const T *>(args.vt);
-    const T *__restrict__ vt2 = vt1 + N;
-    const T *__restrict__ vt3 = vt1 + 2 * (size_t)N;
-    T *__restrict__ out = static_cast<T *>(args.out);
+    const gmem<T> *__restrict__ gam = (const gmem<T> *)args.gam;
+    const gmem<T> *__restrict__ gr1 = (const gmem<T> *)args.grad;
+    const gmem<T> *__restrict__ gr2 = gr1 + N;
+    const gmem<T> *__restrict__ gr3 = gr1 + 2 * (size_t)N;
+    const gmem<T> *__restrict__ vt1 = (const gmem<T> *)args.vt;
+    const gmem<T> *__restrict__ vt2 = vt1 + N;
+    const gmem<T> *__restrict__ vt3 = vt1 + 2 * (size_t)N;
+    gmem<T> *__restrict__ out = (gmem<T> *)args.out;
     const T cs = T(args.cs);
     const bool last = args.last != 0;
 #pragma unroll

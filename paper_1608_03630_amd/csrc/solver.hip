@@ -175,7 +175,9 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
         have = true;
     }
     if (!have) {
-        std::vector<int> cand = {256, 512, 1024, 2048, 4096, L.total};
+        // powers of two, and multiples of 768 for the boxes that fit three
+        // workgroups per CU (256 CUs)
+        std::vector<int> cand = {256, 512, 768, 1024, 1536, 2048, 3072, 4096, L.total};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
             hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
