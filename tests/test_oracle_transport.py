@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle_orders import JOINT_LEVELS, newton_orders, orders, symmetry_orders, time_orders
 
 TWO_PI = 2 * np.pi
 
@@ -210,10 +211,11 @@ def test_hessian_symmetric_and_positive_at_zero(orc):
 @pytest.mark.slow
 def test_gradient_matches_finite_differences_under_refinement(orc):
     """Optimise-then-discretise: <g, vt> is not the derivative of the discrete
-    objective, but the defect against a central difference shrinks as h and
-    dt are refined together."""
+    objective, but the defect against a central difference vanishes as h and
+    dt are refined together, here at observed order about 3 (2.9 and 3.2
+    over 16^3/32^3/48^3 with nt = n/4)."""
     defects = []
-    for n, nt in ((16, 4), (32, 8)):
+    for n, nt in JOINT_LEVELS:
         shape = (n, n, n)
         case = synth.smooth_case(shape)
         P = orc.params(shape, nt, 1e-2)
@@ -226,47 +228,49 @@ def test_gradient_matches_finite_differences_under_refinement(orc):
         Jm, _ = orc.objective(P, case["rhoT"], rhoR, v - eps * vt)
         fd = (Jp - Jm) / (2 * eps)
         defects.append(abs(fd - inner(g, vt)) / abs(fd))
-    assert defects[1] < defects[0] / 3, defects
+    o = orders(defects, [n for n, _ in JOINT_LEVELS])
+    assert min(o) >= 2.5, (defects, o)
 
 
 @pytest.mark.slow
-def test_hessian_symmetry_defect_shrinks(orc):
-    defects = []
-    for n, nt in ((16, 4), (32, 8)):
-        shape = (n, n, n)
-        case = synth.smooth_case(shape)
-        P = orc.params(shape, nt, 1e-2)
-        v = 0.5 * case["v_true"]
-        u = synth.smooth_random_field(shape, 39, kmax=2, ncomp=3)
-        w = synth.smooth_random_field(shape, 40, kmax=2, ncomp=3)
-        Hu = orc.hessian_matvec(P, case["rhoT"], v, u)
-        Hw = orc.hessian_matvec(P, case["rhoT"], v, w)
-        a, b = inner(Hu, w), inner(u, Hw)
-        defects.append(abs(a - b) / abs(a))
-        assert inner(Hu, u) > 0
-    assert defects[1] < defects[0], defects
+def test_hessian_symmetry_defect_converges_at_high_order(orc):
+    """Optimise-then-discretise: the discrete GN Hessian is symmetric only in
+    the limit. Every piece of it (RK2 in time, eq. (7); trapezoid
+    quadrature of b~, eq. (5e); tricubic interpolation) is at least second
+    order, so the defect |<Hu,w> - <u,Hw>| / |<Hu,w>| must fall at order >= 2
+    under joint refinement (observed about 4.6). A first-order mistake in the
+    time levels of the incremental source (eq. (5a)) or in the quadrature
+    weights leaves an O(dt) asymmetry: order about 1."""
+    r = symmetry_orders(orc)
+    assert r["positive"]
+    assert min(r["order"]) >= 2.0, r
 
 
 @pytest.mark.slow
 def test_gauss_newton_equals_newton_at_the_true_velocity(orc):
     """At the velocity that generated rho_R (same discretisation) the adjoint
-    vanishes, so the Gauss-Newton Hessian is the full Hessian: central
-    differences of the gradient approach H vt under refinement."""
-    defects = []
-    for n, nt in ((16, 4), (32, 8)):
-        shape = (n, n, n)
-        case = synth.smooth_case(shape)
-        P = orc.params(shape, nt, 1e-2)
-        vs = case["v_true"]
-        rhoR = orc.transport_forward(P, vs, case["rhoT"])
-        vt = synth.smooth_random_field(shape, 41, kmax=2, ncomp=3)
-        H = orc.hessian_matvec(P, case["rhoT"], vs, vt)
-        eps = 1e-4
-        gp, _, _ = orc.gradient(P, case["rhoT"], rhoR, vs + eps * vt)
-        gm, _, _ = orc.gradient(P, case["rhoT"], rhoR, vs - eps * vt)
-        fd = (gp - gm) / (2 * eps)
-        defects.append(np.sqrt(inner(fd - H, fd - H) / inner(H, H)))
-    assert defects[1] < defects[0], defects
+    vanishes, so the Gauss-Newton Hessian is the full Hessian (section II-B):
+    central differences of the gradient approach H vt under joint refinement
+    at second order or better (observed about 2.6); a first-order slip in
+    the time levels of the incremental state gives about 1."""
+    r = newton_orders(orc)
+    assert min(r["order"]) >= 2.0, r
+
+
+@pytest.mark.slow
+def test_gradient_and_hessian_are_second_order_in_time(orc):
+    """The time discretisation of the whole reduced gradient (eqs. (2b), (3),
+    (4)) and of the GN matvec (eqs. (5a), (5c), (5e)) at a fixed v != 0:
+    RK2 steps (eq. (7)) and trapezoid sums are second order in dt, so g and
+    H vt at nt = 4, 8, 16 approach the nt = 128 solution on the same grid at
+    observed order about 2 (1.93 / 1.75 for g, 2.00 / 1.84 for H vt at 32^3;
+    the second halving is pulled down by interpolation error that
+    accumulates over the steps of the nt = 128 solution). Uniform weights
+    1/(nt+1) in b, or the source of the incremental state taken at t^n
+    instead of t^{n+1} in the corrector, are first-order mistakes (order
+    about 1.05)."""
+    r = time_orders(orc)
+    assert min(r["g_order"]) >= 1.6 and min(r["H_order"]) >= 1.6, r
 
 
 # ------------------------------------------------------------- deformation
