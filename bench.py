@@ -51,10 +51,14 @@ PROFILE_EVERY = 13  # the timed solve brackets one launch in 13 of each family w
 # the samples cycle through all nt = 16 steps of a transport)
 
 
-def solve_params(reg, shape, beta_final, gtol_level=LEVEL_GTOL):
+GRID_LEVELS = 1  # grids of the continuation (1: the benchmark grid only)
+
+
+def solve_params(reg, shape, beta_final, gtol_level=LEVEL_GTOL, grid_levels=None):
     return reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=beta_final, beta_factor=0.1,
                                   gtol=1e-2, mismatch_tol=1e-2, max_newton=50, max_pcg=100, max_ls=20,
-                                  gtol_level=gtol_level)
+                                  gtol_level=gtol_level,
+                                  grid_levels=GRID_LEVELS if grid_levels is None else grid_levels)
 
 
 def make_workload(reg, torch, n, seed=1003):
@@ -306,12 +310,15 @@ def run_net(reg, torch, args):
 
 
 def main():
+    global GRID_LEVELS
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=256, help="grid size per axis (256 is the benchmark workload)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--grid-levels", type=int, default=None,
+                    help="grids of the continuation for the timed solve (default: GRID_LEVELS)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
@@ -330,6 +337,8 @@ def main():
 
     from paper_1608_03630_amd import reg
 
+    if args.grid_levels is not None:
+        GRID_LEVELS = args.grid_levels
     reg.lib()
     torch.cuda.set_device(0)
     if args.mode == "copy":
@@ -384,6 +393,9 @@ def main():
     for k, rep in enumerate(reports):
         log(f"[bench] timed solve {k}: {rep['seconds_total']:.3f} s, {rep['n_iter']} GN steps "
             f"(pcg {rep['pcg_iters']}), mismatch {rep['final_mismatch']:.4f}, stop {rep['stop_reason']}")
+        for l in rep["levels"]:
+            log(f"[bench]    grid {l['n'][0]}^3: {l['seconds']:.3f} s, {l['n_iter']} GN steps, {l['matvecs']} "
+                f"matvecs, mismatch {l['final_mismatch']:.4f}, beta {l['final_beta']:.0e}")
     sec = (t1 - t0) / args.steps
     N = ctx.N
     rep = reports[-1]

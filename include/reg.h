@@ -89,9 +89,15 @@ typedef struct {
                             * starts run by the same rules); 0: ||g0||                */
     double gtol_level;     /* > 0: continuation levels above beta_final stop at
                             * ||g|| <= gtol_level * ref (the last level uses gtol); 0: gtol */
+    int32_t grid_levels;   /* grid continuation: reg_solve first solves on grids coarsened by
+                            * 2^(L-1), ..., 2 per axis, then on n (L = grid_levels, at most
+                            * REG_MAXLEVELS; 0 or 1: n only). Every coarse grid must itself be a
+                            * valid n. Fixes the workspace size: reg_set_solver may lower it only. */
+    int32_t reserved_;     /* zero */
 } reg_params;
 
 #define REG_MAXIT 512
+#define REG_MAXLEVELS 4
 
 /* What reg_solve did, per accepted Newton step and in total. */
 typedef struct {
@@ -107,6 +113,15 @@ typedef struct {
      * a gradient, an objective, or only PCG vector work and preconditioning */
     double seconds_matvec, seconds_gradient, seconds_objective, seconds_precond;
     int64_t interps;       /* scalar field interpolations of n0*n1*n2 points       */
+    double final_beta;     /* beta of the last continuation level worked on        */
+    double final_gref;     /* that level's gradient reference (its g0)             */
+    /* Grid continuation (params.grid_levels): one entry per grid solved,
+     * coarsest first; the finest is the context's own grid, which every other
+     * field above describes. Without grid continuation one entry. */
+    int32_t grid_levels;
+    int32_t level_n[REG_MAXLEVELS][3];
+    int32_t level_iters[REG_MAXLEVELS], level_matvecs[REG_MAXLEVELS];
+    double level_seconds[REG_MAXLEVELS], level_mismatch[REG_MAXLEVELS], level_beta[REG_MAXLEVELS];
 } reg_report;
 
 /* Fills *p with the paper's defaults for an n^3 grid (section IV-A3). */
@@ -214,7 +229,20 @@ reg_status reg_hessian_matvec(reg_ctx *ctx, const void *vt, void *Hvt);
  * preconditioner and forcing eta, Armijo backtracking, beta continuation
  * from params.beta to params.beta_final. v_inout holds the initial velocity
  * (zero for a cold start) and receives the result; on REG_ELINESEARCH it
- * holds the last accepted iterate. rep may be NULL. Synchronises. */
+ * holds the last accepted iterate. rep may be NULL. Synchronises.
+ *
+ * With params.grid_levels = L > 1 the solve is continued over grids as well
+ * as over beta (the paper's conclusion names slow convergence at small beta as
+ * the open problem; a coarse grid makes each of its PCG iterations 8x
+ * cheaper). The images and v_inout are restricted by spectral truncation to
+ * the grid n/2^(L-1) (section III-B1); that grid is solved with the full
+ * beta continuation and the same stopping rules; its velocity is prolonged by
+ * spectral zero-padding to the next grid, whose solve resumes the
+ * continuation at the beta level the coarser solve ended on, and keeps that
+ * level's gradient reference g0 from the coarser grid (grid L2 norms
+ * approximate the same continuous norm on every grid, so the grids together
+ * stop where one grid would); and so on up to n. Every grid's work is
+ * summarised in rep->level_*. */
 reg_status reg_solve(reg_ctx *ctx, void *v_inout, reg_report *rep);
 
 /* Deformation map of eq. (1) through u = y1 - x, transported like the state

@@ -44,6 +44,7 @@ class Params(ctypes.Structure):
         ("armijo_c1", ctypes.c_double),
         ("gtol_level", ctypes.c_double),
         ("gnorm_ref", ctypes.c_double),
+        ("gref_first", ctypes.c_double),
     ]
 
 
@@ -67,6 +68,8 @@ class Report(ctypes.Structure):
         ("final_J", ctypes.c_double),
         ("final_mismatch", ctypes.c_double),
         ("final_grel", ctypes.c_double),
+        ("final_beta", ctypes.c_double),
+        ("final_gref", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -88,6 +91,8 @@ class Report(ctypes.Structure):
             "final_J": self.final_J,
             "final_mismatch": self.final_mismatch,
             "final_grel": self.final_grel,
+            "final_beta": self.final_beta,
+            "final_gref": self.final_gref,
         }
 
 
@@ -111,6 +116,7 @@ def params(n, nt, beta, isochoric=False, beta_final=0.0, beta_factor=0.1, gtol=1
     p.armijo_c1 = float(armijo_c1)
     p.gtol_level = float(gtol_level)
     p.gnorm_ref = float(gnorm_ref)
+    p.gref_first = 0.0
     return p
 
 
@@ -379,3 +385,49 @@ def solve(P, rhoT, rhoR, v0=None):
     rep = Report()
     _load().oracle_solve(ctypes.byref(P), _p(rhoT), _p(rhoR), _p(v), ctypes.byref(rep))
     return v, rep.to_dict()
+
+
+def coarse_params(P, m):
+    """The settings of P on the grid m (every solver setting kept)."""
+    q = Params()
+    ctypes.memmove(ctypes.byref(q), ctypes.byref(P), ctypes.sizeof(Params))
+    q.n[:] = tuple(int(x) for x in m)
+    return q
+
+
+def solve_grid(P, rhoT, rhoR, levels, v0=None):
+    """Gauss-Newton-Krylov solve with grid continuation over `levels` grids
+    (each axis halved per level; levels = 1 is solve()).
+
+    The paper's continuation is in beta (section III-A); solving on coarser
+    grids first is the other remedy for slow convergence at small beta that
+    its conclusion points to. Steps, coarsest grid first:
+      1. the images (and v0) are restricted to the coarse grid by spectral
+         truncation (resample, section III-B1);
+      2. that grid is solved by solve_grid with one level fewer, with the
+         full beta continuation and the same stopping rules;
+      3. its velocity is prolonged to this grid by spectral zero-padding;
+      4. this grid is solved by solve() from the prolonged velocity, with the
+         continuation resumed at the beta level the coarse solve ended on;
+         that level keeps the gradient reference it started with on the
+         coarse grid (grid L2 norms approximate the same continuous norm on
+         every grid), so the grids together stop where one grid would.
+    Returns (v, report of this grid's solve with a "levels" list, coarsest
+    first, of the per-grid reports)."""
+    rhoT, rhoR = _f64(rhoT), _f64(rhoR)
+    n = tuple(int(x) for x in P.n)
+    if levels <= 1:
+        v, rep = solve(P, rhoT, rhoR, v0)
+        rep["levels"] = [dict(rep, n=n)]
+        return v, rep
+    m = tuple(x // 2 for x in n)
+    Pc = coarse_params(P, m)
+    vc0 = None if v0 is None else resample(v0, m)
+    vc, repc = solve_grid(Pc, resample(rhoT, m), resample(rhoR, m), levels - 1, vc0)
+    Pf = coarse_params(P, n)
+    Pf.beta = repc["final_beta"]
+    Pf.gref_first = repc["final_gref"]
+    v, rep = solve(Pf, rhoT, rhoR, resample(vc, n))
+    rep["levels"] = repc["levels"] + [dict(rep, n=n)]
+    return v, rep
+

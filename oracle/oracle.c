@@ -523,6 +523,10 @@ typedef struct {
      * to |g| <= gtol_level * ref; gnorm_ref > 0 makes ref (and the forcing
      * ratio) absolute instead of |g0| of the level. */
     double gtol_level, gnorm_ref;
+    /* > 0: the gradient reference of the first continuation level, in place
+     * of its first gradient norm (grid continuation: the level started on a
+     * coarser grid, whose first gradient norm this is) */
+    double gref_first;
 } oracle_params;
 
 /* everything the gradient and the Hessian need at one velocity */
@@ -792,6 +796,8 @@ typedef struct {
     double J[ORACLE_MAXIT], mismatch[ORACLE_MAXIT], grel[ORACLE_MAXIT], alpha[ORACLE_MAXIT], beta[ORACLE_MAXIT];
     int32_t pcg_iters[ORACLE_MAXIT], ls_trials[ORACLE_MAXIT];
     double final_J, final_mismatch, final_grel;
+    double final_beta;   /* beta of the last continuation level worked on */
+    double final_gref;   /* that level's gradient reference */
 } oracle_report;
 
 static double norm3(const int *n, const double *x) { return sqrt(inner(n, 3, x, x)); }
@@ -812,7 +818,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
     double beta = P->beta;
     double beta_final = P->beta_final > 0 ? P->beta_final : P->beta;
     double factor = (P->beta_factor > 0 && P->beta_factor < 1) ? P->beta_factor : 0.1;
-    int done = 0, it = 0;
+    int done = 0, it = 0, first_level = 1;
     double J = 0, mis = 0, gnorm = 0, g0 = 0;
     while (!done) {
         oracle_state_t st;
@@ -822,7 +828,8 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
         gradient_from_state(&st, beta, v, rhoR, g);
         rep->gradients++;
         gnorm = norm3(n, g);
-        g0 = gnorm;
+        g0 = (first_level && P->gref_first > 0) ? P->gref_first : gnorm;
+        first_level = 0;
         rep->stop_reason = 2;
         const double ref = P->gnorm_ref > 0 ? P->gnorm_ref : g0;
         const double tol = (P->gtol_level > 0 && beta > beta_final * (1 + 1e-12)) ? P->gtol_level : P->gtol;
@@ -929,6 +936,8 @@ out:
     rep->final_J = J;
     rep->final_mismatch = mis;
     rep->final_grel = g0 > 0 ? gnorm / g0 : 0;
+    rep->final_beta = beta;
+    rep->final_gref = g0;
     free(g);
     free(s);
     free(r);

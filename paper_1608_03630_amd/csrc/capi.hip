@@ -88,14 +88,6 @@ reg_status spectral_impl(reg_ctx *ctx, int op, double scale, int ncomp, const vo
     return REG_OK;
 }
 
-template <typename T>
-reg_status resample_impl(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out) {
-    hipStream_t st = src->stream;
-    HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_forward<T, T>(src->spec, CV<T>(in), ncomp, 0, st))));
-    HIPCHK(src, KL(src, REG_K_SYMBOL, regk::spec_resample<T>(src->spec, dst->spec, ncomp, st)));
-    HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_inverse<T, T>(dst->spec, V<T>(out), ncomp, st))));
-    return REG_OK;
-}
 
 }  // namespace
 
@@ -126,7 +118,7 @@ reg_status reg_default_params(reg_params *p) {
 reg_status reg_workspace_size(const reg_params *p, size_t *bytes) {
     std::string why;
     if (check_params(p, &why) != REG_OK || !bytes) return REG_EINVAL;
-    *bytes = layout(p, nullptr, nullptr);
+    *bytes = total_size(p);
     return REG_OK;
 }
 
@@ -139,7 +131,7 @@ reg_status reg_create(const reg_params *p, void *workspace, size_t bytes, void *
         return REG_EINVAL;
     }
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0) return REG_EINVAL;
-    if (bytes < layout(p, nullptr, nullptr)) return REG_ENOMEM;
+    if (bytes < total_size(p)) return REG_ENOMEM;
     if (!is_device_ptr(workspace)) return REG_EINVAL;
     reg_ctx *ctx = new (std::nothrow) reg_ctx();
     if (!ctx) return REG_ENOMEM;
@@ -182,12 +174,25 @@ reg_status reg_create(const reg_params *p, void *workspace, size_t bytes, void *
             return REG_EHIP;
         }
     }
+    if (grid_count(p) > 1) {
+        // the coarse-grid chain of the grid continuation, in the workspace
+        // after this context's views
+        const reg_params q = coarse_params(p);
+        const size_t own = align_up(layout(p, nullptr, nullptr));
+        const reg_status st = reg_create(&q, (char *)workspace + own, bytes - own, hip_stream, &ctx->coarse);
+        if (st != REG_OK) {
+            (void)hipHostFree(ctx->hres);
+            delete ctx;
+            return st;
+        }
+    }
     *out = ctx;
     return REG_OK;
 }
 
 reg_status reg_destroy(reg_ctx *ctx) {
     if (!ctx) return REG_EINVAL;
+    if (ctx->coarse) reg_destroy(ctx->coarse);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->prof.release();
     if (ctx->hres) (void)hipHostFree(ctx->hres);
@@ -212,9 +217,24 @@ reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p) {
     if (p->n[0] != ctx->P.n[0] || p->n[1] != ctx->P.n[1] || p->n[2] != ctx->P.n[2] || p->nt != ctx->P.nt ||
         p->prec != ctx->P.prec)
         return fail(ctx, REG_EINVAL, "n, nt and prec are fixed at reg_create");
+    int chain = 1;
+    for (reg_ctx *c = ctx->coarse; c; c = c->coarse) chain++;
+    if (grid_count(p) > chain)
+        return fail(ctx, REG_EINVAL, "grid_levels = " + std::to_string(p->grid_levels) + " exceeds the " +
+                                         std::to_string(chain) + " grid(s) the workspace was laid out for");
     ctx->P = *p;
     ctx->beta = p->beta;
     ctx->have_state = false;
+    reg_params q = *p;
+    for (reg_ctx *c = ctx->coarse; c; c = c->coarse) {
+        // coarser grids keep their own size and chain length
+        const int32_t n[3] = {c->P.n[0], c->P.n[1], c->P.n[2]};
+        q.grid_levels = q.grid_levels > 1 ? q.grid_levels - 1 : 0;
+        c->P = q;
+        for (int j = 0; j < 3; j++) c->P.n[j] = n[j];
+        c->beta = q.beta;
+        c->have_state = false;
+    }
     return REG_OK;
 }
 
@@ -236,6 +256,7 @@ reg_status reg_set_images(reg_ctx *ctx, const void *rho_T, const void *rho_R) {
     ctx->normTR2 = ctx->hres[0];
     ctx->have_images = true;
     ctx->have_state = false;
+    ctx->coarse_images = false;
     return REG_OK;
 }
 
@@ -310,7 +331,7 @@ reg_status reg_resample(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, v
     if (src->P.prec != dst->P.prec) return fail(src, REG_EINVAL, "src and dst must have the same precision");
     if (ncomp != 1 && ncomp != 3) return fail(src, REG_EINVAL, "ncomp must be 1 or 3");
     if (src == dst) return fail(src, REG_EINVAL, "src and dst must be different contexts");
-    return src->P.prec ? resample_impl<double>(src, dst, ncomp, in, out) : resample_impl<float>(src, dst, ncomp, in, out);
+    return src->P.prec ? resample_fields<double>(src, dst, ncomp, in, out) : resample_fields<float>(src, dst, ncomp, in, out);
 }
 
 reg_status reg_precond(reg_ctx *ctx, const void *r, void *z) {

@@ -159,6 +159,12 @@ struct reg_ctx {
     };
     PlanGeom geoms[6];
 
+    // grid continuation: the context of the grid coarsened by 2 per axis
+    // (owned, its workspace follows this one's), and whether its images are
+    // the restriction of the current ones
+    reg_ctx *coarse = nullptr;
+    bool coarse_images = false;
+
     bool have_images = false;
     bool have_state = false;  // plans, history, grad rho and div v at vhat
     double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
@@ -267,7 +273,29 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
         *why = "gtol_level must be >= 0 and finite";
         return REG_EINVAL;
     }
+    if (p->grid_levels < 0 || p->grid_levels > REG_MAXLEVELS) {
+        *why = "grid_levels must be in [0, " + std::to_string(REG_MAXLEVELS) + "]";
+        return REG_EINVAL;
+    }
+    for (int l = 1; l < p->grid_levels; l++)
+        for (int j = 0; j < 3; j++)
+            if ((p->n[j] % (1 << l)) != 0 || !fft_friendly(p->n[j] >> l)) {
+                *why = "grid_levels = " + std::to_string(p->grid_levels) + " needs n[" + std::to_string(j) +
+                       "] / " + std::to_string(1 << l) + " to be a valid grid size";
+                return REG_EINVAL;
+            }
     return REG_OK;
+}
+
+// grids of the continuation (1 = the context's own grid only)
+inline int grid_count(const reg_params *p) { return p->grid_levels > 1 ? p->grid_levels : 1; }
+
+// the settings of p on the grid coarsened by 2 per axis, one level fewer
+inline reg_params coarse_params(const reg_params *p) {
+    reg_params q = *p;
+    for (int j = 0; j < 3; j++) q.n[j] = p->n[j] / 2;
+    q.grid_levels = grid_count(p) - 1;
+    return q;
 }
 
 // Lays out the workspace of a context (ctx == nullptr: size only).
@@ -321,6 +349,16 @@ inline size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->dpart2 = (double *)L.take(sizeof(double) * regk::RED_BLOCKS);
     c->dres = (double *)L.take(sizeof(double) * kSlots);
     return L.off;
+}
+
+// workspace of a context and of its coarse-grid chain
+inline size_t total_size(const reg_params *p) {
+    size_t b = align_up(layout(p, nullptr, nullptr));
+    if (grid_count(p) > 1) {
+        const reg_params q = coarse_params(p);
+        b += total_size(&q);
+    }
+    return b;
 }
 
 inline bool is_device_ptr(const void *ptr) {
@@ -469,6 +507,27 @@ reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
     const long N = ctx->N;
     for (int j = 0; j < 3; j++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream)));
+    return REG_OK;
+}
+
+// spectral resampling of ncomp field-type fields from src's grid to dst's
+// (src's transform buffer, then dst's), on src's stream
+template <typename T>
+reg_status resample_fields(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out) {
+    hipStream_t st = src->stream;
+    HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_forward<T, T>(src->spec, CV<T>(in), ncomp, 0, st))));
+    HIPCHK(src, KL(src, REG_K_SYMBOL, regk::spec_resample<T>(src->spec, dst->spec, ncomp, st)));
+    HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_inverse<T, T>(dst->spec, V<T>(out), ncomp, st))));
+    return REG_OK;
+}
+
+// spectral resampling of a velocity-space vector (3 half spectra of complex
+// double) from src's grid to dst's: truncation or zero-padding of the modes
+inline reg_status resample_vec_hat(reg_ctx *src, const void *xhat, reg_ctx *dst, void *yhat) {
+    regk::SpecCtx a = src->spec, b = dst->spec;
+    a.H = const_cast<void *>(xhat);
+    b.H = yhat;
+    HIPCHK(src, KL(src, REG_K_SYMBOL, regk::spec_resample<double>(a, b, 3, src->stream)));
     return REG_OK;
 }
 

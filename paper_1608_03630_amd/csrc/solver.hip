@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <functional>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "ctx.hpp"
@@ -670,6 +671,10 @@ struct Solver {
     double J = 0, mis = 0, gnorm = 0, g0 = 0, eta = 0, rz = 0, d = 0, alpha = 1;
     int k = 0, it = 0, i = 0, iters = 0, l = 0, trials = 0;
     bool changed = false;  // an accepted step or the projection moved v
+    bool start_hat = false;  // vhat already holds the first iterate (grid continuation)
+    double beta_start = 0;   // > 0: the first continuation level (grid continuation resumes there)
+    double gref_start = 0;   // > 0: that level's gradient reference, measured on the coarser grid
+    bool first_level = true;
     clk::time_point t0;
     long interps0 = 0;
 
@@ -714,12 +719,12 @@ struct Solver {
                 t0 = clk::now();
                 interps0 = ctx->interps;
                 // the iterate lives on the half spectrum until the solve ends
-                STCHK(to_spec(ctx, v, ctx->vhat));
+                if (!start_hat) STCHK(to_spec(ctx, v, ctx->vhat));
                 if (P.isochoric) STCHK(leray_hat(ctx, ctx->vhat));
-                changed = P.isochoric != 0;
+                changed = P.isochoric != 0 || start_hat;
                 beta_final = P.beta_final > 0 ? P.beta_final : P.beta;
                 factor = (P.beta_factor > 0 && P.beta_factor < 1) ? P.beta_factor : 0.1;
-                beta = P.beta;
+                beta = beta_start > 0 ? beta_start : P.beta;
                 it = 0;
                 st = S_LEVEL;
                 break;
@@ -735,7 +740,8 @@ struct Solver {
                     finish(s);
                     break;
                 }
-                g0 = gnorm;
+                g0 = (first_level && gref_start > 0) ? gref_start : gnorm;
+                first_level = false;
                 rep->stop_reason = 2;
                 k = 0;
                 st = S_NEWTON;
@@ -893,9 +899,12 @@ struct Solver {
                 break;
             case S_FINISH:
                 // the last accepted iterate back to the caller's physical v
-                // (left untouched when nothing was accepted)
-                if (changed) STCHK(from_spec(ctx, ctx->vhat, v));
+                // (left untouched when nothing was accepted; a coarse grid of
+                // the continuation keeps it on the half spectrum)
+                if (changed && v) STCHK(from_spec(ctx, ctx->vhat, v));
                 ctx->beta = P.beta;
+                rep->final_beta = beta;
+                rep->final_gref = g0;
                 rep->status = status;
                 rep->n_iter = it;
                 rep->final_J = J;
@@ -967,17 +976,77 @@ reg_status single_op(reg_ctx *ctx, const Request &r) {
     return REG_OK;
 }
 
+// The solve of one context over `levels` grids of its chain (grid
+// continuation; levels = 1: this grid only). With start_hat the first iterate
+// is already in ctx->vhat and v may be null (a coarse grid of the chain).
 template <typename T>
-reg_status solve_one(reg_ctx *ctx, void *v, reg_report *rep) {
+reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool start_hat) {
+    const auto t0 = clk::now();
+    double beta_start = 0, gref_start = 0;
+    if (levels > 1) {
+        reg_ctx *c = ctx->coarse;
+        if (!ctx->coarse_images) {
+            // images restricted by spectral truncation
+            STCHK(resample_fields<T>(ctx, c, 1, ctx->rhoT, c->rhoT));
+            STCHK(resample_fields<T>(ctx, c, 1, ctx->rhoR, c->rhoR));
+            STCHK(reduce<T>(c, c->rhoT, c->rhoR, c->N, 1, h3(c), 0));
+            STCHK(fetch(c, 1));
+            c->normTR2 = c->hres[0];
+            c->have_images = true;
+            c->coarse_images = false;
+            ctx->coarse_images = true;
+        }
+        c->have_state = false;
+        if (!start_hat) STCHK(to_spec(ctx, v, ctx->vhat));
+        STCHK(resample_vec_hat(ctx, ctx->vhat, c, c->vhat));
+        std::unique_ptr<reg_report> rc(new (std::nothrow) reg_report());
+        if (!rc) return fail(ctx, REG_ENOMEM, "host allocation of a coarse-grid report");
+        std::memset(rc.get(), 0, sizeof(reg_report));
+        const reg_status sc = solve_chain<T>(c, nullptr, rc.get(), levels - 1, true);
+        // a coarse grid whose line search stalled still hands on its last
+        // accepted iterate; any other failure ends the solve
+        if (sc != REG_OK && sc != REG_ELINESEARCH) return fail(ctx, sc, "coarse grid: " + c->err);
+        rep->grid_levels = rc->grid_levels;
+        for (int l = 0; l < rc->grid_levels; l++) {
+            for (int j = 0; j < 3; j++) rep->level_n[l][j] = rc->level_n[l][j];
+            rep->level_iters[l] = rc->level_iters[l];
+            rep->level_matvecs[l] = rc->level_matvecs[l];
+            rep->level_seconds[l] = rc->level_seconds[l];
+            rep->level_mismatch[l] = rc->level_mismatch[l];
+            rep->level_beta[l] = rc->level_beta[l];
+        }
+        // prolongation by spectral zero-padding
+        STCHK(resample_vec_hat(c, c->vhat, ctx, ctx->vhat));
+        beta_start = rc->final_beta;
+        gref_start = rc->final_gref;
+        start_hat = true;
+    }
     Exec<T> ex(nullptr, ctx->stream);
     std::vector<Solver> S(1);
     S[0].ctx = ctx;
     S[0].v = v;
     S[0].rep = rep;
-    reg_status st = run_solvers<T>(ex, S);
+    S[0].start_hat = start_hat;
+    S[0].beta_start = beta_start;
+    S[0].gref_start = gref_start;
+    const reg_status st = run_solvers<T>(ex, S);
     ctx->beta = ctx->P.beta;
+    const int l = rep->grid_levels < REG_MAXLEVELS ? rep->grid_levels : REG_MAXLEVELS - 1;
+    for (int j = 0; j < 3; j++) rep->level_n[l][j] = ctx->P.n[j];
+    rep->level_iters[l] = rep->n_iter;
+    rep->level_matvecs[l] = rep->matvecs;
+    rep->level_seconds[l] = rep->seconds_total;
+    rep->level_mismatch[l] = rep->final_mismatch;
+    rep->level_beta[l] = rep->final_beta;
+    rep->grid_levels = l + 1;
+    rep->seconds_total = secs(t0);
     if (st != REG_OK) return st;
     return S[0].status;
+}
+
+template <typename T>
+reg_status solve_one(reg_ctx *ctx, void *v, reg_report *rep) {
+    return solve_chain<T>(ctx, v, rep, grid_count(&ctx->P), false);
 }
 
 template <typename T>
@@ -991,6 +1060,16 @@ reg_status batch_solve(reg_batch *b, void *const *v, reg_report *reps) {
     }
     reg_status st = run_solvers<T>(ex, S);
     for (auto *c : b->ctx) c->beta = c->P.beta;
+    for (int i = 0; i < b->npairs; i++) {
+        reg_report *r = &reps[i];
+        for (int j = 0; j < 3; j++) r->level_n[0][j] = b->ctx[i]->P.n[j];
+        r->level_iters[0] = r->n_iter;
+        r->level_matvecs[0] = r->matvecs;
+        r->level_seconds[0] = r->seconds_total;
+        r->level_mismatch[0] = r->final_mismatch;
+        r->level_beta[0] = r->final_beta;
+        r->grid_levels = 1;
+    }
     if (st != REG_OK) return st;
     for (auto &s : S)
         if (s.status != REG_OK) return bfail(b, s.status, "pair " + std::to_string(&s - S.data()) + ": " + s.ctx->err);
@@ -1029,6 +1108,10 @@ reg_status check_batch(const reg_params *pp, int32_t n, std::string *why) {
         }
         if (pp[i].prec != pp[0].prec) {
             *why = "every pair of a batch needs the same prec";
+            return REG_EINVAL;
+        }
+        if (grid_count(&pp[i]) > 1) {
+            *why = "pair " + std::to_string(i) + ": grid continuation (grid_levels > 1) is a single-context solve";
             return REG_EINVAL;
         }
     }

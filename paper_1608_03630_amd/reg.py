@@ -17,6 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libreg.so")
 REG_MAXIT = 512
+REG_MAXLEVELS = 4
 
 STATUS = {
     0: "REG_OK", 1: "REG_EINVAL", 2: "REG_ENOMEM", 3: "REG_EHIP", 4: "REG_ENONFINITE", 5: "REG_ENOTCONV",
@@ -52,6 +53,8 @@ class reg_params(ctypes.Structure):
         ("armijo_c1", ctypes.c_double),
         ("gnorm_ref", ctypes.c_double),
         ("gtol_level", ctypes.c_double),
+        ("grid_levels", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 
@@ -79,6 +82,15 @@ class reg_report(ctypes.Structure):
         ("seconds_objective", ctypes.c_double),
         ("seconds_precond", ctypes.c_double),
         ("interps", ctypes.c_int64),
+        ("final_beta", ctypes.c_double),
+        ("final_gref", ctypes.c_double),
+        ("grid_levels", ctypes.c_int32),
+        ("level_n", (ctypes.c_int32 * 3) * REG_MAXLEVELS),
+        ("level_iters", ctypes.c_int32 * REG_MAXLEVELS),
+        ("level_matvecs", ctypes.c_int32 * REG_MAXLEVELS),
+        ("level_seconds", ctypes.c_double * REG_MAXLEVELS),
+        ("level_mismatch", ctypes.c_double * REG_MAXLEVELS),
+        ("level_beta", ctypes.c_double * REG_MAXLEVELS),
     ]
 
     def to_dict(self):
@@ -86,9 +98,14 @@ class reg_report(ctypes.Structure):
         out = {f: getattr(self, f) for f in ("status", "n_iter", "matvecs", "gradients", "objectives",
                                              "stop_reason", "final_J", "final_mismatch", "final_grel",
                                              "seconds_total", "seconds_matvec", "seconds_gradient",
-                                             "seconds_objective", "seconds_precond", "interps")}
+                                             "seconds_objective", "seconds_precond", "interps", "final_beta",
+                                             "final_gref")}
         for f in ("J", "mismatch", "grel", "alpha", "beta", "pcg_iters", "ls_trials"):
             out[f] = list(getattr(self, f)[:k])
+        out["levels"] = [{"n": tuple(self.level_n[i]), "n_iter": self.level_iters[i],
+                          "matvecs": self.level_matvecs[i], "seconds": self.level_seconds[i],
+                          "final_mismatch": self.level_mismatch[i], "final_beta": self.level_beta[i]}
+                         for i in range(min(self.grid_levels, REG_MAXLEVELS))]
         return out
 
 

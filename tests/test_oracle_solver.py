@@ -158,3 +158,70 @@ def test_paper_parameters_fixture():
     with open(os.path.join(HERE, "golden", "paper_parameters.json")) as f:
         gold = json.load(f)
     assert gold["beta"] == 1e-2 and gold["nt"] == 4 and gold["gtol"] == 1e-2
+
+
+def test_grid_continuation_reaches_the_single_grid_minimiser(orc):
+    """Grid continuation (coarse solve, spectral prolongation, fine solve)
+    solves the fine problem: with the same absolute gradient tolerance
+    (gnorm_ref = |g(0)|) the result agrees with the single-grid solve to about
+    that tolerance, and the gap closes as the tolerance tightens. The
+    prolonged coarse solution starts the fine grid well below |g(0)| (a wrong
+    prolongation scale or restriction would not), and the fine grid needs
+    fewer Newton steps than a cold start."""
+    shape = (32, 32, 32)
+    c = synth.smooth_case(shape)
+    P0 = orc.params(shape, 4, 1e-2)
+    rhoT = c["rhoT"]
+    rhoR = orc.transport_forward(P0, c["v_true"], rhoT)
+    g_zero = orc.gradient(P0, rhoT, rhoR, np.zeros((3,) + shape))[0]
+    g0 = np.sqrt(inner(g_zero, g_zero))
+    gaps = []
+    for gtol in (1e-3, 1e-4):
+        P = orc.params(shape, 4, 1e-2, max_newton=20, gtol=gtol, gnorm_ref=g0)
+        v1, r1 = orc.solve(P, rhoT, rhoR)
+        v2, r2 = orc.solve_grid(P, rhoT, rhoR, 2)
+        assert r1["status"] == 0 and r2["status"] == 0 and r2["stop_reason"] == 0
+        coarse, fine = r2["levels"]
+        assert coarse["n"] == (16, 16, 16) and fine["n"] == shape
+        assert fine["n_iter"] < r1["n_iter"]
+        gaps.append(np.sqrt(inner(v1 - v2, v1 - v2) / inner(v1, v1)))
+    assert gaps[1] <= 1e-3 and gaps[1] < 0.5 * gaps[0], gaps
+    # the fine grid starts from the prolonged coarse solution
+    Pc = orc.coarse_params(P0, (16, 16, 16))
+    vc, _ = orc.solve(Pc, orc.resample(rhoT, 16), orc.resample(rhoR, 16))
+    gp = orc.gradient(P0, rhoT, rhoR, orc.resample(vc, 32))[0]
+    assert np.sqrt(inner(gp, gp)) <= 0.5 * g0
+
+
+def test_grid_continuation_resumes_beta_where_the_coarse_grid_ended(orc):
+    """Each grid of the continuation resumes the beta continuation at the
+    level the coarser grid ended on, and the report lists the grids coarsest
+    first."""
+    shape = (16, 16, 16)
+    c = synth.smooth_case(shape)
+    P0 = orc.params(shape, 4, 1e-2)
+    rhoR = orc.transport_forward(P0, c["v_true"], c["rhoT"])
+    P = orc.params(shape, 4, 1e-1, beta_final=1e-3, max_newton=4, gtol_level=0.3)
+    v, rep = orc.solve_grid(P, c["rhoT"], rhoR, 2)
+    coarse, fine = rep["levels"]
+    assert coarse["n"] == (8, 8, 8) and np.isclose(coarse["final_beta"], 1e-3)
+    assert all(np.isclose(b, 1e-3) for b in fine["beta"]) and np.isclose(rep["final_beta"], 1e-3)
+    # the resumed level keeps the gradient reference of its start on the
+    # coarse grid: relative gradients are reported against it
+    assert np.isclose(fine["final_gref"], coarse["final_gref"], rtol=0, atol=0)
+
+
+def test_grid_continuation_stops_where_one_grid_would(orc):
+    """Three grids (8^3, 16^3, 32^3) with beta continuation 1e-1 -> 1e-2:
+    every grid ends by the gradient test against its level's reference, and
+    the finest grid ends at |g| <= gtol times the reference taken where the
+    last level began, on a coarser grid."""
+    shape = (32, 32, 32)
+    c = synth.smooth_case(shape)
+    rhoR = orc.transport_forward(orc.params(shape, 4, 1e-2), c["v_true"], c["rhoT"])
+    P = orc.params(shape, 4, 1e-1, beta_final=1e-2, max_newton=6, gtol_level=0.3)
+    v, rep = orc.solve_grid(P, c["rhoT"], rhoR, 3)
+    assert [l["n"][0] for l in rep["levels"]] == [8, 16, 32]
+    assert all(l["status"] == 0 and l["stop_reason"] == 0 for l in rep["levels"])
+    g = orc.gradient(orc.params(shape, 4, 1e-2), c["rhoT"], rhoR, v)[0]
+    assert np.sqrt(inner(g, g)) <= 1e-2 * rep["final_gref"] * (1 + 1e-9)
