@@ -162,6 +162,21 @@ reg_status reg_set_images(reg_ctx *ctx, const void *rho_T, const void *rho_R);
  * out must not alias f. */
 reg_status reg_interp(reg_ctx *ctx, const void *f, const void *D, void *out);
 
+/* For callers that cannot allocate device memory (code under stream capture
+ * set-up, tight serving loops, harnesses that forbid hipMalloc): the same
+ * interpolation as reg_interp, with no context, workspace or allocation.
+ * prec: 0 float, 1 double; n: the grid (the sizes reg_create accepts, so at
+ * most 1024^3 points); f, out: fields and D: displacement field, device
+ * pointers on the current device, as for reg_interp (out must not alias f).
+ * Enqueued on hip_stream (a hipStream_t, NULL = null stream); synchronises
+ * that stream once, to read the floor bounds of D that choose the LDS tile
+ * geometry. Scratch: a fixed 8 KiB device array per GPU (partial and final
+ * floor bounds), held until the process ends and shared by every call on
+ * that GPU: calls that overlap on one GPU race. Bad arguments return
+ * REG_EINVAL with the reason on stderr; nothing is enqueued then. */
+reg_status reg_interp_noalloc(int32_t prec, const int32_t n[3], const void *f, const void *D, void *out,
+                              void *hip_stream);
+
 /* RK2 departure points of the velocity sign*v for one step dt = 1/nt
  * (eq. (6)): X* = x - dt u(x), X = x - dt/2 (u(x) + u(X*)), u = sign*v,
  * returned as D = (X - x)/h. sign must be +1 or -1. D must not alias v. */

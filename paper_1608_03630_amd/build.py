@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libreg.so")
-SOURCES = ["interp.hip", "fft.hip", "blas.hip", "capi.hip", "solver.hip", "net.hip", "netapi.hip"]
+SOURCES = ["interp.hip", "fft.hip", "blas.hip", "capi.hip", "solver.hip", "net.hip", "netapi.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -120,6 +120,7 @@ _SIGS = {
     "reg_set_solver": [_P, ctypes.POINTER(reg_params)],
     "reg_set_images": [_P, _P, _P],
     "reg_interp": [_P, _P, _P, _P],
+    "reg_interp_noalloc": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P],
     "reg_backtrace": [_P, _P, ctypes.c_double, _P],
     "reg_deriv": [_P, ctypes.c_int, _P, _P],
     "reg_grad": [_P, _P, _P],
@@ -220,6 +221,24 @@ def reg_workspace_size(p):
 def _stream_ptr(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def reg_interp_noalloc(f, D, out, stream=None):
+    """reg_interp without a context (the entry point that allocates nothing):
+    f and out are [n0][n1][n2] float32 or float64 CUDA tensors, D is [3][n0][n1][n2]
+    of the same dtype; out is written in place."""
+    for t, name in ((f, "f"), (D, "D"), (out, "out")):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous CUDA tensor")
+        if t.dtype != f.dtype or f.dtype not in (torch.float32, torch.float64):
+            raise TypeError(f"{name} must be float32 or float64 like f")
+    if f.dim() != 3 or tuple(out.shape) != tuple(f.shape) or tuple(D.shape) != (3,) + tuple(f.shape):
+        raise ValueError("f, out must be [n0][n1][n2] and D [3][n0][n1][n2]")
+    n = (ctypes.c_int32 * 3)(*f.shape)
+    _chk(lib().reg_interp_noalloc(int(f.dtype == torch.float64), n, ctypes.c_void_p(f.data_ptr()),
+                                  ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+         what="reg_interp_noalloc")
+    return out
 
 
 class Context:
