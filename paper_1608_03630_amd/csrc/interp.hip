@@ -590,41 +590,73 @@ __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &t
     }
 }
 
+// The cubic Lagrange basis of lagrange4 times 6 (10 operations instead of
+// 14); a stencil sum with three such factors is 216 times the interpolant.
 template <typename T>
-__device__ __forceinline__ int canon_base(int il, T d, int lo, int B, T w[4]) {
+__device__ __forceinline__ void lagrange4_x6(T t, T w[4]) {
+    const T tm1 = t - T(1), tm2 = t - T(2), tp1 = t + T(1);
+    const T a = t * tm1;              // t (t - 1)
+    const T c = (t * T(3) + T(3)) * tm2;  // 3 (t + 1) (t - 2)
+    w[0] = -(a * tm2);
+    w[1] = c * tm1;
+    w[2] = -(c * t);
+    w[3] = a * tp1;
+}
+
+// Local stencil start along one axis and the (scaled) weights. The floor is
+// clamped in floating point to [flo_min, flo_min + B - 4], the floors whose
+// stencil lies inside the box, so the index needs no integer clamp; a NaN
+// displacement maps to flo_min (the clamp takes the non-NaN operand).
+template <typename T>
+__device__ __forceinline__ int canon_base(T d, T flo_min, T flo_max, int shift, T w[4]) {
     const T fl = flo(d);
-    lagrange4(d - fl, w);
-    const T flc = fmin(fmax(fl, T(-1e6)), T(1e6));
-    return min(max(il + (int)flc - 1 - lo, 0), B - 4);
+    lagrange4_x6(d - fl, w);
+    return (int)fmin(fmax(fl, flo_min), flo_max) + shift;
+}
+
+// Element at a 32-bit byte offset from a uniform base: the load or store
+// then takes the scalar-base + 32-bit vector-offset address form (the
+// canonical kernels run on single-precision grids of at most 2^30 points, so
+// every field offset fits). Non-temporal for the per-point streams.
+template <typename T>
+__device__ __forceinline__ T ld_nt(const gmem<T> *base, unsigned byte_off) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const gmem<T> *>(reinterpret_cast<const gmem<char> *>(base) + byte_off));
+}
+template <typename T>
+__device__ __forceinline__ void st_at(gmem<T> *base, unsigned byte_off, T v) {
+    *reinterpret_cast<gmem<T> *>(reinterpret_cast<gmem<char> *>(base) + byte_off) = v;
+}
+
+// An integer the compiler must treat as unknown: the per-plane LDS offsets go
+// through it so that each plane's 16 reads use immediate offsets from one
+// register, instead of the compiler re-deriving a base per pair of reads from
+// one folded offset (ds_read2 offsets reach only 255 elements).
+__device__ __forceinline__ unsigned opaque(unsigned x) {
+    asm("" : "+v"(x));
+    return x;
 }
 
 // The work of one tile t of one grid (shared by the single-grid and the
-// batched persistent kernels; `box` is the workgroup's LDS).
+// batched persistent kernels; `box` is the workgroup's LDS). Every global
+// operand of the thread's points (displacements, and the Heun factor or
+// vt . grad rho of the epilogue) is requested before the box is staged, so
+// the loop over the points after the barrier issues LDS reads and stores
+// only: a load there would make its wait also wait for the stores before it.
 template <typename T, int MODE, int S>
 __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                            const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
                                            T *box) {
     using K = Canon<S>;
+    static_assert(sizeof(T) == 4, "canonical tiles are single precision");
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const unsigned N = (unsigned)g.N();
     const gmem<T> *__restrict__ D1 = (const gmem<T> *)D;
     const gmem<T> *__restrict__ D2 = D1 + N;
     const gmem<T> *__restrict__ D3 = D1 + 2 * (size_t)N;
     const int i3 = t.t3 * kTile3 + lane;
-    const unsigned line_stride = (unsigned)g.n3;
-    const unsigned p0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3);
-    T d[kLinesPerWave][3];
-#pragma unroll
-    for (int k = 0; k < kLinesPerWave; k++) {
-        const int line = wave + kWaves * k;
-        const int a1 = line >> 3, a2 = line & 7;  // kTile2 == 8
-        const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
-        d[k][0] = __builtin_nontemporal_load(D1 + p);
-        d[k][1] = __builtin_nontemporal_load(D2 + p);
-        d[k][2] = __builtin_nontemporal_load(D3 + p);
-    }
-    stage_box_canon<T, S>(g, tg, t, f, box);
-    __syncthreads();
+    const unsigned line_bytes = (unsigned)g.n3 * sizeof(T);
+    const unsigned b0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3) * sizeof(T);
     const gmem<T> *__restrict__ gam = (const gmem<T> *)args.gam;
     const gmem<T> *__restrict__ gr1 = (const gmem<T> *)args.grad;
     const gmem<T> *__restrict__ gr2 = gr1 + N;
@@ -632,45 +664,71 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     const gmem<T> *__restrict__ vt1 = (const gmem<T> *)args.vt;
     const gmem<T> *__restrict__ vt2 = vt1 + N;
     const gmem<T> *__restrict__ vt3 = vt1 + 2 * (size_t)N;
+    // thread's points: line wave + kWaves k of the tile, i.e. x1 row k and
+    // x2 row `wave` (kWaves == kTile2), at x3 position `lane`
+    static_assert(kWaves == kTile2 && kLinesPerWave == kTile1, "one x2 row per wavefront");
+    const int a2 = wave;
+    T d[kLinesPerWave][3], e[kLinesPerWave];
+#pragma unroll
+    for (int k = 0; k < kLinesPerWave; k++) {
+        const int a1 = k;
+        const unsigned o = b0 + (unsigned)(a1 * g.n2 + a2) * line_bytes;
+        d[k][0] = ld_nt(D1, o);
+        d[k][1] = ld_nt(D2, o);
+        d[k][2] = ld_nt(D3, o);
+        if (MODE == TM_ADJOINT) {
+            e[k] = gam ? ld_nt(gam, o) : T(1);
+        } else if (MODE == TM_INCSTATE) {
+            e[k] = ld_nt(vt1, o) * ld_nt(gr1, o) + ld_nt(vt2, o) * ld_nt(gr2, o) + ld_nt(vt3, o) * ld_nt(gr3, o);
+        }
+    }
+    stage_box_canon<T, S>(g, tg, t, f, box);
+    __syncthreads();
     gmem<T> *__restrict__ out = (gmem<T> *)args.out;
     const T cs = T(args.cs);
     const bool last = args.last != 0;
+    constexpr unsigned kPlane = K::C2 * K::C3;
+    const T f3min = T(tg.lo[2] + 1 - lane), f3max = T(tg.lo[2] + tg.B[2] - 3 - lane);
 #pragma unroll
     for (int k = 0; k < kLinesPerWave; k++) {
-        const int line = wave + kWaves * k;
-        const int a1 = line >> 3, a2 = line & 7;
-        const unsigned p = p0 + (unsigned)(a1 * g.n2 + a2) * line_stride;
-        T e0 = T(1), sv = T(0);
-        if (MODE == TM_ADJOINT) {
-            if (gam) e0 = __builtin_nontemporal_load(gam + p);
-        } else if (MODE == TM_INCSTATE) {
-            sv = __builtin_nontemporal_load(vt1 + p) * __builtin_nontemporal_load(gr1 + p) +
-                 __builtin_nontemporal_load(vt2 + p) * __builtin_nontemporal_load(gr2 + p) +
-                 __builtin_nontemporal_load(vt3 + p) * __builtin_nontemporal_load(gr3 + p);
-        }
+        const int a1 = k;
+        const unsigned o = b0 + (unsigned)(a1 * g.n2 + a2) * line_bytes;
+        // local start l = i_local + floor - 1 - lo, kept in [0, B - 4]
         T w1[4], w2[4], w3[4];
-        const int l1 = canon_base(a1, d[k][0], tg.lo[0], tg.B[0], w1);
-        const int l2 = canon_base(a2, d[k][1], tg.lo[1], tg.B[1], w2);
-        const int l3 = canon_base(lane, d[k][2], tg.lo[2], tg.B[2], w3);
-        const T *base = box + (l1 * K::C2 + l2) * K::C3 + l3;
+        const int l1 = canon_base(d[k][0], T(tg.lo[0] + 1 - a1), T(tg.lo[0] + tg.B[0] - 3 - a1), a1 - 1 - tg.lo[0], w1);
+        const int l2 = canon_base(d[k][1], T(tg.lo[1] + 1 - a2), T(tg.lo[1] + tg.B[1] - 3 - a2), a2 - 1 - tg.lo[1], w2);
+        const int l3 = canon_base(d[k][2], f3min, f3max, lane - 1 - tg.lo[2], w3);
+        // byte offset of the stencil's first value; rows 0-2 of a plane are
+        // read from one base and row 3 (beyond the 255-element reach of a
+        // paired read) from a second one
+        const unsigned eb = (unsigned)((l1 * K::C2 + l2) * K::C3 + l3) * sizeof(T);
+        const char *lds = reinterpret_cast<const char *>(box);
         T acc = T(0);
 #pragma unroll
         for (int a = 0; a < 4; a++) {
+            const T *r0 = reinterpret_cast<const T *>(lds + opaque(eb + a * kPlane * sizeof(T)));
+            const T *r3 = reinterpret_cast<const T *>(lds + opaque(eb + (a * kPlane + 3 * K::C3) * sizeof(T)));
+            T v[4][4];
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) v[b][c] = r0[b * K::C3 + c];
+#pragma unroll
+            for (int c = 0; c < 4; c++) v[3][c] = r3[c];
             T pa = T(0);
 #pragma unroll
-            for (int b = 0; b < 4; b++) {
-                const T *row = base + (a * K::C2 + b) * K::C3;
-                pa += w2[b] * (w3[0] * row[0] + w3[1] * row[1] + w3[2] * row[2] + w3[3] * row[3]);
-            }
+            for (int b = 0; b < 4; b++)
+                pa += w2[b] * (w3[0] * v[b][0] + w3[1] * v[b][1] + w3[2] * v[b][2] + w3[3] * v[b][3]);
             acc += w1[a] * pa;
         }
+        acc *= T(1.0 / 216.0);  // the three scaled weight factors
         if (MODE == TM_INTERP) {
-            out[p] = acc;
+            st_at(out, o, acc);
         } else if (MODE == TM_ADJOINT) {
-            out[p] = acc * e0;
+            st_at(out, o, acc * e[k]);
         } else {
-            const T v = acc + cs * sv;
-            out[p] = last ? -v : v;
+            const T v = acc + cs * e[k];
+            st_at(out, o, last ? -v : v);
         }
     }
 }
@@ -826,18 +884,20 @@ hipError_t launch_tiled(const Grid &g, const TileGeom &tg, const T *f, const T *
     // of the tile) and a floor span the canonical box holds
     const bool whole = g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0;
     const int span = box_span(tg);
-    if (whole && span <= 1 && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 1>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
-        return hipGetLastError();
-    }
-    if (whole && span <= 2 && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
-        return hipGetLastError();
-    }
-    if (whole && span <= kCanonMaxSpan && sizeof(T) == 4) {
-        hipLaunchKernelGGL((k_tiled_canon<T, MODE, kCanonMaxSpan>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f,
-                           D, a);
-        return hipGetLastError();
+    if constexpr (sizeof(T) == 4) {
+        if (whole && span <= 1) {
+            hipLaunchKernelGGL((k_tiled_canon<T, MODE, 1>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
+            return hipGetLastError();
+        }
+        if (whole && span <= 2) {
+            hipLaunchKernelGGL((k_tiled_canon<T, MODE, 2>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg, f, D, a);
+            return hipGetLastError();
+        }
+        if (whole && span <= kCanonMaxSpan) {
+            hipLaunchKernelGGL((k_tiled_canon<T, MODE, kCanonMaxSpan>), dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, tg,
+                               f, D, a);
+            return hipGetLastError();
+        }
     }
     const size_t lds = sizeof(T) * (size_t)tg.B[0] * tg.B[1] * tg.B[2];
     hipLaunchKernelGGL((k_tiled<T, MODE>), dim3(ntiles(g)), dim3(kTileThreads), lds, s, g, tg, f, D, a);
