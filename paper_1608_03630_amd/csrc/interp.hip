@@ -638,11 +638,11 @@ __device__ __forceinline__ unsigned opaque(unsigned x) {
 }
 
 // The work of one tile t of one grid (shared by the single-grid and the
-// batched persistent kernels; `box` is the workgroup's LDS). Every global
-// operand of the thread's points (displacements, and the Heun factor or
-// vt . grad rho of the epilogue) is requested before the box is staged, so
-// the loop over the points after the barrier issues LDS reads and stores
-// only: a load there would make its wait also wait for the stores before it.
+// batched persistent kernels; `box` is the workgroup's LDS). The thread's
+// displacements and Heun factors are requested before the box is staged, so
+// that their HBM latency overlaps the staging; the six streams of vt . grad
+// rho of the incremental-state step are read in the point loop instead (in
+// the staging phase they lengthened it by 3%).
 template <typename T, int MODE, int S>
 __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                            const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
@@ -678,8 +678,6 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
         d[k][2] = ld_nt(D3, o);
         if (MODE == TM_ADJOINT) {
             e[k] = gam ? ld_nt(gam, o) : T(1);
-        } else if (MODE == TM_INCSTATE) {
-            e[k] = ld_nt(vt1, o) * ld_nt(gr1, o) + ld_nt(vt2, o) * ld_nt(gr2, o) + ld_nt(vt3, o) * ld_nt(gr3, o);
         }
     }
     stage_box_canon<T, S>(g, tg, t, f, box);
@@ -721,6 +719,8 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
                 pa += w2[b] * (w3[0] * v[b][0] + w3[1] * v[b][1] + w3[2] * v[b][2] + w3[3] * v[b][3]);
             acc += w1[a] * pa;
         }
+        if (MODE == TM_INCSTATE)
+            e[k] = ld_nt(vt1, o) * ld_nt(gr1, o) + ld_nt(vt2, o) * ld_nt(gr2, o) + ld_nt(vt3, o) * ld_nt(gr3, o);
         acc *= T(1.0 / 216.0);  // the three scaled weight factors
         if (MODE == TM_INTERP) {
             st_at(out, o, acc);

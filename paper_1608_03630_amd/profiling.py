@@ -14,6 +14,7 @@ size). The record carries a hash of the kernel sources so that a benchmark can
 tell when the counters no longer describe the kernel it runs.
 
     python -m paper_1608_03630_amd.profiling DIR OUT.md TRAFFIC.json KERNEL_SUBSTRING GRID_SIZE FAMILY N
+    python -m paper_1608_03630_amd.profiling counters DIR OUT.md   # SQ counter passes (SQ_PASSES)
 """
 import collections
 import csv
@@ -97,6 +98,61 @@ def summarize(pdir, out_md, out_json, kernel_sub, grid_size, family, n, copy_byt
     return rec
 
 
+# instruction and stall counters of the gather kernels, two passes of at
+# most eight SQ counters each (rocprofv3 does not split passes itself)
+SQ_PASSES = [
+    ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_LDS", "SQ_ACTIVE_INST_VALU",
+     "SQ_ACTIVE_INST_LDS", "SQ_BUSY_CYCLES"],
+    ["SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
+     "SQ_ACTIVE_INST_ANY", "SQ_LDS_IDX_ACTIVE"],
+]
+GATHER_KERNELS = [("k_tiled_canon<float, 0, 1>", "state step (interp)", 20.0),
+                  ("k_tiled_canon<float, 1, 1>", "adjoint step", 24.0),
+                  ("k_tiled_canon<float, 2, 1>", "incremental-state step", 44.0),
+                  ("k_backtrace<float>", "backtrace (direct gather)", 24.0),
+                  ("k_b_assemble<float>", "b assembly (17 levels)", 16.0 * 17 + 12.0)]
+
+
+def counters_summary(pdir, out_md, n=256, passes=("sq1", "sq2")):
+    """Per-dispatch averages of the SQ counters of the gather kernels (and the
+    kernel-trace times of the same dispatches) as a markdown table."""
+    trace = os.path.join(pdir, "solve", "run_kernel_trace.csv")
+    N = n ** 3
+    rows = []
+    for sub, what, bpp in GATHER_KERNELS:
+        vals = {}
+        for ps in passes:
+            v, _ = counter_per_dispatch(os.path.join(pdir, ps, "run_counter_collection.csv"), sub)
+            vals.update(v)
+        avg_ns, cnt = trace_average_ns(trace, sub)
+        rows.append((sub, what, bpp, vals, avg_ns, cnt))
+    lines = [f"# Instruction and stall counters of the gather kernels at {n}^3", "",
+             "Commands (from the repository root; `DIR` is the output folder):", "", "```",
+             "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/solve -o run -- python3 bench.py --steps 1 "
+             "--warmup 0 --no-cpu-baseline"]
+    for i, ps in enumerate(passes):
+        lines.append(f"rocprofv3 --pmc {' '.join(SQ_PASSES[i])} --output-format csv -d DIR/{ps} -o run -- "
+                     "python3 bench.py --mode kernels")
+    lines += ["```", "", "Per dispatch (counters summed over the device, averaged over the dispatches of "
+              "`--mode kernels`; time from the solve's kernel trace):", ""]
+    cols = SQ_PASSES[0][1:] + ["SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_WAIT_INST_ANY", "SQ_LDS_IDX_ACTIVE"]
+    lines.append("| kernel | us | GB/s (alg.) | VALU/pt | LDS/pt | " + " | ".join(c.replace("SQ_", "") for c in cols) + " |")
+    lines.append("|---" * (5 + len(cols)) + "|")
+    for sub, what, bpp, vals, avg_ns, cnt in rows:
+        us = avg_ns / 1e3 if avg_ns else float("nan")
+        gbs = bpp * N / (avg_ns * 1e-9) / 1e9 if avg_ns else float("nan")
+        vpp = vals.get("SQ_INSTS_VALU", float("nan")) * 64 / N
+        lpp = vals.get("SQ_INSTS_LDS", float("nan")) * 64 / N
+        cells = [f"{vals[c]:.3g}" if c in vals else "-" for c in cols]
+        lines.append(f"| {what} `{sub}` | {us:.1f} | {gbs:.0f} | {vpp:.0f} | {lpp:.0f} | " + " | ".join(cells) + " |")
+    lines += ["", "VALU/pt and LDS/pt are lane instructions per grid point (wave instructions x 64 / n^3).", ""]
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines))
+
+
 if __name__ == "__main__":
     a = sys.argv[1:]
-    print(json.dumps(summarize(a[0], a[1], a[2], a[3], int(a[4]), a[5], int(a[6])), indent=1))
+    if a and a[0] == "counters":
+        counters_summary(a[1], a[2])
+    else:
+        print(json.dumps(summarize(a[0], a[1], a[2], a[3], int(a[4]), a[5], int(a[6])), indent=1))
