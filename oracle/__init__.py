@@ -40,7 +40,7 @@ class Params(ctypes.Structure):
         ("max_newton", ctypes.c_int32),
         ("max_pcg", ctypes.c_int32),
         ("max_ls", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("hessian", ctypes.c_int32),
         ("armijo_c1", ctypes.c_double),
         ("gtol_level", ctypes.c_double),
         ("gnorm_ref", ctypes.c_double),
@@ -97,7 +97,8 @@ class Report(ctypes.Structure):
 
 
 def params(n, nt, beta, isochoric=False, beta_final=0.0, beta_factor=0.1, gtol=1e-2, mismatch_tol=0.0,
-           max_newton=50, max_pcg=100, max_ls=20, forcing=0, armijo_c1=1e-4, gtol_level=0.0, gnorm_ref=0.0):
+           max_newton=50, max_pcg=100, max_ls=20, forcing=0, armijo_c1=1e-4, gtol_level=0.0, gnorm_ref=0.0,
+           hessian=0):
     p = Params()
     n = tuple(int(x) for x in (n if np.ndim(n) else (n, n, n)))
     p.n[:] = n
@@ -112,7 +113,7 @@ def params(n, nt, beta, isochoric=False, beta_final=0.0, beta_factor=0.1, gtol=1
     p.max_newton = int(max_newton)
     p.max_pcg = int(max_pcg)
     p.max_ls = int(max_ls)
-    p.reserved = 0
+    p.hessian = int(hessian)
     p.armijo_c1 = float(armijo_c1)
     p.gtol_level = float(gtol_level)
     p.gnorm_ref = float(gnorm_ref)
@@ -151,6 +152,7 @@ def _load():
         "oracle_transport_adjoint": (I, [P, P, P, P]),
         "oracle_gradient": (I, [P, P, P, P, P, P, P]),
         "oracle_hessian_matvec": (I, [P, P, P, P, P]),
+        "oracle_newton_matvec": (I, [P, P, P, P, P, P]),
         "oracle_objective": (I, [P, P, P, P, P, P]),
         "oracle_deformation": (I, [P, P, P, P, P, P]),
         "oracle_solve": (I, [P, P, P, P, P]),
@@ -354,6 +356,14 @@ def hessian_matvec(P, rhoT, v, vt):
     rhoT, v, vt = _f64(rhoT), _f64(v), _f64(vt)
     out = np.empty_like(vt)
     _chk(_load().oracle_hessian_matvec(ctypes.byref(P), _p(rhoT), _p(v), _p(vt), _p(out)), "hessian_matvec")
+    return out
+
+
+def newton_matvec(P, rhoT, rhoR, v, vt):
+    """Full Newton H(v) vt (every term of eqs. (5a)-(5e))."""
+    rhoT, rhoR, v, vt = _f64(rhoT), _f64(rhoR), _f64(v), _f64(vt)
+    out = np.empty_like(vt)
+    _chk(_load().oracle_newton_matvec(ctypes.byref(P), _p(rhoT), _p(rhoR), _p(v), _p(vt), _p(out)), "newton_matvec")
     return out
 
 

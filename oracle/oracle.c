@@ -516,7 +516,7 @@ typedef struct {
     int32_t forcing; /* 0: eta = min(0.5, r), 1: eta = min(0.5, sqrt(r)), r = |g|/|g0| */
     double gtol, mismatch_tol;
     int32_t max_newton, max_pcg, max_ls;
-    int32_t reserved;
+    int32_t hessian; /* 0: Gauss-Newton (the paper's runs), 1: full Newton */
     double armijo_c1;
     /* Continuation and stopping (section III-A leaves both to the
      * application): gtol_level > 0 solves the levels above beta_final only
@@ -606,9 +606,10 @@ static void accumulate_b(const oracle_state_t *s, const double *lam, double *b) 
     }
 }
 
-/* g = beta lap^2 v + P b with b = int lam grad rho dt (eq. (4)) */
+/* g = beta lap^2 v + P b with b = int lam grad rho dt (eq. (4)); the
+ * adjoint history is copied to lam_out when it is not NULL */
 static void gradient_from_state(const oracle_state_t *s, double beta, const double *v, const double *rhoR,
-                                double *g) {
+                                double *g, double *lam_out) {
     long N = s->N;
     int nt = s->nt;
     double *lam = xmalloc(sizeof(double) * (nt + 1) * N);
@@ -616,6 +617,7 @@ static void gradient_from_state(const oracle_state_t *s, double beta, const doub
     const double *r1 = s->rho + (long)nt * N;
     for (long p = 0; p < N; p++) lam1[p] = rhoR[p] - r1[p];
     oracle_adjoint(s->n, nt, s->Da, s->c, s->cX, lam1, lam);
+    if (lam_out) memcpy(lam_out, lam, sizeof(double) * (nt + 1) * N);
     double *b = xmalloc(sizeof(double) * 3 * N);
     accumulate_b(s, lam, b);
     assemble(s->n, beta, s->iso, v, b, g);
@@ -658,6 +660,78 @@ static void hessian_from_state(const oracle_state_t *s, double beta, const doubl
     free(f0);
     free(lam);
     free(bt);
+}
+
+/* Full Newton Hessian matvec (eqs. (5a)-(5e) with every term): the
+ * incremental adjoint carries the source div(lam vt) of eq. (5c), and b~
+ * gains the term int lam grad rho~ dt. lam is the adjoint history of the
+ * gradient at the same v (levels 0..nt). Each step of the incremental
+ * adjoint is eq. (7) written out with f(nu, x, tau) = nu c(x) + s(x, tau),
+ * s = div(lam vt) at the step's two time levels:
+ *   nu0 = nu(X), f0 = nu0 c(X) + s^k(X), nu* = nu0 + dt f0,
+ *   f* = nu* c(x) + s^{k-1}(x), nu_new = nu0 + dt/2 (f0 + f*). */
+static void newton_from_state(const oracle_state_t *s, double beta, const double *lamg, const double *vt,
+                              double *Hvt) {
+    long N = s->N;
+    int nt = s->nt;
+    double dt = 1.0 / nt;
+    /* incremental state history rho~^0..rho~^nt with f = -vt . grad rho */
+    double *src = xmalloc(sizeof(double) * (nt + 1) * N);
+    for (int k = 0; k <= nt; k++)
+        for (long p = 0; p < N; p++) {
+            const double *gr = s->grho + (long)k * 3 * N;
+            src[(long)k * N + p] = -(vt[p] * gr[p] + vt[N + p] * gr[N + p] + vt[2 * N + p] * gr[2 * N + p]);
+        }
+    double *rt = xmalloc(sizeof(double) * (nt + 1) * N), *nu0 = xmalloc(sizeof(double) * N),
+           *f0 = xmalloc(sizeof(double) * N);
+    memset(rt, 0, sizeof(double) * N);
+    for (int k = 0; k < nt; k++) {
+        oracle_interp(s->n, rt + (long)k * N, s->Df, nu0);
+        oracle_interp(s->n, src + (long)k * N, s->Df, f0);
+        for (long p = 0; p < N; p++)
+            rt[(long)(k + 1) * N + p] = nu0[p] + 0.5 * dt * (f0[p] + src[(long)(k + 1) * N + p]);
+    }
+    /* sources s^k = div(lam^k vt) of the incremental adjoint */
+    double *sk = xmalloc(sizeof(double) * (nt + 1) * N), *lv = xmalloc(sizeof(double) * 3 * N);
+    for (int k = 0; k <= nt; k++) {
+        for (int j = 0; j < 3; j++)
+            for (long p = 0; p < N; p++) lv[j * N + p] = lamg[(long)k * N + p] * vt[j * N + p];
+        oracle_div(s->n, lv, sk + (long)k * N);
+    }
+    /* incremental adjoint lam~^nt..lam~^0 from lam~(1) = -rho~(1) */
+    double *lam = xmalloc(sizeof(double) * (nt + 1) * N), *sX = xmalloc(sizeof(double) * N);
+    for (long p = 0; p < N; p++) lam[(long)nt * N + p] = -rt[(long)nt * N + p];
+    for (int k = nt; k > 0; k--) {
+        oracle_interp(s->n, lam + (long)k * N, s->Da, nu0);
+        oracle_interp(s->n, sk + (long)k * N, s->Da, sX);
+        for (long p = 0; p < N; p++) {
+            double cx = s->c ? s->c[p] : 0.0, cX = s->cX ? s->cX[p] : 0.0;
+            double f00 = nu0[p] * cX + sX[p];
+            double nus = nu0[p] + dt * f00;
+            double fs = nus * cx + sk[(long)(k - 1) * N + p];
+            lam[(long)(k - 1) * N + p] = nu0[p] + 0.5 * dt * (f00 + fs);
+        }
+    }
+    /* b~ = sum_n w_n (lam~^n grad rho^n + lam^n grad rho~^n) */
+    double *bt = xmalloc(sizeof(double) * 3 * N), *gt = xmalloc(sizeof(double) * 3 * N);
+    accumulate_b(s, lam, bt);
+    for (int k = 0; k <= nt; k++) {
+        double w = trap_w(k, nt);
+        oracle_grad(s->n, rt + (long)k * N, gt);
+        for (int j = 0; j < 3; j++)
+            for (long p = 0; p < N; p++) bt[j * N + p] += w * lamg[(long)k * N + p] * gt[j * N + p];
+    }
+    assemble(s->n, beta, s->iso, vt, bt, Hvt);
+    free(src);
+    free(rt);
+    free(nu0);
+    free(f0);
+    free(sk);
+    free(lv);
+    free(lam);
+    free(sX);
+    free(bt);
+    free(gt);
 }
 
 static int check_params(const oracle_params *P) {
@@ -714,7 +788,7 @@ int oracle_gradient(const oracle_params *P, const double *rhoT, const double *rh
     st_complete(&s, v);
     double mis;
     double j = objective(&s, P->beta, v, rhoT, rhoR, &mis);
-    gradient_from_state(&s, P->beta, v, rhoR, g);
+    gradient_from_state(&s, P->beta, v, rhoR, g, NULL);
     if (J) *J = j;
     if (mismatch) *mismatch = mis;
     st_free(&s);
@@ -729,6 +803,26 @@ int oracle_hessian_matvec(const oracle_params *P, const double *rhoT, const doub
     st_forward(&s, P->n, P->nt, P->isochoric, v, rhoT);
     st_complete(&s, v);
     hessian_from_state(&s, P->beta, vt, Hvt);
+    st_free(&s);
+    return 0;
+}
+
+/* exported: full Newton H(v) vt (needs rho_R for the adjoint history) */
+int oracle_newton_matvec(const oracle_params *P, const double *rhoT, const double *rhoR, const double *v,
+                         const double *vt, double *Hvt) {
+    if (check_params(P)) return 1;
+    oracle_state_t s;
+    st_forward(&s, P->n, P->nt, P->isochoric, v, rhoT);
+    st_complete(&s, v);
+    long N = s.N;
+    int nt = s.nt;
+    double *lam = xmalloc(sizeof(double) * (nt + 1) * N), *lam1 = xmalloc(sizeof(double) * N);
+    const double *r1 = s.rho + (long)nt * N;
+    for (long p = 0; p < N; p++) lam1[p] = rhoR[p] - r1[p];
+    oracle_adjoint(s.n, nt, s.Da, s.c, s.cX, lam1, lam);
+    newton_from_state(&s, P->beta, lam, vt, Hvt);
+    free(lam);
+    free(lam1);
     st_free(&s);
     return 0;
 }
@@ -810,6 +904,8 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
     double *g = xmalloc(sizeof(double) * N3), *s = xmalloc(sizeof(double) * N3), *r = xmalloc(sizeof(double) * N3);
     double *z = xmalloc(sizeof(double) * N3), *pp = xmalloc(sizeof(double) * N3), *q = xmalloc(sizeof(double) * N3);
     double *vtrial = xmalloc(sizeof(double) * N3);
+    /* adjoint history of the current gradient (full Newton only) */
+    double *lamg = P->hessian ? xmalloc(sizeof(double) * (P->nt + 1) * N) : NULL;
 
     if (P->isochoric) {
         oracle_leray(n, v, vtrial);
@@ -825,7 +921,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
         st_forward(&st, n, P->nt, P->isochoric, v, rhoT);
         st_complete(&st, v);
         J = objective(&st, beta, v, rhoT, rhoR, &mis);
-        gradient_from_state(&st, beta, v, rhoR, g);
+        gradient_from_state(&st, beta, v, rhoR, g, lamg);
         rep->gradients++;
         gnorm = norm3(n, g);
         g0 = (first_level && P->gref_first > 0) ? P->gref_first : gnorm;
@@ -853,7 +949,8 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
             double rz = inner(n, 3, r, z);
             int iters = 0;
             for (int i = 0; i < P->max_pcg; i++) {
-                hessian_from_state(&st, beta, pp, q);
+                if (P->hessian) newton_from_state(&st, beta, lamg, pp, q);
+                else hessian_from_state(&st, beta, pp, q);
                 rep->matvecs++;
                 iters = i + 1;
                 double kappa = inner(n, 3, pp, q);
@@ -904,7 +1001,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
             st_complete(&st, v);
             J = Jt;
             mis = mist;
-            gradient_from_state(&st, beta, v, rhoR, g);
+            gradient_from_state(&st, beta, v, rhoR, g, lamg);
             rep->gradients++;
             gnorm = norm3(n, g);
             if (it < ORACLE_MAXIT) {
@@ -945,6 +1042,7 @@ out:
     free(pp);
     free(q);
     free(vtrial);
+    free(lamg);
     return rep->status;
 }
 

@@ -94,9 +94,41 @@ def newton_orders(orc):
     return {"defect": defects, "order": orders(defects, [n for n, _ in JOINT_LEVELS])}
 
 
+def full_newton_orders(orc):
+    """At v = v*/2 (lam != 0) central differences of g against the full Newton
+    matvec and against the Gauss-Newton matvec over JOINT_LEVELS, and the
+    Newton matvec's symmetry defect."""
+    dn, dg, sym = [], [], []
+    for n, nt in JOINT_LEVELS:
+        shape = (n, n, n)
+        case = synth.smooth_case(shape)
+        P = orc.params(shape, nt, 1e-2)
+        rhoR = orc.transport_forward(P, case["v_true"], case["rhoT"])
+        v = 0.5 * case["v_true"]
+        vt = synth.smooth_random_field(shape, 41, kmax=2, ncomp=3)
+        Hn = orc.newton_matvec(P, case["rhoT"], rhoR, v, vt)
+        Hg = orc.hessian_matvec(P, case["rhoT"], v, vt)
+        eps = 1e-4
+        gp, _, _ = orc.gradient(P, case["rhoT"], rhoR, v + eps * vt)
+        gm, _, _ = orc.gradient(P, case["rhoT"], rhoR, v - eps * vt)
+        fd = (gp - gm) / (2 * eps)
+        dn.append(np.sqrt(inner(fd - Hn, fd - Hn) / inner(fd, fd)))
+        dg.append(np.sqrt(inner(fd - Hg, fd - Hg) / inner(fd, fd)))
+        u = synth.smooth_random_field(shape, 39, kmax=2, ncomp=3)
+        w = synth.smooth_random_field(shape, 40, kmax=2, ncomp=3)
+        Hu = orc.newton_matvec(P, case["rhoT"], rhoR, v, u)
+        Hw = orc.newton_matvec(P, case["rhoT"], rhoR, v, w)
+        sym.append(abs(inner(Hu, w) - inner(u, Hw)) / abs(inner(Hu, w)))
+    sizes = [n for n, _ in JOINT_LEVELS]
+    return {"newton": dn, "newton_order": orders(dn, sizes), "gauss_newton": dg, "symmetry": sym,
+            "symmetry_order": orders(sym, sizes)}
+
+
 if __name__ == "__main__":
     import oracle
 
     oracle._load()
     out = {"time": time_orders(oracle), "symmetry": symmetry_orders(oracle), "newton": newton_orders(oracle)}
+    if "--full-newton" in sys.argv:
+        out["full_newton"] = full_newton_orders(oracle)
     print(json.dumps(out, default=float))
