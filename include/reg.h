@@ -93,7 +93,10 @@ typedef struct {
                             * 2^(L-1), ..., 2 per axis, then on n (L = grid_levels, at most
                             * REG_MAXLEVELS; 0 or 1: n only). Every coarse grid must itself be a
                             * valid n. Fixes the workspace size: reg_set_solver may lower it only. */
-    int32_t reserved_;     /* zero */
+    int32_t hessian;       /* 0: Gauss-Newton (the paper's runs, section IV-A3); 1: full Newton
+                            * (eqs. (5a)-(5e) with both lam terms). 1 needs a workspace laid
+                            * out for it (an extra adjoint history): reg_set_solver cannot
+                            * switch a Gauss-Newton context to it. Single contexts only. */
 } reg_params;
 
 #define REG_MAXIT 512
@@ -235,9 +238,12 @@ reg_status reg_gradient(reg_ctx *ctx, const void *v, void *g, double *J, double 
 /* Objective and relative mismatch only (plan + state solve). Synchronises. */
 reg_status reg_objective(reg_ctx *ctx, const void *v, double *J, double *mismatch);
 
-/* Gauss-Newton Hessian matvec at the velocity of the last reg_gradient
+/* Hessian matvec at the velocity of the last reg_gradient: Gauss-Newton
  * (eqs. (5a)-(5e) without the two adjoint terms, section II-B): incremental
- * state, incremental adjoint, H vt = beta lap^2 vt + P b~. */
+ * state, incremental adjoint, H vt = beta lap^2 vt + P b~; with
+ * params.hessian = 1 the full Newton matvec, whose incremental adjoint has
+ * the source div(lam vt) and whose b~ adds int lam grad rho~ dt (lam: the
+ * adjoint of that reg_gradient). */
 reg_status reg_hessian_matvec(reg_ctx *ctx, const void *vt, void *Hvt);
 
 /* Gauss-Newton-Krylov solve (section III-A): truncated PCG with the spectral

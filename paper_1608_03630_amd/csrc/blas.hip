@@ -145,9 +145,96 @@ __global__ __launch_bounds__(kThreads) void k_convert(long n, const Ti *__restri
     if (i < n) y[i] = To(x[i]);
 }
 
+// Streaming kernels of the full Newton Hessian matvec (eqs. (5a)-(5e) with
+// the lam terms of section II-B).
+
+// out_j = lam * vt_j for the three components
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale_vec(long n, const T *__restrict__ lam, const T *__restrict__ vt,
+                                                        T *__restrict__ out) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const T l = lam[i];
+    out[i] = l * vt[i];
+    out[n + i] = l * vt[n + i];
+    out[2 * n + i] = l * vt[2 * n + i];
+}
+
+// q += cs * (vt . grad)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_add_vdotgrad(long n, const T *__restrict__ vt, const T *__restrict__ g,
+                                                           T *__restrict__ q, T cs) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    q[i] += cs * (vt[i] * g[i] + vt[n + i] * g[n + i] + vt[2 * n + i] * g[2 * n + i]);
+}
+
+// The source part of one incremental-adjoint step with f = nu c + s (eq. (7)
+// expanded; the nu part, nu(X) gam, is already in out):
+// out += s(X) dt/2 (1 + dt c) + dt/2 s_next, c = div v (null: 0)
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_newton_source(long n, const T *__restrict__ sX,
+                                                            const T *__restrict__ s_next, const T *__restrict__ c,
+                                                            T dt, T *__restrict__ out) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const T h = T(0.5) * dt;
+    const T a = c ? h * (T(1) + dt * c[i]) : h;
+    out[i] += a * sX[i] + h * s_next[i];
+}
+
+// b_j += w lam g_j for the three components
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_b_axpy(long n, T w, const T *__restrict__ lam, const T *__restrict__ g,
+                                                     T *__restrict__ b) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const T s = w * lam[i];
+    b[i] += s * g[i];
+    b[n + i] += s * g[n + i];
+    b[2 * n + i] += s * g[2 * n + i];
+}
+
+// y = a x
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scale(long n, T a, const T *__restrict__ x, T *__restrict__ y) {
+    const long i = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
 inline unsigned nb(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+template <typename T>
+hipError_t launch_scale_vec(long n, const T *lam, const T *vt, T *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_vec<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, lam, vt, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_add_vdotgrad(long n, const T *vt, const T *g, T *q, double cs, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_vdotgrad<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, vt, g, q, T(cs));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_newton_source(long n, const T *sX, const T *s_next, const T *c, double dt, T *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_newton_source<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, sX, s_next, c, T(dt), out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_b_axpy(long n, double w, const T *lam, const T *g, T *b, hipStream_t s) {
+    hipLaunchKernelGGL(k_b_axpy<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(w), lam, g, b);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scale(long n, double a, const T *x, T *y, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale<T>, dim3(nb(n)), dim3(kThreads), 0, s, n, T(a), x, y);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_dot_partials(const T *a, const T *b, long n, int mode, double *partials, hipStream_t s) {
@@ -195,7 +282,12 @@ template hipError_t launch_convert<float, double>(long, const float *, double *,
     template hipError_t launch_dot_partials<T>(const T *, const T *, long, int, double *, hipStream_t);            \
     template hipError_t launch_det_partials<T>(const T *, long, double *, double *, T *, hipStream_t);             \
     template hipError_t launch_fill<T>(long, double, T *, hipStream_t);                                            \
-    template hipError_t launch_copy<T>(long, const T *, T *, hipStream_t);
+    template hipError_t launch_copy<T>(long, const T *, T *, hipStream_t);                                          \
+    template hipError_t launch_scale_vec<T>(long, const T *, const T *, T *, hipStream_t);                         \
+    template hipError_t launch_add_vdotgrad<T>(long, const T *, const T *, T *, double, hipStream_t);             \
+    template hipError_t launch_newton_source<T>(long, const T *, const T *, const T *, double, T *, hipStream_t);  \
+    template hipError_t launch_b_axpy<T>(long, double, const T *, const T *, T *, hipStream_t);                    \
+    template hipError_t launch_scale<T>(long, double, const T *, T *, hipStream_t);
 
 REGK_BLAS_INST(float)
 REGK_BLAS_INST(double)

@@ -219,6 +219,8 @@ reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p) {
         return fail(ctx, REG_EINVAL, "n, nt and prec are fixed at reg_create");
     int chain = 1;
     for (reg_ctx *c = ctx->coarse; c; c = c->coarse) chain++;
+    if (p->hessian && !ctx->lamg)
+        return fail(ctx, REG_EINVAL, "full Newton (hessian = 1) needs a context created with hessian = 1");
     if (grid_count(p) > chain)
         return fail(ctx, REG_EINVAL, "grid_levels = " + std::to_string(p->grid_levels) + " exceeds the " +
                                          std::to_string(chain) + " grid(s) the workspace was laid out for");

@@ -222,5 +222,18 @@ hipError_t launch_copy(long n, const T *x, T *y, hipStream_t s);
 // y = (To) x, element by element
 template <typename Ti, typename To>
 hipError_t launch_convert(long n, const Ti *x, To *y, hipStream_t s);
+// full Newton matvec: out_j = lam vt_j (3 components); q += cs (vt . g);
+// out += s(X) dt/2 (1 + dt c) + dt/2 s_next (c null: 0); b_j += w lam g_j;
+// y = a x
+template <typename T>
+hipError_t launch_scale_vec(long n, const T *lam, const T *vt, T *out, hipStream_t s);
+template <typename T>
+hipError_t launch_add_vdotgrad(long n, const T *vt, const T *g, T *q, double cs, hipStream_t s);
+template <typename T>
+hipError_t launch_newton_source(long n, const T *sX, const T *s_next, const T *c, double dt, T *out, hipStream_t s);
+template <typename T>
+hipError_t launch_b_axpy(long n, double w, const T *lam, const T *g, T *b, hipStream_t s);
+template <typename T>
+hipError_t launch_scale(long n, double a, const T *x, T *y, hipStream_t s);
 
 }  // namespace regk

@@ -140,6 +140,7 @@ struct reg_ctx {
     // workspace views
     void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec;
     void *lamh;        // adjoint levels lam^0..lam^nt
+    void *lamg;        // full Newton: the adjoint levels of the last gradient (null otherwise)
     void *gam, *gam2;  // Heun factor of the adjoint source (cached plan, scratch plan)
     void *vf, *vtf;                                            // velocity copies in the field type
     // velocity space, spectral: [3][Nh] complex double (see vec_symbol)
@@ -273,6 +274,10 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
         *why = "gtol_level must be >= 0 and finite";
         return REG_EINVAL;
     }
+    if (p->hessian != 0 && p->hessian != 1) {
+        *why = "hessian must be 0 (Gauss-Newton) or 1 (full Newton)";
+        return REG_EINVAL;
+    }
     if (p->grid_levels < 0 || p->grid_levels > REG_MAXLEVELS) {
         *why = "grid_levels must be in [0, " + std::to_string(REG_MAXLEVELS) + "]";
         return REG_EINVAL;
@@ -322,6 +327,7 @@ inline size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->lam[0] = L.take(E * N);
     c->lam[1] = L.take(E * N);
     c->lamh = L.take(E * N * nt1);
+    c->lamg = p->hessian ? L.take(E * N * nt1) : nullptr;
     c->gam = L.take(E * N);
     c->gam2 = L.take(E * N);
     c->bvec = L.take(E * 3 * N);

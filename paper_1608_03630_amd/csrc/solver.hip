@@ -223,6 +223,75 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
     return REG_OK;
 }
 
+// Full Newton Hessian matvec of one context (eqs. (5a)-(5e) with both lam
+// terms; single contexts only), from the plans, state history, grad rho^n,
+// div v and its Heun factor of the last gradient and that gradient's adjoint
+// levels (lamg):
+// * incremental state with every level kept (histB, free between a gradient
+//   and the next line search): the fused form q^{n+1} = q^n(X) - dt s^{n+1},
+//   s = vt . grad rho, with rho~^n = q^n + dt/2 s^n;
+// * incremental adjoint from lam~(1) = -rho~(1) with the source
+//   s~ = div(lam vt): each step (eq. (7) expanded) is
+//   lam~(X) gam + s~^k(X) dt/2 (1 + dt c) + dt/2 s~^{k-1};
+// * b~ = sum_n w_n (lam~^n grad rho^n + lam^n grad rho~^n), then the
+//   assembly of the Gauss-Newton matvec.
+// Scratch: du (lam vt and grad rho~^n) and u0 (two source levels and s~(X)).
+template <typename T>
+reg_status newton_matvec(reg_ctx *ctx, const Request &r) {
+    const long N = ctx->N;
+    const int nt = ctx->P.nt;
+    const double dt = 1.0 / nt;
+    hipStream_t st = ctx->stream;
+    if (r.pre) STCHK(field_from_krylov<T>(ctx, r.x, ctx->vtf));
+    else STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
+    const T *vt = CV<T>(ctx->vtf), *grho = CV<T>(ctx->grho), *lamg = CV<T>(ctx->lamg);
+    T *rt = V<T>(ctx->histB), *lam = V<T>(ctx->lamh), *bt = V<T>(ctx->bvec), *w3 = V<T>(ctx->du);
+    T *s_cur = V<T>(ctx->u0), *s_next = s_cur + N, *sX = s_cur + 2 * N;
+    // incremental state: q^0 = -dt/2 s^0, q^{k+1} = q^k(X) - dt s^{k+1},
+    // the last step rho~^nt = q^{nt-1}(X) - dt/2 s^nt
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, vt, grho, rt, -0.5 * dt, st)));
+    for (int k = 0; k < nt; k++) {
+        const bool last = k == nt - 1;
+        HIPCHK(ctx, KL(ctx, REG_K_INCSTATE, regk::launch_incstate_step<T>(
+                                                ctx->g, rt + (long)k * N, CV<T>(ctx->Df), vt, grho + (long)(k + 1) * 3 * N,
+                                                rt + (long)(k + 1) * N, last ? -0.5 * dt : -dt, 0, st,
+                                                geom_of(ctx, ctx->Df))));
+    }
+    // rho~^k = q^k + dt/2 s^k (k = 1..nt-1); rho~^0 = 0
+    for (int k = 1; k < nt; k++)
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_add_vdotgrad<T>(N, vt, grho + (long)k * 3 * N, rt + (long)k * N,
+                                                                      0.5 * dt, st)));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<T>(N, 0.0, rt, st)));
+    // lam~(1) = -rho~(1)
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_scale<T>(N, -1.0, rt + (long)nt * N, lam + (long)nt * N, st)));
+    // incremental adjoint with the source div(lam vt)
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_scale_vec<T>(N, lamg + (long)nt * N, vt, w3, st)));
+    STCHK(divergence<T>(ctx, w3, s_cur));
+    const T *gam = ctx->P.isochoric ? nullptr : CV<T>(ctx->gam);
+    const T *cdiv = ctx->P.isochoric ? nullptr : CV<T>(ctx->c);
+    for (int k = nt; k > 0; k--) {
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_scale_vec<T>(N, lamg + (long)(k - 1) * N, vt, w3, st)));
+        STCHK(divergence<T>(ctx, w3, s_next));
+        HIPCHK(ctx, KL(ctx, REG_K_ADJOINT, regk::launch_adjoint_step<T>(ctx->g, lam + (long)k * N, CV<T>(ctx->Da), gam,
+                                                                        lam + (long)(k - 1) * N, st,
+                                                                        geom_of(ctx, ctx->Da))));
+        HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, s_cur, CV<T>(ctx->Da), sX, st,
+                                                                 geom_of(ctx, ctx->Da))));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_newton_source<T>(N, sX, s_next, cdiv, dt, lam + (long)(k - 1) * N,
+                                                                        st)));
+        std::swap(s_cur, s_next);
+    }
+    // b~ = sum_n w_n lam~^n grad rho^n + sum_n w_n lam^n grad rho~^n
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, lam, grho, bt, st)));
+    for (int k = 0; k <= nt; k++) {
+        const double w = (k == 0 || k == nt) ? 0.5 * dt : dt;
+        STCHK(gradient_fields<T>(ctx, rt + (long)k * N, 1, w3));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_axpy<T>(N, w, lamg + (long)k * N, w3, bt, st)));
+    }
+    if (r.pre) return curvature<T>(ctx, r.x, ctx->bvec, 0);
+    return assemble<T>(ctx, r.x, ctx->bvec, r.y, r.dot ? 1 : 0, 0);
+}
+
 // Operands of one semi-Lagrangian step of one problem.
 template <typename T>
 struct StepArg {
@@ -483,6 +552,10 @@ struct Exec {
                 if (r.op == Op::GRADIENT || r.op == Op::MATVEC)
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, CV<T>(ctx->lamh), CV<T>(ctx->grho),
                                                                                  V<T>(ctx->bvec), ctx->stream)));
+                // the full Newton matvecs at this velocity need its adjoint history
+                if (r.op == Op::GRADIENT && ctx->P.hessian)
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>((long)(nt + 1) * N, CV<T>(ctx->lamh),
+                                                                           V<T>(ctx->lamg), ctx->stream)));
                 if (r.op == Op::GRADIENT) {
                     // g^ = beta |k|^4 v^ + P FFT(b); J and |g|^2 by Parseval
                     STCHK(biharm_partials(ctx, ctx->vhat));
@@ -506,7 +579,7 @@ struct Exec {
         case Op::GRADIENT: ctx->interps += (it.req.reuse ? 0 : nt) + (ctx->P.isochoric ? 0 : 1) + nt; break;
         case Op::OBJECTIVE:
         case Op::FORWARD: ctx->interps += nt; break;
-        case Op::MATVEC: ctx->interps += 2 * nt; break;
+        case Op::MATVEC: ctx->interps += (ctx->P.hessian ? 3 : 2) * nt; break;
         default: break;
         }
     }
@@ -618,7 +691,8 @@ struct Exec {
         std::vector<Item> eager, mv;
         for (auto &it : items) {
             count(it);
-            if (b && b->use_graph && it.req.op == Op::MATVEC) mv.push_back(it);
+            if (it.req.op == Op::MATVEC && it.ctx->P.hessian) STCHK(newton_matvec<T>(it.ctx, it.req));
+            else if (b && b->use_graph && it.req.op == Op::MATVEC) mv.push_back(it);
             else eager.push_back(it);
         }
         if (!eager.empty()) {
@@ -1112,6 +1186,10 @@ reg_status check_batch(const reg_params *pp, int32_t n, std::string *why) {
         }
         if (grid_count(&pp[i]) > 1) {
             *why = "pair " + std::to_string(i) + ": grid continuation (grid_levels > 1) is a single-context solve";
+            return REG_EINVAL;
+        }
+        if (pp[i].hessian) {
+            *why = "pair " + std::to_string(i) + ": the full Newton Hessian (hessian = 1) is a single-context option";
             return REG_EINVAL;
         }
     }

@@ -54,7 +54,7 @@ class reg_params(ctypes.Structure):
         ("gnorm_ref", ctypes.c_double),
         ("gtol_level", ctypes.c_double),
         ("grid_levels", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("hessian", ctypes.c_int32),
     ]
 
 
