@@ -69,7 +69,7 @@ typedef enum {
  * the paper's runs (section IV-A3): beta = 1e-2, nt = 4, gradient tolerance
  * 1e-2, quadratic forcing, no continuation, no incompressibility. */
 typedef struct {
-    int32_t n[3];          /* grid; each even, 2^a 3^b, 8 <= n <= 1024            */
+    int32_t n[3];          /* grid; each even, 2^a 3^b 5^c, 8 <= n <= 1024        */
     int32_t nt;            /* time steps, >= 1                                    */
     double beta;           /* regularisation weight (> 0); first continuation level */
     double beta_final;     /* last continuation level; <= 0 means no continuation */
@@ -210,6 +210,19 @@ reg_status reg_spectral(reg_ctx *ctx, int op, double scale, int ncomp, const voi
  * warm start. Work is enqueued on src's stream and uses both contexts'
  * spectral scratch. */
 reg_status reg_resample(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out);
+
+/* Front end for images that are not periodic (section III-B1): zero padding.
+ * img is an m[0] x m[1] x m[2] field-type array (C order, each m[j] <= n[j]);
+ * out (the context's grid) receives it at offset (n[j] - m[j]) / 2 per axis
+ * and zeros elsewhere. The paper then smooths the padded images with a
+ * spectral Gaussian of one cell (reg_spectral, op 2, scale = the cell width) before the
+ * registration. out must not alias img. */
+reg_status reg_pad(reg_ctx *ctx, const int32_t m[3], const void *img, void *out);
+
+/* The inverse of reg_pad: out (m[0] x m[1] x m[2]) = the centred block of the
+ * field (the context's grid), e.g. to return rho(1) or a map component on the
+ * image's own grid. out must not alias field. */
+reg_status reg_crop(reg_ctx *ctx, const int32_t m[3], const void *field, void *out);
 
 /* Spectral preconditioner of section III-A: z^ = r^/(beta |k|^4) for k != 0,
  * z^_0 = r^_0, followed by P when isochoric (double precision throughout).

@@ -266,6 +266,24 @@ def regulariser(v, beta):
     return _load().oracle_regulariser(_n(v.shape), float(beta), _p(v))
 
 
+def pad(img, n):
+    """Zero padding (section III-B1): the image at offset (n - m) // 2 per
+    axis of an n-sized grid, zeros elsewhere."""
+    img = _f64(img)
+    n = tuple(int(x) for x in n)
+    out = np.zeros(n)
+    o = [(a - b) // 2 for a, b in zip(n, img.shape)]
+    out[o[0]:o[0] + img.shape[0], o[1]:o[1] + img.shape[1], o[2]:o[2] + img.shape[2]] = img
+    return out
+
+
+def crop(f, m):
+    """The centred m-sized block of an n-sized field (the inverse of pad)."""
+    f = _f64(f)
+    o = [(a - b) // 2 for a, b in zip(f.shape, m)]
+    return f[o[0]:o[0] + m[0], o[1]:o[1] + m[1], o[2]:o[2] + m[2]].copy()
+
+
 def resample(u, m):
     """Spectral resampling of a scalar or vector field to the grid m."""
     u = _f64(u)

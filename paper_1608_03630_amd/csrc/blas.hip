@@ -202,9 +202,45 @@ __global__ __launch_bounds__(kThreads) void k_scale(long n, T a, const T *__rest
     if (i < n) y[i] = a * x[i];
 }
 
+// Zero padding of an m-sized image into the centre of the n-sized grid
+// (offset o = (n - m) / 2 per axis), zeros elsewhere; and the inverse crop.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pad(Grid g, int m1, int m2, int m3, int o1, int o2, int o3,
+                                                  const T *__restrict__ img, T *__restrict__ out) {
+    const long p = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (p >= g.N()) return;
+    const int i3 = (int)(p % g.n3), i2 = (int)((p / g.n3) % g.n2), i1 = (int)(p / ((long)g.n2 * g.n3));
+    const int a1 = i1 - o1, a2 = i2 - o2, a3 = i3 - o3;
+    const bool in = a1 >= 0 && a1 < m1 && a2 >= 0 && a2 < m2 && a3 >= 0 && a3 < m3;
+    out[p] = in ? img[((long)a1 * m2 + a2) * m3 + a3] : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_crop(Grid g, int m1, int m2, int m3, int o1, int o2, int o3,
+                                                   const T *__restrict__ f, T *__restrict__ out) {
+    const long q = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (long)m1 * m2 * m3) return;
+    const int a3 = (int)(q % m3), a2 = (int)((q / m3) % m2), a1 = (int)(q / ((long)m2 * m3));
+    out[q] = f[((long)(a1 + o1) * g.n2 + (a2 + o2)) * g.n3 + (a3 + o3)];
+}
+
 inline unsigned nb(long n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
+
+template <typename T>
+hipError_t launch_pad(const Grid &g, const int m[3], const T *img, T *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_pad<T>, dim3(nb(g.N())), dim3(kThreads), 0, s, g, m[0], m[1], m[2], (g.n1 - m[0]) / 2,
+                       (g.n2 - m[1]) / 2, (g.n3 - m[2]) / 2, img, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_crop(const Grid &g, const int m[3], const T *f, T *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_crop<T>, dim3(nb((long)m[0] * m[1] * m[2])), dim3(kThreads), 0, s, g, m[0], m[1], m[2],
+                       (g.n1 - m[0]) / 2, (g.n2 - m[1]) / 2, (g.n3 - m[2]) / 2, f, out);
+    return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_scale_vec(long n, const T *lam, const T *vt, T *out, hipStream_t s) {
@@ -287,7 +323,9 @@ template hipError_t launch_convert<float, double>(long, const float *, double *,
     template hipError_t launch_add_vdotgrad<T>(long, const T *, const T *, T *, double, hipStream_t);             \
     template hipError_t launch_newton_source<T>(long, const T *, const T *, const T *, double, T *, hipStream_t);  \
     template hipError_t launch_b_axpy<T>(long, double, const T *, const T *, T *, hipStream_t);                    \
-    template hipError_t launch_scale<T>(long, double, const T *, T *, hipStream_t);
+    template hipError_t launch_scale<T>(long, double, const T *, T *, hipStream_t);                                \
+    template hipError_t launch_pad<T>(const Grid &, const int *, const T *, T *, hipStream_t);                     \
+    template hipError_t launch_crop<T>(const Grid &, const int *, const T *, T *, hipStream_t);
 
 REGK_BLAS_INST(float)
 REGK_BLAS_INST(double)

@@ -336,6 +336,36 @@ reg_status reg_resample(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, v
     return src->P.prec ? resample_fields<double>(src, dst, ncomp, in, out) : resample_fields<float>(src, dst, ncomp, in, out);
 }
 
+reg_status reg_pad(reg_ctx *ctx, const int32_t m[3], const void *img, void *out) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, img);
+    NEED_DEV(ctx, out);
+    if (!m || m[0] < 1 || m[1] < 1 || m[2] < 1 || m[0] > ctx->g.n1 || m[1] > ctx->g.n2 || m[2] > ctx->g.n3)
+        return fail(ctx, REG_EINVAL, "each m[j] must be in [1, n[j]]");
+    if (img == out) return fail(ctx, REG_EINVAL, "out must not alias img");
+    const int mm[3] = {m[0], m[1], m[2]};
+    if (ctx->P.prec)
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_pad<double>(ctx->g, mm, CV<double>(img), V<double>(out), ctx->stream)));
+    else
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_pad<float>(ctx->g, mm, CV<float>(img), V<float>(out), ctx->stream)));
+    return REG_OK;
+}
+
+reg_status reg_crop(reg_ctx *ctx, const int32_t m[3], const void *field, void *out) {
+    CTX_OK(ctx);
+    NEED_DEV(ctx, field);
+    NEED_DEV(ctx, out);
+    if (!m || m[0] < 1 || m[1] < 1 || m[2] < 1 || m[0] > ctx->g.n1 || m[1] > ctx->g.n2 || m[2] > ctx->g.n3)
+        return fail(ctx, REG_EINVAL, "each m[j] must be in [1, n[j]]");
+    if (field == out) return fail(ctx, REG_EINVAL, "out must not alias field");
+    const int mm[3] = {m[0], m[1], m[2]};
+    if (ctx->P.prec)
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_crop<double>(ctx->g, mm, CV<double>(field), V<double>(out), ctx->stream)));
+    else
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_crop<float>(ctx->g, mm, CV<float>(field), V<float>(out), ctx->stream)));
+    return REG_OK;
+}
+
 reg_status reg_precond(reg_ctx *ctx, const void *r, void *z) {
     CTX_OK(ctx);
     NEED_DEV(ctx, r);

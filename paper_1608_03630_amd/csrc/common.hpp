@@ -235,5 +235,11 @@ template <typename T>
 hipError_t launch_b_axpy(long n, double w, const T *lam, const T *g, T *b, hipStream_t s);
 template <typename T>
 hipError_t launch_scale(long n, double a, const T *x, T *y, hipStream_t s);
+// zero padding of an m[0] x m[1] x m[2] image into the centre of grid g
+// (offset (n - m) / 2 per axis), and the crop of that block back out
+template <typename T>
+hipError_t launch_pad(const Grid &g, const int m[3], const T *img, T *out, hipStream_t s);
+template <typename T>
+hipError_t launch_crop(const Grid &g, const int m[3], const T *f, T *out, hipStream_t s);
 
 }  // namespace regk

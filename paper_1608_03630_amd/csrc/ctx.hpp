@@ -40,6 +40,7 @@ inline bool fft_friendly(int n) {
     if (n < 8 || n > 1024 || (n & 1)) return false;
     while (n % 2 == 0) n /= 2;
     while (n % 3 == 0) n /= 3;
+    while (n % 5 == 0) n /= 5;
     return n == 1;
 }
 
@@ -243,7 +244,7 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
     for (int j = 0; j < 3; j++)
         if (!fft_friendly(p->n[j])) {
             *why = "grid size n[" + std::to_string(j) + "] = " + std::to_string(p->n[j]) +
-                   " must be even, 2^a 3^b and in [8, 1024]";
+                   " must be even, 2^a 3^b 5^c and in [8, 1024]";
             return REG_EINVAL;
         }
     if (p->nt < 1 || p->nt > 4096) {

@@ -3,9 +3,12 @@
 // 1D FFTs along the differentiated axis, while P, lap^2 and lap^-2 are
 // diagonal after a full 3D transform).
 //
-// All transforms are line FFTs in LDS: a workgroup stages L complex lines of
-// one axis as a [j][l] tile (pitch >= L), runs a Stockham autosort FFT with
-// radix-4/2/3 passes between two LDS buffers, and writes the tile back. For
+// Line FFTs of any length 2^a 3^b 5^c up to 1024 run in LDS: a workgroup
+// stages L complex lines of one axis as a [j][l] tile (pitch >= L), runs a
+// Stockham autosort FFT with radix-4/2/3/5 passes between two LDS buffers,
+// and writes the tile back. 256-point lines (two radix-16 passes) keep each
+// thread's 16 elements in registers instead, with one LDS exchange between
+// the passes, reading and writing HBM directly in the 3D transforms. For
 // the x1 and x2 axes the L lines are L adjacent x3 columns, so every global
 // access is a coalesced row of L complex values; for the contiguous x3 axis
 // the lines are loaded along x3 and transposed into the tile. Real data is
@@ -31,6 +34,10 @@ bool make_plan(int n, FftPlan *p) {
     while (m % 3 == 0 && p->npass < 12) {
         p->radix[p->npass++] = 3;
         m /= 3;
+    }
+    while (m % 5 == 0 && p->npass < 12) {
+        p->radix[p->npass++] = 5;
+        m /= 5;
     }
     return m == 1;
 }
@@ -86,7 +93,7 @@ __device__ __forceinline__ C cmul_si(C a, int sign) {
     return r;
 }
 
-// R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4}
+// R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4, 5}
 template <typename T, int R>
 __device__ __forceinline__ void butterfly(cplx_t<T> *v, int sign) {
     using C = cplx_t<T>;
@@ -101,6 +108,30 @@ __device__ __forceinline__ void butterfly(cplx_t<T> *v, int sign) {
         const C a = v[0], b = v[1];
         v[0] = cadd(a, b);
         v[1] = csub(a, b);
+    } else if (R == 5) {
+        // with t1 = v1 + v4, t2 = v2 + v3, t3 = v1 - v4, t4 = v2 - v3:
+        // X0 = v0 + t1 + t2; X1, X4 = a1 +- b1; X2, X3 = a2 +- b2 with
+        // a1 = v0 + c1 t1 + c2 t2, a2 = v0 + c2 t1 + c1 t2,
+        // b1 = sign i (s1 t3 + s2 t4), b2 = sign i (s2 t3 - s1 t4),
+        // c_m = cos(2 pi m / 5), s_m = sin(2 pi m / 5)
+        const T c1 = T(0.30901699437494742410229341718282), c2 = T(-0.80901699437494742410229341718282);
+        const T s1 = T(0.95105651629515357211643933337938), s2 = T(0.58778525229247312916870595463907);
+        const C t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]), t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+        C a1, a2, e1, e2;
+        a1.x = v[0].x + c1 * t1.x + c2 * t2.x;
+        a1.y = v[0].y + c1 * t1.y + c2 * t2.y;
+        a2.x = v[0].x + c2 * t1.x + c1 * t2.x;
+        a2.y = v[0].y + c2 * t1.y + c1 * t2.y;
+        e1.x = s1 * t3.x + s2 * t4.x;
+        e1.y = s1 * t3.y + s2 * t4.y;
+        e2.x = s2 * t3.x - s1 * t4.x;
+        e2.y = s2 * t3.y - s1 * t4.y;
+        const C b1 = cmul_si(e1, sign), b2 = cmul_si(e2, sign);
+        v[0] = cadd(v[0], cadd(t1, t2));
+        v[1] = cadd(a1, b1);
+        v[4] = csub(a1, b1);
+        v[2] = cadd(a2, b2);
+        v[3] = csub(a2, b2);
     } else {  // R == 3
         const T h = T(0.86602540378443864676372317075294);  // sqrt(3)/2
         const C s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
@@ -243,7 +274,8 @@ __device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int
         const int R = pl.radix[ps];
         if (R == 4) fft_pass<T, 4>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         else if (R == 2) fft_pass<T, 2>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
-        else fft_pass<T, 3>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        else if (R == 3) fft_pass<T, 3>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        else fft_pass<T, 5>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         __syncthreads();
         C *t = a;
         a = b;

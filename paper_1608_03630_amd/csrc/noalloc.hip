@@ -86,7 +86,7 @@ extern "C" reg_status reg_interp_noalloc(int32_t prec, const int32_t n[3], const
     if (prec != 0 && prec != 1) return reject("prec must be 0 (float) or 1 (double)");
     if (!n) return reject("n is NULL");
     for (int j = 0; j < 3; j++)
-        if (!regc::fft_friendly(n[j])) return reject("each n[j] must be even, 2^a 3^b and in [8, 1024]");
+        if (!regc::fft_friendly(n[j])) return reject("each n[j] must be even, 2^a 3^b 5^c and in [8, 1024]");
     if (f == out) return reject("out must not alias f");
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) {

@@ -120,6 +120,8 @@ _SIGS = {
     "reg_set_solver": [_P, ctypes.POINTER(reg_params)],
     "reg_set_images": [_P, _P, _P],
     "reg_interp": [_P, _P, _P, _P],
+    "reg_pad": [_P, ctypes.POINTER(ctypes.c_int32), _P, _P],
+    "reg_crop": [_P, ctypes.POINTER(ctypes.c_int32), _P, _P],
     "reg_interp_noalloc": [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P, _P, _P, _P],
     "reg_backtrace": [_P, _P, ctypes.c_double, _P],
     "reg_deriv": [_P, ctypes.c_int, _P, _P],
@@ -349,6 +351,27 @@ class Context:
         out = dst.empty(ncomp) if out is None else out
         _chk(lib().reg_resample(self.handle, dst.handle, ncomp, self._t(x, ncomp, "x"), dst._t(out, ncomp, "out")),
              self.handle, "reg_resample")
+        return out
+
+    def _m(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or not t.is_contiguous() or t.dtype != self.dtype:
+            raise TypeError(f"{name} must be a contiguous {self.dtype} CUDA tensor")
+        if t.dim() != 3:
+            raise ValueError(f"{name} must be [m0][m1][m2]")
+        return (ctypes.c_int32 * 3)(*t.shape), ctypes.c_void_p(t.data_ptr())
+
+    def reg_pad(self, img, out=None):
+        """Zero padding of an image into the centre of this context's grid."""
+        m, p = self._m(img, "img")
+        out = self.empty(1) if out is None else out
+        _chk(lib().reg_pad(self.handle, m, p, self._t(out, 1, "out")), self.handle, "reg_pad")
+        return out
+
+    def reg_crop(self, field, m, out=None):
+        """The centred m[0] x m[1] x m[2] block of a field of this context's grid."""
+        out = torch.empty(tuple(int(x) for x in m), dtype=self.dtype, device=self.device) if out is None else out
+        mm, p = self._m(out, "out")
+        _chk(lib().reg_crop(self.handle, mm, self._t(field, 1, "field"), p), self.handle, "reg_crop")
         return out
 
     def reg_precond(self, r, z=None):

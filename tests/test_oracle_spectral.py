@@ -165,3 +165,14 @@ def test_resample_preserves_band_limited_fields(orc, src, dst):
 
     out = orc.resample(field(src), dst)
     assert np.abs(out - field(dst)).max() <= 1e-12
+
+
+def test_zero_padding_and_crop(orc):
+    """Zero padding (section III-B1) puts the image at the centre offset
+    (n - m) // 2 with zeros around it; cropping the same block returns it."""
+    img = np.arange(3 * 5 * 4, dtype=np.float64).reshape(3, 5, 4) + 1.0
+    out = orc.pad(img, (8, 10, 9))
+    assert out.shape == (8, 10, 9)
+    assert np.array_equal(out[2:5, 2:7, 2:6], img)
+    assert out.sum() == img.sum() and np.count_nonzero(out) == img.size
+    assert np.array_equal(orc.crop(out, img.shape), img)
