@@ -99,16 +99,105 @@ def warm_small(reg, torch):
     ctx.close()
 
 
-def cpu_baseline(counts, n):
-    """The FP64 oracle, as it stands, on a bounded sample: one reduced
-    gradient, one Gauss-Newton matvec and one objective of the same workload
-    at 128^3 (nt = 16), scaled by the grid-size ratio (n/128)^3 and by the
-    number of gradients, matvecs and objectives of the GPU solve."""
+def host_cpu():
+    """The host's processor model and logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "os_cpu_count": os.cpu_count()}
+
+
+def _median_time(fn, runs=5, warm=1):
+    for _ in range(warm):
+        fn()
+    ts = []
+    for _ in range(runs):
+        t = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def oracle_operators(m, runs=5, nt=16, seed=1003):
+    """Median times (runs after one warm-up) of the FP64 oracle's operators on
+    the m^3 phantom workload: one interpolation, the backtrace, the state and
+    adjoint transports, the reduced gradient and the Gauss-Newton matvec."""
     import numpy as np
 
     import oracle
     import synth
 
+    shape = (m, m, m)
+    case = synth.phantom_case(shape, seed)
+    rhoT = oracle.gauss(case["labels"], case["sigma"])
+    P = oracle.params(shape, nt, 1e-2)
+    rhoR = oracle.transport_forward(P, case["v_true"], rhoT)
+    v = 0.5 * case["v_true"]
+    D = oracle.backtrace(v, nt)
+    lam1 = rhoR - rhoT
+    g = [None]
+
+    def grad():
+        g[0] = oracle.gradient(P, rhoT, rhoR, v)[0]
+
+    out = {
+        "interp": _median_time(lambda: oracle.interp(rhoT, D), runs),
+        "backtrace": _median_time(lambda: oracle.backtrace(v, nt), runs),
+        "transport_forward": _median_time(lambda: oracle.transport_forward(P, v, rhoT), runs),
+        "transport_adjoint": _median_time(lambda: oracle.transport_adjoint(P, v, lam1), runs),
+        "gradient": _median_time(grad, runs),
+    }
+    out["matvec"] = _median_time(lambda: oracle.hessian_matvec(P, rhoT, v, g[0]), runs)
+    return out
+
+
+def oracle_smooth32_solve():
+    """Wall time of the oracle's 32^3 smooth-case solve (FP64, nt = 4,
+    beta = 1e-2, at most 5 Newton steps, gtol 1e-2)."""
+    import oracle
+    import synth
+
+    shape = (32, 32, 32)
+    case = synth.smooth_case(shape)
+    P = oracle.params(shape, 4, 1e-2, max_newton=5)
+    rhoR = oracle.transport_forward(P, case["v_true"], case["rhoT"])
+    t = time.perf_counter()
+    _, rep = oracle.solve(P, case["rhoT"], rhoR)
+    return {"seconds": time.perf_counter() - t, "gn_steps": rep["n_iter"], "matvecs": rep["matvecs"]}
+
+
+def cpu_baseline(counts, n):
+    """The FP64 oracle, as it stands, on a bounded sample of the workload
+    (about 20 s on 16 host cores): median times of its operators on the
+    64^3 phantom (five runs after one warm-up), one interpolation on one
+    thread, the 32^3 smooth-case solve measured whole, and one gradient, one
+    Gauss-Newton matvec and one objective at 128^3. The value is an
+    estimate of the 256^3 solve: the 128^3 times scaled by (n/128)^3 and by
+    the GPU solve's numbers of gradients, matvecs and objectives."""
+    import oracle
+    import synth
+
+    cores = oracle.num_threads()
+    ops64 = oracle_operators(64)
+    import numpy as np
+
+    shape64 = (64, 64, 64)
+    case64 = synth.phantom_case(shape64, 1003)
+    f64 = oracle.gauss(case64["labels"], case64["sigma"])
+    D64 = oracle.backtrace(0.5 * case64["v_true"], 16)
+    oracle.set_threads(1)
+    try:
+        one = _median_time(lambda: oracle.interp(f64, D64), 3)
+    finally:
+        oracle.set_threads(cores)
+    solve32 = oracle_smooth32_solve()
     m = 128
     shape = (m, m, m)
     case = synth.phantom_case(shape, 1003)
@@ -125,16 +214,55 @@ def cpu_baseline(counts, n):
     t3 = time.time()
     scale = (n / m) ** 3
     est = scale * (counts["gradients"] * (t1 - t0) + counts["matvecs"] * (t2 - t1) + counts["objectives"] * (t3 - t2))
+    pts64 = 64 ** 3
     return {
         "value": est,
         "unit": "s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
-        "sample": (f"FP64 oracle at 128^3, nt=16: one gradient ({t1 - t0:.2f} s), one GN matvec ({t2 - t1:.2f} s), "
-                   f"one objective ({t3 - t2:.2f} s), measured {t3 - t0:.1f} s; scaled by (n/128)^3 = {scale:g} and "
-                   f"by the GPU solve's {counts['gradients']} gradients, {counts['matvecs']} matvecs and "
+        "estimate": True,
+        "host": host_cpu(),
+        "sample": (f"FP64 oracle on {cores} threads. Measured: operator medians at 64^3 (5 runs after 1 warm-up), "
+                   f"one interpolation on 1 thread, the 32^3 smooth-case solve ({solve32['seconds']:.2f} s), and at "
+                   f"128^3 (nt=16) one gradient ({t1 - t0:.2f} s), one GN matvec ({t2 - t1:.2f} s) and one objective "
+                   f"({t3 - t2:.2f} s). value = ESTIMATE of the {n}^3 solve: the 128^3 times x (n/128)^3 = {scale:g} x "
+                   f"the GPU solve's {counts['gradients']} gradients, {counts['matvecs']} matvecs and "
                    f"{counts['objectives']} objectives"),
+        "operators_64_s": ops64,
+        "interp_64_gpts_s": pts64 / ops64["interp"] / 1e9,
+        "interp_64_one_thread_s": one,
+        "interp_64_one_thread_gpts_s": pts64 / one / 1e9,
+        "solve_smooth32": solve32,
+        "sample_128_s": {"gradient": t1 - t0, "matvec": t2 - t1, "objective": t3 - t2},
     }
+
+
+def run_oracle_plan(args):
+    """The full host-side timing plan of the oracle: operator medians at 64^3,
+    128^3 and 256^3 (5 runs after 1 warm-up), a one-thread interpolation, the
+    32^3 smooth-case solve. Minutes of host time; not part of the default
+    run."""
+    import oracle
+
+    cores = oracle.num_threads()
+    out = {"mode": "oracle", "host": host_cpu(), "threads": cores, "operators_s": {}}
+    for m in (64, 128, 256):
+        log(f"[bench] oracle operators at {m}^3")
+        out["operators_s"][f"{m}^3"] = oracle_operators(m)
+        log(f"[bench]   {out['operators_s'][f'{m}^3']}")
+    import synth
+
+    shape64 = (64, 64, 64)
+    case64 = synth.phantom_case(shape64, 1003)
+    f64 = oracle.gauss(case64["labels"], case64["sigma"])
+    D64 = oracle.backtrace(0.5 * case64["v_true"], 16)
+    oracle.set_threads(1)
+    try:
+        out["interp_64_one_thread_s"] = _median_time(lambda: oracle.interp(f64, D64), 5)
+    finally:
+        oracle.set_threads(cores)
+    out["solve_smooth32"] = oracle_smooth32_solve()
+    print(json.dumps(out), flush=True)
 
 
 # config of the batched workload: (grid, count); every pair like the 128^3
@@ -322,16 +450,21 @@ def main():
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
-    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net", "oracle"], default="solve",
                     help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
                          "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
                          "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch; net: "
-                         "forward pass and training step of the 64^3 warm-start network against the BF16 MFMA peak")
+                         "forward pass and training step of the 64^3 warm-start network against the BF16 MFMA peak; "
+                         "oracle: the host-side timing plan of the FP64 oracle (minutes; no GPU)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
               "in DESIGN.md and is not built", file=sys.stderr)
         sys.exit(2)
+
+    if args.mode == "oracle":
+        run_oracle_plan(args)
+        return
 
     import torch
 
