@@ -150,40 +150,14 @@ def blob_case(n, seed=1002):
 
 
 def blob_case_device(n, seed, device="cuda"):
-    """blob_case with the same draws (same generator calls in the same
-    order), evaluated in float64 with torch on `device`: the training and
-    test sets of the learned warm start are thousands of such pairs, too many
-    to evaluate on the host. Returns torch tensors (rhoT [n1, n2, n3],
-    v_true [3, n1, n2, n3]); they agree with blob_case to rounding."""
+    """blob_case generated on the host (numpy) and copied to `device` as
+    float64 torch tensors (rhoT [n1, n2, n3], v_true [3, n1, n2, n3]); the
+    training and test sets of the learned warm start take their pairs from
+    here. torch only holds the memory."""
     import torch
 
-    n = _shape(n)
-    rng = np.random.default_rng(seed)
-    nblobs = 20
-    centres = rng.uniform(0.0, TWO_PI, size=(nblobs, 3))
-    sigmas = rng.uniform(0.1, 0.4, size=nblobs)
-    amps = rng.uniform(0.5, 1.0, size=nblobs)
-    k = _modes(4)
-    c = rng.standard_normal((3, len(k))) + 1j * rng.standard_normal((3, len(k)))
-    c = 1j * np.cross(k.astype(np.float64).T, c, axis=0)
-    f64 = dict(dtype=torch.float64, device=device)
-    axes = [TWO_PI * torch.arange(m, **f64) / m for m in n]
-    rhoT = torch.zeros(n, **f64)
-    for b in range(nblobs):
-        parts = []
-        for j in range(3):
-            d = axes[j] - centres[b, j]
-            d = torch.remainder(d + np.pi, TWO_PI) - np.pi
-            parts.append(torch.exp(-d * d / (2.0 * sigmas[b] ** 2)))
-        rhoT += amps[b] * parts[0][:, None, None] * parts[1][None, :, None] * parts[2][None, None, :]
-    spec = torch.zeros((3,) + n, dtype=torch.complex128, device=device)
-    idx = tuple(torch.as_tensor(k[:, j] % n[j], device=device) for j in range(3))
-    coef = torch.as_tensor(c, dtype=torch.complex128, device=device)
-    for comp in range(3):
-        spec[comp].index_put_(idx, coef[comp], accumulate=True)
-    v = torch.fft.ifftn(spec, dim=(1, 2, 3)).real * float(np.prod(n))
-    speed = torch.sqrt((v ** 2).sum(0)).max()
-    return rhoT, v * (0.5 / speed)
+    case = blob_case(n, seed)
+    return (torch.from_numpy(case["rhoT"]).to(device), torch.from_numpy(case["v_true"]).to(device))
 
 
 def phantom_case(n, seed=1003):
