@@ -59,9 +59,10 @@ typedef enum {
     REG_ENOMEM = 2,       /* workspace smaller than reg_workspace_size          */
     REG_EHIP = 3,         /* a HIP runtime call failed                          */
     REG_ENONFINITE = 4,   /* NaN/Inf met in an objective, norm or PCG product   */
-    REG_ENOTCONV = 5,     /* reserved                                            */
+    /* 5 is not used: a solve that runs out of Newton steps returns REG_OK and
+     * reports stop_reason 2 */
     REG_ELINESEARCH = 6,  /* Armijo search found no acceptable step              */
-    REG_ENONDIFFEO = 7,   /* reserved                                            */
+    REG_ENONDIFFEO = 7,   /* params.det_check: det grad y1 <= 0 somewhere at the result */
     REG_ENOTIMPL = 8
 } reg_status;
 
@@ -97,6 +98,9 @@ typedef struct {
                             * (eqs. (5a)-(5e) with both lam terms). 1 needs a workspace laid
                             * out for it (an extra adjoint history): reg_set_solver cannot
                             * switch a Gauss-Newton context to it. Single contexts only. */
+    int32_t det_check;     /* 1: reg_solve computes det grad y1 of the result (eq. (1)) into the
+                            * report and returns REG_ENONDIFFEO if its minimum is <= 0 */
+    int32_t reserved_;     /* zero */
 } reg_params;
 
 #define REG_MAXIT 512
@@ -125,6 +129,13 @@ typedef struct {
     int32_t level_n[REG_MAXLEVELS][3];
     int32_t level_iters[REG_MAXLEVELS], level_matvecs[REG_MAXLEVELS];
     double level_seconds[REG_MAXLEVELS], level_mismatch[REG_MAXLEVELS], level_beta[REG_MAXLEVELS];
+    int32_t negative_curvature;  /* PCG runs ended by <p, H p> <= 0 (the step is the iterate so
+                                  * far, or -M g at the first iteration)                  */
+    int32_t descent_fallbacks;   /* Newton steps whose PCG step was no descent direction,
+                                  * replaced by -M g before the line search                 */
+    int64_t fft3d;         /* 3D transforms, one component each (context's grid)       */
+    int64_t fft_lines;     /* line-FFT derivative passes, one field each               */
+    double det_min, det_max;  /* det grad y1 of the result (params.det_check), else 0   */
 } reg_report;
 
 /* Fills *p with the paper's defaults for an n^3 grid (section IV-A3). */

@@ -70,6 +70,8 @@ class Report(ctypes.Structure):
         ("final_grel", ctypes.c_double),
         ("final_beta", ctypes.c_double),
         ("final_gref", ctypes.c_double),
+        ("negative_curvature", ctypes.c_int32),
+        ("descent_fallbacks", ctypes.c_int32),
     ]
 
     def to_dict(self):
@@ -93,6 +95,8 @@ class Report(ctypes.Structure):
             "final_grel": self.final_grel,
             "final_beta": self.final_beta,
             "final_gref": self.final_gref,
+            "negative_curvature": self.negative_curvature,
+            "descent_fallbacks": self.descent_fallbacks,
         }
 
 

@@ -892,6 +892,8 @@ typedef struct {
     double final_J, final_mismatch, final_grel;
     double final_beta;   /* beta of the last continuation level worked on */
     double final_gref;   /* that level's gradient reference */
+    int32_t negative_curvature; /* PCG runs ended by <p, H p> <= 0 */
+    int32_t descent_fallbacks;  /* Newton steps whose PCG step was no descent direction (replaced by -M g) */
 } oracle_report;
 
 static double norm3(const int *n, const double *x) { return sqrt(inner(n, 3, x, x)); }
@@ -955,6 +957,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
                 iters = i + 1;
                 double kappa = inner(n, 3, pp, q);
                 if (kappa <= 0) {
+                    rep->negative_curvature++;
                     if (i == 0) memcpy(s, z, sizeof(double) * N3);
                     break;
                 }
@@ -970,8 +973,17 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
                 for (long t = 0; t < N3; t++) pp[t] = z[t] + bb * pp[t];
                 rz = rz1;
             }
-            /* Armijo backtracking on J(v + alpha s) */
+            /* Armijo backtracking on J(v + alpha s); a step that is not a
+             * descent direction (possible with a truncated or indefinite
+             * solve) is replaced by the preconditioned steepest descent
+             * direction -M g */
             double alpha = 1.0, d = inner(n, 3, g, s);
+            if (!(d < 0)) {
+                for (long t = 0; t < N3; t++) r[t] = -g[t];
+                oracle_precond(n, beta, P->isochoric, r, s);
+                d = inner(n, 3, g, s);
+                rep->descent_fallbacks++;
+            }
             int accepted = 0, trials = 0;
             oracle_state_t tr;
             memset(&tr, 0, sizeof(tr));

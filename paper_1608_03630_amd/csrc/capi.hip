@@ -10,34 +10,6 @@ using namespace regc;
 namespace {
 
 template <typename T>
-reg_status deformation_impl(reg_ctx *ctx, const void *v, void *u_out, double *dmin, double *dmax) {
-    const long N = ctx->N;
-    const int nt = ctx->P.nt;
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));
-    STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Dt));
-    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<T>(3 * N, 0.0, V<T>(ctx->u0), ctx->stream)));
-    void *ub[2] = {ctx->u0, ctx->u1};
-    int cur = 0;
-    for (int k = 0; k < nt; k++) {
-        HIPCHK(ctx, KL(ctx, REG_K_DEFORM, regk::launch_deform_step<T>(ctx->g, V<T>(ub[cur]), CV<T>(ctx->Dt), V<T>(ub[1 - cur]),
-                                                ctx->stream)));
-        cur = 1 - cur;
-    }
-    ctx->interps += 3 * nt;
-    // du[a*3+b] = d_b u_a
-    for (int b = 0; b < 3; b++)
-        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, b, V<T>(ub[cur]), N, V<T>(ctx->du) + b * N, 3 * N, 0, 3,
-                                        ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_det_partials<T>(V<T>(ctx->du), N, ctx->dpart, ctx->dpart2, (T *)nullptr, ctx->stream)));
-    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_minmax(ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->dres, ctx->stream)));
-    if (u_out) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(3 * N, V<T>(ub[cur]), V<T>(u_out), ctx->stream)));
-    STCHK(fetch(ctx, 2));
-    *dmin = ctx->hres[0];
-    *dmax = ctx->hres[1];
-    return REG_OK;
-}
-
-template <typename T>
 reg_status transport_forward_impl(reg_ctx *ctx, const void *v, const void *rho0, void *rho1) {
     const long N = ctx->N;
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));

@@ -171,6 +171,7 @@ struct reg_ctx {
     bool have_state = false;  // plans, history, grad rho and div v at vhat
     double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
     long interps = 0;
+    int64_t fft3d = 0, fft_lines = 0;  // 3D transforms and line-FFT derivatives (one component/field each)
     int64_t epoch = 0;  // bumped whenever a plan (departure points, tile geometry) changes
     std::string err;
 };
@@ -273,6 +274,10 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
     }
     if (!(p->gtol_level >= 0) || !std::isfinite(p->gtol_level)) {
         *why = "gtol_level must be >= 0 and finite";
+        return REG_EINVAL;
+    }
+    if (p->det_check != 0 && p->det_check != 1) {
+        *why = "det_check must be 0 or 1";
         return REG_EINVAL;
     }
     if (p->hessian != 0 && p->hessian != 1) {
@@ -503,6 +508,7 @@ reg_status backtrace_impl(reg_ctx *ctx, const void *v, double sign, void *D) {
 template <typename T>
 reg_status divergence(reg_ctx *ctx, const void *v, void *d) {
     const long N = ctx->N;
+    ctx->fft_lines += 3;
     for (int j = 0; j < 3; j++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(v) + j * N, N, V<T>(d), N, j > 0, 1, ctx->stream)));
     return REG_OK;
@@ -512,6 +518,7 @@ reg_status divergence(reg_ctx *ctx, const void *v, void *d) {
 template <typename T>
 reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
     const long N = ctx->N;
+    ctx->fft_lines += 3 * nf;
     for (int j = 0; j < 3; j++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream)));
     return REG_OK;
@@ -566,12 +573,14 @@ inline reg_status biharm_partials(reg_ctx *ctx, const void *vhat) {
 
 // physical double vector -> spectral
 inline reg_status to_spec(reg_ctx *ctx, const void *v, void *vhat) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<double, double>(ctx->spec, CV<double>(v), 3, vhat, ctx->stream))));
     return REG_OK;
 }
 
 // spectral -> physical double vector (through the scratch spectrum)
 inline reg_status from_spec(reg_ctx *ctx, const void *vhat, void *v) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<double>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<double, double>(ctx->spec, ctx->H, V<double>(v), 3, ctx->stream))));
     return REG_OK;
@@ -580,6 +589,7 @@ inline reg_status from_spec(reg_ctx *ctx, const void *vhat, void *v) {
 // spectral -> field-type vector for the transport (transform in T)
 template <typename T>
 reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<T>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream))));
     return REG_OK;
@@ -589,6 +599,7 @@ reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
 // buffer), read by the first inverse pass
 template <typename T>
 reg_status field_from_krylov(reg_ctx *ctx, const void *p, void *out) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream, p))));
     return REG_OK;
 }
@@ -597,6 +608,7 @@ reg_status field_from_krylov(reg_ctx *ctx, const void *p, void *out) {
 // T); with dot = 1 (2) also dres[slot] = <x, out> (<out, out>)
 template <typename T>
 reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat, int dot = 0, int slot = 0) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
     if (!dot) {
         HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<T>(ctx->spec, regk::VEC_ASSEMBLE, CV<double>(xhat), ctx->H,
@@ -669,6 +681,7 @@ reg_status krylov_axpy(reg_ctx *ctx, const void *x, double a, const void *y, voi
 // field-type vector (FFT(y) stays in the transform buffer)
 template <typename T>
 reg_status curvature(reg_ctx *ctx, const void *p, const void *y, int slot) {
+    ctx->fft3d += 3;
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
     HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::krylov_curvature<T>(ctx->spec, p, ctx->H, ctx->beta, ctx->P.isochoric,
                                                                 ctx->dpart, regk::RED_BLOCKS, ctx->stream)));
@@ -705,6 +718,37 @@ inline void scalars_to_J(reg_ctx *ctx, double *J, double *mis) {
     const double dd = ctx->hres[1];
     if (J) *J = 0.5 * dd + ctx->hres[2];
     if (mis) *mis = ctx->normTR2 > 0 ? std::sqrt(dd / ctx->normTR2) : 0.0;
+}
+
+// The map y1 = x + u of v (eq. (1)): u transported like the state,
+// u^{n+1} = u^n(X) + h D, then det(I + grad u) by spectral derivatives, its
+// minimum and maximum (synchronises). u_out may be null.
+template <typename T>
+reg_status deformation_impl(reg_ctx *ctx, const void *v, void *u_out, double *dmin, double *dmax) {
+    const long N = ctx->N;
+    const int nt = ctx->P.nt;
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * N)));
+    STCHK(plan<T>(ctx, ctx->vf, +1.0, ctx->Dt));
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<T>(3 * N, 0.0, V<T>(ctx->u0), ctx->stream)));
+    void *ub[2] = {ctx->u0, ctx->u1};
+    int cur = 0;
+    for (int k = 0; k < nt; k++) {
+        HIPCHK(ctx, KL(ctx, REG_K_DEFORM, regk::launch_deform_step<T>(ctx->g, V<T>(ub[cur]), CV<T>(ctx->Dt), V<T>(ub[1 - cur]),
+                                                ctx->stream)));
+        cur = 1 - cur;
+    }
+    ctx->interps += 3 * nt;
+    // du[a*3+b] = d_b u_a
+    for (int b = 0; b < 3; b++)
+        HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, b, V<T>(ub[cur]), N, V<T>(ctx->du) + b * N, 3 * N, 0, 3,
+                                        ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_det_partials<T>(V<T>(ctx->du), N, ctx->dpart, ctx->dpart2, (T *)nullptr, ctx->stream)));
+    HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_minmax(ctx->dpart, ctx->dpart2, regk::RED_BLOCKS, ctx->dres, ctx->stream)));
+    if (u_out) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(3 * N, V<T>(ub[cur]), V<T>(u_out), ctx->stream)));
+    STCHK(fetch(ctx, 2));
+    *dmin = ctx->hres[0];
+    *dmax = ctx->hres[1];
+    return REG_OK;
 }
 
 using clk = std::chrono::steady_clock;

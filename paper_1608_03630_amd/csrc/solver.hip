@@ -722,6 +722,7 @@ enum State {
     S_RR_DONE,
     S_ARMIJO,
     S_ARMIJO_D,
+    S_FALLBACK_D,
     S_LS_TRY,
     S_LS_DONE,
     S_NEWTON_GRAD,
@@ -863,6 +864,7 @@ struct Solver {
                     break;
                 }
                 if (kappa <= 0) {  // negative curvature: stop (steepest descent at the first iteration)
+                    rep->negative_curvature++;
                     // (p = M r at the first iteration)
                     if (i == 0) HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(NV, CV<T>(ctx->phat), V<T>(ctx->shat), ctx->stream)));
                     st = S_ARMIJO;
@@ -902,6 +904,25 @@ struct Solver {
                 return REG_OK;
             case S_ARMIJO_D:
                 d = ctx->hres[0];
+                if (!(d < 0)) {
+                    // not a descent direction (a truncated or indefinite
+                    // solve, or round-off in the stored PCG vectors): take
+                    // the preconditioned steepest descent step -M g, with
+                    // d = <g, -M g> = -<r, M r> for r = -g
+                    STCHK(pcg_start<T>(ctx, 0));
+                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>(NV, CV<T>(ctx->phat), V<T>(ctx->shat), ctx->stream)));
+                    queue_fetch(1);
+                    st = S_FALLBACK_D;
+                    return REG_OK;
+                }
+                alpha = 1.0;
+                l = 0;
+                trials = 0;
+                st = S_LS_TRY;
+                break;
+            case S_FALLBACK_D:
+                d = -ctx->hres[0];
+                rep->descent_fallbacks++;
                 alpha = 1.0;
                 l = 0;
                 trials = 0;
@@ -1056,6 +1077,7 @@ reg_status single_op(reg_ctx *ctx, const Request &r) {
 template <typename T>
 reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool start_hat) {
     const auto t0 = clk::now();
+    const int64_t fft3d0 = ctx->fft3d, lines0 = ctx->fft_lines;
     double beta_start = 0, gref_start = 0;
     if (levels > 1) {
         reg_ctx *c = ctx->coarse;
@@ -1113,8 +1135,21 @@ reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool 
     rep->level_mismatch[l] = rep->final_mismatch;
     rep->level_beta[l] = rep->final_beta;
     rep->grid_levels = l + 1;
+    rep->fft3d = ctx->fft3d - fft3d0;
+    rep->fft_lines = ctx->fft_lines - lines0;
+    if (st != REG_OK) {
+        rep->seconds_total = secs(t0);
+        return st;
+    }
+    // the map of the result and det grad y1 (on the caller's grid only)
+    if (ctx->P.det_check && v && (S[0].status == REG_OK || S[0].status == REG_ELINESEARCH)) {
+        STCHK(deformation_impl<T>(ctx, v, nullptr, &rep->det_min, &rep->det_max));
+        if (S[0].status == REG_OK && !(rep->det_min > 0)) {
+            rep->seconds_total = secs(t0);
+            return fail(ctx, REG_ENONDIFFEO, "det grad y1 <= 0 at the result: the map is not a diffeomorphism");
+        }
+    }
     rep->seconds_total = secs(t0);
-    if (st != REG_OK) return st;
     return S[0].status;
 }
 

@@ -20,11 +20,11 @@ REG_MAXIT = 512
 REG_MAXLEVELS = 4
 
 STATUS = {
-    0: "REG_OK", 1: "REG_EINVAL", 2: "REG_ENOMEM", 3: "REG_EHIP", 4: "REG_ENONFINITE", 5: "REG_ENOTCONV",
+    0: "REG_OK", 1: "REG_EINVAL", 2: "REG_ENOMEM", 3: "REG_EHIP", 4: "REG_ENONFINITE",
     6: "REG_ELINESEARCH", 7: "REG_ENONDIFFEO", 8: "REG_ENOTIMPL",
 }
 REG_OK, REG_EINVAL, REG_ENOMEM, REG_EHIP, REG_ENONFINITE = 0, 1, 2, 3, 4
-REG_ELINESEARCH = 6
+REG_ELINESEARCH, REG_ENONDIFFEO = 6, 7
 
 SPEC_BIHARM, SPEC_INVBIHARM, SPEC_GAUSS, SPEC_LERAY = 0, 1, 2, 3
 
@@ -55,6 +55,8 @@ class reg_params(ctypes.Structure):
         ("gtol_level", ctypes.c_double),
         ("grid_levels", ctypes.c_int32),
         ("hessian", ctypes.c_int32),
+        ("det_check", ctypes.c_int32),
+        ("reserved_", ctypes.c_int32),
     ]
 
 
@@ -91,6 +93,12 @@ class reg_report(ctypes.Structure):
         ("level_seconds", ctypes.c_double * REG_MAXLEVELS),
         ("level_mismatch", ctypes.c_double * REG_MAXLEVELS),
         ("level_beta", ctypes.c_double * REG_MAXLEVELS),
+        ("negative_curvature", ctypes.c_int32),
+        ("descent_fallbacks", ctypes.c_int32),
+        ("fft3d", ctypes.c_int64),
+        ("fft_lines", ctypes.c_int64),
+        ("det_min", ctypes.c_double),
+        ("det_max", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -99,7 +107,8 @@ class reg_report(ctypes.Structure):
                                              "stop_reason", "final_J", "final_mismatch", "final_grel",
                                              "seconds_total", "seconds_matvec", "seconds_gradient",
                                              "seconds_objective", "seconds_precond", "interps", "final_beta",
-                                             "final_gref")}
+                                             "final_gref", "negative_curvature", "descent_fallbacks", "fft3d",
+                                             "fft_lines", "det_min", "det_max")}
         for f in ("J", "mismatch", "grel", "alpha", "beta", "pcg_iters", "ls_trials"):
             out[f] = list(getattr(self, f)[:k])
         out["levels"] = [{"n": tuple(self.level_n[i]), "n_iter": self.level_iters[i],

@@ -225,3 +225,26 @@ def test_grid_continuation_stops_where_one_grid_would(orc):
     assert all(l["status"] == 0 and l["stop_reason"] == 0 for l in rep["levels"])
     g = orc.gradient(orc.params(shape, 4, 1e-2), c["rhoT"], rhoR, v)[0]
     assert np.sqrt(inner(g, g)) <= 1e-2 * rep["final_gref"] * (1 + 1e-9)
+
+
+def test_negative_curvature_exit_takes_the_steepest_descent_step(orc):
+    """With rho_R = -5 rho_T shifted by four cells, beta = 1e-3 and the start
+    v0 = 2 v_paper, the first PCG direction p = -M g has <p, H p> < 0 for the
+    full Hessian (eqs. (5a)-(5e); the Gauss-Newton part is positive): PCG
+    stops at once (section III-A truncates at negative curvature) and the
+    Newton step is the preconditioned steepest descent step, so the accepted
+    iterate is v0 - alpha M g with the reported alpha."""
+    hessian = 1
+    shape, nt = (16, 16, 16), 4
+    c = synth.smooth_case(shape)
+    rhoT = c["rhoT"]
+    rhoR = -5.0 * np.roll(rhoT, 4, axis=0)
+    v0 = 2.0 * synth.smooth_velocity_paper(shape)
+    P = orc.params(shape, nt, 1e-3, max_newton=1, hessian=hessian)
+    g = orc.gradient(P, rhoT, rhoR, v0)[0]
+    p = orc.precond(-g, 1e-3)
+    Hp = orc.newton_matvec(P, rhoT, rhoR, v0, p) if hessian else orc.hessian_matvec(P, rhoT, v0, p)
+    assert inner(p, Hp) < 0
+    v, rep = orc.solve(P, rhoT, rhoR, v0)
+    assert rep["negative_curvature"] == 1 and rep["pcg_iters"] == [1] and rep["n_iter"] == 1
+    assert np.allclose(v, v0 + rep["alpha"][0] * p, rtol=0, atol=1e-12 * np.abs(v0).max())
