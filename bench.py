@@ -379,7 +379,7 @@ def run_batch(reg, torch, args):
         "graph": {"captures": st1["graph_captures"] - st0["graph_captures"],
                   "replays": st1["graph_replays"] - st0["graph_replays"],
                   "batched_launches": st1["batched_launches"] - st0["batched_launches"]},
-        "launch": {m: dict(zip(("blocks", "chunked", "variant", "tuned_ms"), b.reg_batch_launch_info(i)))
+        "launch": {m: dict(zip(("blocks", "chunked", "variant", "tile", "tuned_ms"), b.reg_batch_launch_info(i)))
                    for i, m in enumerate(("interp", "adjoint", "incstate"))},
         "kernel_ms": {k: {"launches": n_, "ms": t_} for k, (n_, t_) in prof.items() if n_},
         # one transport = nt steps of every pair, each step one launch per box class

@@ -346,13 +346,22 @@ reg_status reg_batch_ctx(reg_batch *b, int32_t pair, reg_ctx **ctx);
  * matvec eagerly. Results do not depend on these settings. */
 reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, int32_t use_graph);
 
-/* Workgroups, dealing, kernel variant and tuned time (ms, 0 if fixed) of the
- * last batched launch of a step kind: mode 0 interpolation/state, 1 adjoint,
- * 2 incremental state. A step takes one batched launch per LDS box class of
- * its problems: variant 1, 2, 4 for the canonical box of that floor span, 0
- * for the generic box. */
+/* Tile shape of the batched canonical launches: tile1 x tile2 x 64 output
+ * points per workgroup of 64 tile2 threads, one of 4x8 (the default of the
+ * single-problem kernels), 2x8, 8x8, 4x4, 8x4; 0 x 0 lets the launch tuner
+ * pick it per launch (timing every shape whose box fits 64 KB and whose tiles
+ * cover every problem's grid, with the workgroup counts). A fixed shape that
+ * does not fit a launch falls back to the first that does. Results do not
+ * depend on the shape. */
+reg_status reg_batch_set_tile(reg_batch *b, int32_t tile1, int32_t tile2);
+
+/* Workgroups, dealing, kernel variant, tile shape and tuned time (ms, 0 if
+ * fixed) of the last batched launch of a step kind: mode 0
+ * interpolation/state, 1 adjoint, 2 incremental state. A step takes one
+ * batched launch per LDS box class of its problems: variant 1, 2, 4 for the
+ * canonical box of that floor span, 0 for the generic box (4x8 tiles). */
 reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
-                                 double *ms);
+                                 int32_t *tile1, int32_t *tile2, double *ms);
 
 /* Counters: batched step launches, graph captures, graph replays. */
 reg_status reg_batch_stats(reg_batch *b, int64_t *batched_launches, int64_t *graph_captures, int64_t *graph_replays);

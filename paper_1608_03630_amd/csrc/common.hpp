@@ -67,14 +67,25 @@ enum { STEP_INTERP = 0, STEP_ADJOINT = 1, STEP_INCSTATE = 2 };
 bool canonical(const Grid &g, const TileGeom &tg, size_t esz);
 int batch_span(const TileGeom &tg);
 int tiles_of(const Grid &g);
+// Tile shapes T1 x T2 x 64 of the batched canonical kernels (64 T2 threads,
+// T1 points per thread); the pair table counts tiles of the smallest,
+// kUnit1 x kUnit2 x 64 (unit_tiles_of), so that every shape's tile index
+// follows from it. A shape serves a launch when every pair's n1 and n2 are
+// multiples of it and the box of the variant fits 64 KB (batch_tile_ok).
+constexpr int kUnit1 = 2, kUnit2 = 4;
+constexpr int kBatchTileCount = 5;
+constexpr int kBatchTiles[kBatchTileCount][2] = {{4, 8}, {2, 8}, {8, 8}, {4, 4}, {8, 4}};
+int unit_tiles_of(const Grid &g);
+bool batch_tile_ok(int variant, int t1, int t2);
 // One persistent launch of nblocks workgroups (>= 8) over all pairs' tiles
 // (pairs_dev sorted by tile0, total = sum of the pairs' tiles). variant 0:
 // generic tile kernel with `lds` bytes of dynamic LDS (the largest box of the
 // pairs); variant 1, 2, 4: canonical box of that span (float only, every pair
-// canonical with span <= variant).
+// canonical with span <= variant). Tile shape t1 x t2 x 64 (the generic
+// variant takes the default 4 x 8 only); total counts tiles of that shape.
 template <typename T>
 hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep *pairs_dev, int npairs, int total,
-                               int nblocks, int chunked, hipStream_t s);
+                               int nblocks, int chunked, int t1, int t2, hipStream_t s);
 
 // Every launcher enqueues on `s` and returns the hipError_t of the launch. A
 // non-null TileGeom selects the LDS-staged gather for displacements D whose

@@ -538,24 +538,31 @@ constexpr int kCanonMaxSpan = 4;  // largest canonical box: (7+S)(11+S)(67+S) fl
 // pitch is the multiple of 32, else of 16, else the natural one, whichever
 // first reaches the most workgroups per CU (160 KiB of LDS, at most four
 // 512-thread workgroups): 96 for span 1, 80 for spans 2 and 4.
+// The tile is T1 x T2 x kTile3 (4 x 8 x 64 by default; the batched kernels
+// also take the other shapes of kBatchTiles): 64 T2 threads, one x2 row per
+// wavefront, T1 points (x1 rows) per thread. The workgroups per CU are capped
+// by the 32 wavefronts a CU holds.
 constexpr int kLdsPerCu = 160 * 1024;
-template <int S> struct Canon {
-    static constexpr int C1 = kTile1 + 3 + S, C2 = kTile2 + 3 + S, W = kTile3 + 3 + S;
+template <int S, int T1 = kTile1, int T2 = kTile2> struct Canon {
+    static constexpr int C1 = T1 + 3 + S, C2 = T2 + 3 + S, W = kTile3 + 3 + S;
     static constexpr int P32 = (W + 31) / 32 * 32, P16 = (W + 15) / 16 * 16;
+    static constexpr int kMaxWg = 32 / T2;
     static constexpr int wg(int pitch) {
         const int bytes = C1 * C2 * pitch * 4;
-        return bytes > 65536 ? 0 : (kLdsPerCu / bytes < 4 ? kLdsPerCu / bytes : 4);
+        return bytes > 65536 ? 0 : (kLdsPerCu / bytes < kMaxWg ? kLdsPerCu / bytes : kMaxWg);
     }
     static constexpr int best = wg(W) > wg(P16) ? wg(W) : wg(P16);
     static constexpr int C3 = wg(P32) >= best ? P32 : wg(P16) >= best ? P16 : W;
     static constexpr int elems = C1 * C2 * C3;
+    static constexpr bool fits = elems * 4 <= 65536;
 };
 
-template <typename T, int S>
+template <typename T, int S, int T1 = kTile1, int T2 = kTile2>
 __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                                 const T *__restrict__ f, T *box) {
-    using K = Canon<S>;
-    const int o1 = t.t1 * kTile1 + tg.lo[0], o2 = t.t2 * kTile2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
+    using K = Canon<S, T1, T2>;
+    constexpr int kW = T2;  // wavefronts of the workgroup
+    const int o1 = t.t1 * T1 + tg.lo[0], o2 = t.t2 * T2 + tg.lo[1], o3 = t.t3 * kTile3 + tg.lo[2];
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const int B1 = tg.B[0], B2 = tg.B[1], B3 = tg.B[2];
     const int gc0 = wrap_idx(o3 + lane, g.n3), gc1 = wrap_idx(o3 + lane + 64, g.n3);
@@ -576,7 +583,7 @@ __device__ __forceinline__ void stage_box_canon(const Grid &g, const TileGeom &t
                 if (h1) v1[u] = row[gc1];
                 dst[u] = (q1 * K::C2 + q2) * K::C3;
             }
-            next_row(q1, q2, kWaves, B2);
+            next_row(q1, q2, kW, B2);
         }
 #pragma unroll
         for (int u = 0; u < kStageRows; u++) {
@@ -643,11 +650,11 @@ __device__ __forceinline__ unsigned opaque(unsigned x) {
 // that their HBM latency overlaps the staging; the six streams of vt . grad
 // rho of the incremental-state step are read in the point loop instead (in
 // the staging phase they lengthened it by 3%).
-template <typename T, int MODE, int S>
+template <typename T, int MODE, int S, int T1 = kTile1, int T2 = kTile2>
 __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, const TileIdx &t,
                                            const T *__restrict__ f, const T *__restrict__ D, const TileArgs &args,
                                            T *box) {
-    using K = Canon<S>;
+    using K = Canon<S, T1, T2>;
     static_assert(sizeof(T) == 4, "canonical tiles are single precision");
     const int wave = wave_id(), lane = threadIdx.x & 63;
     const unsigned N = (unsigned)g.N();
@@ -656,7 +663,7 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     const gmem<T> *__restrict__ D3 = D1 + 2 * (size_t)N;
     const int i3 = t.t3 * kTile3 + lane;
     const unsigned line_bytes = (unsigned)g.n3 * sizeof(T);
-    const unsigned b0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3) * sizeof(T);
+    const unsigned b0 = (unsigned)(((t.t1 * T1) * g.n2 + t.t2 * T2) * g.n3 + i3) * sizeof(T);
     const gmem<T> *__restrict__ gam = (const gmem<T> *)args.gam;
     const gmem<T> *__restrict__ gr1 = (const gmem<T> *)args.grad;
     const gmem<T> *__restrict__ gr2 = gr1 + N;
@@ -664,13 +671,12 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     const gmem<T> *__restrict__ vt1 = (const gmem<T> *)args.vt;
     const gmem<T> *__restrict__ vt2 = vt1 + N;
     const gmem<T> *__restrict__ vt3 = vt1 + 2 * (size_t)N;
-    // thread's points: line wave + kWaves k of the tile, i.e. x1 row k and
-    // x2 row `wave` (kWaves == kTile2), at x3 position `lane`
-    static_assert(kWaves == kTile2 && kLinesPerWave == kTile1, "one x2 row per wavefront");
+    // thread's points: x1 row k = 0..T1-1 and x2 row `wave` of the tile, at
+    // x3 position `lane`
     const int a2 = wave;
-    T d[kLinesPerWave][3], e[kLinesPerWave];
+    T d[T1][3], e[T1];
 #pragma unroll
-    for (int k = 0; k < kLinesPerWave; k++) {
+    for (int k = 0; k < T1; k++) {
         const int a1 = k;
         const unsigned o = b0 + (unsigned)(a1 * g.n2 + a2) * line_bytes;
         d[k][0] = ld_nt(D1, o);
@@ -680,7 +686,7 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
             e[k] = gam ? ld_nt(gam, o) : T(1);
         }
     }
-    stage_box_canon<T, S>(g, tg, t, f, box);
+    stage_box_canon<T, S, T1, T2>(g, tg, t, f, box);
     __syncthreads();
     gmem<T> *__restrict__ out = (gmem<T> *)args.out;
     const T cs = T(args.cs);
@@ -688,7 +694,7 @@ __device__ __forceinline__ void canon_tile(const Grid &g, const TileGeom &tg, co
     constexpr unsigned kPlane = K::C2 * K::C3;
     const T f3min = T(tg.lo[2] + 1 - lane), f3max = T(tg.lo[2] + tg.B[2] - 3 - lane);
 #pragma unroll
-    for (int k = 0; k < kLinesPerWave; k++) {
+    for (int k = 0; k < T1; k++) {
         const int a1 = k;
         const unsigned o = b0 + (unsigned)(a1 * g.n2 + a2) * line_bytes;
         // local start l = i_local + floor - 1 - lo, kept in [0, B - 4]
@@ -746,9 +752,16 @@ __global__ __launch_bounds__(kTileThreads) void k_tiled_canon(Grid g, TileGeom t
 // XCD's L2 sees neighbouring tiles of one grid; otherwise round-robin. The
 // per-tile work is that of the single-grid kernels (same arithmetic, so a
 // pair's result does not depend on the batch).
-template <class F>
+// Work items count tiles of the launch's shape T1 x T2 x kTile3; the pair
+// table's tile0 counts RATIO times as many: the smallest batch tile
+// (kUnit1 x kUnit2 x kTile3, of which a canonical launch tile holds
+// (T1 / kUnit1) (T2 / kUnit2)), or for the generic kernel the default tile
+// itself (RATIO 1, ragged grids). The pair's box extents are those of the
+// default tile, adjusted to T1 and T2.
+template <int T1, int T2, int RATIO, class F>
 __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, int npairs, int total, int chunked,
                                            F &&work) {
+    constexpr int ratio = RATIO;
     const int nb = gridDim.x;
     int first = 0, end = total, stride = nb, start = blockIdx.x;
     if (chunked) {
@@ -768,20 +781,26 @@ __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, i
     int lo = 0, hi = npairs - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (pairs[mid].tile0 <= item) lo = mid;
+        if (pairs[mid].tile0 / ratio <= item) lo = mid;
         else hi = mid - 1;
     }
-    PairStep ps = pairs[lo];
-    int next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 : total;
+    auto load = [&](int i) {
+        PairStep p = pairs[i];
+        p.tg.B[0] += T1 - kTile1;
+        p.tg.B[1] += T2 - kTile2;
+        return p;
+    };
+    PairStep ps = load(lo);
+    int next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 / ratio : total;
     for (; item < end; item += stride) {
         if (item >= next0) {
-            while (lo + 1 < npairs && pairs[lo + 1].tile0 <= item) lo++;
-            ps = pairs[lo];
-            next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 : total;
+            while (lo + 1 < npairs && pairs[lo + 1].tile0 / ratio <= item) lo++;
+            ps = load(lo);
+            next0 = lo + 1 < npairs ? pairs[lo + 1].tile0 / ratio : total;
         }
         const Grid g = ps.g;
-        const int b = item - ps.tile0;
-        const int nt3 = (g.n3 + kTile3 - 1) / kTile3, nt2 = (g.n2 + kTile2 - 1) / kTile2;
+        const int b = item - ps.tile0 / ratio;
+        const int nt3 = (g.n3 + kTile3 - 1) / kTile3, nt2 = (g.n2 + T2 - 1) / T2;
         TileIdx t;
         t.t3 = b % nt3;
         t.t2 = (b / nt3) % nt2;
@@ -798,15 +817,16 @@ __device__ __forceinline__ void walk_items(const PairStep *__restrict__ pairs, i
     }
 }
 
-template <typename T, int MODE, int S>
-__global__ __launch_bounds__(kTileThreads) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs,
-                                                            int total, int chunked) {
-    __shared__ T box[Canon<S>::elems];
-    walk_items(pairs, npairs, total, chunked,
-               [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
-                   const TileArgs &a) {
-                   canon_tile<T, MODE, S>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
-               });
+template <typename T, int MODE, int S, int T1, int T2>
+__global__ __launch_bounds__(64 * T2) void k_batched_canon(const PairStep *__restrict__ pairs, int npairs, int total,
+                                                           int chunked) {
+    __shared__ T box[Canon<S, T1, T2>::elems];
+    walk_items<T1, T2, (T1 / kUnit1) * (T2 / kUnit2)>(pairs, npairs, total, chunked,
+                       [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
+                           const TileArgs &a) {
+                           canon_tile<T, MODE, S, T1, T2>(g, tg, t, static_cast<const T *>(f),
+                                                          static_cast<const T *>(D), a, box);
+                       });
 }
 
 // The generic body for every pair (dynamic LDS sized for the largest box).
@@ -815,11 +835,12 @@ __global__ __launch_bounds__(kTileThreads) void k_batched_generic(const PairStep
                                                               int total, int chunked) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *box = reinterpret_cast<T *>(smem_raw);
-    walk_items(pairs, npairs, total, chunked,
-               [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
-                   const TileArgs &a) {
-                   generic_tile<T, MODE>(g, tg, t, static_cast<const T *>(f), static_cast<const T *>(D), a, box);
-               });
+    walk_items<kTile1, kTile2, 1>(pairs, npairs, total, chunked,
+                               [&](const Grid &g, const TileGeom &tg, const TileIdx &t, const void *f, const void *D,
+                                   const TileArgs &a) {
+                                   generic_tile<T, MODE>(g, tg, t, static_cast<const T *>(f),
+                                                         static_cast<const T *>(D), a, box);
+                               });
 }
 
 template <typename T>
@@ -917,37 +938,92 @@ int batch_span(const TileGeom &tg) { return box_span(tg); }
 
 int tiles_of(const Grid &g) { return (int)ntiles(g); }
 
+int unit_tiles_of(const Grid &g) {
+    return ((g.n1 + kUnit1 - 1) / kUnit1) * ((g.n2 + kUnit2 - 1) / kUnit2) * ((g.n3 + kTile3 - 1) / kTile3);
+}
+
+namespace {
+
+// the canonical batched kernel of one tile shape, mode and span
+template <int M, int S, int T1, int T2>
+hipError_t launch_canon_shape(const PairStep *pairs, int npairs, int total, int nb, int chunked, hipStream_t s) {
+    if constexpr (Canon<S, T1, T2>::fits) {
+        hipLaunchKernelGGL((k_batched_canon<float, M, S, T1, T2>), dim3(nb), dim3(64 * T2), 0, s, pairs, npairs, total,
+                           chunked);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int M, int S>
+hipError_t launch_canon_tile(int t1, int t2, const PairStep *pairs, int npairs, int total, int nb, int chunked,
+                             hipStream_t s) {
+    if (t1 == 4 && t2 == 8) return launch_canon_shape<M, S, 4, 8>(pairs, npairs, total, nb, chunked, s);
+    if (t1 == 2 && t2 == 8) return launch_canon_shape<M, S, 2, 8>(pairs, npairs, total, nb, chunked, s);
+    if (t1 == 8 && t2 == 8) return launch_canon_shape<M, S, 8, 8>(pairs, npairs, total, nb, chunked, s);
+    if (t1 == 4 && t2 == 4) return launch_canon_shape<M, S, 4, 4>(pairs, npairs, total, nb, chunked, s);
+    if (t1 == 8 && t2 == 4) return launch_canon_shape<M, S, 8, 4>(pairs, npairs, total, nb, chunked, s);
+    return hipErrorInvalidValue;
+}
+
+template <int M>
+hipError_t launch_canon_mode(int variant, int t1, int t2, const PairStep *pairs, int npairs, int total, int nb,
+                             int chunked, hipStream_t s) {
+    if (variant == 1) return launch_canon_tile<M, 1>(t1, t2, pairs, npairs, total, nb, chunked, s);
+    if (variant == 2) return launch_canon_tile<M, 2>(t1, t2, pairs, npairs, total, nb, chunked, s);
+    return launch_canon_tile<M, kCanonMaxSpan>(t1, t2, pairs, npairs, total, nb, chunked, s);
+}
+
+}  // namespace
+
+namespace {
+template <int S>
+bool canon_fits(int t1, int t2) {
+    if (t1 == 4 && t2 == 8) return Canon<S, 4, 8>::fits;
+    if (t1 == 2 && t2 == 8) return Canon<S, 2, 8>::fits;
+    if (t1 == 8 && t2 == 8) return Canon<S, 8, 8>::fits;
+    if (t1 == 4 && t2 == 4) return Canon<S, 4, 4>::fits;
+    if (t1 == 8 && t2 == 4) return Canon<S, 8, 4>::fits;
+    return false;
+}
+}  // namespace
+
+bool batch_tile_ok(int variant, int t1, int t2) {
+    if (variant == 0) return t1 == kTile1 && t2 == kTile2;
+    if (variant == 1) return canon_fits<1>(t1, t2);
+    if (variant == 2) return canon_fits<2>(t1, t2);
+    return canon_fits<kCanonMaxSpan>(t1, t2);
+}
+
 template <typename T>
 hipError_t launch_batched_step(int mode, int variant, size_t lds, const PairStep *pairs_dev, int npairs, int total,
-                               int nblocks_grid, int chunked, hipStream_t s) {
+                               int nblocks_grid, int chunked, int t1, int t2, hipStream_t s) {
     // chunked dealing needs a workgroup on every XCD
     if (npairs < 1 || total < 1 || nblocks_grid < kXcds) return hipErrorInvalidValue;
     const bool canon_variant = variant == 1 || variant == 2 || variant == kCanonMaxSpan;
     if (!canon_variant && variant != 0) return hipErrorInvalidValue;
-    if (variant == 0 && (lds == 0 || lds > 65536)) return hipErrorInvalidValue;
+    if (variant == 0 && (lds == 0 || lds > 65536 || t1 != kTile1 || t2 != kTile2)) return hipErrorInvalidValue;
     if (variant != 0 && sizeof(T) != 4) return hipErrorInvalidValue;
-    const dim3 grid(nblocks_grid), block(kTileThreads);
-#define REGK_BATCH(M)                                                                                               \
-    do {                                                                                                            \
-        if (variant == 0)                                                                                           \
-            hipLaunchKernelGGL((k_batched_generic<T, M>), grid, block, lds, s, pairs_dev, npairs, total, chunked); \
-        else if (variant == 1)                                                                                      \
-            hipLaunchKernelGGL((k_batched_canon<float, M, 1>), grid, block, 0, s, pairs_dev, npairs, total, chunked); \
-        else if (variant == 2)                                                                                      \
-            hipLaunchKernelGGL((k_batched_canon<float, M, 2>), grid, block, 0, s, pairs_dev, npairs, total, chunked); \
-        else                                                                                                        \
-            hipLaunchKernelGGL((k_batched_canon<float, M, kCanonMaxSpan>), grid, block, 0, s, pairs_dev, npairs,    \
-                               total, chunked);                                                                     \
-    } while (0)
-    if (mode == TM_INTERP) REGK_BATCH(TM_INTERP);
-    else if (mode == TM_ADJOINT) REGK_BATCH(TM_ADJOINT);
-    else REGK_BATCH(TM_INCSTATE);
-#undef REGK_BATCH
-    return hipGetLastError();
+    if (variant == 0) {
+        const dim3 grid(nblocks_grid), block(kTileThreads);
+        if (mode == TM_INTERP)
+            hipLaunchKernelGGL((k_batched_generic<T, TM_INTERP>), grid, block, lds, s, pairs_dev, npairs, total, chunked);
+        else if (mode == TM_ADJOINT)
+            hipLaunchKernelGGL((k_batched_generic<T, TM_ADJOINT>), grid, block, lds, s, pairs_dev, npairs, total, chunked);
+        else
+            hipLaunchKernelGGL((k_batched_generic<T, TM_INCSTATE>), grid, block, lds, s, pairs_dev, npairs, total, chunked);
+        return hipGetLastError();
+    }
+    if (mode == TM_INTERP) return launch_canon_mode<TM_INTERP>(variant, t1, t2, pairs_dev, npairs, total, nblocks_grid, chunked, s);
+    if (mode == TM_ADJOINT) return launch_canon_mode<TM_ADJOINT>(variant, t1, t2, pairs_dev, npairs, total, nblocks_grid, chunked, s);
+    return launch_canon_mode<TM_INCSTATE>(variant, t1, t2, pairs_dev, npairs, total, nblocks_grid, chunked, s);
 }
 
-template hipError_t launch_batched_step<float>(int, int, size_t, const PairStep *, int, int, int, int, hipStream_t);
-template hipError_t launch_batched_step<double>(int, int, size_t, const PairStep *, int, int, int, int, hipStream_t);
+template hipError_t launch_batched_step<float>(int, int, size_t, const PairStep *, int, int, int, int, int, int,
+                                               hipStream_t);
+template hipError_t launch_batched_step<double>(int, int, size_t, const PairStep *, int, int, int, int, int, int,
+                                                hipStream_t);
 
 namespace {
 

@@ -65,6 +65,7 @@ int slots_of(const Request &r) {
 struct TuneEntry {
     int blocks = 0;
     int chunked = 1;
+    int t1 = regk::kTile1, t2 = regk::kTile2;  // tile shape t1 x t2 x 64
     double ms = 0;
 };
 std::mutex g_tune_mu;
@@ -91,6 +92,7 @@ struct reg_batch {
     // launch configuration
     int fixed_blocks = 0;  // 0: autotune
     int fixed_chunked = 1;
+    int fixed_t1 = 0, fixed_t2 = 0;  // 0: tile shape autotuned
     int use_graph = 1;
     struct GraphEntry {
         std::vector<int64_t> key;
@@ -126,7 +128,8 @@ int kind_of_mode(int mode) {
     return mode == regk::STEP_INTERP ? REG_K_INTERP : mode == regk::STEP_ADJOINT ? REG_K_ADJOINT : REG_K_INCSTATE;
 }
 
-// One batched step launch: mode, kernel variant, dynamic LDS, table.
+// One batched step launch: mode, kernel variant, dynamic LDS, table; total
+// counts unit tiles (regk::unit_tiles_of).
 struct Launch {
     int mode = 0, variant = 0, n = 0, total = 0;
     size_t lds = 0;
@@ -150,18 +153,52 @@ std::string tune_key(const Launch &L, const regk::PairStep *p, size_t esz) {
 // here, by timing every candidate on this very launch, when the shape is not
 // known yet and the stream is not being captured; every candidate computes
 // the same output from the same inputs).
+// tile shapes t1 x t2 x 64 that a launch can take: the box of the variant
+// fits, and every problem's grid is made of whole tiles
+std::vector<std::pair<int, int>> tile_shapes(const Launch &L, const regk::PairStep *host) {
+    std::vector<std::pair<int, int>> out;
+    if (L.variant == 0) return {{regk::kTile1, regk::kTile2}};  // the generic kernel: default tiles
+    for (int i = 0; i < regk::kBatchTileCount; i++) {
+        const int t1 = regk::kBatchTiles[i][0], t2 = regk::kBatchTiles[i][1];
+        if (!regk::batch_tile_ok(L.variant, t1, t2)) continue;
+        bool ok = true;
+        for (int p = 0; p < L.n && ok; p++) ok = host[p].g.n1 % t1 == 0 && host[p].g.n2 % t2 == 0;
+        if (ok) out.push_back({t1, t2});
+    }
+    return out;
+}
+
 template <typename T>
 reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *host, bool capturing) {
     TuneEntry e;
     bool have = false;
     const std::string key = tune_key(L, host, sizeof(T));
-    auto go = [&](int nb, int chunked) {
-        return regk::launch_batched_step<T>(L.mode, L.variant, L.lds, L.dev, L.n, L.total, nb, chunked, b->stream);
+    // work items of a shape: the launch's unit tiles / the unit tiles per tile
+    auto units = [&](int t1, int t2) { return L.variant == 0 ? 1 : (t1 / regk::kUnit1) * (t2 / regk::kUnit2); };
+    auto go = [&](int nb, int chunked, int t1, int t2) {
+        const int ratio = units(t1, t2);
+        return regk::launch_batched_step<T>(L.mode, L.variant, L.lds, L.dev, L.n, L.total / ratio,
+                                            std::max(8, std::min(nb, L.total / ratio)), chunked, t1, t2, b->stream);
     };
+    const auto shapes = tile_shapes(L, host);
+    if (shapes.empty()) return bfail(b, REG_EINVAL, "no tile shape fits a batched launch");
+    bool fixed_tile = false;
+    for (const auto &sh : shapes)
+        if (sh.first == b->fixed_t1 && sh.second == b->fixed_t2) fixed_tile = true;
     if (b->fixed_blocks > 0) {
         e.blocks = b->fixed_blocks;
         e.chunked = b->fixed_chunked;
+        e.t1 = fixed_tile ? b->fixed_t1 : shapes[0].first;
+        e.t2 = fixed_tile ? b->fixed_t2 : shapes[0].second;
         have = true;
+    } else if (fixed_tile) {
+        // a fixed tile with autotuned blocks: a key of its own
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key + "/t" + std::to_string(b->fixed_t1) + "x" + std::to_string(b->fixed_t2));
+        if (it != g_tune.end()) {
+            e = it->second;
+            have = true;
+        }
     } else {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -171,14 +208,20 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
         }
     }
     if (!have && capturing) {  // no timing under capture: a safe default
-        e.blocks = std::max(8, std::min(L.total, 1024));
+        e.blocks = 1024;
         e.chunked = 1;
+        e.t1 = fixed_tile ? b->fixed_t1 : shapes[0].first;
+        e.t2 = fixed_tile ? b->fixed_t2 : shapes[0].second;
         have = true;
     }
     if (!have) {
-        // powers of two, and multiples of 768 for the boxes that fit three
-        // workgroups per CU (256 CUs)
-        std::vector<int> cand = {256, 512, 768, 1024, 1536, 2048, 3072, 4096, L.total};
+        // tile shapes (or the fixed one) x workgroup counts (powers of two,
+        // multiples of 768 for boxes that fit three workgroups per CU, and
+        // all tiles) x XCD dealing, each timed on this very launch; every
+        // candidate computes the same output from the same inputs
+        std::vector<std::pair<int, int>> cand_shapes = shapes;
+        if (fixed_tile) cand_shapes = {{b->fixed_t1, b->fixed_t2}};
+        const std::vector<int> cand = {256, 512, 768, 1024, 1536, 2048, 3072, 4096, 1 << 30};
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
             hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess)
@@ -186,36 +229,42 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
         TuneEntry best;
         best.ms = 1e30;
         reg_status st = REG_OK;
-        for (int chunked = 1; chunked >= 0 && st == REG_OK; chunked--) {
-            for (int c : cand) {
-                const int nb = std::max(8, std::min(c, L.total));
-                hipError_t he = go(nb, chunked);
-                if (he == hipSuccess) he = hipEventRecord(e0, b->stream);
-                if (he == hipSuccess) he = go(nb, chunked);
-                if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
-                if (he == hipSuccess) he = hipEventSynchronize(e1);
-                float ms = 0;
-                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
-                if (he != hipSuccess) {
-                    st = bfail(b, REG_EHIP, std::string("launch tuner: ") + hipGetErrorString(he));
-                    break;
+        for (const auto &sh : cand_shapes) {
+            const int items = L.total / units(sh.first, sh.second);
+            for (int chunked = 1; chunked >= 0 && st == REG_OK; chunked--) {
+                for (int c : cand) {
+                    const int nb = std::max(8, std::min(c, items));
+                    hipError_t he = go(nb, chunked, sh.first, sh.second);
+                    if (he == hipSuccess) he = hipEventRecord(e0, b->stream);
+                    if (he == hipSuccess) he = go(nb, chunked, sh.first, sh.second);
+                    if (he == hipSuccess) he = hipEventRecord(e1, b->stream);
+                    if (he == hipSuccess) he = hipEventSynchronize(e1);
+                    float ms = 0;
+                    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                    if (he != hipSuccess) {
+                        st = bfail(b, REG_EHIP, std::string("launch tuner: ") + hipGetErrorString(he));
+                        break;
+                    }
+                    if (ms < best.ms) {
+                        best.ms = ms;
+                        best.blocks = nb;
+                        best.chunked = chunked;
+                        best.t1 = sh.first;
+                        best.t2 = sh.second;
+                    }
+                    if (c >= items) break;
                 }
-                if (ms < best.ms) {
-                    best.ms = ms;
-                    best.blocks = nb;
-                    best.chunked = chunked;
-                }
-                if (c >= L.total) break;
             }
+            if (st != REG_OK) break;
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st != REG_OK) return st;
         e = best;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = e;
+        g_tune[fixed_tile ? key + "/t" + std::to_string(b->fixed_t1) + "x" + std::to_string(b->fixed_t2) : key] = e;
     }
-    hipError_t he = timed(b->prof, kind_of_mode(L.mode), [&]() { return go(e.blocks, e.chunked); });
+    hipError_t he = timed(b->prof, kind_of_mode(L.mode), [&]() { return go(e.blocks, e.chunked, e.t1, e.t2); });
     if (he != hipSuccess) return bfail(b, REG_EHIP, std::string("batched step launch: ") + hipGetErrorString(he));
     b->launches++;
     b->last[L.mode] = e;
@@ -343,8 +392,11 @@ struct Exec {
                 ps.canon = regk::canonical(a.ctx->g, *tg, sizeof(T));
                 const int span = regk::batch_span(*tg);
                 const int cls = !ps.canon ? 3 : span <= 1 ? 0 : span <= 2 ? 1 : 2;
+                // canonical classes count unit tiles (any batch tile shape
+                // follows), the generic class the default tiles of its
+                // possibly ragged grids
                 ps.tile0 = total[cls];
-                total[cls] += regk::tiles_of(a.ctx->g);
+                total[cls] += cls == 3 ? regk::tiles_of(a.ctx->g) : regk::unit_tiles_of(a.ctx->g);
                 lds[cls] = std::max(lds[cls], sizeof(T) * (size_t)tg->B[0] * tg->B[1] * tg->B[2]);
                 items[cls].push_back(ps);
                 continue;
@@ -1405,13 +1457,27 @@ reg_status reg_batch_set_launch(reg_batch *b, int32_t blocks, int32_t chunked, i
     return REG_OK;
 }
 
-reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
-                                 double *ms) {
+reg_status reg_batch_set_tile(reg_batch *b, int32_t tile1, int32_t tile2) {
     BATCH_OK(b);
-    if (mode < 0 || mode > 2 || !blocks || !chunked || !variant || !ms) return bfail(b, REG_EINVAL, "bad launch query");
+    bool known = tile1 == 0 && tile2 == 0;
+    for (int i = 0; i < regk::kBatchTileCount; i++)
+        known = known || (regk::kBatchTiles[i][0] == tile1 && regk::kBatchTiles[i][1] == tile2);
+    if (!known) return bfail(b, REG_EINVAL, "tile must be 0 x 0 (autotune) or one of 4x8, 2x8, 8x8, 4x4, 8x4");
+    b->fixed_t1 = tile1;
+    b->fixed_t2 = tile2;
+    return REG_OK;
+}
+
+reg_status reg_batch_launch_info(reg_batch *b, int32_t mode, int32_t *blocks, int32_t *chunked, int32_t *variant,
+                                 int32_t *tile1, int32_t *tile2, double *ms) {
+    BATCH_OK(b);
+    if (mode < 0 || mode > 2 || !blocks || !chunked || !variant || !tile1 || !tile2 || !ms)
+        return bfail(b, REG_EINVAL, "bad launch query");
     *blocks = b->last[mode].blocks;
     *chunked = b->last[mode].chunked;
     *variant = b->last_variant[mode];
+    *tile1 = b->last[mode].t1;
+    *tile2 = b->last[mode].t2;
     *ms = b->last[mode].ms;
     return REG_OK;
 }

@@ -155,7 +155,9 @@ _SIGS = {
     "reg_batch_destroy": [_P],
     "reg_batch_ctx": [_P, ctypes.c_int32, ctypes.POINTER(_P)],
     "reg_batch_set_launch": [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32],
+    "reg_batch_set_tile": [_P, ctypes.c_int32, ctypes.c_int32],
     "reg_batch_launch_info": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                              ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                               ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
     "reg_batch_stats": [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                         ctypes.POINTER(ctypes.c_int64)],
@@ -538,12 +540,18 @@ class Batch:
         _bchk(lib().reg_batch_set_launch(self.handle, int(blocks), int(chunked), int(bool(use_graph))), self.handle,
               "reg_batch_set_launch")
 
+    def reg_batch_set_tile(self, tile1=0, tile2=0):
+        """Fixes the tile shape tile1 x tile2 x 64 of the batched canonical launches (0, 0: autotuned)."""
+        _bchk(lib().reg_batch_set_tile(self.handle, int(tile1), int(tile2)), self.handle, "reg_batch_set_tile")
+
     def reg_batch_launch_info(self, mode):
-        """(workgroups, chunked, kernel variant, tuned ms) of the last batched launch of a step kind."""
+        """(workgroups, chunked, kernel variant, (tile1, tile2), tuned ms) of the last batched launch of a step kind."""
         b, c, v, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        t1, t2 = ctypes.c_int32(), ctypes.c_int32()
         _bchk(lib().reg_batch_launch_info(self.handle, int(mode), ctypes.byref(b), ctypes.byref(c), ctypes.byref(v),
-                                          ctypes.byref(ms)), self.handle, "reg_batch_launch_info")
-        return b.value, c.value, v.value, ms.value
+                                          ctypes.byref(t1), ctypes.byref(t2), ctypes.byref(ms)), self.handle,
+              "reg_batch_launch_info")
+        return b.value, c.value, v.value, (t1.value, t2.value), ms.value
 
     def reg_batch_stats(self):
         a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()

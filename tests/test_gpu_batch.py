@@ -82,7 +82,7 @@ def test_batch_transport_matches_single_and_oracle(reg, cases, prec, scale):
     rb = b.reg_batch_transport_forward(vs, r0)
     torch.cuda.synchronize()
     st = b.reg_batch_stats()
-    say(f"  stats {st}, interp launch (blocks, chunked, variant, ms) {b.reg_batch_launch_info(0)}")
+    say(f"  stats {st}, interp launch (blocks, chunked, variant, tile, ms) {b.reg_batch_launch_info(0)}")
     # single precision always goes through the batched persistent launch;
     # double precision does where its boxes fit the LDS
     if prec == 0:
@@ -108,10 +108,38 @@ def test_batch_launch_shape_does_not_change_results(reg, cases, blocks, chunked)
     fixed = b.reg_batch_transport_forward(vs, r0)
     torch.cuda.synchronize()
     info = b.reg_batch_launch_info(0)
-    say(f"  fixed launch (blocks, chunked, variant, ms) {info}")
+    say(f"  fixed launch (blocks, chunked, variant, tile, ms) {info}")
     assert info[0] == blocks and info[1] == chunked
     for i in range(len(PROBLEMS)):
         assert torch.equal(auto[i], fixed[i]), f"problem {i}"
+
+
+@pytest.mark.parametrize("tile", [(2, 8), (8, 8), (4, 4), (8, 4), (4, 8)])
+def test_batch_tile_shape_does_not_change_results(reg, cases, tile):
+    """Every tile shape of the batched canonical kernels computes each point
+    with the same arithmetic from the same box values: results equal the
+    autotuned launch bit for bit, for the three step kinds (the problems in
+    whole tiles of every shape, so that each launch is canonical and reports
+    the shape it ran)."""
+    idx = [i for i, (s, _, _) in enumerate(PROBLEMS) if s[0] % 8 == 0 and s[1] % 8 == 0 and s[2] % 64 == 0]
+    b = reg.Batch([_params(reg, *PROBLEMS[i]) for i in idx])
+    cs = [cases[i] for i in idx]
+    for j, c in enumerate(cs):
+        b.reg_set_images(j, to_dev(c["rhoT"], b.contexts[j]), to_dev(c["rhoR"], b.contexts[j]))
+    vs = [to_vel(c["v"], ctx) for c, ctx in zip(cs, b.contexts)]
+    r0 = [to_dev(c["rhoT"], ctx) for c, ctx in zip(cs, b.contexts)]
+    auto = b.reg_batch_transport_forward(vs, r0)
+    gauto = [g.clone() for g in b.reg_batch_gradient(vs)[0]]
+    b.reg_batch_set_tile(*tile)
+    fixed = b.reg_batch_transport_forward(vs, r0)
+    info = b.reg_batch_launch_info(0)
+    gfix = b.reg_batch_gradient(vs)[0]
+    torch.cuda.synchronize()
+    say(f"  tile {tile}: interp launch (blocks, chunked, variant, tile, ms) {info}")
+    assert info[2] != 0 and info[3] == tile
+    for i in range(len(idx)):
+        assert torch.equal(auto[i], fixed[i]), f"transport of problem {idx[i]}"
+        assert torch.equal(gauto[i], gfix[i]), f"gradient of problem {idx[i]}"
 
 
 def test_batch_gradient_and_graph_matvec_match_single(reg, cases):
