@@ -746,6 +746,199 @@ __global__ __launch_bounds__(kTileThreads) void k_tiled_canon(Grid g, TileGeom t
     canon_tile<T, MODE, S>(g, tg, tile_of(g), f, D, args, box);
 }
 
+// ------------------------------------------------ RK2 backtrace through LDS
+//
+// The departure points of eq. (6) need v at the predicted points x + D*,
+// D* = c v(x) / h: three gathers with one stencil per point. A workgroup owns
+// a canonical tile; from its points' predictors it reduces its own floor
+// bounds (so one fast region does not widen every tile's box), then stages
+// the three components of v one after another in that box and reads each
+// point's stencil from LDS. A tile whose predictor spans more floors than the
+// box holds, or is not finite, gathers straight from global memory. The
+// result is D = c (v(x) + v(x + D*)) / (2 h).
+
+// the stencil sum of v at one point's predicted position, from a staged
+// canonical box (scaled weights, so the sum is divided by 216 at the end)
+template <int S>
+__device__ __forceinline__ float bt_point(const float *box, const TileGeom &tg, int a1, int a2, int lane, float d1,
+                                          float d2, float d3) {
+    using K = Canon<S>;
+    constexpr unsigned kPlane = K::C2 * K::C3;
+    float w1[4], w2[4], w3[4];
+    const int l1 = canon_base(d1, float(tg.lo[0] + 1 - a1), float(tg.lo[0] + tg.B[0] - 3 - a1), a1 - 1 - tg.lo[0], w1);
+    const int l2 = canon_base(d2, float(tg.lo[1] + 1 - a2), float(tg.lo[1] + tg.B[1] - 3 - a2), a2 - 1 - tg.lo[1], w2);
+    const int l3 = canon_base(d3, float(tg.lo[2] + 1 - lane), float(tg.lo[2] + tg.B[2] - 3 - lane),
+                              lane - 1 - tg.lo[2], w3);
+    const unsigned eb = (unsigned)((l1 * K::C2 + l2) * K::C3 + l3) * sizeof(float);
+    const char *lds = reinterpret_cast<const char *>(box);
+    float acc = 0.f;
+#pragma unroll
+    for (int a = 0; a < 4; a++) {
+        const float *r0 = reinterpret_cast<const float *>(lds + opaque(eb + a * kPlane * sizeof(float)));
+        const float *r3 = reinterpret_cast<const float *>(lds + opaque(eb + (a * kPlane + 3 * K::C3) * sizeof(float)));
+        float pa = 0.f;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const float *r = r0 + b * K::C3;
+            pa += w2[b] * (w3[0] * r[0] + w3[1] * r[1] + w3[2] * r[2] + w3[3] * r[3]);
+        }
+        pa += w2[3] * (w3[0] * r3[0] + w3[1] * r3[1] + w3[2] * r3[2] + w3[3] * r3[3]);
+        acc += w1[a] * pa;
+    }
+    return acc * (1.f / 216.f);
+}
+
+// the three components through a box of span S, each written as soon as it
+// is gathered
+template <int S>
+__device__ __forceinline__ void bt_tile_canon(const Grid &g, const TileGeom &tg, const TileIdx &t,
+                                              const float *__restrict__ v, const float (&u)[kTile1][3], const float c,
+                                              const float ih[3], float *box, float *__restrict__ D, unsigned b0,
+                                              unsigned line_bytes) {
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const unsigned N = (unsigned)g.N();
+    const float hc = 0.5f * c;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        if (j) __syncthreads();  // the previous component's reads are done
+        stage_box_canon<float, S>(g, tg, t, v + (size_t)j * N, box);
+        __syncthreads();
+        gmem<float> *__restrict__ out = (gmem<float> *)D + (size_t)j * N;
+#pragma unroll
+        for (int k = 0; k < kTile1; k++) {
+            // the predictor again for each component, through an opaque copy:
+            // otherwise the compiler keeps all points' weights alive across
+            // the three stagings (120 registers instead of under 80)
+            float d1 = c * u[k][0] * ih[0], d2 = c * u[k][1] * ih[1], d3 = c * u[k][2] * ih[2];
+            asm("" : "+v"(d1), "+v"(d2), "+v"(d3));
+            const float w = bt_point<S>(box, tg, k, wave, lane, d1, d2, d3);
+            st_at(out, b0 + (unsigned)(k * g.n2 + wave) * line_bytes, hc * (u[k][j] + w) * ih[j]);
+        }
+    }
+}
+
+// Launched with eight wavefronts per SIMD requested, so that four workgroups
+// share a CU as their LDS allows: the compiler then fits the kernel in 64
+// registers with a few spilled (at its natural 80 registers only three fit,
+// and a 256^3 backtrace took 413 instead of 380 us).
+__global__ __launch_bounds__(kTileThreads, 8) void k_backtrace_canon(Grid g, const float *__restrict__ v, float c,
+                                                                  float ih1, float ih2, float ih3,
+                                                                  float *__restrict__ D) {
+    constexpr int kElems = Canon<1>::elems > Canon<2>::elems ? Canon<1>::elems : Canon<2>::elems;
+    __shared__ float box[kElems];
+    __shared__ float red[kWaves][6];
+    const TileIdx t = tile_of(g);
+    const int wave = wave_id(), lane = threadIdx.x & 63;
+    const unsigned N = (unsigned)g.N();
+    const unsigned line_bytes = (unsigned)g.n3 * sizeof(float);
+    const int i3 = t.t3 * kTile3 + lane;
+    const unsigned b0 = (unsigned)(((t.t1 * kTile1) * g.n2 + t.t2 * kTile2) * g.n3 + i3) * sizeof(float);
+    const float ih[3] = {ih1, ih2, ih3};
+    // the thread's points (x1 rows k, x2 row `wave`, x3 position `lane`):
+    // ordinary loads, so that the lines stay in L2 for the staging below
+    const gmem<float> *V = (const gmem<float> *)v;
+    float u[kTile1][3];
+    float mn[3], mx[3];
+#pragma unroll
+    for (int k = 0; k < kTile1; k++) {
+        const unsigned o = b0 + (unsigned)(k * g.n2 + wave) * line_bytes;
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            u[k][j] = *reinterpret_cast<const gmem<float> *>(reinterpret_cast<const gmem<char> *>(V + (size_t)j * N) + o);
+            // floor of the predictor, clamped (NaN and infinities become
+            // +-1e6, which no box holds)
+            const float fl = floorf(c * u[k][j] * ih[j]);
+            const float f = fl == fl ? fminf(fmaxf(fl, -1e6f), 1e6f) : 1e6f;
+            mn[j] = k ? fminf(mn[j], f) : f;
+            mx[j] = k ? fmaxf(mx[j], f) : f;
+        }
+    }
+    // the tile's floor bounds: wavefront, then workgroup
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        for (int off = 32; off > 0; off >>= 1) {
+            mn[j] = fminf(mn[j], __shfl_xor(mn[j], off, 64));
+            mx[j] = fmaxf(mx[j], __shfl_xor(mx[j], off, 64));
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            red[wave][2 * j] = mn[j];
+            red[wave][2 * j + 1] = mx[j];
+        }
+    }
+    __syncthreads();
+    float lo[3], hi[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        lo[j] = red[0][2 * j];
+        hi[j] = red[0][2 * j + 1];
+#pragma unroll
+        for (int w = 1; w < kWaves; w++) {
+            lo[j] = fminf(lo[j], red[w][2 * j]);
+            hi[j] = fmaxf(hi[j], red[w][2 * j + 1]);
+        }
+    }
+    const float span = fmaxf(fmaxf(hi[0] - lo[0], hi[1] - lo[1]), hi[2] - lo[2]);
+    if (span <= 2.f) {
+        TileGeom tg;
+        const int tile[3] = {kTile1, kTile2, kTile3};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            tg.lo[j] = (int)lo[j] - 1;
+            tg.B[j] = tile[j] + (int)(hi[j] - lo[j]) + 3;
+        }
+        if (span <= 1.f)
+            bt_tile_canon<1>(g, tg, t, v, u, c, ih, box, D, b0, line_bytes);
+        else
+            bt_tile_canon<2>(g, tg, t, v, u, c, ih, box, D, b0, line_bytes);
+        return;
+    }
+    // rare: one point, one component and one x1 plane at a time (operands
+    // reloaded or recomputed, not indexed from unrolled arrays), so that the
+    // loads of this path do not set the register budget of the kernel
+    const float hc = 0.5f * c;
+    const int i1_0 = t.t1 * kTile1, i2 = t.t2 * kTile2 + wave;
+#pragma unroll 1
+    for (int k = 0; k < kTile1; k++) {
+        const unsigned o = b0 + (unsigned)(k * g.n2 + wave) * line_bytes;
+        const unsigned p = o / sizeof(float);
+        const float x1 = v[p], x2 = v[N + p], x3 = v[2 * (size_t)N + p];
+        float w1[4], w2[4], w3[4];
+        const int s1 = axis_base(i1_0 + k, c * x1 * ih1, g.n1, w1);
+        int o2[4], o3[4];
+        axis_offsets(axis_base(i2, c * x2 * ih2, g.n2, w2), g.n2, g.n3, o2);
+        axis_offsets(axis_base(i3, c * x3 * ih3, g.n3, w3), g.n3, 1, o3);
+#pragma unroll 1
+        for (int j = 0; j < 3; j++) {
+            // 32-bit byte offsets from the component's uniform base (grids
+            // of the canonical kernels hold at most 2^30 points)
+            const gmem<char> *f = reinterpret_cast<const gmem<char> *>((const gmem<float> *)v + (size_t)j * N);
+            float w = 0.f;
+            int r1 = s1;
+#pragma unroll 1
+            for (int a = 0; a < 4; a++) {
+                const float wa = a == 0 ? w1[0] : a == 1 ? w1[1] : a == 2 ? w1[2] : w1[3];
+                float pa = 0.f;
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const unsigned row = (unsigned)(r1 * g.n2 * g.n3 + o2[b]) * sizeof(float);
+                    float x[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        x[q] = *reinterpret_cast<const gmem<float> *>(f + row + (unsigned)o3[q] * sizeof(float));
+                    pa += w2[b] * (w3[0] * x[0] + w3[1] * x[1] + w3[2] * x[2] + w3[3] * x[3]);
+                }
+                w += wa * pa;
+                r1 = r1 + 1 == g.n1 ? 0 : r1 + 1;
+            }
+            const float xj = j == 0 ? x1 : j == 1 ? x2 : x3, ihj = j == 0 ? ih1 : j == 1 ? ih2 : ih3;
+            st_at((gmem<float> *)D + (size_t)j * N, o, hc * (xj + w) * ihj);
+        }
+    }
+}
+
 // Batched persistent variants: gridDim.x workgroups walk a work list of
 // (pair, tile) items over all pairs of a batch (pairs sorted by tile0). With
 // `chunked` the items are dealt to the XCDs in contiguous chunks, so that each
@@ -843,20 +1036,49 @@ __global__ __launch_bounds__(kTileThreads) void k_batched_generic(const PairStep
                                });
 }
 
+// Floor bounds of D, one partial per block. Wide blocks with four loads per
+// stream in flight: the partial buffer allows only RED_BLOCKS / 6 blocks, and
+// with 256 threads those kept too few loads in flight to stream D at HBM
+// rate. Floors are exact in T, so min and max are taken in T; NaN entries
+// are skipped (the gathers clamp their floors into the box).
+constexpr int kBoundThreads = 1024;
+
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_floor_bounds(Grid g, const T *__restrict__ D,
-                                                           double *__restrict__ partials) {
+__global__ __launch_bounds__(kBoundThreads) void k_floor_bounds(Grid g, const T *__restrict__ D,
+                                                                double *__restrict__ partials) {
     const long N = g.N();
-    double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (long i = (long)blockIdx.x * kThreads + threadIdx.x; i < N; i += (long)gridDim.x * kThreads) {
+    const long stride = (long)gridDim.x * kBoundThreads;
+    T mn[3], mx[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        mn[j] = T(INFINITY);
+        mx[j] = T(-INFINITY);
+    }
+    long i = (long)blockIdx.x * kBoundThreads + threadIdx.x;
+    for (; i + 3 * stride < N; i += 4 * stride) {
+        T x[3][4];
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int u = 0; u < 4; u++) x[j][u] = D[j * N + i + u * stride];
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const T fl = flo(x[j][u]);
+                mn[j] = fmin(mn[j], fl);
+                mx[j] = fmax(mx[j], fl);
+            }
+    }
+    for (; i < N; i += stride) {
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            const double fl = floor((double)D[j * N + i]);
+            const T fl = flo(D[j * N + i]);
             mn[j] = fmin(mn[j], fl);
             mx[j] = fmax(mx[j], fl);
         }
     }
-    __shared__ double sm[6][kThreads / 64];
+    __shared__ T sm[6][kBoundThreads / 64];
 #pragma unroll
     for (int j = 0; j < 3; j++) {
         for (int off = 32; off > 0; off >>= 1) {
@@ -871,9 +1093,9 @@ __global__ __launch_bounds__(kThreads) void k_floor_bounds(Grid g, const T *__re
     __syncthreads();
     if (threadIdx.x < 6) {
         const bool is_min = (threadIdx.x & 1) == 0;
-        double v = sm[threadIdx.x][0];
-        for (int i = 1; i < kThreads / 64; i++) v = is_min ? fmin(v, sm[threadIdx.x][i]) : fmax(v, sm[threadIdx.x][i]);
-        partials[6 * blockIdx.x + threadIdx.x] = v;
+        T v = sm[threadIdx.x][0];
+        for (int w = 1; w < kBoundThreads / 64; w++) v = is_min ? fmin(v, sm[threadIdx.x][w]) : fmax(v, sm[threadIdx.x][w]);
+        partials[6 * blockIdx.x + threadIdx.x] = (double)v;
     }
 }
 
@@ -1047,7 +1269,7 @@ bool tile_geom(const double fmin[3], const double fmax[3], size_t elem, TileGeom
 
 template <typename T>
 hipError_t launch_floor_bounds(const Grid &g, const T *D, double *partials, int nb, hipStream_t s) {
-    hipLaunchKernelGGL(k_floor_bounds<T>, dim3(nb), dim3(kThreads), 0, s, g, D, partials);
+    hipLaunchKernelGGL(k_floor_bounds<T>, dim3(nb), dim3(kBoundThreads), 0, s, g, D, partials);
     return hipGetLastError();
 }
 
@@ -1070,6 +1292,14 @@ hipError_t launch_interp(const Grid &g, const T *f, const T *D, T *out, hipStrea
 template <typename T>
 hipError_t launch_backtrace(const Grid &g, const T *v, double sign_dt, T *D, hipStream_t s) {
     const double pi2 = 6.283185307179586476925286766559;
+    if constexpr (sizeof(T) == 4) {
+        // whole canonical tiles: the LDS form
+        if (g.n1 % kTile1 == 0 && g.n2 % kTile2 == 0 && g.n3 % kTile3 == 0) {
+            hipLaunchKernelGGL(k_backtrace_canon, dim3(ntiles(g)), dim3(kTileThreads), 0, s, g, v, T(-sign_dt),
+                               T(g.n1 / pi2), T(g.n2 / pi2), T(g.n3 / pi2), D);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL(k_backtrace<T>, dim3(nblocks(g.N())), dim3(kThreads), 0, s, g, v, T(-sign_dt),
                        T(g.n1 / pi2), T(g.n2 / pi2), T(g.n3 / pi2), D);
     return hipGetLastError();

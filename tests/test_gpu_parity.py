@@ -152,6 +152,40 @@ def test_backtrace(reg, prec, sign):
     assert rel_l2(D, ref) <= TOL[("backtrace", prec)]
 
 
+def _tile_spans(Dstar, tile=(4, 8, 64)):
+    """Largest floor span of the predictor over each 4 x 8 x 64 tile, in
+    classes 0..3 (3 meaning 3 or more)."""
+    fl = np.floor(Dstar)
+    n1, n2, n3 = fl.shape[1:]
+    t = fl.reshape(3, n1 // tile[0], tile[0], n2 // tile[1], tile[1], n3 // tile[2], tile[2])
+    sp = (t.max(axis=(2, 4, 6)) - t.min(axis=(2, 4, 6))).max(axis=0)
+    return np.bincount(np.minimum(sp.ravel().astype(int), 3), minlength=4)
+
+
+@pytest.mark.parametrize("sign", [1, -1])
+@pytest.mark.parametrize("cells", [0.3, 1.5, 8.0])
+def test_backtrace_whole_tiles(reg, sign, cells):
+    """FP32 grids of whole 4 x 8 x 64 tiles take the LDS backtrace, in which
+    each tile sizes its box from its own predictors D* = dt v / h. A predictor
+    of at most 0.3 cells keeps every tile within floor span 1; 1.5 cells mixes
+    span-1 and span-2 boxes with tiles that gather from global memory (span 3
+    or more), in one launch; 8 cells sends every tile to the global gather."""
+    shape, nt = (16, 32, 128), 4
+    Dstar = synth.displacement(shape, 107, max_cells=cells)
+    spans = _tile_spans(Dstar)
+    say(f"  cells {cells}: tiles by predictor span {spans.tolist()}")
+    if cells == 1.5:
+        assert spans[1] > 0 and spans[2] > 0 and spans[3] > 0
+    h = 2 * np.pi / np.array(shape)
+    v = rounded(Dstar * (nt * h)[:, None, None, None], 0)
+    ctx = make_ctx(reg, shape, 0, nt=nt)
+    D = to_host(ctx.reg_backtrace(to_vel(v, ctx), sign))
+    ref = oracle.backtrace(v, nt, sign)
+    err = rel_l2(D, ref)
+    say(f"  sign {sign}: rel-L2 {err:.2e}")
+    assert err <= TOL[("backtrace", 0)]
+
+
 # ---------------------------------------------------------------- spectral
 @pytest.mark.parametrize("prec", [1, 0])
 @pytest.mark.parametrize("shape", [RAGGED, CUBE, WIDE, WIDE17, LONG3, X3TAIL])
