@@ -600,6 +600,10 @@ def main():
         "gn_steps": rep["n_iter"],
         "matvecs": rep["matvecs"],
         "pcg_iters": rep["pcg_iters"],
+        "solve_alg_bytes": rep["alg_bytes"],
+        "solve_alg_gb_s": rep["alg_bytes"] / rep["seconds_total"] / 1e9,
+        "fft3d": rep["fft3d"],
+        "fft_lines": rep["fft_lines"],
         "interp_gpts_s": gpts,
         "interp_gb_s": interp_gbs,
         "kernel_ms": {k: {"timed_launches": n_, "avg_ms": (t_ / n_ if n_ else None)} for k, (n_, t_) in prof.items()},

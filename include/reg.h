@@ -136,6 +136,12 @@ typedef struct {
     int64_t fft3d;         /* 3D transforms, one component each (context's grid)       */
     int64_t fft_lines;     /* line-FFT derivative passes, one field each               */
     double det_min, det_max;  /* det grad y1 of the result (params.det_check), else 0   */
+    /* Algorithmic HBM bytes of the kernels the solve launched, on every grid:
+     * each kernel's operands read and written once (transport steps, plans,
+     * derivatives, 3D transforms, velocity-space passes, reductions). A model
+     * from operand sizes and launch counts, not a counter reading; divided by
+     * seconds_total it is the solve's average algorithmic bandwidth.        */
+    double alg_bytes;
 } reg_report;
 
 /* Fills *p with the paper's defaults for an n^3 grid (section IV-A3). */

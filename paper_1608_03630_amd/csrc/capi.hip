@@ -22,6 +22,7 @@ reg_status transport_forward_impl(reg_ctx *ctx, const void *v, const void *rho0,
         src = dst;
     }
     ctx->interps += ctx->P.nt;
+    alg_fields(ctx, 5.0 * ctx->P.nt);
     return REG_OK;
 }
 
@@ -36,6 +37,7 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
         STCHK(divergence<T>(ctx, ctx->vf, ctx->c2));
         HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<T>(ctx->g, CV<T>(ctx->c2), CV<T>(ctx->Dt), V<T>(ctx->cX2), ctx->stream, geom_of(ctx, ctx->Dt))));
         ctx->interps += 1;
+        alg_fields(ctx, 5 + 3);  // div v interpolated, Heun factor
     }
     if (src)
         HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_gamma<T>(N, CV<T>(ctx->c2), CV<T>(ctx->cX2), V<T>(ctx->gam2), 1.0 / nt,
@@ -48,6 +50,7 @@ reg_status transport_adjoint_impl(reg_ctx *ctx, const void *v, const void *lam1,
         in = out;
     }
     ctx->interps += nt;
+    alg_fields(ctx, (src ? 6.0 : 5.0) * nt);
     return REG_OK;
 }
 
@@ -241,6 +244,7 @@ reg_status reg_interp(reg_ctx *ctx, const void *f, const void *D, void *out) {
     NEED_DEV(ctx, out);
     if (f == out) return fail(ctx, REG_EINVAL, "out must not alias f");
     ctx->interps++;
+    alg_fields(ctx, 5);
     if (ctx->P.prec) {
         STCHK(measure_plan<double>(ctx, D));
         HIPCHK(ctx, KL(ctx, REG_K_INTERP, regk::launch_interp<double>(ctx->g, CV<double>(f), CV<double>(D), V<double>(out), ctx->stream, geom_of(ctx, D))));

@@ -172,6 +172,7 @@ struct reg_ctx {
     double normTR2 = 0;       // <rho_T - rho_R, rho_T - rho_R>
     long interps = 0;
     int64_t fft3d = 0, fft_lines = 0;  // 3D transforms and line-FFT derivatives (one component/field each)
+    double alg_bytes = 0;              // algorithmic HBM bytes of the kernels launched (see alg_fields)
     int64_t epoch = 0;  // bumped whenever a plan (departure points, tile geometry) changes
     std::string err;
 };
@@ -428,6 +429,24 @@ hipError_t to_field(reg_ctx *ctx, const void *src, void *dst, long n) {
     return regk::launch_convert<double, float>(n, CV<double>(src), V<float>(dst), ctx->stream);
 }
 
+// Algorithmic HBM bytes: what each launched kernel must read and write at
+// least (each operand once), summed per launch for reg_report.alg_bytes; a
+// model from the operand sizes, not a counter reading. Fields count N
+// elements, velocity-space vectors 3 Nh complex values, of the given type.
+inline void alg_fields(reg_ctx *ctx, double fields, size_t esz) {
+    ctx->alg_bytes += fields * (double)ctx->N * (double)esz;
+}
+inline void alg_fields(reg_ctx *ctx, double fields) { alg_fields(ctx, fields, ctx->esz); }
+inline void alg_vecs(reg_ctx *ctx, double vectors, size_t esz) {
+    ctx->alg_bytes += vectors * 6.0 * (double)ctx->Nh * (double)esz;
+}
+// ncomp 3D real transforms in a type of esz bytes: the x3 pass reads the
+// real field and writes the half spectrum, each of the two strided passes
+// reads and writes it in place
+inline void alg_fft3d(reg_ctx *ctx, int ncomp, size_t esz) {
+    ctx->alg_bytes += ncomp * ((double)ctx->N + 10.0 * (double)ctx->Nh) * (double)esz;
+}
+
 // reads kSlots doubles back (synchronises)
 inline reg_status fetch(reg_ctx *ctx, int nslots) {
     HIPCHK(ctx, hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * nslots, hipMemcpyDeviceToHost, ctx->stream));
@@ -439,6 +458,7 @@ inline reg_status fetch(reg_ctx *ctx, int nslots) {
 // dres[slot] = scale * reduction
 template <typename T>
 reg_status reduce(reg_ctx *ctx, const void *a, const void *b, long n, int mode, double scale, int slot) {
+    ctx->alg_bytes += (b ? 2.0 : 1.0) * (double)n * sizeof(T);
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_dot_partials<T>(CV<T>(a), CV<T>(b ? b : a), n, mode, ctx->dpart, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, scale, ctx->dres + slot, ctx->stream)));
     return REG_OK;
@@ -452,6 +472,7 @@ constexpr int kSlotPlanA = 8, kSlotPlanB = 16;
 // floor bounds of D over the grid into dres[slot..slot+5] (partials in `part`)
 template <typename T>
 reg_status bounds_enqueue(reg_ctx *ctx, const void *D, double *part, int slot) {
+    alg_fields(ctx, 3);
     const int nb = regk::RED_BLOCKS / 6;
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_floor_bounds<T>(ctx->g, CV<T>(D), part, nb, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize_bounds(part, nb, ctx->dres + slot, ctx->stream)));
@@ -477,6 +498,7 @@ template <typename T>
 reg_status plan_enqueue(reg_ctx *ctx, const void *vf, double sign, void *D, double *part, int slot) {
     HIPCHK(ctx, KL(ctx, REG_K_BACKTRACE, regk::launch_backtrace<T>(ctx->g, CV<T>(vf), sign / ctx->P.nt, V<T>(D), ctx->stream)));
     ctx->interps += 3;
+    alg_fields(ctx, 6);  // v in, D out (the gathers' halos come from cache)
     return bounds_enqueue<T>(ctx, D, part, slot);
 }
 
@@ -501,6 +523,8 @@ reg_status plan(reg_ctx *ctx, const void *vf, double sign, void *D) {
 // public backtrace: v is a velocity-space double vector
 template <typename T>
 reg_status backtrace_impl(reg_ctx *ctx, const void *v, double sign, void *D) {
+    alg_fields(ctx, 3, sizeof(double));
+    alg_fields(ctx, 3);
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, to_field<T>(ctx, v, ctx->vf, 3 * ctx->N)));
     return plan<T>(ctx, ctx->vf, sign, D);
 }
@@ -509,6 +533,7 @@ template <typename T>
 reg_status divergence(reg_ctx *ctx, const void *v, void *d) {
     const long N = ctx->N;
     ctx->fft_lines += 3;
+    alg_fields(ctx, 6);
     for (int j = 0; j < 3; j++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(v) + j * N, N, V<T>(d), N, j > 0, 1, ctx->stream)));
     return REG_OK;
@@ -519,6 +544,7 @@ template <typename T>
 reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
     const long N = ctx->N;
     ctx->fft_lines += 3 * nf;
+    alg_fields(ctx, 6.0 * nf);
     for (int j = 0; j < 3; j++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, j, CV<T>(u), N, V<T>(out) + j * N, 3 * N, 0, nf, ctx->stream)));
     return REG_OK;
@@ -529,6 +555,9 @@ reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
 template <typename T>
 reg_status resample_fields(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out) {
     hipStream_t st = src->stream;
+    alg_fft3d(src, ncomp, sizeof(T));
+    src->alg_bytes += ncomp * 2.0 * ((double)src->Nh + (double)dst->Nh) * sizeof(T);
+    alg_fft3d(dst, ncomp, sizeof(T));
     HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_forward<T, T>(src->spec, CV<T>(in), ncomp, 0, st))));
     HIPCHK(src, KL(src, REG_K_SYMBOL, regk::spec_resample<T>(src->spec, dst->spec, ncomp, st)));
     HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_inverse<T, T>(dst->spec, V<T>(out), ncomp, st))));
@@ -538,6 +567,7 @@ reg_status resample_fields(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in
 // spectral resampling of a velocity-space vector (3 half spectra of complex
 // double) from src's grid to dst's: truncation or zero-padding of the modes
 inline reg_status resample_vec_hat(reg_ctx *src, const void *xhat, reg_ctx *dst, void *yhat) {
+    src->alg_bytes += 6.0 * ((double)src->Nh + (double)dst->Nh) * sizeof(double);
     regk::SpecCtx a = src->spec, b = dst->spec;
     a.H = const_cast<void *>(xhat);
     b.H = yhat;
@@ -566,6 +596,7 @@ inline reg_status reg_term_to_slot(reg_ctx *ctx, int slot) {
 
 // sum_k w |k|^4 |v^|^2 partials of a spectral vector into dpart2
 inline reg_status biharm_partials(reg_ctx *ctx, const void *vhat) {
+    alg_vecs(ctx, 1, sizeof(double));
     HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_dot_partials(ctx->spec, 1, CV<double>(vhat), nullptr, ctx->dpart2,
                                                              regk::RED_BLOCKS, ctx->stream)));
     return REG_OK;
@@ -574,6 +605,7 @@ inline reg_status biharm_partials(reg_ctx *ctx, const void *vhat) {
 // physical double vector -> spectral
 inline reg_status to_spec(reg_ctx *ctx, const void *v, void *vhat) {
     ctx->fft3d += 3;
+    alg_fft3d(ctx, 3, sizeof(double));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<double, double>(ctx->spec, CV<double>(v), 3, vhat, ctx->stream))));
     return REG_OK;
 }
@@ -581,6 +613,8 @@ inline reg_status to_spec(reg_ctx *ctx, const void *v, void *vhat) {
 // spectral -> physical double vector (through the scratch spectrum)
 inline reg_status from_spec(reg_ctx *ctx, const void *vhat, void *v) {
     ctx->fft3d += 3;
+    alg_vecs(ctx, 2, sizeof(double));
+    alg_fft3d(ctx, 3, sizeof(double));
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<double>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<double, double>(ctx->spec, ctx->H, V<double>(v), 3, ctx->stream))));
     return REG_OK;
@@ -590,6 +624,9 @@ inline reg_status from_spec(reg_ctx *ctx, const void *vhat, void *v) {
 template <typename T>
 reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
     ctx->fft3d += 3;
+    alg_vecs(ctx, 1, sizeof(double));
+    alg_vecs(ctx, 1, sizeof(T));
+    alg_fft3d(ctx, 3, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::vec_load<T>(ctx->spec, CV<double>(vhat), ctx->H, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream))));
     return REG_OK;
@@ -600,6 +637,7 @@ reg_status spec_to_field(reg_ctx *ctx, const void *vhat, void *out) {
 template <typename T>
 reg_status field_from_krylov(reg_ctx *ctx, const void *p, void *out) {
     ctx->fft3d += 3;
+    alg_fft3d(ctx, 3, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse_from<T, T>(ctx->spec, ctx->H, V<T>(out), 3, ctx->stream, p))));
     return REG_OK;
 }
@@ -609,6 +647,9 @@ reg_status field_from_krylov(reg_ctx *ctx, const void *p, void *out) {
 template <typename T>
 reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat, int dot = 0, int slot = 0) {
     ctx->fft3d += 3;
+    alg_fft3d(ctx, 3, sizeof(T));
+    alg_vecs(ctx, out_hat ? 2 : 1, sizeof(double));  // x^ in, out^ out when wanted
+    alg_vecs(ctx, 1, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
     if (!dot) {
         HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<T>(ctx->spec, regk::VEC_ASSEMBLE, CV<double>(xhat), ctx->H,
@@ -630,6 +671,8 @@ reg_status assemble(reg_ctx *ctx, const void *xhat, const void *y, void *out_hat
 // dres[slot] = <r, M r>
 template <typename T>
 reg_status pcg_start(reg_ctx *ctx, int slot) {
+    alg_vecs(ctx, 1, sizeof(double));
+    alg_vecs(ctx, 3, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_start<T>(ctx->spec, CV<double>(ctx->ghat), ctx->beta, ctx->P.isochoric,
                                                          ctx->shat, ctx->rhat, ctx->phat, ctx->dpart,
                                                          regk::RED_BLOCKS, ctx->stream)));
@@ -643,6 +686,7 @@ reg_status pcg_start(reg_ctx *ctx, int slot) {
 // dres[slot_rz] = <r, M r>
 template <typename T>
 reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
+    alg_vecs(ctx, 6, sizeof(T));  // p, the b~ transform, s, r in; s, r out
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_step<T>(ctx->spec, a, ctx->phat, ctx->H, ctx->beta, ctx->P.isochoric,
                                                         ctx->shat, ctx->rhat, ctx->dpart, ctx->dpart2,
                                                         regk::RED_BLOCKS, ctx->stream)));
@@ -655,6 +699,7 @@ reg_status pcg_step(reg_ctx *ctx, double a, int slot_rr, int slot_rz) {
 // next PCG direction p = M r + b p
 template <typename T>
 reg_status pcg_direction(reg_ctx *ctx, double b) {
+    alg_vecs(ctx, 3, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::pcg_direction<T>(ctx->spec, ctx->rhat, b, ctx->beta, ctx->P.isochoric,
                                                              ctx->phat, ctx->stream)));
     return REG_OK;
@@ -663,6 +708,8 @@ reg_status pcg_direction(reg_ctx *ctx, double b) {
 // dres[slot] = <a, b> for a velocity vector a and a PCG vector b
 template <typename T>
 reg_status krylov_dot(reg_ctx *ctx, const void *a, const void *b, int slot) {
+    alg_vecs(ctx, 1, sizeof(double));
+    alg_vecs(ctx, 1, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::krylov_dot_partials<T>(ctx->spec, CV<double>(a), b, ctx->dpart,
                                                                    regk::RED_BLOCKS, ctx->stream)));
     HIPCHK(ctx, KL(ctx, REG_K_REDUCE, regk::launch_finalize(ctx->dpart, regk::RED_BLOCKS, h3(ctx) / (double)ctx->N,
@@ -673,6 +720,8 @@ reg_status krylov_dot(reg_ctx *ctx, const void *a, const void *b, int slot) {
 // out = x + a y for velocity vectors x, out and a PCG vector y
 template <typename T>
 reg_status krylov_axpy(reg_ctx *ctx, const void *x, double a, const void *y, void *out) {
+    alg_vecs(ctx, 2, sizeof(double));
+    alg_vecs(ctx, 1, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::krylov_axpy<T>(ctx->spec, CV<double>(x), a, y, V<double>(out), ctx->stream)));
     return REG_OK;
 }
@@ -682,6 +731,8 @@ reg_status krylov_axpy(reg_ctx *ctx, const void *x, double a, const void *y, voi
 template <typename T>
 reg_status curvature(reg_ctx *ctx, const void *p, const void *y, int slot) {
     ctx->fft3d += 3;
+    alg_fft3d(ctx, 3, sizeof(T));
+    alg_vecs(ctx, 2, sizeof(T));
     HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_forward_to<T, T>(ctx->spec, CV<T>(y), 3, ctx->H, ctx->stream))));
     HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::krylov_curvature<T>(ctx->spec, p, ctx->H, ctx->beta, ctx->P.isochoric,
                                                                 ctx->dpart, regk::RED_BLOCKS, ctx->stream)));
@@ -692,6 +743,7 @@ reg_status curvature(reg_ctx *ctx, const void *p, const void *y, int slot) {
 
 // z^ = M r^: inverse biharmonic (identity at k = 0), then P when isochoric
 inline reg_status precond_hat(reg_ctx *ctx, const void *rhat, void *zhat) {
+    alg_vecs(ctx, 2, sizeof(double));
     HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::vec_symbol<double>(ctx->spec, regk::VEC_PRECOND, CV<double>(rhat), nullptr,
                                                                ctx->beta, ctx->P.isochoric, V<double>(zhat), ctx->stream)));
     return REG_OK;
@@ -738,6 +790,7 @@ reg_status deformation_impl(reg_ctx *ctx, const void *v, void *u_out, double *dm
         cur = 1 - cur;
     }
     ctx->interps += 3 * nt;
+    alg_fields(ctx, 3 + 9.0 * nt + 18 + 9);  // zero u, the steps, the nine derivatives, det
     // du[a*3+b] = d_b u_a
     for (int b = 0; b < 3; b++)
         HIPCHK(ctx, KL(ctx, REG_K_DERIV, regk::spec_deriv<T>(ctx->spec, b, V<T>(ub[cur]), N, V<T>(ctx->du) + b * N, 3 * N, 0, 3,

@@ -624,14 +624,39 @@ struct Exec {
         }
     }
 
+    // Interpolations and the algorithmic bytes of the item's transport steps
+    // and pointwise field passes, in fields per point: a state step reads D
+    // and the gathered field and writes one (5), an adjoint step also reads
+    // its Heun factor (6; 5 when isochoric), an incremental-state step reads
+    // vt and grad rho^n as well (11), the b assembly reads lam^n and
+    // grad rho^n at every level and writes b. Plans, derivatives, transforms
+    // and velocity-space passes count where they are launched.
     void count(const Item &it) {
         reg_ctx *ctx = it.ctx;
         const int nt = ctx->P.nt;
+        const double adj = ctx->P.isochoric ? 5 : 6, bsum = 4.0 * (nt + 1) + 3;
         switch (it.req.op) {
-        case Op::GRADIENT: ctx->interps += (it.req.reuse ? 0 : nt) + (ctx->P.isochoric ? 0 : 1) + nt; break;
+        case Op::GRADIENT:
+            ctx->interps += (it.req.reuse ? 0 : nt) + (ctx->P.isochoric ? 0 : 1) + nt;
+            alg_fields(ctx, (it.req.reuse ? 0 : 2 + 5.0 * nt) + (ctx->P.isochoric ? 0 : 5 + 3) + 3 + adj * nt + bsum +
+                                (ctx->P.hessian ? 2.0 * (nt + 1) : 0));
+            break;
         case Op::OBJECTIVE:
-        case Op::FORWARD: ctx->interps += nt; break;
-        case Op::MATVEC: ctx->interps += (ctx->P.hessian ? 3 : 2) * nt; break;
+            ctx->interps += nt;
+            alg_fields(ctx, 2 + 5.0 * nt);
+            break;
+        case Op::FORWARD:
+            ctx->interps += nt;
+            alg_fields(ctx, 5.0 * nt);
+            break;
+        case Op::MATVEC:
+            ctx->interps += (ctx->P.hessian ? 3 : 2) * nt;
+            alg_fields(ctx, 7 + 11.0 * nt + adj * nt + bsum);
+            // full Newton: rho~ from q, lam vt, the interpolated source and
+            // its Heun update, and the lam grad rho~ part of b~
+            if (ctx->P.hessian)
+                alg_fields(ctx, 8.0 * (nt - 1) + 3 + 7.0 * (nt + 1) + 5.0 * nt + (adj - 1) * nt + 10.0 * (nt + 1));
+            break;
         default: break;
         }
     }
@@ -804,6 +829,7 @@ struct Solver {
     bool first_level = true;
     clk::time_point t0;
     long interps0 = 0;
+    double alg0 = 0;
 
     bool done() const { return st == S_DONE; }
 
@@ -845,6 +871,7 @@ struct Solver {
             case S_START: {
                 t0 = clk::now();
                 interps0 = ctx->interps;
+                alg0 = ctx->alg_bytes;
                 // the iterate lives on the half spectrum until the solve ends
                 if (!start_hat) STCHK(to_spec(ctx, v, ctx->vhat));
                 if (P.isochoric) STCHK(leray_hat(ctx, ctx->vhat));
@@ -1058,6 +1085,7 @@ struct Solver {
                 rep->final_mismatch = mis;
                 rep->final_grel = g0 > 0 ? gnorm / g0 : 0;
                 rep->interps = ctx->interps - interps0;
+                rep->alg_bytes = ctx->alg_bytes - alg0;
                 rep->seconds_total = secs(t0);
                 st = S_DONE;
                 return REG_OK;
@@ -1130,6 +1158,8 @@ template <typename T>
 reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool start_hat) {
     const auto t0 = clk::now();
     const int64_t fft3d0 = ctx->fft3d, lines0 = ctx->fft_lines;
+    const double alg_start = ctx->alg_bytes;
+    double alg_coarse = 0;  // the coarser grids' solves
     double beta_start = 0, gref_start = 0;
     if (levels > 1) {
         reg_ctx *c = ctx->coarse;
@@ -1167,6 +1197,7 @@ reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool 
         STCHK(resample_vec_hat(c, c->vhat, ctx, ctx->vhat));
         beta_start = rc->final_beta;
         gref_start = rc->final_gref;
+        alg_coarse = rc->alg_bytes;
         start_hat = true;
     }
     Exec<T> ex(nullptr, ctx->stream);
@@ -1189,19 +1220,24 @@ reg_status solve_chain(reg_ctx *ctx, void *v, reg_report *rep, int levels, bool 
     rep->grid_levels = l + 1;
     rep->fft3d = ctx->fft3d - fft3d0;
     rep->fft_lines = ctx->fft_lines - lines0;
-    if (st != REG_OK) {
+    // wall clock and algorithmic bytes of everything above, every grid
+    auto finish = [&]() {
         rep->seconds_total = secs(t0);
+        rep->alg_bytes = ctx->alg_bytes - alg_start + alg_coarse;
+    };
+    if (st != REG_OK) {
+        finish();
         return st;
     }
     // the map of the result and det grad y1 (on the caller's grid only)
     if (ctx->P.det_check && v && (S[0].status == REG_OK || S[0].status == REG_ELINESEARCH)) {
         STCHK(deformation_impl<T>(ctx, v, nullptr, &rep->det_min, &rep->det_max));
         if (S[0].status == REG_OK && !(rep->det_min > 0)) {
-            rep->seconds_total = secs(t0);
+            finish();
             return fail(ctx, REG_ENONDIFFEO, "det grad y1 <= 0 at the result: the map is not a diffeomorphism");
         }
     }
-    rep->seconds_total = secs(t0);
+    finish();
     return S[0].status;
 }
 

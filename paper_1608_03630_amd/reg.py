@@ -99,6 +99,7 @@ class reg_report(ctypes.Structure):
         ("fft_lines", ctypes.c_int64),
         ("det_min", ctypes.c_double),
         ("det_max", ctypes.c_double),
+        ("alg_bytes", ctypes.c_double),
     ]
 
     def to_dict(self):
@@ -108,7 +109,7 @@ class reg_report(ctypes.Structure):
                                              "seconds_total", "seconds_matvec", "seconds_gradient",
                                              "seconds_objective", "seconds_precond", "interps", "final_beta",
                                              "final_gref", "negative_curvature", "descent_fallbacks", "fft3d",
-                                             "fft_lines", "det_min", "det_max")}
+                                             "fft_lines", "det_min", "det_max", "alg_bytes")}
         for f in ("J", "mismatch", "grel", "alpha", "beta", "pcg_iters", "ls_trials"):
             out[f] = list(getattr(self, f)[:k])
         out["levels"] = [{"n": tuple(self.level_n[i]), "n_iter": self.level_iters[i],

@@ -355,6 +355,14 @@ def test_smooth_case_solve_fp64_matches_oracle(reg):
     assert rep["n_iter"] == rep_ref["n_iter"] and rep["stop_reason"] == rep_ref["stop_reason"]
     assert rel_l2(to_host(v), v_ref) <= 1e-9
     assert np.allclose(rep["J"], rep_ref["J"], rtol=1e-10, atol=0)
+    # algorithmic bytes: at least the transport part of every Gauss-Newton
+    # matvec (incremental-state init 7 fields, steps 11 and 6 per time step,
+    # b~ over nt + 1 levels), at most a generous multiple of all operations
+    N, esz = np.prod(shape), 8
+    per_mv = 7 + 17 * nt + 4 * (nt + 1) + 3
+    ops = rep["matvecs"] + rep["gradients"] + rep["objectives"]
+    say(f"  alg bytes {rep['alg_bytes']:.3e} = {rep['alg_bytes'] / (N * esz * rep['matvecs']):.0f} fields per matvec")
+    assert rep["matvecs"] * per_mv * N * esz <= rep["alg_bytes"] <= 4 * ops * per_mv * N * esz
 
 
 def test_continuation_with_loose_levels_matches_oracle(reg):
