@@ -109,7 +109,8 @@ SQ_PASSES = [
 GATHER_KERNELS = [("k_tiled_canon<float, 0, 1>", "state step (interp)", 20.0),
                   ("k_tiled_canon<float, 1, 1>", "adjoint step", 24.0),
                   ("k_tiled_canon<float, 2, 1>", "incremental-state step", 44.0),
-                  ("k_backtrace<float>", "backtrace (direct gather)", 24.0),
+                  ("k_backtrace_canon", "backtrace (LDS tiles)", 24.0),
+                  ("k_floor_bounds<float>", "floor bounds of D", 12.0),
                   ("k_b_assemble<float>", "b assembly (17 levels)", 16.0 * 17 + 12.0)]
 
 
