@@ -114,19 +114,21 @@ def host_cpu():
     return {"model": model, "os_cpu_count": os.cpu_count()}
 
 
-def _median_time(fn, runs=5, warm=1):
+def _median_time(fn, runs=5, warm=1, tag=None):
     for _ in range(warm):
         fn()
     ts = []
-    for _ in range(runs):
+    for i in range(runs):
         t = time.perf_counter()
         fn()
         ts.append(time.perf_counter() - t)
+        if tag:
+            log(f"[bench]   {tag} run {i + 1}/{runs}: {ts[-1]:.2f} s")
     ts.sort()
     return ts[len(ts) // 2]
 
 
-def oracle_operators(m, runs=5, nt=16, seed=1003):
+def oracle_operators(m, runs=5, nt=16, seed=1003, verbose=False):
     """Median times (runs after one warm-up) of the FP64 oracle's operators on
     the m^3 phantom workload: one interpolation, the backtrace, the state and
     adjoint transports, the reduced gradient and the Gauss-Newton matvec."""
@@ -148,14 +150,19 @@ def oracle_operators(m, runs=5, nt=16, seed=1003):
     def grad():
         g[0] = oracle.gradient(P, rhoT, rhoR, v)[0]
 
+    def tag(name):
+        return f"{m}^3 {name}" if verbose else None
+
     out = {
-        "interp": _median_time(lambda: oracle.interp(rhoT, D), runs),
-        "backtrace": _median_time(lambda: oracle.backtrace(v, nt), runs),
-        "transport_forward": _median_time(lambda: oracle.transport_forward(P, v, rhoT), runs),
-        "transport_adjoint": _median_time(lambda: oracle.transport_adjoint(P, v, lam1), runs),
-        "gradient": _median_time(grad, runs),
+        "interp": _median_time(lambda: oracle.interp(rhoT, D), runs, tag=tag("interp")),
+        "backtrace": _median_time(lambda: oracle.backtrace(v, nt), runs, tag=tag("backtrace")),
+        "transport_forward": _median_time(lambda: oracle.transport_forward(P, v, rhoT), runs,
+                                          tag=tag("transport_forward")),
+        "transport_adjoint": _median_time(lambda: oracle.transport_adjoint(P, v, lam1), runs,
+                                          tag=tag("transport_adjoint")),
+        "gradient": _median_time(grad, runs, tag=tag("gradient")),
     }
-    out["matvec"] = _median_time(lambda: oracle.hessian_matvec(P, rhoT, v, g[0]), runs)
+    out["matvec"] = _median_time(lambda: oracle.hessian_matvec(P, rhoT, v, g[0]), runs, tag=tag("matvec"))
     return out
 
 
@@ -249,7 +256,7 @@ def run_oracle_plan(args):
     out = {"mode": "oracle", "host": host_cpu(), "threads": cores, "operators_s": {}}
     for m in (64, 128, 256):
         log(f"[bench] oracle operators at {m}^3")
-        out["operators_s"][f"{m}^3"] = oracle_operators(m)
+        out["operators_s"][f"{m}^3"] = oracle_operators(m, verbose=True)
         log(f"[bench]   {out['operators_s'][f'{m}^3']}")
     import synth
 
