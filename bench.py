@@ -273,6 +273,31 @@ def run_oracle_plan(args):
     print(json.dumps(out), flush=True)
 
 
+def warm_start_side(reg, torch, ctx):
+    """The benchmark solve started from the learned warm start (row a14; the
+    network was trained on blob pairs, so the phantom lies outside its
+    training distribution): proposal plus solve, timed together, not part of
+    `value`."""
+    import numpy as np
+
+    from paper_1608_03630_amd import warmstart
+
+    net = reg.Net(warmstart.NET_N)
+    net.reg_net_set_params(torch.from_numpy(np.load(warmstart.WEIGHTS)).cuda())
+    ctx.reg_set_solver(solve_params(reg, ctx.shape, METRIC_BETA_FINAL))
+    vw, fb, dmin = net.reg_warmstart(ctx)
+    _, mis0 = ctx.reg_objective(vw)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    vw, fb, dmin = net.reg_warmstart(ctx, vw)
+    _, r = ctx.reg_solve(vw)
+    torch.cuda.synchronize()
+    out = {"seconds": time.perf_counter() - ts, "proposal_mismatch": mis0, "fallback": fb, "proposal_det_min": dmin,
+           "final_mismatch": r["final_mismatch"], "gn_steps": r["n_iter"], "matvecs": r["matvecs"]}
+    net.close()
+    return out
+
+
 # config of the batched workload: (grid, count); every pair like the 128^3
 # blob workload (FP32 fields, nt = 8, isochoric, beta = 1e-3)
 BATCH_SIZES = [(64, 8), (128, 8), (192, 6), (256, 2)]
@@ -562,6 +587,10 @@ def main():
         f"mismatch {strict['final_mismatch']:.4f}")
     sched = side_run(SCHEDULE_BETA_FINAL, 0.0)
     log(f"[bench] schedule to beta 1e-4: {sched['seconds']:.3f} s, mismatch {sched['final_mismatch']:.4f}")
+    warm = warm_start_side(reg, torch, ctx)
+    log(f"[bench] from the learned warm start: {warm['seconds']:.3f} s (proposal mismatch "
+        f"{warm['proposal_mismatch']:.4f}, fallback {warm['fallback']}), {warm['matvecs']} matvecs, "
+        f"mismatch {warm['final_mismatch']:.4f}")
 
     # dominant transport kernel and its roofline (HIP events on the library's stream)
     kinds = {k: prof[k] for k in BYTES_PER_POINT if prof[k][0] > 0}
@@ -610,6 +639,7 @@ def main():
         "beta_reached": min(rep["beta"]) if rep["beta"] else None,
         "every_level_to_1e-2": strict,
         "schedule_to_1e-4": sched,
+        "from_warm_start": warm,
         "stop_reason": ["gradient tolerance", "mismatch", "step limit"][rep["stop_reason"]],
         "gn_steps": rep["n_iter"],
         "matvecs": rep["matvecs"],

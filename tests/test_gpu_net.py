@@ -84,12 +84,15 @@ def test_every_layer_forward_matches_oracle(reg, n):
         assert err <= 1e-2
 
 
-def test_whole_forward_matches_oracle(reg):
-    net, layers, T, R = _setup(reg, 21)
+@pytest.mark.parametrize("n", [16, 32, 64])
+def test_whole_forward_matches_oracle(reg, n):
+    """Up to 64^3, the grid the warm start runs the network on (the oracle's
+    direct sums take about half a minute there)."""
+    net, layers, T, R = _setup(reg, 21, n)
     v = net.reg_net_forward(_gpu(T), _gpu(R)).double().cpu().numpy()
     ref, _ = onet.forward(layers, np.stack([T, R]).astype(np.float64))
     err = rel_l2(v, ref)
-    say(f"  network output rel-L2 {err:.2e}")
+    say(f"  {n}^3 network output rel-L2 {err:.2e}")
     assert err <= 3e-2
 
 
