@@ -555,9 +555,10 @@ reg_status gradient_fields(reg_ctx *ctx, const void *u, int nf, void *out) {
 template <typename T>
 reg_status resample_fields(reg_ctx *src, reg_ctx *dst, int ncomp, const void *in, void *out) {
     hipStream_t st = src->stream;
+    // all of it on src's account: the work runs on src's stream
     alg_fft3d(src, ncomp, sizeof(T));
     src->alg_bytes += ncomp * 2.0 * ((double)src->Nh + (double)dst->Nh) * sizeof(T);
-    alg_fft3d(dst, ncomp, sizeof(T));
+    src->alg_bytes += ncomp * ((double)dst->N + 10.0 * (double)dst->Nh) * sizeof(T);
     HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_forward<T, T>(src->spec, CV<T>(in), ncomp, 0, st))));
     HIPCHK(src, KL(src, REG_K_SYMBOL, regk::spec_resample<T>(src->spec, dst->spec, ncomp, st)));
     HIPCHK(src, KL(src, REG_K_FFT3D, (regk::spec_inverse<T, T>(dst->spec, V<T>(out), ncomp, st))));
