@@ -329,27 +329,168 @@ __global__ __launch_bounds__(kThreads) void k_wgrad(WgradArgs a) {
     if (t == 13 && threadIdx.x < a.cout) a.bias_partials[(long)blockIdx.x * a.cout + threadIdx.x] = bsum;
 }
 
+// Weight gradients of stride-1 layers on 32^3 and finer grids, tiled like
+// k_conv_tiled. A workgroup owns one block of 16 input channels
+// (blockIdx.y), the nine taps of one x1 offset d1 = blockIdx.z - 1 and the
+// wgrad_chunk(P) / 256 consecutive 4x4x16 tiles of its chunk. Per tile it
+// stages the output-side gradient of all cout channels ([channel][point],
+// the point order of the K dimension) and the four x1 planes of the layer
+// input's 6x6x18 halo that its taps reach, for its 16 channels
+// ([channel][h1][h2][h3]), once, then forms the products of its taps from
+// LDS with v_mfma_f32_16x16x32_bf16 (K = the tile's 256 points, 32 at a
+// time); each wavefront keeps the accumulators of its taps (9 d1 + wave +
+// 4 u) across the chunk's tiles. Splitting the taps over three workgroups
+// triples the workgroups of a launch (a 64^3 layer has only 128 chunks). A tap's x3 offset makes its 8-point input fragment start
+// 0, 1 or 2 elements into an aligned 16-element window read as two 16-byte
+// LDS loads; the odd case is cut out with funnel shifts. The partials and
+// the bias partials have the layout of k_wgrad's.
+constexpr int kWTile = kCT1 * kCT2 * kCT3;  // 256 points
+constexpr int kWPitchZ = kWTile + 8;        // dz rows: 132 dwords, 4 mod 32 (conflict-free fragments)
+constexpr int kWRowX = 24;                  // halo x3 rows: 18 used of 24 (the 16-element windows)
+constexpr int kWPitchX = kCH1 * kCH2 * kWRowX + 8;  // per channel: 436 dwords, 4 mod 32
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int NCB>
+__global__ __launch_bounds__(kThreads) void k_wgrad_tiled(WgradArgs a) {
+    __shared__ __align__(16) uint16_t sdz[NCB * 16 * kWPitchZ];
+    __shared__ __align__(16) uint16_t sx[16 * kWPitchX];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int n = a.n_out;  // == a.n_in
+    const long P = (long)n * n * n;
+    const int nt3 = n / kCT3, nt2 = n / kCT2;
+    const int tpc = wgrad_chunk(P) / kWTile;  // tiles per chunk
+    const int cout = NCB * 16, ci0 = 16 * (int)blockIdx.y;
+    const int z = (int)blockIdx.z;  // d1 + 1
+    v4f acc[3][NCB];
+#pragma unroll
+    for (int u = 0; u < 3; u++)
+#pragma unroll
+        for (int b = 0; b < NCB; b++) acc[u][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    for (int ti = 0; ti < tpc; ti++) {
+        const int tile = (int)blockIdx.x * tpc + ti;
+        const int t3 = tile % nt3, t2 = (tile / nt3) % nt2, t1 = tile / (nt3 * nt2);
+        const int o1 = t1 * kCT1, o2 = t2 * kCT2, o3 = t3 * kCT3;
+        // output-side gradient: point pp = (4 a1 + a2) 16 + a3, 4 channels a load
+        for (int e = threadIdx.x; e < kWTile * NCB * 4; e += kThreads) {
+            const int pp = e / (NCB * 4), c = (e - pp * (NCB * 4)) * 4;
+            const int a1 = pp >> 6, a2 = (pp >> 4) & 3, a3 = pp & 15;
+            const long p = ((long)(o1 + a1) * n + o2 + a2) * n + o3 + a3;
+            const v4s v = *reinterpret_cast<const v4s *>(a.dz + p * a.dz_cs + c);
+#pragma unroll
+            for (int i = 0; i < 4; i++) sdz[(c + i) * kWPitchZ + pp] = (uint16_t)v[i];
+        }
+        // halo planes h1 = z .. z + 3 of channels [ci0, ci0 + 16), 8 channels a load
+        for (int e = threadIdx.x; e < kCT1 * kCH2 * kCH3 * 2; e += kThreads) {
+            const int hp = e >> 1, half = e & 1;
+            const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = z + hp / (kCH3 * kCH2);
+            const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
+            const long q = ((long)x1 * n + x2) * n + x3;
+            const v8s v = *reinterpret_cast<const v8s *>(a.x + q * a.x_cs + ci0 + 8 * half);
+            const int row = (h1 * kCH2 + h2) * kWRowX + h3;
+#pragma unroll
+            for (int i = 0; i < 8; i++) sx[(8 * half + i) * kWPitchX + row] = (uint16_t)v[i];
+        }
+        __syncthreads();
+        if (blockIdx.y == 0 && z == 0 && threadIdx.x < cout) {
+            const v8s *zr = reinterpret_cast<const v8s *>(sdz + threadIdx.x * kWPitchZ);
+            for (int k = 0; k < kWTile / 8; k++) {
+                const v8s z = zr[k];
+#pragma unroll
+                for (int i = 0; i < 8; i++) bsum += bf2f((uint16_t)z[i]);
+            }
+        }
+        // K chunk m: x3 rows pb = 2m + (g >> 1) of the tile, points 8 (g & 1) .. + 7
+#pragma unroll 1
+        for (int m = 0; m < kWTile / 32; m++) {
+            v8s av[NCB];
+#pragma unroll
+            for (int b = 0; b < NCB; b++)
+                av[b] = *reinterpret_cast<const v8s *>(sdz + (16 * b + r) * kWPitchZ + 32 * m + 8 * g);
+            const int pb = 2 * m + (g >> 1);
+            const int a1 = pb >> 2, a2 = pb & 3;
+#pragma unroll
+            for (int u = 0; u < 3; u++) {
+                const int tl = wave + 4 * u;  // tap within the d1 plane
+                if (tl >= 9) continue;
+                const int d1 = z - 1, d2 = tl / 3 - 1, sh = tl % 3;  // sh = 1 + d3
+                const v4i *w = reinterpret_cast<const v4i *>(
+                    sx + r * kWPitchX + ((a1 + 1 + d1) * kCH2 + a2 + 1 + d2) * kWRowX + 8 * (g & 1));
+                const v4i w0 = w[0], w1 = w[1];
+                v4i bx;
+                if (sh == 0) {
+                    bx = w0;
+                } else if (sh == 2) {
+                    bx = v4i{w0[1], w0[2], w0[3], w1[0]};
+                } else {
+                    bx = v4i{(int)__builtin_amdgcn_alignbit(w0[1], w0[0], 16),
+                             (int)__builtin_amdgcn_alignbit(w0[2], w0[1], 16),
+                             (int)__builtin_amdgcn_alignbit(w0[3], w0[2], 16),
+                             (int)__builtin_amdgcn_alignbit(w1[0], w0[3], 16)};
+                }
+#pragma unroll
+                for (int b = 0; b < NCB; b++)
+                    acc[u][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, av[b]),
+                                                                        __builtin_bit_cast(v8bf, bx), acc[u][b], 0, 0,
+                                                                        0);
+            }
+        }
+        __syncthreads();  // both buffers are restaged for the next tile
+    }
+    // partials[chunk][t][co][ci]: lane holds D[4 g + i][r] = (co 16 b + 4 g + i, ci ci0 + r)
+#pragma unroll
+    for (int u = 0; u < 3; u++) {
+        const int tl = wave + 4 * u;
+        if (tl >= 9) continue;
+        const int t = 9 * z + tl;
+        float *out = a.partials + ((long)blockIdx.x * 27 + t) * a.cout * a.cin;
+#pragma unroll
+        for (int b = 0; b < NCB; b++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) out[(16 * b + 4 * g + i) * a.cin + ci0 + r] = acc[u][b][i];
+    }
+    if (blockIdx.y == 0 && z == 0 && threadIdx.x < cout)
+        a.bias_partials[(long)blockIdx.x * a.cout + threadIdx.x] = bsum;
+}
+
 // dW[co][ci][t] += scale * sum over chunks and db[co] += scale * sum over
-// chunks (fixed order); real channels only. Threads run over (t, co, ci)
-// with ci fastest, so that the partial reads are coalesced.
+// chunks; real channels only. A workgroup sums 16 consecutive outputs
+// (e = (t, co, ci), ci fastest, then the biases) over all chunks: thread
+// (slice, j) adds chunks slice, slice + 16, ... of output j, and the 16
+// slice sums are added in a fixed order, so the result is deterministic.
+constexpr int kRedW = 16, kRedS = kThreads / kRedW;  // outputs x chunk slices per workgroup
+
 __global__ __launch_bounds__(kThreads) void k_wgrad_reduce(const float *__restrict__ partials,
                                                            const float *__restrict__ bias_partials, int chunks,
                                                            int cout, int cin, int cout_real, int cin_real, float scale,
                                                            float *__restrict__ dW, float *__restrict__ db) {
-    const int e = blockIdx.x * kThreads + threadIdx.x;
+    __shared__ float red[kRedS][kRedW + 1];
+    const int j = threadIdx.x % kRedW, sl = threadIdx.x / kRedW;
+    const int e = blockIdx.x * kRedW + j;
     const int nw = cout_real * cin_real * 27;
+    float s = 0.f;
     if (e < nw) {
         const int ci = e % cin_real, co = (e / cin_real) % cout_real, t = e / (cin_real * cout_real);
         const long stride = 27L * cout * cin;
         const float *p = partials + ((long)t * cout + co) * cin + ci;
-        float s = 0.f;
-        for (int c = 0; c < chunks; c++) s += p[c * stride];
-        dW[((long)co * cin_real + ci) * 27 + t] += scale * s;
+        for (int c = sl; c < chunks; c += kRedS) s += p[c * stride];
     } else if (e < nw + cout_real) {
         const int co = e - nw;
-        float s = 0.f;
-        for (int c = 0; c < chunks; c++) s += bias_partials[(long)c * cout + co];
-        db[co] += scale * s;
+        for (int c = sl; c < chunks; c += kRedS) s += bias_partials[(long)c * cout + co];
+    }
+    red[sl][j] = s;
+    __syncthreads();
+    if (sl == 0 && e < nw + cout_real) {
+        float tot = 0.f;
+        for (int k = 0; k < kRedS; k++) tot += red[k][j];
+        if (e < nw) {
+            const int ci = e % cin_real, co = (e / cin_real) % cout_real, t = e / (cin_real * cout_real);
+            dW[((long)co * cin_real + ci) * 27 + t] += scale * tot;
+        } else {
+            db[e - nw] += scale * tot;
+        }
     }
 }
 
@@ -552,6 +693,16 @@ hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {
     const long P = (long)a.n_out * a.n_out * a.n_out;
     if (P % kSlice || a.cin % 16 || a.cout % 16 || a.cin > 64 || a.cout > 64 || a.x_cs % 4 || a.dz_cs % 4)
         return hipErrorInvalidValue;
+    // stride-1 layers on 32^3 and finer grids: the tiled kernel (whole
+    // 4x4x16 tiles, whole chunks of them, 16-byte input loads)
+    if (mode == CONV_FWD1 && a.n_in == a.n_out && a.n_out >= 32 && a.n_out % kCT3 == 0 && a.x_cs % 8 == 0 &&
+        wgrad_chunk(P) % kWTile == 0 && (a.cout == 16 || a.cout == 32 || a.cout == 64)) {
+        const dim3 gt(wgrad_chunks(a.n_out), a.cin / 16, 3);
+        if (a.cout == 16) hipLaunchKernelGGL(k_wgrad_tiled<1>, gt, dim3(kThreads), 0, s, a);
+        else if (a.cout == 32) hipLaunchKernelGGL(k_wgrad_tiled<2>, gt, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL(k_wgrad_tiled<4>, gt, dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
     const dim3 grid(wgrad_chunks(a.n_out), 27);
     if (mode == CONV_FWD1) hipLaunchKernelGGL(k_wgrad<CONV_FWD1>, grid, dim3(kThreads), 0, s, a);
     else if (mode == CONV_FWD2) hipLaunchKernelGGL(k_wgrad<CONV_FWD2>, grid, dim3(kThreads), 0, s, a);
@@ -562,7 +713,8 @@ hipError_t launch_wgrad(int mode, const WgradArgs &a, hipStream_t s) {
 hipError_t launch_wgrad_reduce(const float *partials, const float *bias_partials, int chunks, int cout, int cin,
                                int cout_real, int cin_real, float scale, float *dW, float *db, hipStream_t s) {
     const long n = (long)cout_real * cin_real * 27 + cout_real;
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(blocks(n)), dim3(kThreads), 0, s, partials, bias_partials, chunks, cout,
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((unsigned)((n + kRedW - 1) / kRedW)), dim3(kThreads), 0, s, partials,
+                       bias_partials, chunks, cout,
                        cin, cout_real, cin_real, scale, dW, db);
     return hipGetLastError();
 }
