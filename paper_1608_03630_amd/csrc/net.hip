@@ -576,12 +576,20 @@ __global__ __launch_bounds__(kThreads) void k_mse(const float *__restrict__ v, c
     if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
 }
 
-__global__ void k_sum(const double *__restrict__ partials, int n, double scale, double *__restrict__ out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; i++) s += partials[i];
-        *out += scale * s;
+// *out += scale * sum(partials), one workgroup: strided per-thread sums,
+// then a tree in LDS (a fixed order)
+__global__ __launch_bounds__(kThreads) void k_sum(const double *__restrict__ partials, int n, double scale,
+                                                  double *__restrict__ out) {
+    __shared__ double sm[kThreads];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kThreads) s += partials[i];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *out += scale * sm[0];
 }
 
 // Adam with bias-corrected moments, FP32
@@ -748,7 +756,7 @@ int mse_blocks(long P) { return (int)blocks(P); }
 hipError_t launch_mse(const float *v, const float *tgt, long P, double *partials, double *loss_acc, double scale,
                       uint16_t *dz, hipStream_t s) {
     hipLaunchKernelGGL(k_mse, dim3(blocks(P)), dim3(kThreads), 0, s, v, tgt, P, partials, dz);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, partials, (int)blocks(P), scale, loss_acc);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(kThreads), 0, s, partials, (int)blocks(P), scale, loss_acc);
     return hipGetLastError();
 }
 
