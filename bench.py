@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per grid point and launch of each transport kernel family
-# in single precision (what the method must move)
+# in single precision (what the method must move: each operand once)
 BYTES_PER_POINT = {
     "interp": 20.0,     # D (3 x 4) + gathered field 4 + out 4
     "backtrace": 24.0,  # v (3 x 4) + D out (3 x 4)
@@ -493,8 +493,8 @@ def main():
                          "oracle: the host-side timing plan of the FP64 oracle (minutes; no GPU)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is a design "
-              "in DESIGN.md and is not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the slab decomposition over several GPUs "
+              "is a design, not built", file=sys.stderr)
         sys.exit(2)
 
     if args.mode == "oracle":
