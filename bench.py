@@ -53,12 +53,13 @@ PROFILE_EVERY = 13  # the timed solve brackets one launch in 13 of each family w
 
 GRID_LEVELS = 1  # grids of the continuation (1: the benchmark grid only)
 MAX_PCG = 100  # PCG iterations per Newton step at most
+RECOMPUTE_GRAD_RHO = 0  # 1: keep one level of grad rho^n and recompute it where needed
 
 
 def solve_params(reg, shape, beta_final, gtol_level=LEVEL_GTOL, grid_levels=None):
     return reg.reg_default_params(shape, nt=16, prec=0, beta=1e-1, beta_final=beta_final, beta_factor=0.1,
                                   gtol=1e-2, mismatch_tol=1e-2, max_newton=50, max_pcg=MAX_PCG, max_ls=20,
-                                  gtol_level=gtol_level,
+                                  gtol_level=gtol_level, recompute_grad_rho=RECOMPUTE_GRAD_RHO,
                                   grid_levels=GRID_LEVELS if grid_levels is None else grid_levels)
 
 
@@ -471,7 +472,7 @@ def run_net(reg, torch, args):
 
 
 def main():
-    global GRID_LEVELS, MAX_PCG
+    global GRID_LEVELS, MAX_PCG, RECOMPUTE_GRAD_RHO
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -482,6 +483,8 @@ def main():
                     help="grids of the continuation for the timed solve (default: GRID_LEVELS)")
     ap.add_argument("--max-pcg", type=int, default=None,
                     help="PCG iterations per Newton step at most (default: MAX_PCG)")
+    ap.add_argument("--recompute-grad-rho", action="store_true",
+                    help="keep one level of grad rho^n and recompute it where needed (smaller workspace)")
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
@@ -509,6 +512,8 @@ def main():
         GRID_LEVELS = args.grid_levels
     if args.max_pcg is not None:
         MAX_PCG = args.max_pcg
+    if args.recompute_grad_rho:
+        RECOMPUTE_GRAD_RHO = 1
     reg.lib()
     torch.cuda.set_device(0)
     if args.mode == "copy":
@@ -633,6 +638,7 @@ def main():
             "grid": [args.n] * 3,
             "nt": 16,
             "max_pcg": MAX_PCG,
+            "recompute_grad_rho": RECOMPUTE_GRAD_RHO,
             "grid_levels": GRID_LEVELS,
         },
         "final_mismatch": rep["final_mismatch"],

@@ -100,7 +100,11 @@ typedef struct {
                             * switch a Gauss-Newton context to it. Single contexts only. */
     int32_t det_check;     /* 1: reg_solve computes det grad y1 of the result (eq. (1)) into the
                             * report and returns REG_ENONDIFFEO if its minimum is <= 0 */
-    int32_t reserved_;     /* zero */
+    int32_t recompute_grad_rho; /* 0: keep grad rho^n of every time level (3 (nt+1) fields of the
+                            * workspace); 1: keep one level and recompute grad rho^n by line FFTs
+                            * wherever it is needed (section III-C1): the workspace shrinks by
+                            * 3 nt fields, each transport step costs one more gradient. Fixes the
+                            * workspace: reg_set_solver cannot turn it off. Not with hessian = 1. */
 } reg_params;
 
 #define REG_MAXIT 512

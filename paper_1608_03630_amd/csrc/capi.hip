@@ -196,6 +196,9 @@ reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p) {
     for (reg_ctx *c = ctx->coarse; c; c = c->coarse) chain++;
     if (p->hessian && !ctx->lamg)
         return fail(ctx, REG_EINVAL, "full Newton (hessian = 1) needs a context created with hessian = 1");
+    if (!p->recompute_grad_rho && ctx->grho_levels == 1)
+        return fail(ctx, REG_EINVAL, "a context created with recompute_grad_rho = 1 has no room for grad rho of "
+                                     "every level");
     if (grid_count(p) > chain)
         return fail(ctx, REG_EINVAL, "grid_levels = " + std::to_string(p->grid_levels) + " exceeds the " +
                                          std::to_string(chain) + " grid(s) the workspace was laid out for");

@@ -140,6 +140,7 @@ struct reg_ctx {
 
     // workspace views
     void *rhoT, *rhoR, *histA, *histB, *grho, *Df, *Da, *Dt, *c, *cX, *c2, *cX2, *lam[2], *bvec;
+    long grho_levels = 0;  // levels of grad rho^n the workspace holds: nt + 1, or 1 (recomputed)
     void *lamh;        // adjoint levels lam^0..lam^nt
     void *lamg;        // full Newton: the adjoint levels of the last gradient (null otherwise)
     void *gam, *gam2;  // Heun factor of the adjoint source (cached plan, scratch plan)
@@ -285,6 +286,14 @@ inline reg_status check_params(const reg_params *p, std::string *why) {
         *why = "hessian must be 0 (Gauss-Newton) or 1 (full Newton)";
         return REG_EINVAL;
     }
+    if (p->recompute_grad_rho != 0 && p->recompute_grad_rho != 1) {
+        *why = "recompute_grad_rho must be 0 or 1";
+        return REG_EINVAL;
+    }
+    if (p->recompute_grad_rho && p->hessian) {
+        *why = "the full Newton Hessian (hessian = 1) needs grad rho of every level (recompute_grad_rho = 0)";
+        return REG_EINVAL;
+    }
     if (p->grid_levels < 0 || p->grid_levels > REG_MAXLEVELS) {
         *why = "grid_levels must be in [0, " + std::to_string(REG_MAXLEVELS) + "]";
         return REG_EINVAL;
@@ -323,7 +332,8 @@ inline size_t layout(const reg_params *p, char *base, reg_ctx *ctx) {
     c->rhoR = L.take(E * N);
     c->histA = L.take(E * N * nt1);
     c->histB = L.take(E * N * nt1);
-    c->grho = L.take(E * 3 * N * nt1);
+    c->grho_levels = p->recompute_grad_rho ? 1 : nt1;
+    c->grho = L.take(E * 3 * N * c->grho_levels);
     c->Df = L.take(E * 3 * N);
     c->Da = L.take(E * 3 * N);
     c->Dt = L.take(E * 3 * N);

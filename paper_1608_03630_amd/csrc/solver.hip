@@ -285,6 +285,28 @@ reg_status batched_launch(reg_batch *b, const Launch &L, const regk::PairStep *h
 // * b~ = sum_n w_n (lam~^n grad rho^n + lam^n grad rho~^n), then the
 //   assembly of the Gauss-Newton matvec.
 // Scratch: du (lam vt and grad rho~^n) and u0 (two source levels and s~(X)).
+// b = sum_n w_n lam^n grad rho^n (trapezoid weights, eqs. (4), (5e)) from the
+// kept levels of grad rho in one pass, or, with recompute_grad_rho, level by
+// level: grad rho^n of the state history into the one kept level, then
+// b += w_n lam^n grad rho^n (the same products and order of additions).
+template <typename T>
+reg_status b_sum(reg_ctx *ctx, const T *lam, T *b) {
+    const long N = ctx->N;
+    const int nt = ctx->P.nt;
+    if (!ctx->P.recompute_grad_rho) {
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, lam, CV<T>(ctx->grho), b, ctx->stream)));
+        return REG_OK;
+    }
+    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_fill<T>(3 * N, 0.0, b, ctx->stream)));
+    for (int n = 0; n <= nt; n++) {
+        const double w = (n == 0 || n == nt) ? 0.5 / nt : 1.0 / nt;
+        STCHK(gradient_fields<T>(ctx, CV<T>(ctx->histA) + (long)n * N, 1, ctx->grho));
+        HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_axpy<T>(N, w, lam + (long)n * N, CV<T>(ctx->grho), b,
+                                                                 ctx->stream)));
+    }
+    return REG_OK;
+}
+
 template <typename T>
 reg_status newton_matvec(reg_ctx *ctx, const Request &r) {
     const long N = ctx->N;
@@ -509,6 +531,7 @@ struct Exec {
                     (void)N;
                     if (r.pre) STCHK(field_from_krylov<T>(ctx, r.x, ctx->vtf));
                     else STCHK(spec_to_field<T>(ctx, r.x, ctx->vtf));
+                    if (ctx->P.recompute_grad_rho) STCHK(gradient_fields<T>(ctx, ctx->histA, 1, ctx->grho));
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_incstate_init<T>(ctx->g, CV<T>(ctx->vtf), V<T>(ctx->grho),
                                                                                     V<T>(ctx->lam[1]), -0.5 * dt, ctx->stream)));
                     return REG_OK;
@@ -541,13 +564,21 @@ struct Exec {
                     StepArg<T> a{ctx, CV<T>(ctx->lam[cur]), CV<T>(ctx->Df),
                                  last ? V<T>(ctx->lamh) + (long)nt * N : V<T>(ctx->lam[1 - cur])};
                     a.vt = CV<T>(ctx->vtf);
-                    a.grad = CV<T>(ctx->grho) + (long)(k + 1) * 3 * N;
+                    a.grad = CV<T>(ctx->grho) + (ctx->P.recompute_grad_rho ? 0 : (long)(k + 1) * 3 * N);
                     a.cs = last ? -0.5 * dt : -dt;
                     a.last = last;
                     inc.push_back(a);
                 }
             }
             sl_step(P, regk::STEP_INTERP, fw, dev_region);
+            // grad rho^{k+1} of the contexts that recompute it, just before the step reads it
+            for (const auto &a : inc) {
+                reg_ctx *ctx = a.ctx;
+                if (!ctx->P.recompute_grad_rho) continue;
+                P.ops.push_back([ctx, k]() -> reg_status {
+                    return gradient_fields<T>(ctx, CV<T>(ctx->histA) + (long)(k + 1) * ctx->N, 1, ctx->grho);
+                });
+            }
             sl_step(P, regk::STEP_INCSTATE, inc, dev_region);
         }
         // gradient: grad rho^n, div v and its Heun factor, adjoint final value
@@ -556,7 +587,8 @@ struct Exec {
             if (it.req.op != Op::GRADIENT) continue;
             reg_ctx *ctx = it.ctx;
             P.ops.push_back([ctx]() -> reg_status {
-                STCHK(gradient_fields<T>(ctx, ctx->histA, ctx->P.nt + 1, ctx->grho));
+                // (recomputed level by level in the b sum otherwise)
+                if (!ctx->P.recompute_grad_rho) STCHK(gradient_fields<T>(ctx, ctx->histA, ctx->P.nt + 1, ctx->grho));
                 if (!ctx->P.isochoric) STCHK(divergence<T>(ctx, ctx->vf, ctx->c));
                 return REG_OK;
             });
@@ -601,9 +633,7 @@ struct Exec {
             P.ops.push_back([ctx, r]() -> reg_status {
                 const long N = ctx->N;
                 const int nt = ctx->P.nt;
-                if (r.op == Op::GRADIENT || r.op == Op::MATVEC)
-                    HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_b_assemble<T>(N, nt, CV<T>(ctx->lamh), CV<T>(ctx->grho),
-                                                                                 V<T>(ctx->bvec), ctx->stream)));
+                if (r.op == Op::GRADIENT || r.op == Op::MATVEC) STCHK(b_sum<T>(ctx, CV<T>(ctx->lamh), V<T>(ctx->bvec)));
                 // the full Newton matvecs at this velocity need its adjoint history
                 if (r.op == Op::GRADIENT && ctx->P.hessian)
                     HIPCHK(ctx, KL(ctx, REG_K_VECTOR, regk::launch_copy<T>((long)(nt + 1) * N, CV<T>(ctx->lamh),
@@ -634,7 +664,10 @@ struct Exec {
     void count(const Item &it) {
         reg_ctx *ctx = it.ctx;
         const int nt = ctx->P.nt;
-        const double adj = ctx->P.isochoric ? 5 : 6, bsum = 4.0 * (nt + 1) + 3;
+        const double adj = ctx->P.isochoric ? 5 : 6;
+        // b sum: one pass over the kept levels, or (recomputed grad rho) a
+        // zero fill and an update of b per level
+        const double bsum = ctx->P.recompute_grad_rho ? 3 + 10.0 * (nt + 1) : 4.0 * (nt + 1) + 3;
         switch (it.req.op) {
         case Op::GRADIENT:
             ctx->interps += (it.req.reuse ? 0 : nt) + (ctx->P.isochoric ? 0 : 1) + nt;

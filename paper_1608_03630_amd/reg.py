@@ -56,7 +56,7 @@ class reg_params(ctypes.Structure):
         ("grid_levels", ctypes.c_int32),
         ("hessian", ctypes.c_int32),
         ("det_check", ctypes.c_int32),
-        ("reserved_", ctypes.c_int32),
+        ("recompute_grad_rho", ctypes.c_int32),
     ]
 
 

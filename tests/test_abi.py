@@ -76,7 +76,8 @@ def test_workspace_size_scales_with_grid(lib):
 @pytest.mark.parametrize("bad", [dict(n=(14, 32, 32)), dict(n=(32, 32, 22)), dict(n=(32, 32, 6)),
                                  dict(n=(32, 15, 32)), dict(n=(2048, 8, 8)), dict(nt=0), dict(beta=0.0),
                                  dict(beta=-1.0), dict(prec=2), dict(max_pcg=0), dict(gtol=-1.0), dict(hessian=2),
-                                 dict(det_check=2), dict(grid_levels=5), dict(n=(24, 24, 24), grid_levels=3)])
+                                 dict(det_check=2), dict(grid_levels=5), dict(n=(24, 24, 24), grid_levels=3),
+                                 dict(recompute_grad_rho=2), dict(recompute_grad_rho=1, hessian=1)])
 def test_bad_parameters_are_rejected(lib, bad):
     from paper_1608_03630_amd import reg
 
@@ -85,6 +86,15 @@ def test_bad_parameters_are_rejected(lib, bad):
     with pytest.raises(reg.RegError) as e:
         reg.reg_workspace_size(p)
     assert e.value.status == reg.REG_EINVAL
+
+
+def test_recomputed_grad_rho_shrinks_the_workspace(lib):
+    from paper_1608_03630_amd import reg
+
+    for prec, esz in ((0, 4), (1, 8)):
+        kept = reg.reg_workspace_size(reg.reg_default_params((64, 64, 64), nt=16, prec=prec))
+        rec = reg.reg_workspace_size(reg.reg_default_params((64, 64, 64), nt=16, prec=prec, recompute_grad_rho=1))
+        assert kept - rec == 3 * 16 * 64 ** 3 * esz
 
 
 def test_create_rejects_null_workspace(lib):
