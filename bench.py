@@ -246,6 +246,68 @@ def cpu_baseline(counts, n):
     }
 
 
+CONFIG2 = dict(shape=(128, 128, 128), nt=8, beta=1e-3, seed=1002, max_newton=20)
+
+
+def oracle_blob128_solve():
+    """Wall time of the oracle's solve of the 128^3 isochoric blob problem
+    (seed 1002, nt = 8, beta = 1e-3, gtol 1e-2, FP64), rho_R from its own
+    transport of the true velocity."""
+    import oracle
+    import synth
+
+    c = CONFIG2
+    case = synth.blob_case(c["shape"], seed=c["seed"])
+    P = oracle.params(c["shape"], c["nt"], c["beta"], isochoric=True, max_newton=c["max_newton"])
+    rhoR = oracle.transport_forward(P, case["v_true"], case["rhoT"])
+    t = time.perf_counter()
+    _, rep = oracle.solve(P, case["rhoT"], rhoR)
+    return {"seconds": time.perf_counter() - t, "gn_steps": rep["n_iter"], "matvecs": rep["matvecs"],
+            "final_mismatch": rep["final_mismatch"]}
+
+
+def run_config2(reg, torch):
+    """The 128^3 isochoric blob problem (seed 1002, nt = 8, beta = 1e-3)
+    solved from v = 0 on the GPU with FP64 fields and with FP32 fields (FP64
+    reductions and velocity in both), after one untimed solve each: time,
+    Newton steps, matvecs, final mismatch, and the FP32-vs-FP64 differences
+    of v and rho_1. rho_R is the library's own FP64 transport of the true
+    velocity (input preparation)."""
+    import numpy as np
+
+    import synth
+
+    c = CONFIG2
+    case = synth.blob_case(c["shape"], seed=c["seed"])
+    out = {"mode": "config2", "workload": "128^3 isochoric blob pair (seed 1002, 20 blobs, |k|<=4 divergence-free "
+           "velocity of max speed 0.5), nt=8, beta=1e-3, gtol 1e-2", "runs": {}}
+    res, rhoR64 = {}, None
+    for prec in (1, 0):
+        dt = torch.float64 if prec else torch.float32
+        ctx = reg.Context(reg.reg_default_params(c["shape"], nt=c["nt"], prec=prec, beta=c["beta"], isochoric=1,
+                                                 max_newton=c["max_newton"]))
+        rhoT = torch.from_numpy(case["rhoT"]).to("cuda", dt)
+        if rhoR64 is None:
+            rhoR64 = ctx.reg_transport_forward(torch.from_numpy(case["v_true"]).cuda(), rhoT).clone()
+        ctx.reg_set_images(rhoT, rhoR64.to(dt))
+        ctx.reg_solve()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        v, rep = ctx.reg_solve()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t
+        rho1 = ctx.reg_transport_forward(v, rhoT).double().cpu().numpy()
+        res[prec] = (v.cpu().numpy(), rho1)
+        out["runs"]["f64" if prec else "f32"] = {"seconds": sec, "gn_steps": rep["n_iter"], "matvecs": rep["matvecs"],
+                                                 "pcg_iters": rep["pcg_iters"], "final_mismatch": rep["final_mismatch"]}
+        log(f"[bench] config 2, {'FP64' if prec else 'FP32'} fields: {sec:.3f} s, {rep['n_iter']} GN steps, "
+            f"{rep['matvecs']} matvecs, mismatch {rep['final_mismatch']:.6f}")
+        ctx.close()
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    out["fp32_vs_fp64"] = {"v_rel_l2": rel(res[0][0], res[1][0]), "rho1_rel_l2": rel(res[0][1], res[1][1])}
+    print(json.dumps(out), flush=True)
+
+
 def run_oracle_plan(args):
     """The full host-side timing plan of the oracle: operator medians at 64^3,
     128^3 and 256^3 (5 runs after 1 warm-up), a one-thread interpolation, the
@@ -271,6 +333,9 @@ def run_oracle_plan(args):
     finally:
         oracle.set_threads(cores)
     out["solve_smooth32"] = oracle_smooth32_solve()
+    log("[bench] oracle solve of the 128^3 blob problem")
+    os.environ["ORACLE_PROGRESS"] = "1"  # one line per Newton step and per ten PCG iterations
+    out["solve_blob128"] = oracle_blob128_solve()
     print(json.dumps(out), flush=True)
 
 
@@ -488,12 +553,14 @@ def main():
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
-    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net", "oracle"], default="solve",
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net", "oracle", "config2"],
+                    default="solve",
                     help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
                          "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
                          "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch; net: "
                          "forward pass and training step of the 64^3 warm-start network against the BF16 MFMA peak; "
-                         "oracle: the host-side timing plan of the FP64 oracle (minutes; no GPU)")
+                         "oracle: the host-side timing plan of the FP64 oracle (minutes; no GPU); config2: the "
+                         "128^3 isochoric blob problem solved with FP32 and with FP64 fields")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the slab decomposition over several GPUs "
@@ -529,6 +596,9 @@ def main():
         return
     if args.mode == "net":
         run_net(reg, torch, args)
+        return
+    if args.mode == "config2":
+        run_config2(reg, torch)
         return
     if args.mode == "kernels":
         ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)

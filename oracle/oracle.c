@@ -29,6 +29,7 @@
 #include <complex.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -899,6 +900,7 @@ typedef struct {
 static double norm3(const int *n, const double *x) { return sqrt(inner(n, 3, x, x)); }
 
 int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR, double *v, oracle_report *rep) {
+    const int progress = getenv("ORACLE_PROGRESS") != NULL;
     if (check_params(P)) return 1;
     memset(rep, 0, sizeof(*rep));
     const int *n = P->n;
@@ -955,6 +957,7 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
                 else hessian_from_state(&st, beta, pp, q);
                 rep->matvecs++;
                 iters = i + 1;
+                if (progress && iters % 10 == 0) fprintf(stderr, "[oracle]   pcg iteration %d\n", iters);
                 double kappa = inner(n, 3, pp, q);
                 if (kappa <= 0) {
                     rep->negative_curvature++;
@@ -1025,6 +1028,11 @@ int oracle_solve(const oracle_params *P, const double *rhoT, const double *rhoR,
                 rep->pcg_iters[it] = iters;
                 rep->ls_trials[it] = trials;
             }
+            /* a line per accepted step on stderr when ORACLE_PROGRESS is set,
+             * so that long runs show that they advance (no arithmetic here) */
+            if (progress)
+                fprintf(stderr, "[oracle] step %d: beta %.1e, J %.6e, mismatch %.6f, |g|/|g0| %.3e, pcg %d\n", it,
+                        beta, J, mis, g0 > 0 ? gnorm / g0 : 0.0, iters);
             it++;
             rep->stop_reason = 2;
         }
