@@ -370,6 +370,46 @@ BATCH_SIZES = [(64, 8), (128, 8), (192, 6), (256, 2)]
 BATCH_NT = 8
 
 
+def small_pair_batch(reg, torch, count=32, n=64, seed0=4100):
+    """Side measurement: `count` pairs of n^3 (config-4 style, seeds seed0+i)
+    as one batch against one after another on the same contexts, after one
+    untimed batched solve (launch tuning). Small grids leave most of the GPU
+    idle one at a time; that is where the batch pays."""
+    import numpy as np
+
+    import synth
+
+    params = [reg.reg_default_params((n, n, n), nt=BATCH_NT, prec=0, beta=1e-3, isochoric=1, gtol=1e-2,
+                                     max_newton=50, max_pcg=100, max_ls=20) for _ in range(count)]
+    b = reg.Batch(params)
+    vt_true, rhoT = [], []
+    for i in range(count):
+        case = synth.blob_case((n, n, n), seed=seed0 + i)
+        rhoT.append(torch.from_numpy(case["rhoT"].astype(np.float32)).cuda())
+        vt_true.append(torch.from_numpy(case["v_true"]).cuda())
+    rhoR = b.reg_batch_transport_forward(vt_true, rhoT)
+    for i in range(count):
+        b.reg_set_images(i, rhoT[i], rhoR[i])
+    vs = [torch.zeros((3, n, n, n), dtype=torch.float64, device="cuda") for _ in range(count)]
+    b.reg_batch_solve(vs)
+    for v in vs:
+        v.zero_()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    b.reg_batch_solve(vs)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    t = time.perf_counter()
+    for i, c in enumerate(b.contexts):
+        vs[i].zero_()
+        c.reg_solve(vs[i])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t
+    log(f"[bench] {count} pairs of {n}^3: batch {tb:.3f} s, one after another {ts:.3f} s ({ts / tb:.2f}x)")
+    b.close()
+    return {"pairs": count, "n": n, "batch_seconds": tb, "sequential_seconds": ts, "batch_speedup": ts / tb}
+
+
 def run_batch(reg, torch, args):
     """24 independent pairs of mixed sizes solved together: one persistent
     launch per transport step and LDS box class, autotuned launch shapes, graph-replayed
@@ -452,6 +492,7 @@ def run_batch(reg, torch, args):
     b.reg_batch_profile(False)
     pts = sum(s[0] * s[1] * s[2] for s in shapes)
     n_int, ms_int = p2["interp"]
+    small = small_pair_batch(reg, torch)
     out = {
         "metric": "batched registration throughput (24 mixed-size pairs, one persistent launch per transport step and box class)",
         "value": len(shapes) / sec,
@@ -474,6 +515,7 @@ def run_batch(reg, torch, args):
         },
         "per_size": per_size,
         "sequential": {"seconds": seq_sec, "pairs_per_s": len(shapes) / seq_sec},
+        "small_pairs": small,
         "batch_speedup": seq_sec / sec,
         "graph": {"captures": st1["graph_captures"] - st0["graph_captures"],
                   "replays": st1["graph_replays"] - st0["graph_replays"],
