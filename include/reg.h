@@ -448,6 +448,19 @@ reg_status reg_net_activation(reg_net *net, int32_t layer, float *out);
 reg_status reg_net_loss_grad(reg_net *net, const float *rho_T, const float *rho_R, const float *target, float *grad,
                              double *loss);
 
+/* Backward pass of the last reg_net_forward for any loss L: dv = dL/dv
+ * (device floats [3][n^3], the layout of reg_net_forward's v) in, grad =
+ * dL/dparams (param_count device floats) out; the same kernels as
+ * reg_net_loss_grad after its MSE head. REG_EINVAL without a preceding
+ * reg_net_forward (set_params, loss_grad, train_step and warm starts reset
+ * it). Synchronises. */
+reg_status reg_net_backward(reg_net *net, const float *dv, float *grad);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) of the
+ * parameters with the given gradient (param_count device floats, e.g. from
+ * reg_net_backward), then the BF16 weight copies refreshed. Synchronises. */
+reg_status reg_net_step(reg_net *net, const float *grad, double lr);
+
 /* One Adam step on the mean loss over `batch` samples (host arrays of device
  * pointers to float n^3 images and [3][n^3] targets); returns the mean loss
  * before the step. Synchronises. */

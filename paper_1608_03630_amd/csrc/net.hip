@@ -548,6 +548,17 @@ __global__ __launch_bounds__(kThreads) void k_pack_input(const float *__restrict
     x[e] = c == 0 ? f2bf(a[p]) : c == 1 ? f2bf(b[p]) : (uint16_t)0;
 }
 
+// the head's pre-activation gradient dz[p][16] = scale dv[c][p] for an
+// arbitrary loss (channels >= 3 zero)
+__global__ __launch_bounds__(kThreads) void k_pack_head_grad(const float *__restrict__ dv, long P, float scale,
+                                                             uint16_t *__restrict__ dz) {
+    const long e = (long)blockIdx.x * kThreads + threadIdx.x;
+    if (e >= P * 16) return;
+    const int c = (int)(e & 15);
+    const long p = e >> 4;
+    dz[e] = c < 3 ? f2bf(scale * dv[c * P + p]) : (uint16_t)0;
+}
+
 // MSE: per-block partial sums of (v - t)^2 (double) and the head's
 // pre-activation gradient dz[p][16] = 2 (v - t) / numel (channels >= 3 zero)
 __global__ __launch_bounds__(kThreads) void k_mse(const float *__restrict__ v, const float *__restrict__ tgt, long P,
@@ -752,6 +763,11 @@ hipError_t launch_pack_input(const float *a, const float *b, long P, uint16_t *x
 }
 
 int mse_blocks(long P) { return (int)blocks(P); }
+
+hipError_t launch_pack_head_grad(const float *dv, long P, float scale, uint16_t *dz, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_head_grad, dim3(blocks(P * 16)), dim3(kThreads), 0, s, dv, P, scale, dz);
+    return hipGetLastError();
+}
 
 hipError_t launch_mse(const float *v, const float *tgt, long P, double *partials, double *loss_acc, double scale,
                       uint16_t *dz, hipStream_t s) {

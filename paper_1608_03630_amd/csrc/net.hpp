@@ -57,6 +57,7 @@ hipError_t launch_mask(const uint16_t *src, int src_cs, long P, int C, const uin
                        hipStream_t s);
 hipError_t launch_pack_input(const float *a, const float *b, long P, uint16_t *x, hipStream_t s);
 int mse_blocks(long P);
+hipError_t launch_pack_head_grad(const float *dv, long P, float scale, uint16_t *dz, hipStream_t s);
 hipError_t launch_mse(const float *v, const float *tgt, long P, double *partials, double *loss_acc, double scale,
                       uint16_t *dz, hipStream_t s);
 hipError_t launch_adam(long n, float *w, const float *g, float *m, float *v, float lr, float b1, float b2, float eps,

@@ -63,6 +63,7 @@ struct reg_net {
     double *hloss = nullptr;  // pinned
     int step = 0;
     bool weights_packed = false;
+    bool have_forward = false;  // activations of a reg_net_forward are in place
     // warm start: a single-precision context on the network grid (spectral
     // resampling) and the network's input / output fields there
     reg_ctx *rctx = nullptr;
@@ -261,12 +262,11 @@ reg_status wgrad(reg_net *net, int l, const uint16_t *x, int x_cs, const uint16_
 
 // loss and parameter gradients of one sample, accumulated (grads, loss) with
 // weight `scale`
-reg_status backward(reg_net *net, const float *target, float scale) {
+// the backward pass from the head's pre-activation gradient in dz11 (the
+// gradient of one sample's loss); the batch weight `scale` enters the weight
+// and bias reductions
+reg_status backward_from_head(reg_net *net, float scale) {
     const long P1 = net->P1, P2 = net->P2;
-    NHIP(net, regn::launch_mse(net->v, target, P1, net->mse_part, net->loss, scale / (3.0 * P1), net->dz11,
-                               net->stream));
-    // dz11 is the gradient of this sample's loss; the batch weight `scale`
-    // enters the weight and bias reductions
     STCHK(wgrad(net, 11, net->m1, 16, net->dz11, scale));
     STCHK(conv_bwd(net, 11, net->dz11, net->dz10, 16, net->m1, 16));
     STCHK(wgrad(net, 10, net->cat1, 32, net->dz10, scale));
@@ -297,6 +297,13 @@ reg_status backward(reg_net *net, const float *target, float scale) {
     STCHK(conv_bwd(net, 1, net->dz1, net->dz0, 16, net->e1a, 16));
     STCHK(wgrad(net, 0, net->x0, 16, net->dz0, scale));
     return REG_OK;
+}
+
+// the MSE loss of the last forward pass against `target` and its backward pass
+reg_status backward(reg_net *net, const float *target, float scale) {
+    NHIP(net, regn::launch_mse(net->v, target, net->P1, net->mse_part, net->loss, scale / (3.0 * net->P1), net->dz11,
+                               net->stream));
+    return backward_from_head(net, scale);
 }
 
 #define NET_OK(net)                                   \
@@ -390,6 +397,7 @@ const char *reg_net_last_error(const reg_net *net) { return net ? net->err.c_str
 reg_status reg_net_set_params(reg_net *net, const float *params) {
     NET_OK(net);
     NET_DEV(net, params);
+    net->have_forward = false;
     NHIP(net, hipMemcpyAsync(net->params, params, sizeof(float) * net->count, hipMemcpyDeviceToDevice, net->stream));
     NHIP(net, regn::launch_fill_f32(net->count, 0.f, net->adam_m, net->stream));
     NHIP(net, regn::launch_fill_f32(net->count, 0.f, net->adam_v, net->stream));
@@ -409,8 +417,10 @@ reg_status reg_net_forward(reg_net *net, const float *rhoT, const float *rhoR, f
     NET_DEV(net, rhoT);
     NET_DEV(net, rhoR);
     NET_DEV(net, v);
+    net->have_forward = false;
     STCHK(forward(net, rhoT, rhoR));
     NHIP(net, hipMemcpyAsync(v, net->v, sizeof(float) * 3 * net->P1, hipMemcpyDeviceToDevice, net->stream));
+    net->have_forward = true;
     return REG_OK;
 }
 
@@ -439,6 +449,7 @@ reg_status reg_net_loss_grad(reg_net *net, const float *rhoT, const float *rhoR,
     NET_DEV(net, target);
     NET_DEV(net, grad);
     if (!loss) return nfail(net, REG_EINVAL, "loss is NULL");
+    net->have_forward = false;
     NHIP(net, regn::launch_fill_f32(net->count, 0.f, net->grads, net->stream));
     NHIP(net, regk::launch_fill<double>(1, 0.0, net->loss, net->stream));
     STCHK(forward(net, rhoT, rhoR));
@@ -450,9 +461,37 @@ reg_status reg_net_loss_grad(reg_net *net, const float *rhoT, const float *rhoR,
     return REG_OK;
 }
 
+reg_status reg_net_backward(reg_net *net, const float *dv, float *grad) {
+    NET_OK(net);
+    NET_DEV(net, dv);
+    NET_DEV(net, grad);
+    if (!net->have_forward) return nfail(net, REG_EINVAL, "reg_net_backward needs a reg_net_forward before it");
+    NHIP(net, regn::launch_fill_f32(net->count, 0.f, net->grads, net->stream));
+    NHIP(net, regn::launch_pack_head_grad(dv, net->P1, 1.f, net->dz11, net->stream));
+    STCHK(backward_from_head(net, 1.f));
+    NHIP(net, hipMemcpyAsync(grad, net->grads, sizeof(float) * net->count, hipMemcpyDeviceToDevice, net->stream));
+    NHIP(net, hipStreamSynchronize(net->stream));
+    return REG_OK;
+}
+
+reg_status reg_net_step(reg_net *net, const float *grad, double lr) {
+    NET_OK(net);
+    NET_DEV(net, grad);
+    if (!(lr > 0) || !std::isfinite(lr)) return nfail(net, REG_EINVAL, "lr must be positive");
+    NHIP(net, hipMemcpyAsync(net->grads, grad, sizeof(float) * net->count, hipMemcpyDeviceToDevice, net->stream));
+    net->step++;
+    NHIP(net, regn::launch_adam(net->count, net->params, net->grads, net->adam_m, net->adam_v, (float)lr, 0.9f, 0.999f,
+                                1e-8f, net->step, net->stream));
+    STCHK(pack_weights(net));
+    net->have_forward = false;
+    NHIP(net, hipStreamSynchronize(net->stream));
+    return REG_OK;
+}
+
 reg_status reg_net_train_step(reg_net *net, int32_t batch, const float *const *rhoT, const float *const *rhoR,
                               const float *const *target, double lr, double *loss) {
     NET_OK(net);
+    net->have_forward = false;
     if (batch < 1 || !rhoT || !rhoR || !target || !loss) return nfail(net, REG_EINVAL, "bad batch arguments");
     if (!(lr > 0) || !std::isfinite(lr)) return nfail(net, REG_EINVAL, "lr must be positive");
     for (int b = 0; b < batch; b++) {
@@ -481,6 +520,7 @@ reg_status reg_net_train_step(reg_net *net, int32_t batch, const float *const *r
 reg_status reg_warmstart(reg_ctx *ctx, reg_net *net, void *v_out, int32_t *used_fallback, double *detmin) {
     CTX_OK(ctx);
     if (!net) return fail(ctx, REG_EINVAL, "net is NULL");
+    net->have_forward = false;
     NEED_DEV(ctx, v_out);
     if (!used_fallback) return fail(ctx, REG_EINVAL, "used_fallback is NULL");
     if (ctx->P.prec != 0) return fail(ctx, REG_EINVAL, "the warm start needs a single-precision context");

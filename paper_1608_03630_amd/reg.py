@@ -178,6 +178,8 @@ _SIGS = {
     "reg_net_forward": [_P, _P, _P, _P],
     "reg_net_activation": [_P, ctypes.c_int32, _P],
     "reg_net_loss_grad": [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "reg_net_backward": [_P, _P, _P],
+    "reg_net_step": [_P, _P, ctypes.c_double],
     "reg_net_train_step": [_P, ctypes.c_int32, ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P),
                            ctypes.c_double, ctypes.POINTER(ctypes.c_double)],
     "reg_warmstart": [_P, _P, _P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
@@ -690,6 +692,17 @@ class Net:
                                       self._f(target, 3 * self.P, "target"), self._f(g, self.count, "grad"),
                                       ctypes.byref(loss)), self.handle, "reg_net_loss_grad")
         return loss.value, g
+
+    def reg_net_backward(self, dv):
+        """dL/dparams for dL/dv = dv after reg_net_forward."""
+        g = torch.empty(self.count, dtype=torch.float32, device=self.device)
+        _nchk(lib().reg_net_backward(self.handle, self._f(dv, 3 * self.P, "dv"), self._f(g, self.count, "grad")),
+              self.handle, "reg_net_backward")
+        return g
+
+    def reg_net_step(self, grad, lr=1e-3):
+        _nchk(lib().reg_net_step(self.handle, self._f(grad, self.count, "grad"), float(lr)), self.handle,
+              "reg_net_step")
 
     def reg_net_train_step(self, rhoTs, rhoRs, targets, lr=1e-3):
         n = len(rhoTs)

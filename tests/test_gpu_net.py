@@ -114,6 +114,37 @@ def test_loss_and_parameter_gradients_match_oracle(reg, n):
         assert ew <= 5e-2 and eb <= 5e-2
 
 
+def test_backward_and_step_compose_the_training_step(reg):
+    """reg_net_backward with dv = d(MSE)/dv after reg_net_forward gives the
+    gradient of reg_net_loss_grad (the same BF16 head gradient, the same
+    kernels), and reg_net_step with it moves the parameters exactly as
+    reg_net_train_step on that one sample; backward without a forward is
+    refused."""
+    n = N
+    net, layers, T, R = _setup(reg, 41, n)
+    target = synth.smooth_random_field((n, n, n), 44, kmax=3, ncomp=3).astype(np.float32) * 0.1
+    with pytest.raises(reg.RegError):
+        net.reg_net_backward(torch.zeros(3 * n ** 3, device="cuda"))
+    _, g_ref = net.reg_net_loss_grad(_gpu(T), _gpu(R), _gpu(target))
+    v = net.reg_net_forward(_gpu(T), _gpu(R))
+    dv = (2.0 / (3 * n ** 3)) * (v - _gpu(target))
+    g = net.reg_net_backward(dv)
+    torch.cuda.synchronize()
+    err = rel_l2(g.double().cpu().numpy(), g_ref.double().cpu().numpy())
+    say(f"  backward against loss_grad: rel-L2 {err:.1e}")
+    assert err <= 1e-6
+    p0 = net.reg_net_get_params().clone()
+    net.reg_net_train_step([_gpu(T)], [_gpu(R)], [_gpu(target)], lr=1e-3)
+    p_train = net.reg_net_get_params().clone()
+    net.reg_net_set_params(p0)
+    _, g1 = net.reg_net_loss_grad(_gpu(T), _gpu(R), _gpu(target))
+    net.reg_net_step(g1, lr=1e-3)
+    p_step = net.reg_net_get_params()
+    torch.cuda.synchronize()
+    assert torch.equal(p_train, p_step)
+    assert not torch.equal(p_step, p0)
+
+
 def test_first_adam_step_is_the_closed_form(reg):
     net, layers, T, R = _setup(reg, 41)
     target = np.zeros((3, N, N, N), np.float32)
