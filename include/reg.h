@@ -168,6 +168,17 @@ const char *reg_last_error(const reg_ctx *ctx);
 /* Changes beta (> 0) used by reg_gradient, reg_hessian_matvec, reg_precond. */
 reg_status reg_set_beta(reg_ctx *ctx, double beta);
 
+/* Progress log of reg_solve (and of this context's problem in
+ * reg_batch_solve): after every accepted Newton step fn(json, user) receives
+ * one line of JSON, {"n": [n0, n1, n2], "step": k, "beta": .., "J": ..,
+ * "mismatch": .., "grel": ||g||/ref, "alpha": .., "pcg": .., "ls": ..,
+ * "matvecs": .., "seconds": ..}, the string valid during the call only. With
+ * grid continuation the coarser grids log too ("n" tells them apart). fn
+ * runs on the calling host thread between GPU work and must not call the
+ * library with this context. fn = NULL turns the log off. */
+typedef void (*reg_log_fn)(const char *json, void *user);
+reg_status reg_set_log(reg_ctx *ctx, reg_log_fn fn, void *user);
+
 /* Replaces the solver settings of the context (beta and its continuation,
  * isochoric, tolerances, iteration limits, forcing, Armijo constant,
  * gnorm_ref); n, nt and prec must equal those given to reg_create.

@@ -185,6 +185,15 @@ reg_status reg_set_beta(reg_ctx *ctx, double beta) {
     return REG_OK;
 }
 
+reg_status reg_set_log(reg_ctx *ctx, reg_log_fn fn, void *user) {
+    CTX_OK(ctx);
+    for (reg_ctx *c = ctx; c; c = c->coarse) {
+        c->log_fn = fn;
+        c->log_user = user;
+    }
+    return REG_OK;
+}
+
 reg_status reg_set_solver(reg_ctx *ctx, const reg_params *p) {
     CTX_OK(ctx);
     std::string why;

@@ -174,6 +174,8 @@ struct reg_ctx {
     long interps = 0;
     int64_t fft3d = 0, fft_lines = 0;  // 3D transforms and line-FFT derivatives (one component/field each)
     double alg_bytes = 0;              // algorithmic HBM bytes of the kernels launched (see alg_fields)
+    reg_log_fn log_fn = nullptr;       // progress log of the solves (reg_set_log)
+    void *log_user = nullptr;
     int64_t epoch = 0;  // bumped whenever a plan (departure points, tile geometry) changes
     std::string err;
 };

@@ -20,6 +20,7 @@
 // arguments are those of the single-problem path, so a problem's result does
 // not depend on the batch it runs in.
 #include <algorithm>
+#include <cstdio>
 #include <functional>
 #include <map>
 #include <memory>
@@ -1084,6 +1085,16 @@ struct Solver {
                     rep->beta[it] = beta;
                     rep->pcg_iters[it] = iters;
                     rep->ls_trials[it] = trials;
+                }
+                if (ctx->log_fn) {
+                    char line[512];
+                    std::snprintf(line, sizeof(line),
+                                  "{\"n\": [%d, %d, %d], \"step\": %d, \"beta\": %.6e, \"J\": %.17g, "
+                                  "\"mismatch\": %.17g, \"grel\": %.17g, \"alpha\": %.17g, \"pcg\": %d, \"ls\": %d, "
+                                  "\"matvecs\": %d, \"seconds\": %.6f}",
+                                  ctx->P.n[0], ctx->P.n[1], ctx->P.n[2], it, beta, J, mis, g0 > 0 ? gnorm / g0 : 0.0,
+                                  alpha, iters, trials, rep->matvecs, secs(t0));
+                    ctx->log_fn(line, ctx->log_user);
                 }
                 it++;
                 rep->stop_reason = 2;

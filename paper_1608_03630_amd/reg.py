@@ -10,6 +10,7 @@ The library must be built (``__graft_entry__.build()`` or
 raises if ``libreg.so`` is missing. There is no fallback path.
 """
 import ctypes
+import json
 import os
 
 import torch
@@ -121,7 +122,11 @@ class reg_report(ctypes.Structure):
 
 _lib = None
 _P = ctypes.c_void_p
+# reg_log_fn: void (*)(const char *json, void *user)
+LOG_FN = ctypes.CFUNCTYPE(None, ctypes.c_char_p, ctypes.c_void_p)
+
 _SIGS = {
+    "reg_set_log": [_P, LOG_FN, _P],
     "reg_default_params": [ctypes.POINTER(reg_params)],
     "reg_workspace_size": [ctypes.POINTER(reg_params), ctypes.POINTER(ctypes.c_size_t)],
     "reg_create": [ctypes.POINTER(reg_params), _P, ctypes.c_size_t, _P, ctypes.POINTER(_P)],
@@ -315,6 +320,15 @@ class Context:
     # ------------------------------------------------------ entry points
     def reg_set_beta(self, beta):
         _chk(lib().reg_set_beta(self.handle, float(beta)), self.handle, "reg_set_beta")
+
+    def reg_set_log(self, fn=None):
+        """fn(dict) after every accepted Newton step of reg_solve (None: off)."""
+        if fn is None:
+            self._log_cb = None
+            _chk(lib().reg_set_log(self.handle, LOG_FN(), None), self.handle, "reg_set_log")
+            return
+        self._log_cb = LOG_FN(lambda line, user: fn(json.loads(line.decode())))
+        _chk(lib().reg_set_log(self.handle, self._log_cb, None), self.handle, "reg_set_log")
 
     def reg_set_solver(self, params):
         _chk(lib().reg_set_solver(self.handle, ctypes.byref(params)), self.handle, "reg_set_solver")

@@ -97,6 +97,12 @@ def test_recomputed_grad_rho_shrinks_the_workspace(lib):
         assert kept - rec == 3 * 16 * 64 ** 3 * esz
 
 
+def test_log_needs_a_context(lib):
+    from paper_1608_03630_amd import reg
+
+    assert lib.reg_set_log(None, reg.LOG_FN(), None) == reg.REG_EINVAL
+
+
 def test_create_rejects_null_workspace(lib):
     from paper_1608_03630_amd import reg
 

@@ -54,8 +54,13 @@ def test_grid_continuation_fp64_matches_oracle(reg, levels, kw, vtol):
     v_ref, rep_ref = oracle.solve_grid(P, rhoT, rhoR, levels)
     ctx = reg.Context(reg.reg_default_params(shape, nt=nt, prec=1, grid_levels=levels, **kw))
     ctx.reg_set_images(to_dev(rhoT, ctx), to_dev(rhoR, ctx))
+    log = []
+    ctx.reg_set_log(log.append)
     v, rep = ctx.reg_solve()
     assert rep["status"] == 0 and len(rep["levels"]) == levels
+    # every grid logs its accepted steps, coarsest first
+    assert [sum(1 for e in log if e["n"] == list(l["n"])) for l in rep["levels"]] == \
+        [l["n_iter"] for l in rep["levels"]]
     assert _levels_match(rep, rep_ref)
     assert rep["pcg_iters"] == rep_ref["pcg_iters"] and rep["beta"] == rep_ref["beta"]
     assert rel_l2(to_host(v), v_ref) <= vtol

@@ -349,8 +349,15 @@ def test_smooth_case_solve_fp64_matches_oracle(reg):
     v_ref, rep_ref = oracle.solve(P, case["rhoT"], rhoR)
     ctx = make_ctx(reg, shape, 1, nt=nt, max_newton=5)
     ctx.reg_set_images(to_dev(case["rhoT"], ctx), to_dev(rhoR, ctx))
+    log = []
+    ctx.reg_set_log(log.append)
     v, rep = ctx.reg_solve()
+    ctx.reg_set_log(None)
     say(f"  gpu pcg={rep['pcg_iters']} oracle pcg={rep_ref['pcg_iters']} mis={rep['final_mismatch']:.6f}")
+    # the progress log: one line per accepted step, the report's values
+    assert [e["step"] for e in log] == list(range(rep["n_iter"]))
+    assert [e["J"] for e in log] == rep["J"] and [e["pcg"] for e in log] == rep["pcg_iters"]
+    assert all(e["n"] == list(shape) for e in log) and log[-1]["matvecs"] == rep["matvecs"]
     assert rep["pcg_iters"] == rep_ref["pcg_iters"]
     assert rep["n_iter"] == rep_ref["n_iter"] and rep["stop_reason"] == rep_ref["stop_reason"]
     assert rel_l2(to_host(v), v_ref) <= 1e-9
