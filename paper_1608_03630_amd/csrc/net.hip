@@ -186,14 +186,26 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
         for (int b = 0; b < NB; b++) acc[m][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const int ccin = a.cin >> 4;
     for (int c = 0; c < ccin; c++) {
-        // halo of channels [16c, 16c + 16): two 16-byte pieces per point
-        for (int e = threadIdx.x; e < kCHalo * 2; e += kThreads) {
-            const int hp = e >> 1, half = e & 1;
-            const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = hp / (kCH3 * kCH2);
-            const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
-            const long q = ((long)x1 * n + x2) * n + x3;
-            *reinterpret_cast<v8s *>(halo + hp * 16 + 8 * half) =
-                *reinterpret_cast<const v8s *>(a.in + q * a.in_cs + 16 * c + 8 * half);
+        // halo of channels [16c, 16c + 16): two 16-byte pieces per point,
+        // all of a thread's pieces requested before the first LDS store (the
+        // kernel waits on these loads, not on the matrix cores)
+        constexpr int kPieces = (kCHalo * 2 + kThreads - 1) / kThreads;
+        v8s piece[kPieces];
+#pragma unroll
+        for (int u = 0; u < kPieces; u++) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < kCHalo * 2) {
+                const int hp = e >> 1, half = e & 1;
+                const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = hp / (kCH3 * kCH2);
+                const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
+                const long q = ((long)x1 * n + x2) * n + x3;
+                piece[u] = *reinterpret_cast<const v8s *>(a.in + q * a.in_cs + 16 * c + 8 * half);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPieces; u++) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < kCHalo * 2) *reinterpret_cast<v8s *>(halo + (e >> 1) * 16 + 8 * (e & 1)) = piece[u];
         }
         __syncthreads();
         // nine (d1, d2) rows of taps, the three d3 taps of a row unrolled
