@@ -147,6 +147,20 @@ def counters_summary(pdir, out_md, n=256, passes=("sq1", "sq2")):
         cells = [f"{vals[c]:.3g}" if c in vals else "-" for c in cols]
         lines.append(f"| {what} `{sub}` | {us:.1f} | {gbs:.0f} | {vpp:.0f} | {lpp:.0f} | " + " | ".join(cells) + " |")
     lines += ["", "VALU/pt and LDS/pt are lane instructions per grid point (wave instructions x 64 / n^3).", ""]
+    # the three limits of each kernel against its time
+    lines += ["Limits per launch (MI355X: 256 CUs at 2.4 GHz; one wave64 VALU instruction per clock per CU with "
+              "packed FP32 off; LDS index unit busy for SQ_LDS_IDX_ACTIVE cycles summed over the CUs; HBM at "
+              "8 TB/s for the algorithmic bytes):", "",
+              "| kernel | us | VALU floor us | LDS busy us | HBM floor us | time / largest |", "|---|---|---|---|---|---|"]
+    cu_hz = 256 * 2.4e9
+    for sub, what, bpp, vals, avg_ns, cnt in rows:
+        us = avg_ns / 1e3 if avg_ns else float("nan")
+        valu = vals.get("SQ_INSTS_VALU", float("nan")) / cu_hz * 1e6
+        lds = vals.get("SQ_LDS_IDX_ACTIVE", float("nan")) / cu_hz * 1e6
+        hbm = bpp * N / 8e12 * 1e6
+        top = max(x for x in (valu, lds, hbm) if x == x)
+        lines.append(f"| {what} | {us:.1f} | {valu:.1f} | {lds:.1f} | {hbm:.1f} | {us / top:.2f} |")
+    lines.append("")
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
 
