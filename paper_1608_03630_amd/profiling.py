@@ -14,7 +14,7 @@ size). The record carries a hash of the kernel sources so that a benchmark can
 tell when the counters no longer describe the kernel it runs.
 
     python -m paper_1608_03630_amd.profiling DIR OUT.md TRAFFIC.json KERNEL_SUBSTRING GRID_SIZE FAMILY N
-    python -m paper_1608_03630_amd.profiling counters DIR OUT.md   # SQ counter passes (SQ_PASSES)
+    python -m paper_1608_03630_amd.profiling counters DIR OUT.md   # SQ counter passes (SQ_PASSES), L2 pass
 """
 import collections
 import csv
@@ -106,6 +106,7 @@ SQ_PASSES = [
     ["SQ_WAVE_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
      "SQ_ACTIVE_INST_ANY", "SQ_LDS_IDX_ACTIVE"],
 ]
+L2_PASS = ["TCC_HIT_sum", "TCC_MISS_sum", "TCC_REQ_sum"]
 GATHER_KERNELS = [("k_tiled_canon<float, 0, 1>", "state step (interp)", 20.0),
                   ("k_tiled_canon<float, 1, 1>", "adjoint step", 24.0),
                   ("k_tiled_canon<float, 2, 1>", "incremental-state step", 44.0),
@@ -161,6 +162,20 @@ def counters_summary(pdir, out_md, n=256, passes=("sq1", "sq2")):
         top = max(x for x in (valu, lds, hbm) if x == x)
         lines.append(f"| {what} | {us:.1f} | {valu:.1f} | {lds:.1f} | {hbm:.1f} | {us / top:.2f} |")
     lines.append("")
+    l2 = os.path.join(pdir, "l2", "run_counter_collection.csv")
+    if os.path.exists(l2):
+        lines += ["L2 (TCC) requests and hit rate per dispatch, from a pass of its own:", "", "```",
+                  f"rocprofv3 --pmc {' '.join(L2_PASS)} --output-format csv -d DIR/l2 -o run -- python3 bench.py "
+                  "--mode kernels", "```", "",
+                  "| kernel | L2 requests | requests/pt | hit rate |", "|---|---|---|---|"]
+        for sub, what, bpp, _, _, _ in rows:
+            v, _ = counter_per_dispatch(l2, sub)
+            hit, miss, req = v.get("TCC_HIT_sum"), v.get("TCC_MISS_sum"), v.get("TCC_REQ_sum")
+            if hit is None or miss is None or req is None:
+                continue
+            rate = hit / (hit + miss) if hit + miss > 0 else float("nan")
+            lines.append(f"| {what} | {req:.3g} | {req / N:.2f} | {rate:.3f} |")
+        lines.append("")
     with open(out_md, "w") as f:
         f.write("\n".join(lines))
 
