@@ -260,8 +260,6 @@ reg_status wgrad(reg_net *net, int l, const uint16_t *x, int x_cs, const uint16_
     return REG_OK;
 }
 
-// loss and parameter gradients of one sample, accumulated (grads, loss) with
-// weight `scale`
 // the backward pass from the head's pre-activation gradient in dz11 (the
 // gradient of one sample's loss); the batch weight `scale` enters the weight
 // and bias reductions
@@ -299,7 +297,9 @@ reg_status backward_from_head(reg_net *net, float scale) {
     return REG_OK;
 }
 
-// the MSE loss of the last forward pass against `target` and its backward pass
+// the MSE loss of the last forward pass against `target` and its backward
+// pass: loss and parameter gradients of one sample, accumulated into loss and
+// grads with weight `scale`
 reg_status backward(reg_net *net, const float *target, float scale) {
     NHIP(net, regn::launch_mse(net->v, target, net->P1, net->mse_part, net->loss, scale / (3.0 * net->P1), net->dz11,
                                net->stream));
