@@ -413,7 +413,7 @@ reg_status reg_batch_solve(reg_batch *b, void *const *v_inout, reg_report *repor
 
 /* A small network proposes the initial velocity of a solve (not part of the
  * paper, whose solver starts from v = 0 or the previous continuation level;
- * the solver stays the judge). It is a 3-level 3D convolutional
+ * the solver decides whether to use it). It is a 3-level 3D convolutional
  * encoder-decoder on an n^3 grid (n = 64 in use): twelve 3x3x3 convolutions
  * with circular padding (channels 2->16->16, stride-2 16->32, 32->32,
  * stride-2 32->64, 64->64, 64->64, nearest upsampling, 64->32, concat with

@@ -3,7 +3,7 @@
 // concatenation) that maps the template and reference images on a 64^3 grid
 // to an initial velocity. Not part of the paper's method: its Gauss-Newton
 // solve starts from v = 0 (or the previous continuation level); this network
-// only proposes the starting point and the solver stays the judge.
+// only proposes the starting point; the solver decides whether to use it.
 //
 // Convolutions are implicit GEMMs on the matrix cores: for 16 output points
 // (M) x 16 output channels (N), the K dimension runs over (tap, input

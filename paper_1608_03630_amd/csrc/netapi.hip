@@ -544,7 +544,7 @@ reg_status reg_warmstart(reg_ctx *ctx, reg_net *net, void *v_out, int32_t *used_
         HIPCHK(ctx, KL(ctx, REG_K_SYMBOL, regk::spec_symbol<double>(ctx->spec, regk::SYM_LERAY, 0.0, 3, 1, ctx->stream)));
         HIPCHK(ctx, KL(ctx, REG_K_FFT3D, (regk::spec_inverse<double, double>(ctx->spec, V<double>(v_out), 3, ctx->stream))));
     }
-    // the solver stays the judge: accept the proposal only if its map is a
+    // the solver decides: accept the proposal only if its map is a
     // diffeomorphism on the grid (det grad y1 > 0 everywhere)
     double dmin = 0, dmax = 0;
     STCHK(reg_deformation(ctx, v_out, nullptr, &dmin, &dmax));
