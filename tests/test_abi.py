@@ -147,3 +147,22 @@ def test_product_package_does_not_reach_the_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text and "liboracle" not in text, f
+
+
+def test_binding_fails_loudly_without_the_library():
+    """With libreg.so absent the binding raises on first use; there is no
+    fallback path (run in a fresh interpreter so the loaded library of this
+    process is not involved)."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1608_03630_amd import reg\n"
+        "reg.LIB_PATH = '/nonexistent/libreg.so'\n"
+        "try:\n"
+        "    reg.reg_default_params((32, 32, 32))\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % ROOT)
+    r = subprocess.run(["python3", "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "missing" in r.stdout
