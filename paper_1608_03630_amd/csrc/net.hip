@@ -158,19 +158,37 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
 // Stride-1 convolutions (forward and backward data) as an LDS-tiled implicit
 // GEMM. A workgroup owns a 4 x 4 x 16 tile of output points. For each chunk
 // of 16 input channels it stages the tile's 6 x 6 x 18 halo in LDS
-// ([halo point][16 channels], 20.7 KB) and runs all 27 taps from there: each
-// of its four wavefronts takes four x3 rows of 16 points (one MFMA row block
-// each) and NB output channel blocks starting at blockIdx.y * NB, reading per
-// tap 4 activation fragments from LDS and NB weight fragments from the cache
-// for 4 NB MFMAs.
+// ([halo point][16 channels], 20.7 KB) together with the chunk's weights of
+// all 27 taps and its NB output channel blocks (13.8 KB per block), and runs
+// all 27 taps from there: each of its
+// four wavefronts takes four x3 rows of 16 points (one MFMA row block each)
+// and NB output channel blocks starting at blockIdx.y * NB, reading per tap 4
+// activation and NB weight fragments from LDS for 4 NB MFMAs.
 constexpr int kCT1 = 4, kCT2 = 4, kCT3 = 16;                      // output tile
 constexpr int kCH1 = kCT1 + 2, kCH2 = kCT2 + 2, kCH3 = kCT3 + 2;  // its halo
 constexpr int kCHalo = kCH1 * kCH2 * kCH3;                        // 648 points
+
+// Halo points are 32 bytes (16 channels), so the 16 points of one MFMA row
+// block (consecutive h3) would put the same 8-byte channel group of every
+// fourth point in the same LDS banks. The four 8-byte groups of a point are
+// therefore stored rotated by an XOR with (h3 / 4) mod 4: any four points of
+// a row block that share banks then read four different positions. The swizzle
+// depends on h3 only, so reads of the same h3 in other (h1, h2) rows keep one
+// base address.
+__device__ __forceinline__ int halo_group(int h3, int grp) { return grp ^ ((h3 >> 2) & 3); }
+// The staged weights take 16-byte slots (the direct loads move whole pieces),
+// so only the two halves of an output's 16 inputs can trade places: rows
+// 8..15 store them swapped.
+__device__ __forceinline__ int w_swap(int r) { return (r >> 3) & 1; }
 
 template <int MODE, int NB>
 __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
     static_assert(MODE == CONV_FWD1 || MODE == CONV_BWD1, "stride-1 modes only");
     __shared__ __align__(16) uint16_t halo[kCHalo * 16];
+    // weights of the chunk as [tap][block][output][16 inputs], padded to whole
+    // rounds of 256 16-byte pieces
+    constexpr int kWPieces = 27 * NB * 16 * 2, kWRounds = (kWPieces + kThreads - 1) / kThreads;
+    __shared__ __align__(16) uint16_t wl[kWRounds * kThreads * 8];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4, r = lane & 15;
     const int n = a.n_out;  // == a.n_in
@@ -190,6 +208,25 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
         // all of a thread's pieces requested before the first LDS store (the
         // kernel waits on these loads, not on the matrix cores)
         constexpr int kPieces = (kCHalo * 2 + kThreads - 1) / kThreads;
+        // weights: 16-byte piece e = ((t NB + b) 16 + r) 2 + sh holds eight
+        // inputs of output channel (cb0 + b) 16 + r of tap t, loaded straight
+        // into LDS (piece e at byte 16 e: a wavefront's 64 pieces land
+        // contiguously from its wave-uniform base). Slot sh holds input half
+        // sh ^ w_swap(r), which keeps the B fragments' 8-byte reads of rows r
+        // and r + 8 in different banks.
+#pragma unroll
+        for (int u = 0; u < kWRounds; u++) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < kWPieces) {
+                const int sh = e & 1, row = e >> 1;  // row = (t * NB + b) * 16 + r
+                const int r16 = row & 15, tb = row >> 4, b = tb % NB, t = tb / NB;
+                const uint16_t *src = a.w + ((long)t * a.cout + (cb0 + b) * 16 + r16) * a.cin + 16 * c +
+                                      8 * (sh ^ w_swap(r16));
+                uint16_t *dst = wl + 8 * (u * kThreads + 64 * wave);
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                                 (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
+            }
+        }
         v8s piece[kPieces];
 #pragma unroll
         for (int u = 0; u < kPieces; u++) {
@@ -205,8 +242,15 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
 #pragma unroll
         for (int u = 0; u < kPieces; u++) {
             const int e = threadIdx.x + u * kThreads;
-            if (e < kCHalo * 2) *reinterpret_cast<v8s *>(halo + (e >> 1) * 16 + 8 * (e & 1)) = piece[u];
+            if (e < kCHalo * 2) {
+                // groups 2 half and 2 half + 1 of point hp land in the 16-byte
+                // slot half ^ (s / 2), in swapped order when s is odd
+                const int hp = e >> 1, half = e & 1, sw = halo_group(hp % kCH3, 0);
+                const v8s v = (sw & 1) ? __builtin_shufflevector(piece[u], piece[u], 4, 5, 6, 7, 0, 1, 2, 3) : piece[u];
+                *reinterpret_cast<v8s *>(halo + hp * 16 + 8 * (half ^ (sw >> 1))) = v;
+            }
         }
+        __builtin_amdgcn_s_waitcnt(0);  // the direct weight loads have landed in LDS
         __syncthreads();
         // nine (d1, d2) rows of taps, the three d3 taps of a row unrolled
 #pragma unroll 1
@@ -218,13 +262,13 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
             v4s bv[NB];
 #pragma unroll
             for (int b = 0; b < NB; b++)
-                bv[b] = *reinterpret_cast<const v4s *>(a.w + ((long)t * a.cout + (cb0 + b) * 16 + r) * a.cin + 16 * c +
-                                                       4 * g);
+                bv[b] = *reinterpret_cast<const v4s *>(wl + ((t * NB + b) * 16 + r) * 16 + 4 * (g ^ (w_swap(r) << 1)));
 #pragma unroll
             for (int m = 0; m < 4; m++) {
                 const int pb = 4 * wave + m;  // x3 row (a1, a2) = (pb / 4, pb % 4)
                 const int h1 = pb / kCT2 + 1 + sg * d1, h2 = pb % kCT2 + 1 + sg * d2, h3 = r + 1 + sg * d3;
-                const v4s av = *reinterpret_cast<const v4s *>(halo + ((h1 * kCH2 + h2) * kCH3 + h3) * 16 + 4 * g);
+                const v4s av =
+                    *reinterpret_cast<const v4s *>(halo + ((h1 * kCH2 + h2) * kCH3 + h3) * 16 + 4 * halo_group(h3, g));
 #pragma unroll
                 for (int b = 0; b < NB; b++)
                     acc[m][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[b], acc[m][b], 0, 0, 0);
