@@ -429,25 +429,39 @@ __global__ __launch_bounds__(kThreads) void k_wgrad_tiled(WgradArgs a) {
         const int tile = (int)blockIdx.x * tpc + ti;
         const int t3 = tile % nt3, t2 = (tile / nt3) % nt2, t1 = tile / (nt3 * nt2);
         const int o1 = t1 * kCT1, o2 = t2 * kCT2, o3 = t3 * kCT3;
-        // output-side gradient: point pp = (4 a1 + a2) 16 + a3, 4 channels a load
-        for (int e = threadIdx.x; e < kWTile * NCB * 4; e += kThreads) {
-            const int pp = e / (NCB * 4), c = (e - pp * (NCB * 4)) * 4;
+        // output-side gradient: points pp, pp + 1 (pp = (4 a1 + a2) 16 + a3,
+        // a3 even) of 4 channels a thread, transposed two points per 32-bit
+        // LDS store
+        // (the channel group is the slow index: a wavefront's stores then
+        // fill consecutive dwords of one channel row)
+        for (int e = threadIdx.x; e < kWTile / 2 * NCB * 4; e += kThreads) {
+            const int pp = 2 * (e % (kWTile / 2)), c = (e / (kWTile / 2)) * 4;
             const int a1 = pp >> 6, a2 = (pp >> 4) & 3, a3 = pp & 15;
             const long p = ((long)(o1 + a1) * n + o2 + a2) * n + o3 + a3;
-            const v4s v = *reinterpret_cast<const v4s *>(a.dz + p * a.dz_cs + c);
+            const v4s v0 = *reinterpret_cast<const v4s *>(a.dz + p * a.dz_cs + c);
+            const v4s v1 = *reinterpret_cast<const v4s *>(a.dz + (p + 1) * a.dz_cs + c);
 #pragma unroll
-            for (int i = 0; i < 4; i++) sdz[(c + i) * kWPitchZ + pp] = (uint16_t)v[i];
+            for (int i = 0; i < 4; i++)
+                *reinterpret_cast<uint32_t *>(sdz + (c + i) * kWPitchZ + pp) =
+                    (uint32_t)(uint16_t)v0[i] | ((uint32_t)(uint16_t)v1[i] << 16);
         }
-        // halo planes h1 = z .. z + 3 of channels [ci0, ci0 + 16), 8 channels a load
-        for (int e = threadIdx.x; e < kCT1 * kCH2 * kCH3 * 2; e += kThreads) {
-            const int hp = e >> 1, half = e & 1;
-            const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = z + hp / (kCH3 * kCH2);
-            const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
-            const long q = ((long)x1 * n + x2) * n + x3;
-            const v8s v = *reinterpret_cast<const v8s *>(a.x + q * a.x_cs + ci0 + 8 * half);
+        // halo planes h1 = z .. z + 3 of channels [ci0, ci0 + 16): points h3,
+        // h3 + 1 (h3 even) of 8 channels a thread, two points per 32-bit store
+        // (the channel half is the slow index, for the same reason)
+        constexpr int kXPairs = kCT1 * kCH2 * (kCH3 / 2);
+        for (int e = threadIdx.x; e < kXPairs * 2; e += kThreads) {
+            const int hp2 = e % kXPairs, half = e / kXPairs;
+            const int h3 = 2 * (hp2 % (kCH3 / 2)), h2 = (hp2 / (kCH3 / 2)) % kCH2, h1 = z + hp2 / ((kCH3 / 2) * kCH2);
+            const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n);
+            const int x3a = wrap(o3 + h3 - 1, n), x3b = wrap(o3 + h3, n);
+            const long q = ((long)x1 * n + x2) * n;
+            const v8s v0 = *reinterpret_cast<const v8s *>(a.x + (q + x3a) * a.x_cs + ci0 + 8 * half);
+            const v8s v1 = *reinterpret_cast<const v8s *>(a.x + (q + x3b) * a.x_cs + ci0 + 8 * half);
             const int row = (h1 * kCH2 + h2) * kWRowX + h3;
 #pragma unroll
-            for (int i = 0; i < 8; i++) sx[(8 * half + i) * kWPitchX + row] = (uint16_t)v[i];
+            for (int i = 0; i < 8; i++)
+                *reinterpret_cast<uint32_t *>(sx + (8 * half + i) * kWPitchX + row) =
+                    (uint32_t)(uint16_t)v0[i] | ((uint32_t)(uint16_t)v1[i] << 16);
         }
         __syncthreads();
         if (blockIdx.y == 0 && z == 0 && threadIdx.x < cout) {
