@@ -200,3 +200,35 @@ def test_batch_solve_matches_single(reg, cases):
                   "final_mismatch", "J", "mismatch", "pcg_iters", "ls_trials", "interps"):
             assert reps[i][k] == rep[k], f"{k} of problem {i}"
         assert rep["final_mismatch"] < 1.0
+
+
+def test_failing_problem_leaves_the_others_untouched(reg, cases):
+    """A NaN in one problem's reference image: that problem stops with
+    REG_ENONFINITE at its first gradient (v left at its initial value), the
+    batch returns that status, and every other problem still solves exactly
+    as it does alone."""
+    kw = dict(max_newton=3, max_pcg=8, gtol=1e-3)
+    bad = 1
+    b = reg.Batch([_params(reg, s, nt, iso, **kw) for s, nt, iso in PROBLEMS])
+    for i, c in enumerate(cases):
+        ctx = b.contexts[i]
+        rhoR = c["rhoR"].copy()
+        if i == bad:
+            rhoR[3, 5, 7] = np.nan
+        b.reg_set_images(i, to_dev(c["rhoT"], ctx), to_dev(rhoR, ctx))
+    with pytest.raises(reg.RegError) as e:
+        b.reg_batch_solve()
+    assert e.value.status == reg.REG_ENONFINITE
+    vb, reps = b.reg_batch_solve(raise_on_error=False)
+    torch.cuda.synchronize()
+    say("  " + ", ".join(f"status {r['status']} {r['n_iter']} it" for r in reps))
+    assert reps[bad]["status"] == reg.REG_ENONFINITE and reps[bad]["n_iter"] == 0
+    assert torch.count_nonzero(vb[bad]).item() == 0
+    singles = _singles(reg, cases, **kw)
+    for i, ctx in enumerate(singles):
+        if i == bad:
+            continue
+        v, rep = ctx.reg_solve()
+        torch.cuda.synchronize()
+        assert reps[i]["status"] == 0 and torch.equal(vb[i], v), f"problem {i}"
+        assert reps[i]["pcg_iters"] == rep["pcg_iters"] and reps[i]["final_J"] == rep["final_J"]
