@@ -118,7 +118,25 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
             src[m] = in + (long)q * a.in_cs + 4 * g;
         }
         const uint16_t *wt = W + ((long)t * a.cout + 16 * NB * blockIdx.y + r) * a.cin + 4 * g;
-        for (int c = 0; c < ccin; c++) {
+        int c = 0;
+        if constexpr (MB == 1 && NB == 1) {
+            // the small grids' form (one wavefront per SIMD, nothing else to
+            // hide a fragment load behind): four channel chunks' loads in
+            // flight before their matrix products, in the same order of
+            // accumulation
+            for (; c + 4 <= ccin; c += 4) {
+                v4s av4[4], bv4[4];
+#pragma unroll
+                for (int q = 0; q < 4; q++) {
+                    av4[q] = ok[0] ? *reinterpret_cast<const v4s *>(src[0] + 16 * (c + q)) : v4s{0, 0, 0, 0};
+                    bv4[q] = *reinterpret_cast<const v4s *>(wt + 16 * (c + q));
+                }
+#pragma unroll
+                for (int q = 0; q < 4; q++)
+                    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av4[q], bv4[q], acc[0][0], 0, 0, 0);
+            }
+        }
+        for (; c < ccin; c++) {
             v4s av[MB], bv[NB];
 #pragma unroll
             for (int m = 0; m < MB; m++)
