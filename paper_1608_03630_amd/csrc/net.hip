@@ -173,6 +173,76 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
         }
 }
 
+// Backward data of a stride-2 convolution (CONV_BWD2) by output parity. An
+// output point (2I + p1, 2J + p2, 2K + p3) of the fine grid receives only the
+// taps whose offset has the parity of p along every axis (d = 0 for p = 0,
+// d = +1 or -1 for p = 1: 1 to 8 of the 27 taps), whose sources are I (and
+// I + 1 for d = -1). A wavefront takes 16 points of one parity class along
+// x3 and all NB output channel blocks, and runs only those taps, in the
+// order of the general kernel: the products it skips are exact zeros, so
+// the result is the same.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_conv_bwd2(ConvArgs a) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+    const int nc = a.n_in, nf = a.n_out, kb = nc / 16;
+    long w = (long)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);  // wavefront index
+    if (w >= 8L * nc * nc * kb) return;
+    const int K0 = (int)(w % kb) * 16;
+    w /= kb;
+    const int J = (int)(w % nc);
+    w /= nc;
+    const int I = (int)(w % nc), cls = (int)(w / nc);
+    const int p1 = cls >> 2, p2 = (cls >> 1) & 1, p3 = cls & 1;
+    v4f acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; b++) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+    const int ccin = a.cin >> 4;
+    const int K = K0 + r;  // this lane's A-row point
+    // taps per axis: d = 0 (source I) for even p, d = -1 (source I + 1) and
+    // d = +1 (source I) for odd p, in ascending d
+    for (int u1 = 0; u1 <= p1; u1++) {
+        const int d1 = p1 ? 2 * u1 - 1 : 0, s1 = d1 < 0 ? (I + 1 == nc ? 0 : I + 1) : I;
+        for (int u2 = 0; u2 <= p2; u2++) {
+            const int d2 = p2 ? 2 * u2 - 1 : 0, s2 = d2 < 0 ? (J + 1 == nc ? 0 : J + 1) : J;
+            for (int u3 = 0; u3 <= p3; u3++) {
+                const int d3 = p3 ? 2 * u3 - 1 : 0, s3 = d3 < 0 ? (K + 1 == nc ? 0 : K + 1) : K;
+                const int t = (d1 + 1) * 9 + (d2 + 1) * 3 + (d3 + 1);
+                const uint16_t *src = a.in + ((long)(s1 * nc + s2) * nc + s3) * a.in_cs + 4 * g;
+                const uint16_t *wt = a.w + ((long)t * a.cout + r) * a.cin + 4 * g;
+                for (int c = 0; c < ccin; c++) {
+                    const v4s av = *reinterpret_cast<const v4s *>(src + 16 * c);
+#pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        const v4s bv = *reinterpret_cast<const v4s *>(wt + (long)b * 16 * a.cin + 16 * c);
+                        acc[b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[b], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // epilogue: lane holds D[4g+i][r] = (point K0+4g+i of the class row, channel b*16+r)
+    const long P = (long)nf * nf * nf;
+    const long prow = ((long)(2 * I + p1) * nf + (2 * J + p2)) * nf + p3;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const int co = b * 16 + r;
+        const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const long p = prow + 2 * (K0 + 4 * g + i);
+            float v = acc[b][i] + bias;
+            if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
+            if (a.relu) v = fmaxf(v, 0.f);
+            if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
+            if (a.out_f32) {
+                if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
+            } else {
+                a.out[p * a.out_cs + co] = f2bf(v);
+            }
+        }
+    }
+}
+
 // Stride-1 convolutions (forward and backward data) as an LDS-tiled implicit
 // GEMM. A workgroup owns a 4 x 4 x 16 tile of output points. For each chunk
 // of 16 input channels it stages the tile's 6 x 6 x 18 halo in LDS
@@ -828,6 +898,14 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
         if (mode == CONV_FWD1) REGN_TILED(CONV_FWD1);
         else REGN_TILED(CONV_BWD1);
 #undef REGN_TILED
+        return hipGetLastError();
+    }
+    if (mode == CONV_BWD2 && a.n_out == 2 * a.n_in && a.n_in % 16 == 0) {
+        const long waves = 8L * a.n_in * a.n_in * (a.n_in / 16);
+        const dim3 g2((unsigned)((waves + 3) / 4));
+        if (NB == 1) hipLaunchKernelGGL(k_conv_bwd2<1>, g2, dim3(kThreads), 0, s, a);
+        else if (NB == 2) hipLaunchKernelGGL(k_conv_bwd2<2>, g2, dim3(kThreads), 0, s, a);
+        else hipLaunchKernelGGL(k_conv_bwd2<4>, g2, dim3(kThreads), 0, s, a);
         return hipGetLastError();
     }
     const unsigned nb = (unsigned)((P / (wide ? 64 : 16) + 3) / 4);
