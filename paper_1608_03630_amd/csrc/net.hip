@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
 // d = +1 or -1 for p = 1: 1 to 8 of the 27 taps), whose sources are I (and
 // I + 1 for d = -1). A wavefront takes 16 points of one parity class along
 // x3 and all NB output channel blocks, and runs only those taps, in the
-// order of the general kernel: the products it skips are exact zeros, so
-// the result is the same.
+// order of the general kernel: the products it skips are those of zero
+// activations, which add nothing to the general kernel's sums.
 template <int NB>
 __global__ __launch_bounds__(kThreads) void k_conv_bwd2(ConvArgs a) {
     const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
