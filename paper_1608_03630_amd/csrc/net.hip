@@ -908,11 +908,14 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
         else hipLaunchKernelGGL(k_conv_bwd2<4>, g2, dim3(kThreads), 0, s, a);
         return hipGetLastError();
     }
-    const unsigned nb = (unsigned)((P / (wide ? 64 : 16) + 3) / 4);
-    const dim3 grid(nb, wide ? 1 : NB);
+    // a stride-2 forward onto a 32^3 grid takes the small-grid form too:
+    // with 64 points per wavefront it would fill only half of the SIMDs
+    const bool wide_direct = wide && !(mode == CONV_FWD2 && P <= 32768);
+    const unsigned nb = (unsigned)((P / (wide_direct ? 64 : 16) + 3) / 4);
+    const dim3 grid(nb, wide_direct ? 1 : NB);
 #define REGN_CONV(M)                                                                                  \
     do {                                                                                              \
-        if (!wide) hipLaunchKernelGGL((k_conv<M, 1, 1>), grid, dim3(kThreads), 0, s, a);             \
+        if (!wide_direct) hipLaunchKernelGGL((k_conv<M, 1, 1>), grid, dim3(kThreads), 0, s, a);      \
         else if (NB == 1) hipLaunchKernelGGL((k_conv<M, 1, 4>), grid, dim3(kThreads), 0, s, a);      \
         else if (NB == 2) hipLaunchKernelGGL((k_conv<M, 2, 4>), grid, dim3(kThreads), 0, s, a);      \
         else hipLaunchKernelGGL((k_conv<M, 4, 4>), grid, dim3(kThreads), 0, s, a);                   \
