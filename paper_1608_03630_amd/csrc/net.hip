@@ -173,6 +173,67 @@ __global__ __launch_bounds__(kThreads) void k_conv(ConvArgs a) {
         }
 }
 
+// The small-grid form with the taps split over the workgroup: its four
+// wavefronts share one block of 16 output points and one 16-channel output
+// block, each runs the taps t = w, w + 4, ... (7, 7, 7, 6 of them), and the
+// four partial sums are added in a fixed order through LDS. On a 16^3 grid
+// the general kernel leaves one wavefront per SIMD running 27 taps in a row,
+// each waiting on its fragment loads; here there are four, with a quarter of
+// the taps each.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_conv_ksplit(ConvArgs a) {
+    __shared__ v4f red[kThreads / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, r = lane & 15;
+    const int n = a.n_out;
+    const long p0 = (long)blockIdx.x * 16;  // P is a multiple of 16: every block is whole
+    const long pa = p0 + r;
+    const int i = (int)(pa / ((long)n * n)), j = (int)((pa / n) % n), k = (int)(pa % n);
+    int c1[3], c2[3], c3[3];
+#pragma unroll
+    for (int d = -1; d <= 1; d++) {
+        c1[d + 1] = source_axis<MODE>(i, d, a.n_out, a.n_in);
+        c2[d + 1] = source_axis<MODE>(j, d, a.n_out, a.n_in);
+        c3[d + 1] = source_axis<MODE>(k, d, a.n_out, a.n_in);
+    }
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    const int ccin = a.cin >> 4;
+    for (int t = wave; t < 27; t += kThreads / 64) {
+        const int x1 = c1[t / 9], x2 = c2[(t / 3) % 3], x3 = c3[t % 3];
+        const bool ok = (x1 | x2 | x3) >= 0;
+        const uint16_t *src = a.in + (long)(ok ? (x1 * a.n_in + x2) * a.n_in + x3 : 0) * a.in_cs + 4 * g;
+        const uint16_t *wt = a.w + ((long)t * a.cout + 16 * (int)blockIdx.y + r) * a.cin + 4 * g;
+        for (int c = 0; c < ccin; c++) {
+            const v4s av = ok ? *reinterpret_cast<const v4s *>(src + 16 * c) : v4s{0, 0, 0, 0};
+            const v4s bv = *reinterpret_cast<const v4s *>(wt + 16 * c);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+        }
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0) return;
+    v4f sum = red[0][lane];
+#pragma unroll
+    for (int w = 1; w < kThreads / 64; w++) sum += red[w][lane];
+    // epilogue: lane holds D[4g+i][r] = (point p0+4g+i, channel blockIdx.y*16+r)
+    const long P = (long)n * n * n;
+    const int co = (int)blockIdx.y * 16 + r;
+    const float bias = (a.bias && co < a.cout_real) ? a.bias[co] : 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const long p = p0 + 4 * g + q;
+        float v = sum[q] + bias;
+        if (a.add) v += bf2f(a.add[p * a.add_cs + co]);
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask && !(bf2f(a.mask[p * a.mask_cs + co]) > 0.f)) v = 0.f;
+        if (a.out_f32) {
+            if (co < a.cout_real) a.out_f32[(long)co * P + p] = v;
+        } else {
+            a.out[p * a.out_cs + co] = f2bf(v);
+        }
+    }
+}
+
 // Backward data of a stride-2 convolution (CONV_BWD2) by output parity. An
 // output point (2I + p1, 2J + p2, 2K + p3) of the fine grid receives only the
 // taps whose offset has the parity of p along every axis (d = 0 for p = 0,
@@ -906,6 +967,17 @@ hipError_t launch_conv(int mode, const ConvArgs &a, hipStream_t s) {
         if (NB == 1) hipLaunchKernelGGL(k_conv_bwd2<1>, g2, dim3(kThreads), 0, s, a);
         else if (NB == 2) hipLaunchKernelGGL(k_conv_bwd2<2>, g2, dim3(kThreads), 0, s, a);
         else hipLaunchKernelGGL(k_conv_bwd2<4>, g2, dim3(kThreads), 0, s, a);
+        return hipGetLastError();
+    }
+    // the 16^3 grid (and smaller): taps split over each workgroup's waves
+    if (P <= 4096 && mode != CONV_BWD2) {
+        const dim3 gk((unsigned)(P / 16), NB);
+        switch (mode) {
+        case CONV_FWD1: hipLaunchKernelGGL(k_conv_ksplit<CONV_FWD1>, gk, dim3(kThreads), 0, s, a); break;
+        case CONV_FWD2: hipLaunchKernelGGL(k_conv_ksplit<CONV_FWD2>, gk, dim3(kThreads), 0, s, a); break;
+        case CONV_BWD1: hipLaunchKernelGGL(k_conv_ksplit<CONV_BWD1>, gk, dim3(kThreads), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     // a stride-2 forward onto a 32^3 grid takes the small-grid form too:
