@@ -183,8 +183,9 @@ def test_batch_gradient_and_graph_matvec_match_single(reg, cases):
         assert torch.equal(eager[i], H), f"eager matvec, problem {i}"
 
 
-def test_batch_solve_matches_single(reg, cases):
-    kw = dict(max_newton=3, max_pcg=8, gtol=1e-3)
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_solve_matches_single(reg, cases, prec):
+    kw = dict(max_newton=3, max_pcg=8, gtol=1e-3, prec=prec)
     b = _batch(reg, cases, **kw)
     vb, reps = b.reg_batch_solve()
     torch.cuda.synchronize()
