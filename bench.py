@@ -82,6 +82,29 @@ def make_workload(reg, torch, n, seed=1003):
     return ctx, rhoT, rhoR, v_true
 
 
+def run_grid_sweep(reg, torch, n):
+    """Grid continuation on the benchmark workload (one context with room for
+    three grids): each (grids, level tolerance) setting solved twice from
+    v = 0 and the second solve reported with its per-grid breakdown, one JSON
+    line per setting."""
+    global GRID_LEVELS
+    GRID_LEVELS = 3
+    warm_small(reg, torch)
+    ctx, rhoT, rhoR, v_true = make_workload(reg, torch, n)
+    v = torch.zeros((3,) + ctx.shape, dtype=torch.float64, device="cuda")
+    for grids, gl in [(1, 0.3), (2, 0.3), (3, 0.3), (2, 0.0), (3, 0.0), (3, 0.1)]:
+        ctx.reg_set_solver(solve_params(reg, ctx.shape, METRIC_BETA_FINAL, gl, grid_levels=grids))
+        for _ in range(2):
+            v.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep = ctx.reg_solve(v)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        print(json.dumps({"mode": "grid", "grids": grids, "gtol_level": gl, "seconds": dt,
+                          "final_mismatch": rep["final_mismatch"], "levels": rep["levels"]}), flush=True)
+
+
 def warm_small(reg, torch):
     """One 64^3 solve so that every kernel has been loaded and run."""
     import numpy as np
@@ -595,14 +618,15 @@ def main():
     ap.add_argument("--traffic", type=str, default=os.path.join(ROOT, "profiles", "traffic_256.json"),
                     help="rocprof traffic record of the dominant kernel (see paper_1608_03630_amd/profiling.py); "
                          "used only if it was taken on the current kernel sources")
-    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net", "oracle", "config2"],
+    ap.add_argument("--mode", choices=["solve", "kernels", "copy", "batch", "net", "oracle", "config2", "grid"],
                     default="solve",
                     help="solve: the benchmark; kernels: one gradient and three Gauss-Newton matvecs of the same "
                          "workload (a short run for hardware-counter passes); copy: a 256 MiB device copy, the "
                          "calibration of the byte counters; batch: 24 mixed-size pairs solved as one batch; net: "
                          "forward pass and training step of the 64^3 warm-start network against the BF16 MFMA peak; "
                          "oracle: the host-side timing plan of the FP64 oracle (minutes; no GPU); config2: the "
-                         "128^3 isochoric blob problem solved with FP32 and with FP64 fields")
+                         "128^3 isochoric blob problem solved with FP32 and with FP64 fields; grid: the benchmark "
+                         "solved with one, two and three grids of continuation and three level tolerances")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the slab decomposition over several GPUs "
@@ -641,6 +665,9 @@ def main():
         return
     if args.mode == "config2":
         run_config2(reg, torch)
+        return
+    if args.mode == "grid":
+        run_grid_sweep(reg, torch, args.n)
         return
     if args.mode == "kernels":
         ctx, rhoT, rhoR, v_true = make_workload(reg, torch, args.n)
