@@ -318,13 +318,14 @@ constexpr int kCH1 = kCT1 + 2, kCH2 = kCT2 + 2, kCH3 = kCT3 + 2;  // its halo
 constexpr int kCHalo = kCH1 * kCH2 * kCH3;                        // 648 points
 
 // Halo points are 32 bytes (16 channels), so the 16 points of one MFMA row
-// block (consecutive h3) would put the same 8-byte channel group of every
-// fourth point in the same LDS banks. The four 8-byte groups of a point are
-// therefore stored rotated by an XOR with (h3 / 4) mod 4: any four points of
-// a row block that share banks then read four different positions. The swizzle
-// depends on h3 only, so reads of the same h3 in other (h1, h2) rows keep one
-// base address.
-__device__ __forceinline__ int halo_group(int h3, int grp) { return grp ^ ((h3 >> 2) & 3); }
+// block (consecutive h3) would put the same 8-byte channel group of points
+// eight apart in the same LDS banks. The halo is staged by 16-byte direct
+// loads, which move whole halves of a point, so the two halves trade places
+// where bit 3 of h3 is set: points h3 and h3 + 8 then read different
+// positions. The swizzle depends on h3 only, so reads of the same h3 in other
+// (h1, h2) rows keep one base address.
+__device__ __forceinline__ int halo_swap(int h3) { return (h3 >> 3) & 1; }
+__device__ __forceinline__ int halo_group(int h3, int grp) { return grp ^ (halo_swap(h3) << 1); }
 // The staged weights take 16-byte slots (the direct loads move whole pieces),
 // so only the two halves of an output's 16 inputs can trade places: rows
 // 8..15 store them swapped.
@@ -353,9 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
         for (int b = 0; b < NB; b++) acc[m][b] = v4f{0.f, 0.f, 0.f, 0.f};
     const int ccin = a.cin >> 4;
     for (int c = 0; c < ccin; c++) {
-        // halo of channels [16c, 16c + 16): two 16-byte pieces per point,
-        // all of a thread's pieces requested before the first LDS store (the
-        // kernel waits on these loads, not on the matrix cores)
+        // halo of channels [16c, 16c + 16): two 16-byte pieces per point
         constexpr int kPieces = (kCHalo * 2 + kThreads - 1) / kThreads;
         // weights: 16-byte piece e = ((t NB + b) 16 + r) 2 + sh holds eight
         // inputs of output channel (cb0 + b) 16 + r of tap t, loaded straight
@@ -376,30 +375,23 @@ __global__ __launch_bounds__(kThreads) void k_conv_tiled(ConvArgs a) {
                                                  (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
             }
         }
-        v8s piece[kPieces];
+        // halo piece e (half sh of point hp = e / 2) goes straight into LDS at
+        // byte 16 e, holding the point's channel half sh ^ halo_swap(h3)
 #pragma unroll
         for (int u = 0; u < kPieces; u++) {
             const int e = threadIdx.x + u * kThreads;
             if (e < kCHalo * 2) {
-                const int hp = e >> 1, half = e & 1;
+                const int hp = e >> 1, sh = e & 1;
                 const int h3 = hp % kCH3, h2 = (hp / kCH3) % kCH2, h1 = hp / (kCH3 * kCH2);
                 const int x1 = wrap(o1 + h1 - 1, n), x2 = wrap(o2 + h2 - 1, n), x3 = wrap(o3 + h3 - 1, n);
                 const long q = ((long)x1 * n + x2) * n + x3;
-                piece[u] = *reinterpret_cast<const v8s *>(a.in + q * a.in_cs + 16 * c + 8 * half);
+                const uint16_t *src = a.in + q * a.in_cs + 16 * c + 8 * (sh ^ halo_swap(h3));
+                uint16_t *dst = halo + 8 * (u * kThreads + 64 * wave);
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                                 (__attribute__((address_space(3))) void *)dst, 16, 0, 0);
             }
         }
-#pragma unroll
-        for (int u = 0; u < kPieces; u++) {
-            const int e = threadIdx.x + u * kThreads;
-            if (e < kCHalo * 2) {
-                // groups 2 half and 2 half + 1 of point hp land in the 16-byte
-                // slot half ^ (s / 2), in swapped order when s is odd
-                const int hp = e >> 1, half = e & 1, sw = halo_group(hp % kCH3, 0);
-                const v8s v = (sw & 1) ? __builtin_shufflevector(piece[u], piece[u], 4, 5, 6, 7, 0, 1, 2, 3) : piece[u];
-                *reinterpret_cast<v8s *>(halo + hp * 16 + 8 * (half ^ (sw >> 1))) = v;
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(0);  // the direct weight loads have landed in LDS
+        __builtin_amdgcn_s_waitcnt(0);  // the direct halo and weight loads have landed in LDS
         __syncthreads();
         // nine (d1, d2) rows of taps, the three d3 taps of a row unrolled
 #pragma unroll 1
