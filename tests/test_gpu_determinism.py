@@ -2,10 +2,12 @@
 order-dependent reductions: every sum (the FP64 inner products, the b
 quadrature, the network's weight gradients) has a fixed tree. So the same
 call on the same inputs gives the same bits, in a second call on the same
-context, and in a fresh context whose workspace was filled with NaN before
-it was handed over (nothing reads workspace memory it has not written).
+context, and in a fresh context created on a workspace filled with NaN bytes
+(nothing reads workspace memory it has not written).
 Checked for the gradient, the Hessian matvec, the forward transport and a
 whole solve (velocity and report), in both precisions."""
+import ctypes
+
 import pytest
 import torch
 
@@ -30,16 +32,23 @@ def reg():
 
 
 def _poisoned_context(reg, p):
-    """A context whose workspace is a block the caching allocator just held
-    as NaN bytes."""
+    """A context created by reg_create on a workspace that holds NaN bytes
+    (0xFF) everywhere; close it with _close_poisoned."""
     nbytes = reg.reg_workspace_size(p)
-    junk = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
-    ptr = junk.data_ptr()
+    ws = torch.full((nbytes,), 0xFF, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    del junk
-    ctx = reg.Context(p)
-    assert ctx.workspace.data_ptr() == ptr, "the workspace did not reuse the poisoned block"
+    h = ctypes.c_void_p()
+    reg._chk(reg.lib().reg_create(ctypes.byref(p), ctypes.c_void_p(ws.data_ptr()), nbytes, reg._stream_ptr(None),
+                                  ctypes.byref(h)), what="reg_create")
+    ctx = reg.Context(p, borrowed=h)
+    ctx.poisoned_workspace = ws  # the context's memory: kept alive with it
     return ctx
+
+
+def _close_poisoned(reg, ctx):
+    torch.cuda.synchronize()
+    reg.lib().reg_destroy(ctx.handle)
+    ctx.handle = None
 
 
 def _calls(ctx, rhoT, rhoR, v, vt):
@@ -66,7 +75,7 @@ def test_repeat_and_fresh_context_give_the_same_bits(reg, shape, nt, iso, prec):
     ctx.close()
     ctx2 = _poisoned_context(reg, p)
     c, sc = _calls(ctx2, rhoT, rhoR, v, vt)
-    ctx2.close()
+    _close_poisoned(reg, ctx2)
     for name, x, y, z in zip(("gradient", "matvec", "transport"), a, b, c):
         assert torch.equal(x, y), f"{name}: second call differs"
         assert torch.equal(x, z), f"{name}: fresh context differs"
@@ -90,7 +99,10 @@ def test_solve_is_reproducible(reg, prec):
         vel, rep = ctx.reg_solve()
         torch.cuda.synchronize()
         runs.append((vel.clone(), {k: rep[k] for k in REPORT_KEYS}))
-        ctx.close()
+        if fresh:
+            _close_poisoned(reg, ctx)
+        else:
+            ctx.close()
     (v0, r0), (v1, r1), (v2, r2) = runs
     assert torch.equal(v0, v1) and torch.equal(v0, v2)
     assert r0 == r1 == r2
