@@ -23,7 +23,7 @@ template <> struct cplx_of<float> { using type = float2; };
 template <> struct cplx_of<double> { using type = double2; };
 template <typename T> using cplx_t = typename cplx_of<T>::type;
 
-// Radix plan of one line length: radices 4, then 2, then 3 (Stockham order).
+// Radix plan of one line length: radices 8, then 4, 2, 3 and 5 (Stockham order).
 struct FftPlan {
     int n;
     int npass;

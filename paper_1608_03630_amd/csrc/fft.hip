@@ -5,7 +5,7 @@
 //
 // Line FFTs of any length 2^a 3^b 5^c up to 1024 run in LDS: a workgroup
 // stages L complex lines of one axis as a [j][l] tile (pitch >= L), runs a
-// Stockham autosort FFT with radix-4/2/3/5 passes between two LDS buffers,
+// Stockham autosort FFT with radix-8/4/2/3/5 passes between two LDS buffers,
 // and writes the tile back. 256-point lines (two radix-16 passes) keep each
 // thread's 16 elements in registers instead, with one LDS exchange between
 // the passes, reading and writing HBM directly in the 3D transforms. For
@@ -23,6 +23,10 @@ bool make_plan(int n, FftPlan *p) {
     p->n = n;
     p->npass = 0;
     int m = n;
+    while (m % 8 == 0 && p->npass < 12) {
+        p->radix[p->npass++] = 8;
+        m /= 8;
+    }
     while (m % 4 == 0 && p->npass < 12) {
         p->radix[p->npass++] = 4;
         m /= 4;
@@ -93,11 +97,34 @@ __device__ __forceinline__ C cmul_si(C a, int sign) {
     return r;
 }
 
-// R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4, 5}
+// R-point DFT with kernel exp(sign 2 pi i r q / R), R in {2, 3, 4, 5, 8}
 template <typename T, int R>
 __device__ __forceinline__ void butterfly(cplx_t<T> *v, int sign) {
     using C = cplx_t<T>;
-    if (R == 4) {
+    if (R == 8) {
+        // even and odd samples through 4-point DFTs, then X_k = E_k + w^k O_k
+        // and X_{k+4} = E_k - w^k O_k with w = exp(sign 2 pi i / 8) =
+        // h (1 + sign i), w^2 = sign i, w^3 = h (-1 + sign i), h = sqrt(2)/2
+        C e[4] = {v[0], v[2], v[4], v[6]}, o[4] = {v[1], v[3], v[5], v[7]};
+        butterfly<T, 4>(e, sign);
+        butterfly<T, 4>(o, sign);
+        const T h = T(0.70710678118654752440084436210485);
+        C t1 = cadd(o[1], cmul_si(o[1], sign));
+        t1.x *= h;
+        t1.y *= h;
+        const C t2 = cmul_si(o[2], sign);
+        C t3 = csub(cmul_si(o[3], sign), o[3]);
+        t3.x *= h;
+        t3.y *= h;
+        v[0] = cadd(e[0], o[0]);
+        v[4] = csub(e[0], o[0]);
+        v[1] = cadd(e[1], t1);
+        v[5] = csub(e[1], t1);
+        v[2] = cadd(e[2], t2);
+        v[6] = csub(e[2], t2);
+        v[3] = cadd(e[3], t3);
+        v[7] = csub(e[3], t3);
+    } else if (R == 4) {
         const C s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
         const C s13 = cadd(v[1], v[3]), d13 = cmul_si(csub(v[1], v[3]), sign);
         v[0] = cadd(s02, s13);
@@ -272,7 +299,8 @@ __device__ cplx_t<T> *lds_fft(cplx_t<T> *a, cplx_t<T> *b, const FftPlan &pl, int
     int Ns = 1;
     for (int ps = 0; ps < pl.npass; ps++) {
         const int R = pl.radix[ps];
-        if (R == 4) fft_pass<T, 4>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        if (R == 8) fft_pass<T, 8>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
+        else if (R == 4) fft_pass<T, 4>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         else if (R == 2) fft_pass<T, 2>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         else if (R == 3) fft_pass<T, 3>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
         else fft_pass<T, 5>(a, b, pl.n, Ns, lgL, pitch, sign, tw);
