@@ -73,7 +73,8 @@ def test_workspace_size_scales_with_grid(lib):
     assert 7.5 < b / a < 8.5 and 1.2 < c / b < 2.0
 
 
-@pytest.mark.parametrize("bad", [dict(n=(14, 32, 32)), dict(n=(32, 32, 22)), dict(n=(32, 32, 6)),
+@pytest.mark.parametrize("bad", [dict(n=(0, 32, 32)), dict(n=(0, 0, 0)), dict(n=(-8, 32, 32)),
+                                 dict(n=(14, 32, 32)), dict(n=(32, 32, 22)), dict(n=(32, 32, 6)),
                                  dict(n=(32, 15, 32)), dict(n=(2048, 8, 8)), dict(nt=0), dict(beta=0.0),
                                  dict(beta=-1.0), dict(prec=2), dict(max_pcg=0), dict(gtol=-1.0), dict(hessian=2),
                                  dict(det_check=2), dict(grid_levels=5), dict(n=(24, 24, 24), grid_levels=3),
@@ -137,6 +138,28 @@ def test_batch_rejects_mixed_precision_and_bad_problems(lib):
     arr = (reg.reg_params * 1)(reg.reg_default_params(32))
     assert lib.reg_batch_create(arr, 1, None, 1 << 30, None, ctypes.byref(h)) == reg.REG_EINVAL and not h.value
     assert lib.reg_batch_create(arr, 0, None, 1 << 30, None, ctypes.byref(h)) == reg.REG_EINVAL
+
+
+def test_empty_batch_is_rejected(lib):
+    from paper_1608_03630_amd import reg
+
+    p = reg.reg_default_params(32)
+    b = ctypes.c_size_t(7)
+    for npairs in (0, -1):
+        assert lib.reg_batch_workspace_size(ctypes.byref(p), npairs, ctypes.byref(b)) == reg.REG_EINVAL
+
+
+@pytest.mark.parametrize("prec,n,alias", [(2, (8, 8, 8), False), (0, None, False), (0, (0, 8, 8), False),
+                                          (0, (8, 0, 8), False), (1, (8, 8, -8), False), (0, (2048, 8, 8), False),
+                                          (0, (8, 8, 9), False), (0, (8, 8, 8), True)])
+def test_noalloc_interp_rejects_bad_arguments_before_the_device(lib, prec, n, alias):
+    # every check here precedes the first HIP call, so the placeholder
+    # addresses are never dereferenced
+    from paper_1608_03630_amd import reg
+
+    nn = (ctypes.c_int32 * 3)(*n) if n is not None else None
+    f, D, out = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x1000 if alias else 0x3000)
+    assert lib.reg_interp_noalloc(prec, nn, f, D, out, None) == reg.REG_EINVAL
 
 
 def test_product_package_does_not_reach_the_oracle():
